@@ -1,0 +1,24 @@
+"""CPU FP64 oracle — TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never calls it and
+shares no code with it.
+
+Contents
+  mg_oracle.c   plain C: operator, right-hand side, CG, lexicographic
+                Gauss-Seidel V-cycle (built into liboracle.so by build.py)
+  oracle.py     ctypes front end + a pure-Python dense assembly for tiny grids
+  nn_oracle.py  FP64 NumPy forward/backward of the 3D conv network layers
+"""
+from .oracle import (  # noqa: F401
+    build,
+    apply,
+    rhs,
+    residual,
+    solve_cg,
+    solve_vcycle,
+    solve_reference,
+    dense_matrix,
+    dense_solve,
+    num_levels,
+)

@@ -1,0 +1,206 @@
+"""Front end of the CPU FP64 oracle (test infrastructure only).
+
+The heavy lifting is plain C in ``mg_oracle.c``; this module compiles it with
+gcc, marshals NumPy arrays through ctypes and adds a pure-Python dense
+assembly of the same discrete operator for tiny grids (brute-force checks).
+
+Discrete problem (paper Sec. 2: potential and radiative-transfer equations,
+second-order cell-centred finite volumes; see mg_oracle.c for the formulas):
+
+    (A u)_P = a u_P + h^-2 [ sum_interior beta_f (u_P - u_N) + sum_Dirichlet 2 beta_P u_P ]
+    b_P     = f_P + h^-2 sum_Dirichlet 2 beta_P g
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mg_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+DIRICHLET, NEUMANN = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (OpenMP for the CG vector loops)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-march=x86-64-v3", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+               "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+                build(force=True)
+            lib = ctypes.CDLL(_LIB_PATH)
+            dp = ctypes.POINTER(ctypes.c_double)
+            ip = ctypes.POINTER(ctypes.c_int)
+            c_int, c_dbl = ctypes.c_int, ctypes.c_double
+            lib.orc_apply.argtypes = [c_int, c_int, c_int, c_dbl, c_dbl, dp, ip, dp, dp]
+            lib.orc_apply.restype = None
+            lib.orc_rhs.argtypes = [c_int, c_int, c_int, c_dbl, c_dbl, dp, ip, dp, dp, dp]
+            lib.orc_rhs.restype = None
+            lib.orc_residual.argtypes = [c_int, c_int, c_int, c_dbl, c_dbl, dp, ip, dp, dp, dp, dp, dp]
+            lib.orc_residual.restype = c_dbl
+            lib.orc_cg.argtypes = [c_int, c_int, c_int, c_dbl, c_dbl, dp, ip, dp, dp, dp, c_dbl, c_int, dp]
+            lib.orc_cg.restype = c_int
+            lib.orc_vcycle_solve.argtypes = [c_int, c_int, c_int, c_dbl, c_dbl, dp, ip, dp, dp, dp, c_dbl,
+                                             c_int, c_int, c_int, c_int, dp, dp]
+            lib.orc_vcycle_solve.restype = c_int
+            lib.orc_num_levels.argtypes = [c_int, c_int, c_int, c_int]
+            lib.orc_num_levels.restype = c_int
+            _lib = lib
+    return _lib
+
+
+def _dp(arr: Optional[np.ndarray]):
+    if arr is None:
+        return ctypes.POINTER(ctypes.c_double)()
+    assert arr.dtype == np.float64 and arr.flags.c_contiguous
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _prob_args(p):
+    bct = np.array([DIRICHLET if t == "D" else NEUMANN for t in p.bc_types()], dtype=np.int32)
+    g = np.array(p.bc_values(), dtype=np.float64)
+    eps = None if p.eps is None else np.ascontiguousarray(p.eps, dtype=np.float64)
+    return bct, g, eps
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def apply(p, u: np.ndarray) -> np.ndarray:
+    """A u with homogeneous boundary values."""
+    lib = _load()
+    bct, _, eps = _prob_args(p)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.empty_like(u)
+    lib.orc_apply(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(u), _dp(out))
+    return out
+
+
+def rhs(p) -> np.ndarray:
+    """b = f plus the Dirichlet boundary terms."""
+    lib = _load()
+    bct, g, eps = _prob_args(p)
+    f = np.ascontiguousarray(p.f, dtype=np.float64)
+    b = np.empty_like(f)
+    lib.orc_rhs(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(g), _dp(f), _dp(b))
+    return b
+
+
+def residual(p, u: np.ndarray) -> Tuple[np.ndarray, float, float]:
+    """(r = b - A u, ||r||_2, ||b||_2)."""
+    lib = _load()
+    bct, g, eps = _prob_args(p)
+    f = np.ascontiguousarray(p.f, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    r = np.empty_like(f)
+    bn = ctypes.c_double(0.0)
+    rn = lib.orc_residual(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(g), _dp(f), _dp(u), _dp(r),
+                          ctypes.byref(bn))
+    return r, float(rn), float(bn.value)
+
+
+def solve_cg(p, rtol: float = 1e-13, maxit: int = 200000, u0: Optional[np.ndarray] = None):
+    """Plain CG; returns (u, iterations, relative residual)."""
+    lib = _load()
+    bct, g, eps = _prob_args(p)
+    f = np.ascontiguousarray(p.f, dtype=np.float64)
+    u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, order="C")
+    rel = ctypes.c_double(0.0)
+    it = lib.orc_cg(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(g), _dp(f), _dp(u), rtol, maxit,
+                    ctypes.byref(rel))
+    return u, int(it), float(rel.value)
+
+
+def solve_vcycle(p, rtol: float = 1e-13, max_cycles: int = 100, nu1: int = 2, nu2: int = 2,
+                 coarsest_max: int = 2, u0: Optional[np.ndarray] = None, history: bool = False):
+    """Lexicographic Gauss-Seidel V(nu1,nu2) cycles; returns (u, cycles, relres[, history])."""
+    lib = _load()
+    bct, g, eps = _prob_args(p)
+    f = np.ascontiguousarray(p.f, dtype=np.float64)
+    u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, order="C")
+    rel = ctypes.c_double(0.0)
+    hist = np.zeros(max_cycles, dtype=np.float64)
+    c = lib.orc_vcycle_solve(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(g), _dp(f), _dp(u), rtol,
+                             max_cycles, nu1, nu2, coarsest_max, ctypes.byref(rel), _dp(hist))
+    if history:
+        return u, int(c), float(rel.value), hist[:c].copy()
+    return u, int(c), float(rel.value)
+
+
+def solve_reference(p, rtol: float = 1e-13) -> np.ndarray:
+    """u* to relative residual rtol (V-cycle oracle; CG finishes the job if
+    the V-cycle stalls above rtol)."""
+    u, _, rel = solve_vcycle(p, rtol=rtol, max_cycles=200)
+    if rel > rtol:
+        u, _, rel = solve_cg(p, rtol=rtol, u0=u)
+    return u
+
+
+def num_levels(nx: int, ny: int, nz: int, coarsest_max: int = 2) -> int:
+    return int(_load().orc_num_levels(nx, ny, nz, coarsest_max))
+
+
+# ---------------------------------------------------------------- dense
+
+
+def dense_matrix(p) -> Tuple[np.ndarray, np.ndarray]:
+    """Assemble (A, b) cell by cell from the definition, in pure Python.
+
+    Written independently of mg_oracle.c: it walks the six neighbours of
+    every cell and adds the face term of the second-order cell-centred
+    discretisation (harmonic-mean interior faces, linear Dirichlet ghosts,
+    zero Neumann flux).  Only for tiny grids (n <= ~2000)."""
+    nx, ny, nz = p.nx, p.ny, p.nz
+    n = nx * ny * nz
+    A = np.zeros((n, n))
+    b = np.array(p.f, dtype=np.float64).reshape(-1).copy()
+    ih2 = 1.0 / (p.h * p.h)
+    beta = np.ones((nz, ny, nx)) if p.eps is None else np.asarray(p.eps, dtype=np.float64)
+    types = p.bc_types()
+    vals = p.bc_values()
+    steps = [(-1, 0, 0, 0), (1, 0, 0, 1), (0, -1, 0, 2), (0, 1, 0, 3), (0, 0, -1, 4), (0, 0, 1, 5)]
+
+    def lin(i, j, k):
+        return (k * ny + j) * nx + i
+
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                P = lin(i, j, k)
+                A[P, P] += p.a
+                bP = beta[k, j, i]
+                for di, dj, dk, face in steps:
+                    ii, jj, kk = i + di, j + dj, k + dk
+                    if 0 <= ii < nx and 0 <= jj < ny and 0 <= kk < nz:
+                        bN = beta[kk, jj, ii]
+                        bf = 2.0 * bP * bN / (bP + bN)
+                        A[P, P] += ih2 * bf
+                        A[P, lin(ii, jj, kk)] -= ih2 * bf
+                    elif types[face] == "D":
+                        A[P, P] += 2.0 * ih2 * bP
+                        b[P] += 2.0 * ih2 * bP * vals[face]
+    return A, b
+
+
+def dense_solve(p) -> np.ndarray:
+    A, b = dense_matrix(p)
+    return np.linalg.solve(A, b).reshape(p.nz, p.ny, p.nx)
