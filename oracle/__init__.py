@@ -17,8 +17,10 @@ from .oracle import (  # noqa: F401
     residual,
     solve_cg,
     solve_vcycle,
+    rbgs,
     solve_reference,
     dense_matrix,
     dense_solve,
     num_levels,
+    threads,
 )

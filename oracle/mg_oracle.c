@@ -40,6 +40,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_DIRICHLET 0
 #define ORC_NEUMANN 1
@@ -478,4 +481,41 @@ int orc_num_levels(int nx, int ny, int nz, int coarsest_max) {
         ++n;
     }
     return n;
+}
+
+/* Red-black Gauss-Seidel sweeps of the finest-level equation (the paper's
+ * smoother, Sec. 2 item (ii)): first every red cell ((i+j+k) even), then
+ * every black cell, each set to the value that zeroes its own residual.
+ * A red cell's neighbours are all black (and vice versa), so the order
+ * inside a colour does not matter. */
+void orc_rbgs(int nx, int ny, int nz, double h, double a, const double *eps, const int *bct,
+              const double *g, const double *f, double *u, int sweeps) {
+    orc_level L;
+    make_level0(&L, nx, ny, nz, h, a, eps, bct);
+    size_t n = ncell(&L);
+    double *b = (double *)malloc(n * sizeof(double));
+    bc_rhs(&L, eps, g, f, b);
+    const double ih2 = 1.0 / (h * h);
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        if (((i + j + k) & 1) != colour) continue;
+                        double o, d;
+                        cell_terms(&L, u, i, j, k, &o, &d);
+                        size_t p = idx(&L, i, j, k);
+                        u[p] = (b[p] + ih2 * o) / (a + ih2 * d);
+                    }
+    free(b);
+    level_free(&L);
+}
+
+/* Threads the oracle's parallel loops use (1 without OpenMP). */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -61,6 +61,10 @@ def _load():
             lib.orc_vcycle_solve.argtypes = [c_int, c_int, c_int, c_dbl, c_dbl, dp, ip, dp, dp, dp, c_dbl,
                                              c_int, c_int, c_int, c_int, dp, dp]
             lib.orc_vcycle_solve.restype = c_int
+            lib.orc_rbgs.argtypes = [c_int, c_int, c_int, c_dbl, c_dbl, dp, ip, dp, dp, dp, c_int]
+            lib.orc_rbgs.restype = None
+            lib.orc_threads.argtypes = []
+            lib.orc_threads.restype = c_int
             lib.orc_num_levels.argtypes = [c_int, c_int, c_int, c_int]
             lib.orc_num_levels.restype = c_int
             _lib = lib
@@ -146,6 +150,16 @@ def solve_vcycle(p, rtol: float = 1e-13, max_cycles: int = 100, nu1: int = 2, nu
     return u, int(c), float(rel.value)
 
 
+def rbgs(p, u: np.ndarray, sweeps: int = 1) -> np.ndarray:
+    """Red-black Gauss-Seidel sweeps (red = (i+j+k) even first) from u."""
+    lib = _load()
+    bct, g, eps = _prob_args(p)
+    f = np.ascontiguousarray(p.f, dtype=np.float64)
+    out = np.array(u, dtype=np.float64, order="C")
+    lib.orc_rbgs(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(g), _dp(f), _dp(out), sweeps)
+    return out
+
+
 def solve_reference(p, rtol: float = 1e-13) -> np.ndarray:
     """u* to relative residual rtol (V-cycle oracle; CG finishes the job if
     the V-cycle stalls above rtol)."""
@@ -153,6 +167,11 @@ def solve_reference(p, rtol: float = 1e-13) -> np.ndarray:
     if rel > rtol:
         u, _, rel = solve_cg(p, rtol=rtol, u0=u)
     return u
+
+
+def threads() -> int:
+    """Threads used by the oracle's OpenMP loops."""
+    return int(_load().orc_threads())
 
 
 def num_levels(nx: int, ny: int, nz: int, coarsest_max: int = 2) -> int:

@@ -1,0 +1,94 @@
+// Context layout shared by the host-side parts of the engine
+// (mg_engine.hip, mg_batched.hip, mg_autotune.hip).
+#pragma once
+
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "mg.h"
+#include "mg_internal.h"
+
+namespace mg {
+
+constexpr int kMaxLevels = 24;
+
+struct Level {
+    int nx = 0, ny = 0, nz = 0;
+    size_t n = 0;
+    double h = 0.0;
+    double *fbx = nullptr, *fby = nullptr, *fbz = nullptr;  // FP64 face coefficients
+    void *lbx = nullptr, *lby = nullptr, *lbz = nullptr;    // low-precision copies
+    double *u = nullptr, *t = nullptr, *b = nullptr;        // FP64 work (levels >= 1)
+    void *ul = nullptr, *tl = nullptr, *bl = nullptr;       // low-precision work
+};
+
+// One level as seen by a V-cycle: storage type, operator and arrays.
+struct LvView {
+    int st = ST_F64;
+    Geo G{};
+    Coef C{};
+    size_t n = 0;
+    void *u = nullptr, *t = nullptr;
+    const void *b = nullptr;
+    void *bw = nullptr;      // writable alias of b (target of the restriction)
+    bool fixed_u = false;    // u is the caller's array: the result must end there
+    bool with_g = false;     // boundary values apply (finest level of the FP64 solve)
+};
+
+struct BatchPlan;  // mg_batched.hip
+
+}  // namespace mg
+
+struct mg_ctx {
+    mg_desc d{};
+    hipStream_t stream = nullptr;
+    int lp_store = -1;  // ST_F32 / ST_BF16 for refinement, -1 for MG_FP64
+    int nlev = 0, tail = 0;
+    mg::Level L[mg::kMaxLevels];
+    bool has_eps = false;
+    double *eps = nullptr;
+    void *eps_lp = nullptr;
+    double a = 0.0;
+    int bcmask = 0;
+    double g[6] = {0, 0, 0, 0, 0, 0};
+    bool coeffs = false;
+    unsigned version = 0;  // bumped by every mg_set_coeffs
+    double *xalt = nullptr;
+    int *d_done = nullptr;             // device convergence flag of the running solve
+    hipEvent_t ev_cyc[2] = {nullptr, nullptr};
+    mg::RedWs ws{};
+    double *h_pin = nullptr;
+    int tile64 = 0, zc64 = 0, tile_lp = 0, zc_lp = 0;
+    mg::TailDesc tails[2];  // [0]: homogeneous, [1]: with boundary values
+    std::vector<void *> allocs;
+    mg::BatchPlan *plan = nullptr;  // cached batch plan owned by this context (first of a batch)
+    // measurement hook (mg_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // start/stop pairs
+    std::vector<double> ev_bytes;
+    int ev_used = 0;
+    long t_launches = 0;
+    double t_ms = 0.0, t_bytes = 0.0;
+    std::string t_kernel;
+};
+
+namespace mg {
+
+using Ctx = ::mg_ctx;
+
+extern thread_local std::string g_err;
+int set_err(int code, const char *fmt, ...);
+Geo level_geo(const Ctx *c, int l, bool with_g);
+Coef level_coef(const Ctx *c, int l, bool lowp);
+void build_tail(const Ctx *c, TailDesc &D, bool with_g);
+int tile_for(const Ctx *c, const Geo &G, int st, int l, int *zc);
+int vcycle(Ctx *c, std::vector<LvView> &V, int l, bool zero_start, const int *done = nullptr);
+void fp64_view(Ctx *c, std::vector<LvView> &V, const double *f, double *x);
+void lowp_view(Ctx *c, std::vector<LvView> &V);
+int read_results(Ctx *c, int n);
+void batch_release(Ctx *c);
+int timing_flush(Ctx *c);
+hipError_t timed_smooth(Ctx *c, int l, const LvView &W, bool zin, int tile, int zc, const int *done = nullptr);
+
+}  // namespace mg

@@ -1,0 +1,741 @@
+// Host driver of the multigrid engine and the C ABI declared in mg.h.
+//
+// A context owns the level hierarchy of one grid and operator.  mg_solve
+// runs V-cycles (MG_FP64) or FP64 iterative refinement around
+// low-precision V-cycles (MG_FP32_IR, MG_BF16_IR); every arithmetic step is
+// a HIP kernel enqueued on the context's stream, and the host reads back
+// one residual norm per cycle to decide convergence.
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mg.h"
+#include "mg_engine.h"
+
+namespace mg {
+
+thread_local std::string g_err;
+
+int set_err(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define CK(expr)                                                                                   \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return set_err(MG_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),       \
+                           __FILE__, __LINE__);                                                    \
+    } while (0)
+
+static void *dalloc(Ctx *c, size_t bytes) {
+    void *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    c->allocs.push_back(p);
+    return p;
+}
+
+static void dfree(Ctx *c, void *&p) {
+    if (!p) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    (void)hipFree(p);
+    p = nullptr;
+}
+
+Geo level_geo(const Ctx *c, int l, bool with_g) {
+    const Level &L = c->L[l];
+    Geo G;
+    G.nx = L.nx;
+    G.ny = L.ny;
+    G.nz = L.nz;
+    G.bcmask = c->bcmask;
+    G.h2 = L.h * L.h;
+    G.ah2 = c->a * G.h2;
+    G.ih2 = 1.0 / G.h2;
+    G.a = c->a;
+    for (int d = 0; d < 6; ++d) G.g[d] = (with_g && l == 0) ? c->g[d] : 0.0;
+    return G;
+}
+
+Coef level_coef(const Ctx *c, int l, bool lowp) {
+    Coef C{};
+    if (!c->has_eps) {
+        C.mode = COEF_CONST;
+        return C;
+    }
+    if (l == 0) {
+        C.mode = COEF_CELL;
+        C.eps = lowp ? c->eps_lp : (const void *)c->eps;
+        return C;
+    }
+    C.mode = COEF_FACE;
+    const Level &L = c->L[l];
+    if (lowp) {
+        C.bx = L.lbx;
+        C.by = L.lby;
+        C.bz = L.lbz;
+    } else {
+        C.bx = L.fbx;
+        C.by = L.fby;
+        C.bz = L.fbz;
+    }
+    return C;
+}
+
+void build_tail(const Ctx *c, TailDesc &D, bool with_g) {
+    std::memset(&D, 0, sizeof D);
+    D.nlev = c->nlev - c->tail;
+    D.mode = c->has_eps ? COEF_FACE : COEF_CONST;
+    D.bcmask = c->bcmask;
+    for (int d = 0; d < 6; ++d) D.g[d] = (with_g && c->tail == 0) ? c->g[d] : 0.0;
+    D.nu1 = std::max(1, c->d.nu1);
+    D.nu2 = std::max(1, c->d.nu2);
+    D.ncyc = 1;
+    for (int q = 0; q < D.nlev; ++q) {
+        const Level &L = c->L[c->tail + q];
+        TailLevel &T = D.L[q];
+        T.nx = L.nx;
+        T.ny = L.ny;
+        T.nz = L.nz;
+        T.h2 = L.h * L.h;
+        T.ah2 = c->a * T.h2;
+        T.bx = L.fbx;
+        T.by = L.fby;
+        T.bz = L.fbz;
+    }
+    const TailLevel &Lc = D.L[D.nlev - 1];
+    D.cg_maxit = 2 * Lc.nx * Lc.ny * Lc.nz + 50;
+    D.cg_rtol = 1e-13;
+    tail_layout(D);
+}
+
+// ------------------------------------------------------------ V-cycle
+
+int tile_for(const Ctx *c, const Geo &G, int st, int l, int *zc) {
+    int t = 0, z = 0;
+    if (l == 0) {
+        t = (st == ST_F64) ? c->tile64 : c->tile_lp;
+        z = (st == ST_F64) ? c->zc64 : c->zc_lp;
+    }
+    if (t <= 0) t = default_tile(G, st);
+    if (z <= 0) z = default_zchunk(G, t);
+    *zc = z;
+    return t;
+}
+
+// One V-cycle from level l of a view, starting from zero when zero_start
+// (otherwise from view[l].u).  The result is in view[l].u afterwards (the
+// pointer may have been swapped with view[l].t).  Every kernel returns at
+// once when *done is set.
+int vcycle(Ctx *c, std::vector<LvView> &V, int l, bool zero_start, const int *done) {
+    hipStream_t s = c->stream;
+    LvView &W = V[l];
+    if (l == c->tail) {
+        CK(tail_solve(s, W.st, c->tails[W.st == ST_F64 && W.with_g ? 1 : 0], W.b,
+                      zero_start ? nullptr : W.u, W.u, done));
+        return MG_OK;
+    }
+    int zc;
+    const int tile = tile_for(c, W.G, W.st, l, &zc);
+    bool zin = zero_start;
+    for (int q = 0; q < c->d.nu1; ++q) {
+        CK(timed_smooth(c, l, W, zin, tile, zc, done));
+        std::swap(W.u, W.t);
+        zin = false;
+    }
+    if (zin) CK(fill_zero(s, W.u, W.n * store_size(W.st), done));
+    RrCheck chk;
+    chk.done_in = done;
+    CK(resid_restrict(s, W.st, W.G, W.C, W.u, W.b, V[l + 1].st, V[l + 1].bw, chk));
+    int rc = vcycle(c, V, l + 1, true, done);
+    if (rc != MG_OK) return rc;
+    CK(prolong_add(s, W.st, W.G, W.u, V[l + 1].st, V[l + 1].G, V[l + 1].u, done));
+    for (int q = 0; q < c->d.nu2; ++q) {
+        CK(timed_smooth(c, l, W, false, tile, zc, done));
+        std::swap(W.u, W.t);
+    }
+    return MG_OK;
+}
+
+void fp64_view(Ctx *c, std::vector<LvView> &V, const double *f, double *x) {
+    V.assign(c->tail + 1, LvView{});
+    for (int l = 0; l <= c->tail; ++l) {
+        LvView &W = V[l];
+        W.st = ST_F64;
+        W.G = level_geo(c, l, true);
+        W.C = level_coef(c, l, false);
+        W.n = c->L[l].n;
+        W.with_g = (l == 0);
+        if (l == 0) {
+            W.u = x;
+            W.t = c->xalt;
+            W.b = f;
+            W.fixed_u = true;
+        } else {
+            W.u = c->L[l].u;
+            W.t = c->L[l].t;
+            W.b = c->L[l].b;
+            W.bw = c->L[l].b;
+        }
+    }
+}
+
+void lowp_view(Ctx *c, std::vector<LvView> &V) {
+    V.assign(c->tail + 1, LvView{});
+    for (int l = 0; l <= c->tail; ++l) {
+        LvView &W = V[l];
+        W.st = c->lp_store;
+        W.G = level_geo(c, l, false);
+        W.C = level_coef(c, l, true);
+        W.n = c->L[l].n;
+        W.u = c->L[l].ul;
+        W.t = c->L[l].tl;
+        W.b = c->L[l].bl;
+        W.bw = c->L[l].bl;
+    }
+}
+
+static const char *mode_name(int m) {
+    return m == COEF_CELL ? "cell-eps" : (m == COEF_FACE ? "face" : "const");
+}
+
+// Finest-level smoother launch, bracketed by events while timing is on.
+hipError_t timed_smooth(Ctx *c, int l, const LvView &W, bool zin, int tile, int zc, const int *done) {
+    const bool rec = c->timing && l == 0 && c->ev_used + 2 <= (int)c->ev.size();
+    if (rec) {
+        hipError_t e = hipEventRecord(c->ev[c->ev_used], c->stream);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = smooth(c->stream, W.st, W.G, W.C, W.u, W.t, W.b, zin, tile, zc, done);
+    if (e != hipSuccess || !rec) return e;
+    e = hipEventRecord(c->ev[c->ev_used + 1], c->stream);
+    if (e != hipSuccess) return e;
+    // algorithmic bytes: read u (unless zero), b and eps once, write u once
+    const double es = (double)store_size(W.st);
+    const int arrays = (zin ? 0 : 1) + 1 + (W.C.mode == COEF_CELL ? 1 : 0) + 1;
+    c->ev_bytes[c->ev_used / 2] = (double)W.n * es * arrays;
+    c->ev_used += 2;
+    if (c->t_kernel.empty()) {
+        int tx, ty;
+        tile_shape(tile, &tx, &ty);
+        char buf[160];
+        snprintf(buf, sizeof buf, "rbgs_col_k<%s,%s,%d,%d,zero_in=%d> (finest-level fused red-black sweep)",
+                 W.st == ST_F64 ? "double" : (W.st == ST_F32 ? "float" : "bf16"), mode_name(W.C.mode), tx,
+                 ty, (int)zin);
+        c->t_kernel = buf;
+    }
+    return hipSuccess;
+}
+
+int timing_flush(Ctx *c) {
+    if (!c->timing || c->ev_used == 0) return MG_OK;
+    CK(hipStreamSynchronize(c->stream));
+    for (int q = 0; q + 1 < c->ev_used; q += 2) {
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, c->ev[q], c->ev[q + 1]));
+        c->t_ms += ms;
+        c->t_bytes += c->ev_bytes[q / 2];
+        c->t_launches++;
+    }
+    c->ev_used = 0;
+    return MG_OK;
+}
+
+int read_results(Ctx *c, int n) {
+    CK(hipMemcpyAsync(c->h_pin, c->ws.result, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CK(hipStreamSynchronize(c->stream));
+    return MG_OK;
+}
+
+}  // namespace mg
+
+using namespace mg;
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+void mg_desc_default(mg_desc *d, int nx, int ny, int nz, double h) {
+    if (!d) return;
+    d->nx = nx;
+    d->ny = ny;
+    d->nz = nz;
+    d->h = h;
+    d->precision = MG_FP64;
+    d->nu1 = 2;
+    d->nu2 = 2;
+    d->bottom_max = 16;
+    d->max_cycles = 50;
+    d->rtol = 1e-10;
+}
+
+const char *mg_last_error(void) { return g_err.c_str(); }
+
+int mg_create(const mg_desc *d, void *hip_stream, mg_ctx **out) {
+    if (out) *out = nullptr;
+    if (!d || !out) return set_err(MG_EINVAL, "mg_create: null argument");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1)
+        return set_err(MG_EINVAL, "mg_create: dimensions must be >= 1 (got %d x %d x %d)", d->nx,
+                       d->ny, d->nz);
+    if ((double)d->nx * d->ny * d->nz > 4.0e9)
+        return set_err(MG_EINVAL, "mg_create: grid too large");
+    if (!(d->h > 0.0) || !std::isfinite(d->h)) return set_err(MG_EINVAL, "mg_create: h must be > 0");
+    if (d->precision < MG_FP64 || d->precision > MG_BF16_IR)
+        return set_err(MG_EINVAL, "mg_create: unknown precision %d", d->precision);
+    if (d->nu1 < 0 || d->nu2 < 0 || d->nu1 > 8 || d->nu2 > 8 || d->nu1 + d->nu2 < 1)
+        return set_err(MG_EINVAL, "mg_create: nu1, nu2 must be in 0..8 with nu1 + nu2 >= 1");
+    if (d->bottom_max < 2 || d->bottom_max > 16)
+        return set_err(MG_EINVAL, "mg_create: bottom_max must be in 2..16");
+    if (d->max_cycles < 1) return set_err(MG_EINVAL, "mg_create: max_cycles must be >= 1");
+    if (!(d->rtol > 0.0) || !(d->rtol < 1.0)) return set_err(MG_EINVAL, "mg_create: rtol must be in (0,1)");
+
+    Ctx *c = new Ctx();
+    c->d = *d;
+    c->stream = (hipStream_t)hip_stream;
+    c->lp_store = d->precision == MG_FP32_IR ? ST_F32 : (d->precision == MG_BF16_IR ? ST_BF16 : -1);
+    // hierarchy: halve every axis while all are even and the largest exceeds 1
+    int nx = d->nx, ny = d->ny, nz = d->nz;
+    double h = d->h;
+    c->nlev = 0;
+    c->tail = -1;
+    for (;;) {
+        if (c->nlev >= kMaxLevels) break;
+        Level &L = c->L[c->nlev];
+        L.nx = nx;
+        L.ny = ny;
+        L.nz = nz;
+        L.n = (size_t)nx * ny * nz;
+        L.h = h;
+        const int mx = std::max(nx, std::max(ny, nz));
+        if (c->tail < 0 && mx <= d->bottom_max) c->tail = c->nlev;
+        c->nlev++;
+        if (nx % 2 || ny % 2 || nz % 2 || mx <= 1) break;
+        nx /= 2;
+        ny /= 2;
+        nz /= 2;
+        h *= 2.0;
+    }
+    if (c->tail < 0) {
+        delete c;
+        return set_err(MG_EINVAL,
+                       "mg_create: %d x %d x %d cannot be coarsened to a grid with every axis <= "
+                       "bottom_max = %d (each axis must be m * 2^k with the same k)",
+                       d->nx, d->ny, d->nz, d->bottom_max);
+    }
+    if (c->nlev - c->tail > kTailMaxLevels) {
+        delete c;
+        return set_err(MG_EINVAL, "mg_create: too many bottom levels");
+    }
+    TailDesc probe;
+    build_tail(c, probe, false);
+    if (!tail_layout(probe)) {
+        delete c;
+        return set_err(MG_EINVAL, "mg_create: bottom grid does not fit the bottom solver");
+    }
+    // buffers
+    bool ok = true;
+    const size_t n0 = c->L[0].n;
+    c->xalt = (double *)dalloc(c, n0 * 8);
+    ok &= c->xalt != nullptr;
+    for (int l = 1; l <= c->tail; ++l) {
+        Level &L = c->L[l];
+        L.u = (double *)dalloc(c, L.n * 8);
+        L.t = (double *)dalloc(c, L.n * 8);
+        L.b = (double *)dalloc(c, L.n * 8);
+        ok &= L.u && L.t && L.b;
+    }
+    if (c->lp_store >= 0) {
+        const size_t es = store_size(c->lp_store);
+        for (int l = 0; l <= c->tail; ++l) {
+            Level &L = c->L[l];
+            L.ul = dalloc(c, L.n * es);
+            L.tl = dalloc(c, L.n * es);
+            L.bl = dalloc(c, L.n * es);
+            ok &= L.ul && L.tl && L.bl;
+        }
+    }
+    c->d_done = (int *)dalloc(c, sizeof(int) * 4);
+    ok &= c->d_done != nullptr;
+    for (int q = 0; q < 2 && ok; ++q) ok &= hipEventCreateWithFlags(&c->ev_cyc[q], hipEventDisableTiming) == hipSuccess;
+    c->ws.partials = (double *)dalloc(c, sizeof(double) * kRedSlots * kMaxRedBlocks * 2);
+    c->ws.counter = (unsigned *)dalloc(c, sizeof(unsigned) * kRedSlots);
+    c->ws.result = (double *)dalloc(c, sizeof(double) * kRedSlots);
+    ok &= c->ws.partials && c->ws.counter && c->ws.result;
+    if (ok && hipHostMalloc((void **)&c->h_pin, sizeof(double) * kRedSlots, hipHostMallocDefault) !=
+                  hipSuccess)
+        ok = false;
+    if (!ok) {
+        mg_destroy(c);
+        return set_err(MG_ENOMEM, "mg_create: device allocation failed");
+    }
+    if (hipMemsetAsync(c->ws.counter, 0, sizeof(unsigned) * kRedSlots, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        mg_destroy(c);
+        return set_err(MG_EDEVICE, "mg_create: initialisation failed");
+    }
+    *out = c;
+    return MG_OK;
+}
+
+int mg_destroy(mg_ctx *c) {
+    if (!c) return MG_OK;
+    (void)hipStreamSynchronize(c->stream);
+    batch_release(c);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    for (int q = 0; q < 2; ++q)
+        if (c->ev_cyc[q]) (void)hipEventDestroy(c->ev_cyc[q]);
+    c->ev.clear();
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
+    delete c;
+    return MG_OK;
+}
+
+int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) {
+    if (!c || !bc) return set_err(MG_EINVAL, "mg_set_coeffs: null argument");
+    if (!(a >= 0.0) || !std::isfinite(a)) return set_err(MG_EINVAL, "mg_set_coeffs: a must be finite and >= 0");
+    int mask = 0;
+    for (int f = 0; f < 6; ++f) {
+        if (bc->type[f] != MG_BC_DIRICHLET && bc->type[f] != MG_BC_NEUMANN)
+            return set_err(MG_EINVAL, "mg_set_coeffs: unknown boundary type %d on face %d", bc->type[f], f);
+        if (bc->type[f] == MG_BC_DIRICHLET) {
+            if (!std::isfinite(bc->value[f]))
+                return set_err(MG_EINVAL, "mg_set_coeffs: non-finite boundary value on face %d", f);
+            mask |= 1 << f;
+        }
+    }
+    if (a == 0.0 && mask == 0)
+        return set_err(MG_EINVAL, "mg_set_coeffs: singular operator (a = 0 and no Dirichlet face)");
+    hipStream_t s = c->stream;
+    const size_t n0 = c->L[0].n;
+    c->coeffs = false;
+    if (eps_dev) {
+        if (!c->eps) {
+            c->eps = (double *)dalloc(c, n0 * 8);
+            if (!c->eps) return set_err(MG_ENOMEM, "mg_set_coeffs: allocation failed");
+        }
+        CK(hipMemcpyAsync(c->eps, eps_dev, n0 * 8, hipMemcpyDeviceToDevice, s));
+        CK(count_bad(s, c->eps, n0, c->ws, 0));
+        int rc = read_results(c, 1);
+        if (rc) return rc;
+        if (c->h_pin[0] != 0.0)
+            return set_err(MG_EINVAL, "mg_set_coeffs: %.0f coefficient entries are not finite and > 0",
+                           c->h_pin[0]);
+        // face coefficients of every level (level 0 only while coarsening,
+        // unless the bottom solver starts at level 0)
+        for (int l = 0; l < c->nlev; ++l) {
+            Level &L = c->L[l];
+            if (!L.fbx) {
+                L.fbx = (double *)dalloc(c, (size_t)(L.nx + 1) * L.ny * L.nz * 8);
+                L.fby = (double *)dalloc(c, (size_t)L.nx * (L.ny + 1) * L.nz * 8);
+                L.fbz = (double *)dalloc(c, (size_t)L.nx * L.ny * (L.nz + 1) * 8);
+                if (!L.fbx || !L.fby || !L.fbz) return set_err(MG_ENOMEM, "mg_set_coeffs: allocation failed");
+            }
+            Geo G = level_geo(c, l, false);
+            if (l == 0) CK(faces_from_cell(s, G, c->eps, L.fbx, L.fby, L.fbz));
+            else {
+                Geo Gf = level_geo(c, l - 1, false);
+                const Level &F = c->L[l - 1];
+                CK(coarsen_faces(s, Gf, F.fbx, F.fby, F.fbz, G, L.fbx, L.fby, L.fbz));
+            }
+        }
+        if (c->lp_store >= 0) {
+            const size_t es = store_size(c->lp_store);
+            if (!c->eps_lp) c->eps_lp = dalloc(c, n0 * es);
+            if (!c->eps_lp) return set_err(MG_ENOMEM, "mg_set_coeffs: allocation failed");
+            CK(convert(s, c->eps, c->lp_store, c->eps_lp, n0));
+            for (int l = 1; l < c->tail; ++l) {
+                Level &L = c->L[l];
+                const size_t nfx = (size_t)(L.nx + 1) * L.ny * L.nz, nfy = (size_t)L.nx * (L.ny + 1) * L.nz,
+                             nfz = (size_t)L.nx * L.ny * (L.nz + 1);
+                if (!L.lbx) {
+                    L.lbx = dalloc(c, nfx * es);
+                    L.lby = dalloc(c, nfy * es);
+                    L.lbz = dalloc(c, nfz * es);
+                    if (!L.lbx || !L.lby || !L.lbz) return set_err(MG_ENOMEM, "mg_set_coeffs: allocation failed");
+                }
+                CK(convert(s, L.fbx, c->lp_store, L.lbx, nfx));
+                CK(convert(s, L.fby, c->lp_store, L.lby, nfy));
+                CK(convert(s, L.fbz, c->lp_store, L.lbz, nfz));
+            }
+        }
+        c->has_eps = true;
+    } else {
+        c->has_eps = false;
+    }
+    c->a = a;
+    c->bcmask = mask;
+    for (int f = 0; f < 6; ++f) c->g[f] = (mask >> f & 1) ? bc->value[f] : 0.0;
+    build_tail(c, c->tails[0], false);
+    build_tail(c, c->tails[1], true);
+    CK(hipStreamSynchronize(s));
+    c->coeffs = true;
+    c->version++;
+    return MG_OK;
+}
+
+// Result slots of the reduction workspace used by a solve.
+enum { SLOT_R0 = 0, SLOT_B = 1, SLOT_CYC = 2 /* and 3, alternating */ };
+
+static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_stats *st) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = c->stream;
+    const size_t n0 = c->L[0].n;
+    mg_stats S{};
+    const Geo G0 = level_geo(c, 0, true);
+    const Coef C0 = level_coef(c, 0, false);
+    int *done = c->d_done;
+    int rc;
+    // ||b|| and the residual of the starting iterate
+    if (!(flags & MG_GUESS)) CK(fill_zero(s, x, n0 * 8));
+    CK(fill_zero(s, done, sizeof(int)));
+    CK(norm2_resid(s, ST_F64, G0, C0, x, f, c->ws, SLOT_R0, SLOT_B));
+    if ((rc = read_results(c, 2))) return rc;
+    const double bn = std::sqrt(c->h_pin[SLOT_B]);
+    double rn = std::sqrt(c->h_pin[SLOT_R0]);
+    if (!std::isfinite(bn) || !std::isfinite(rn))
+        return set_err(MG_EINVAL, "mg_solve: right-hand side or initial guess is not finite");
+    if (bn == 0.0) {
+        CK(fill_zero(s, x, n0 * 8));
+        CK(hipStreamSynchronize(s));
+        if (st) *st = S;
+        return MG_OK;
+    }
+    if ((flags & MG_GUESS) && rn > bn) {
+        CK(fill_zero(s, x, n0 * 8));
+        S.fell_back = 1;
+        rn = bn;
+    }
+    S.rel_res0 = rn / bn;
+    const double rtol = c->d.rtol;
+    if (S.rel_res0 <= rtol) {
+        CK(hipStreamSynchronize(s));
+        S.rel_res = S.rel_res0;
+        if (st) *st = S;
+        return MG_OK;
+    }
+    RrCheck chk;
+    chk.ws = c->ws;
+    chk.ref_slot = SLOT_B;
+    chk.rtol2 = rtol * rtol;
+    chk.done_out = done;
+    chk.done_in = done;
+
+    // The solve is a pipeline of steps c = 0, 1, ...: check(c) produces the
+    // residual norm of the current iterate (and sets *done when it meets the
+    // tolerance); advance(c) performs one more cycle.  check(c+1) and
+    // advance(c) are enqueued before the host reads the norm of check(c), so
+    // the GPU never waits for the host; once *done is set every later kernel
+    // returns at once.
+    std::vector<LvView> V;
+    const bool lowp = c->lp_store >= 0;
+    double *cur = x, *oth = c->xalt;  // FP64 iterate and its spare buffer
+    if (lowp) lowp_view(c, V);
+    else fp64_view(c, V, f, x);
+    auto check = [&](int cyc) -> int {
+        chk.slot = SLOT_CYC + (cyc & 1);
+        if (lowp) {
+            // FP64 residual of the starting iterate, cast into the inner
+            // right-hand side (later steps get it from advance())
+            if (cyc == 0) CK(ir_update_resid(s, G0, C0, cur, nullptr, nullptr, f, c->lp_store, V[0].bw, chk));
+        } else if (c->tail == 0) {
+            CK(norm2_resid(s, ST_F64, G0, C0, cur, f, c->ws, chk.slot, -1, &chk));
+        } else {
+            // level-0 pre-smoothing, then residual + restriction with the norm
+            LvView &W = V[0];
+            W.u = cur;
+            W.t = oth;
+            int zc;
+            const int tile = tile_for(c, W.G, W.st, 0, &zc);
+            for (int q = 0; q < c->d.nu1; ++q) {
+                CK(timed_smooth(c, 0, W, false, tile, zc, done));
+                std::swap(W.u, W.t);
+            }
+            cur = (double *)W.u;
+            oth = (double *)W.t;
+            CK(resid_restrict(s, ST_F64, W.G, W.C, W.u, W.b, V[1].st, V[1].bw, chk));
+        }
+        CK(hipMemcpyAsync(c->h_pin + chk.slot, c->ws.result + chk.slot, sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+        CK(hipEventRecord(c->ev_cyc[cyc & 1], s));
+        return MG_OK;
+    };
+    auto advance = [&](int cyc) -> int {
+        if (lowp) {
+            // inner low-precision V-cycle on A e = r, then x += e (the check
+            // of the next step computes the new residual from x and e)
+            int r = vcycle(c, V, 0, true, done);
+            if (r) return r;
+            RrCheck k2 = chk;
+            k2.slot = SLOT_CYC + ((cyc + 1) & 1);
+            CK(ir_update_resid(s, G0, C0, cur, V[0].u, oth, f, c->lp_store, V[0].bw, k2));
+            std::swap(cur, oth);
+        } else if (c->tail == 0) {
+            CK(tail_solve(s, ST_F64, c->tails[1], f, cur, cur, done));
+        } else {
+            // coarse correction of the restricted residual, then post-smoothing
+            LvView &W = V[0];
+            int r = vcycle(c, V, 1, true, done);
+            if (r) return r;
+            CK(prolong_add(s, ST_F64, W.G, cur, ST_F64, V[1].G, V[1].u, done));
+            W.u = cur;
+            W.t = oth;
+            int zc;
+            const int tile = tile_for(c, W.G, W.st, 0, &zc);
+            for (int q = 0; q < c->d.nu2; ++q) {
+                CK(timed_smooth(c, 0, W, false, tile, zc, done));
+                std::swap(W.u, W.t);
+            }
+            cur = (double *)W.u;
+            oth = (double *)W.t;
+        }
+        return MG_OK;
+    };
+
+    if ((rc = check(0))) return rc;
+    double *at_check[2] = {cur, nullptr};
+    int cycles = 0;
+    double rel = S.rel_res0;
+    double *final_x = cur;
+    bool converged = false;
+    for (int cyc = 0;; ++cyc) {
+        if (cyc < c->d.max_cycles) {
+            if ((rc = advance(cyc))) return rc;
+            if ((rc = check(cyc + 1))) return rc;
+            at_check[(cyc + 1) & 1] = cur;
+        }
+        CK(hipEventSynchronize(c->ev_cyc[cyc & 1]));
+        rel = std::sqrt(c->h_pin[SLOT_CYC + (cyc & 1)]) / bn;
+        final_x = at_check[cyc & 1];
+        cycles = cyc;
+        if (rel <= rtol) {
+            converged = true;
+            break;
+        }
+        if (cyc >= c->d.max_cycles) break;
+        if (!std::isfinite(rel) || rel > 1e6 * std::max(1.0, S.rel_res0)) {
+            CK(hipStreamSynchronize(s));
+            S.cycles = cycles;
+            S.rel_res = rel;
+            if (st) *st = S;
+            return set_err(MG_EDIVERGED, "mg_solve: residual diverged (%g) after %d cycles", rel, cycles);
+        }
+    }
+    // the iterate that passed the test may sit in the spare buffer
+    if (final_x != x) CK(copy_f64(s, final_x, x, n0));
+    CK(hipStreamSynchronize(s));
+    if ((rc = timing_flush(c))) return rc;
+    S.cycles = cycles;
+    S.rel_res = rel;
+    S.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (st) *st = S;
+    return converged ? MG_OK : MG_NOT_CONVERGED;
+}
+
+int mg_solve(mg_ctx *c, const double *f_dev, double *x_dev, unsigned flags, mg_stats *st) {
+    if (!c || !f_dev || !x_dev) return set_err(MG_EINVAL, "mg_solve: null argument");
+    if (!c->coeffs) return set_err(MG_EINVAL, "mg_solve: mg_set_coeffs has not succeeded");
+    if (flags & ~(unsigned)MG_GUESS) return set_err(MG_EINVAL, "mg_solve: unknown flags 0x%x", flags);
+    return solve_impl(c, f_dev, x_dev, flags, st);
+}
+
+int mg_residual(mg_ctx *c, const double *f_dev, const double *x_dev, double *r_dev, double *rnorm,
+                double *bnorm) {
+    if (!c || !f_dev || !x_dev) return set_err(MG_EINVAL, "mg_residual: null argument");
+    if (!c->coeffs) return set_err(MG_EINVAL, "mg_residual: mg_set_coeffs has not succeeded");
+    hipStream_t s = c->stream;
+    const Geo G0 = level_geo(c, 0, true);
+    const Coef C0 = level_coef(c, 0, false);
+    if (r_dev) CK(resid_out(s, G0, C0, x_dev, f_dev, r_dev));
+    CK(norm2_resid(s, ST_F64, G0, C0, x_dev, f_dev, c->ws, 0, 1));
+    int rc = read_results(c, 2);
+    if (rc) return rc;
+    if (rnorm) *rnorm = std::sqrt(c->h_pin[0]);
+    if (bnorm) *bnorm = std::sqrt(c->h_pin[1]);
+    return MG_OK;
+}
+
+int mg_smooth(mg_ctx *c, const double *f_dev, double *x_dev, int sweeps) {
+    if (!c || !f_dev || !x_dev) return set_err(MG_EINVAL, "mg_smooth: null argument");
+    if (!c->coeffs) return set_err(MG_EINVAL, "mg_smooth: mg_set_coeffs has not succeeded");
+    if (sweeps < 0) return set_err(MG_EINVAL, "mg_smooth: sweeps must be >= 0");
+    hipStream_t s = c->stream;
+    const Geo G0 = level_geo(c, 0, true);
+    const Coef C0 = level_coef(c, 0, false);
+    int zc;
+    const int tile = tile_for(c, G0, ST_F64, 0, &zc);
+    double *u = x_dev, *t = c->xalt;
+    for (int q = 0; q < sweeps; ++q) {
+        CK(smooth(s, ST_F64, G0, C0, u, t, f_dev, false, tile, zc));
+        std::swap(u, t);
+    }
+    if (u != x_dev) CK(copy_f64(s, u, x_dev, c->L[0].n));
+    CK(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
+int mg_num_levels(const mg_ctx *c) { return c ? c->nlev : 0; }
+
+int mg_level_dims(const mg_ctx *c, int l, int *nx, int *ny, int *nz) {
+    if (!c || l < 0 || l >= c->nlev) return set_err(MG_EINVAL, "mg_level_dims: bad level");
+    if (nx) *nx = c->L[l].nx;
+    if (ny) *ny = c->L[l].ny;
+    if (nz) *nz = c->L[l].nz;
+    return MG_OK;
+}
+
+int mg_tile_shape(int t, int *tx, int *ty) {
+    if (t < 1 || t > MG_NUM_TILES) return set_err(MG_EINVAL, "mg_tile_shape: tile must be 1..%d", MG_NUM_TILES);
+    tile_shape(t, tx, ty);
+    return MG_OK;
+}
+
+int mg_set_tiling(mg_ctx *c, int tile, int zchunk) {
+    if (!c) return set_err(MG_EINVAL, "mg_set_tiling: null context");
+    if (tile < 0 || tile > MG_NUM_TILES || zchunk < 0)
+        return set_err(MG_EINVAL, "mg_set_tiling: tile must be 0..%d and zchunk >= 0", MG_NUM_TILES);
+    c->tile64 = c->tile_lp = tile;
+    c->zc64 = c->zc_lp = zchunk;
+    return MG_OK;
+}
+
+int mg_timing(mg_ctx *c, int enable) {
+    if (!c) return set_err(MG_EINVAL, "mg_timing: null context");
+    if (enable && c->ev.empty()) {
+        c->ev.resize(1024);
+        for (auto &e : c->ev) CK(hipEventCreate(&e));
+        c->ev_bytes.resize(512);
+    }
+    c->timing = enable != 0;
+    c->ev_used = 0;
+    c->t_launches = 0;
+    c->t_ms = 0.0;
+    c->t_bytes = 0.0;
+    c->t_kernel.clear();
+    return MG_OK;
+}
+
+int mg_timing_read(const mg_ctx *c, long *launches, double *ms, double *bytes, const char **kernel) {
+    if (!c) return set_err(MG_EINVAL, "mg_timing_read: null context");
+    if (launches) *launches = c->t_launches;
+    if (ms) *ms = c->t_ms;
+    if (bytes) *bytes = c->t_bytes;
+    if (kernel) *kernel = c->t_kernel.c_str();
+    return MG_OK;
+}
+
+}  // extern "C"

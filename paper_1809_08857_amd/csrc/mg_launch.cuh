@@ -1,0 +1,176 @@
+// Host launchers of the stencil kernels for one storage type T.  Included
+// once per storage type (mg_kern_f64.hip, mg_kern_f32.hip, mg_kern_bf16.hip).
+#pragma once
+
+#include "mg_stencil.cuh"
+
+namespace mg {
+
+// (TX, TY) of the smoother tile variants.
+constexpr int kTileTX[kNumTiles + 1] = {0, 64, 128, 64, 32, 32, 16};
+constexpr int kTileTY[kNumTiles + 1] = {0, 16, 8, 8, 8, 4, 8};
+
+template <class T>
+inline void coef_ptrs(const Coef &C, const T *&eps, const T *&bx, const T *&by, const T *&bz) {
+    eps = static_cast<const T *>(C.eps);
+    bx = static_cast<const T *>(C.bx);
+    by = static_cast<const T *>(C.by);
+    bz = static_cast<const T *>(C.bz);
+}
+
+// Prefetch depth of the column-pair smoother (planes in flight per array).
+constexpr int kSmoothPD = 2;
+
+template <class T, int MODE, int TX, int TY>
+hipError_t smooth_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *uin, void *uout,
+                       const void *b, bool zero_in, int cz, const int *done) {
+    const T *eps, *bx, *by, *bz;
+    coef_ptrs<T>(Cf, eps, bx, by, bz);
+    const int tiles_x = (G.nx + TX - 1) / TX, tiles_y = (G.ny + TY - 1) / TY;
+    const int chunks = (G.nz + cz - 1) / cz;
+    const int nblk = tiles_x * tiles_y * chunks;
+    const dim3 grid(nblk), block((TX + 4) / 2 * (TY + 4));
+    if (zero_in)
+        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, true, kSmoothPD>), grid, block, 0, s,
+                           static_cast<const T *>(uin), static_cast<T *>(uout),
+                           static_cast<const T *>(b), eps, bx, by, bz, G, cz, tiles_x, tiles_y, nblk, done);
+    else
+        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, false, kSmoothPD>), grid, block, 0, s,
+                           static_cast<const T *>(uin), static_cast<T *>(uout),
+                           static_cast<const T *>(b), eps, bx, by, bz, G, cz, tiles_x, tiles_y, nblk, done);
+    return hipGetLastError();
+}
+
+template <class T, int MODE>
+hipError_t smooth_mode(hipStream_t s, const Geo &G, const Coef &Cf, const void *uin, void *uout,
+                       const void *b, bool zero_in, int tile, int cz, const int *done) {
+    switch (tile) {
+        case 1: return smooth_tile<T, MODE, 64, 16>(s, G, Cf, uin, uout, b, zero_in, cz, done);
+        case 2: return smooth_tile<T, MODE, 128, 8>(s, G, Cf, uin, uout, b, zero_in, cz, done);
+        case 3: return smooth_tile<T, MODE, 64, 8>(s, G, Cf, uin, uout, b, zero_in, cz, done);
+        case 4: return smooth_tile<T, MODE, 32, 8>(s, G, Cf, uin, uout, b, zero_in, cz, done);
+        case 5: return smooth_tile<T, MODE, 32, 4>(s, G, Cf, uin, uout, b, zero_in, cz, done);
+        case 6: return smooth_tile<T, MODE, 16, 8>(s, G, Cf, uin, uout, b, zero_in, cz, done);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class T>
+hipError_t smooth_T(hipStream_t s, const Geo &G, const Coef &Cf, const void *uin, void *uout,
+                    const void *b, bool zero_in, int tile, int cz, const int *done) {
+    if (cz < 1) return hipErrorInvalidValue;
+    switch (Cf.mode) {
+        case COEF_CONST: return smooth_mode<T, COEF_CONST>(s, G, Cf, uin, uout, b, zero_in, tile, cz, done);
+        case COEF_CELL: return smooth_mode<T, COEF_CELL>(s, G, Cf, uin, uout, b, zero_in, tile, cz, done);
+        case COEF_FACE: return smooth_mode<T, COEF_FACE>(s, G, Cf, uin, uout, b, zero_in, tile, cz, done);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class T, int MODE, int TX, int TY>
+hipError_t rr_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, const void *b, void *bc,
+                   const RrCheck &chk) {
+    const T *eps, *bx, *by, *bz;
+    coef_ptrs<T>(Cf, eps, bx, by, bz);
+    const int tiles_x = (G.nx + TX - 1) / TX, tiles_y = (G.ny + TY - 1) / TY;
+    const long cols = (long)tiles_x * tiles_y;
+    long chunks = (512 + cols - 1) / cols;
+    long maxch = G.nz / 8;
+    if (maxch < 1) maxch = 1;
+    if (chunks > maxch) chunks = maxch;
+    int cz = (int)((G.nz + chunks - 1) / chunks);
+    cz += cz & 1;  // chunks hold whole coarse planes
+    const int nblk = tiles_x * tiles_y * ((G.nz + cz - 1) / cz);
+    constexpr int NTH = ((TX + 4) / 2 * (TY + 2) + 63) / 64 * 64;
+    if (chk.slot >= 0 && nblk > kMaxRedBlocks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((rr_col_k<T, MODE, TX, TY, kSmoothPD>), dim3(nblk), dim3(NTH), 0, s,
+                       static_cast<const T *>(u), static_cast<const T *>(b), eps, bx, by, bz, G,
+                       static_cast<T *>(bc), cz, tiles_x, tiles_y, nblk, chk.ws, chk.slot, chk.ref_slot,
+                       chk.rtol2, chk.done_out, chk.done_in);
+    return hipGetLastError();
+}
+
+template <class T, int MODE>
+hipError_t rr_mode(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, const void *b, void *bc,
+                   const RrCheck &chk) {
+    if (G.nx >= 64 && G.ny >= 16) return rr_tile<T, MODE, 64, 16>(s, G, Cf, u, b, bc, chk);
+    if (G.nx >= 64) return rr_tile<T, MODE, 64, 8>(s, G, Cf, u, b, bc, chk);
+    if (G.nx >= 32) return rr_tile<T, MODE, 32, 8>(s, G, Cf, u, b, bc, chk);
+    return rr_tile<T, MODE, 16, 8>(s, G, Cf, u, b, bc, chk);
+}
+
+template <class T>
+hipError_t resid_restrict_T(hipStream_t s, const Geo &G, const Coef &Cf, const void *u,
+                            const void *b, void *bc, const RrCheck &chk) {
+    if ((G.nx | G.ny | G.nz) & 1) return hipErrorInvalidValue;
+    switch (Cf.mode) {
+        case COEF_CONST: return rr_mode<T, COEF_CONST>(s, G, Cf, u, b, bc, chk);
+        case COEF_CELL: return rr_mode<T, COEF_CELL>(s, G, Cf, u, b, bc, chk);
+        case COEF_FACE: return rr_mode<T, COEF_FACE>(s, G, Cf, u, b, bc, chk);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class T>
+hipError_t prolong_T(hipStream_t s, const Geo &G, void *u, const Geo &Gc, const void *e, const int *done) {
+    dim3 grid, block;
+    int kz;
+    brick_shape(Gc.nx, G.ny, G.nz, 0, &grid, &block, &kz);
+    hipLaunchKernelGGL((prolong_k<T, T>), grid, block, 0, s, static_cast<T *>(u),
+                       static_cast<const T *>(e), G, Gc, done);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t norm2_T(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, const void *b,
+                   const RedWs &ws, int slot, int bslot, const RrCheck *chk) {
+    const int ref = chk ? chk->ref_slot : -1;
+    const double rt2 = chk ? chk->rtol2 : 0.0;
+    int *dout = chk ? chk->done_out : nullptr;
+    const int *din = chk ? chk->done_in : nullptr;
+    const T *eps, *bx, *by, *bz;
+    coef_ptrs<T>(Cf, eps, bx, by, bz);
+    dim3 grid, block;
+    int kz;
+    brick_shape(G.nx, G.ny, G.nz, kMaxRedBlocks, &grid, &block, &kz);
+    const T *uu = static_cast<const T *>(u), *bb = static_cast<const T *>(b);
+    switch (Cf.mode) {
+        case COEF_CONST:
+            hipLaunchKernelGGL((norm2_resid_k<T, COEF_CONST>), grid, block, 0, s, uu, bb, eps,
+                               bx, by, bz, G, ws, slot, bslot, kz, ref, rt2, dout, din);
+            break;
+        case COEF_CELL:
+            hipLaunchKernelGGL((norm2_resid_k<T, COEF_CELL>), grid, block, 0, s, uu, bb, eps,
+                               bx, by, bz, G, ws, slot, bslot, kz, ref, rt2, dout, din);
+            break;
+        case COEF_FACE:
+            hipLaunchKernelGGL((norm2_resid_k<T, COEF_FACE>), grid, block, 0, s, uu, bb, eps,
+                               bx, by, bz, G, ws, slot, bslot, kz, ref, rt2, dout, din);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mg
+
+// Exported per-type entry points (names suffixed by the storage type).
+#define MG_DEFINE_TYPE_ENTRIES(T, SUF)                                                              \
+    namespace mg {                                                                                  \
+    hipError_t smooth_##SUF(hipStream_t s, const Geo &G, const Coef &C, const void *uin, void *uout, \
+                            const void *b, bool zin, int tile, int cz, const int *done) {           \
+        return smooth_T<T>(s, G, C, uin, uout, b, zin, tile, cz, done);                             \
+    }                                                                                               \
+    hipError_t resid_restrict_##SUF(hipStream_t s, const Geo &G, const Coef &C, const void *u,       \
+                                    const void *b, void *bc, const RrCheck &chk) {                  \
+        return resid_restrict_T<T>(s, G, C, u, b, bc, chk);                                         \
+    }                                                                                               \
+    hipError_t prolong_##SUF(hipStream_t s, const Geo &G, void *u, const Geo &Gc, const void *e,     \
+                             const int *done) {                                                     \
+        return prolong_T<T>(s, G, u, Gc, e, done);                                                  \
+    }                                                                                               \
+    hipError_t norm2_##SUF(hipStream_t s, const Geo &G, const Coef &C, const void *u, const void *b, \
+                           const RedWs &ws, int slot, int bslot, const RrCheck *chk) {              \
+        return norm2_T<T>(s, G, C, u, b, ws, slot, bslot, chk);                                     \
+    }                                                                                               \
+    }

@@ -1,0 +1,399 @@
+// Set-up kernels, FP64 refinement kernels and the storage-type dispatch of
+// the stencil launchers.
+#include "mg_stencil.cuh"
+
+namespace mg {
+
+#define MG_DECLARE_TYPE_ENTRIES(SUF)                                                                \
+    hipError_t smooth_##SUF(hipStream_t, const Geo &, const Coef &, const void *, void *,          \
+                            const void *, bool, int, int, const int *);                             \
+    hipError_t resid_restrict_##SUF(hipStream_t, const Geo &, const Coef &, const void *,           \
+                                    const void *, void *, const RrCheck &);                         \
+    hipError_t prolong_##SUF(hipStream_t, const Geo &, void *, const Geo &, const void *,           \
+                             const int *);                                                          \
+    hipError_t norm2_##SUF(hipStream_t, const Geo &, const Coef &, const void *, const void *,      \
+                           const RedWs &, int, int, const RrCheck *);
+MG_DECLARE_TYPE_ENTRIES(f64)
+MG_DECLARE_TYPE_ENTRIES(f32)
+MG_DECLARE_TYPE_ENTRIES(bf16)
+
+hipError_t smooth(hipStream_t s, int st, const Geo &G, const Coef &C, const void *uin, void *uout,
+                  const void *b, bool zero_in, int tile, int zchunk, const int *done) {
+    switch (st) {
+        case ST_F64: return smooth_f64(s, G, C, uin, uout, b, zero_in, tile, zchunk, done);
+        case ST_F32: return smooth_f32(s, G, C, uin, uout, b, zero_in, tile, zchunk, done);
+        case ST_BF16: return smooth_bf16(s, G, C, uin, uout, b, zero_in, tile, zchunk, done);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t resid_restrict(hipStream_t s, int st, const Geo &G, const Coef &C, const void *u,
+                          const void *b, int stc, void *bc, const RrCheck &chk) {
+    if (stc != st) return hipErrorInvalidValue;
+    switch (st) {
+        case ST_F64: return resid_restrict_f64(s, G, C, u, b, bc, chk);
+        case ST_F32: return resid_restrict_f32(s, G, C, u, b, bc, chk);
+        case ST_BF16: return resid_restrict_bf16(s, G, C, u, b, bc, chk);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t prolong_add(hipStream_t s, int st, const Geo &G, void *u, int stc, const Geo &Gc,
+                       const void *e, const int *done) {
+    if (stc != st) return hipErrorInvalidValue;
+    switch (st) {
+        case ST_F64: return prolong_f64(s, G, u, Gc, e, done);
+        case ST_F32: return prolong_f32(s, G, u, Gc, e, done);
+        case ST_BF16: return prolong_bf16(s, G, u, Gc, e, done);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t norm2_resid(hipStream_t s, int st, const Geo &G, const Coef &C, const void *u,
+                       const void *b, const RedWs &ws, int slot, int bslot, const RrCheck *chk) {
+    switch (st) {
+        case ST_F64: return norm2_f64(s, G, C, u, b, ws, slot, bslot, chk);
+        case ST_F32: return norm2_f32(s, G, C, u, b, ws, slot, bslot, chk);
+        case ST_BF16: return norm2_bf16(s, G, C, u, b, ws, slot, bslot, chk);
+    }
+    return hipErrorInvalidValue;
+}
+
+void tile_shape(int t, int *tx, int *ty) {
+    static const int TX[kNumTiles + 1] = {0, 64, 128, 64, 32, 32, 16};
+    static const int TY[kNumTiles + 1] = {0, 16, 8, 8, 8, 4, 8};
+    if (t < 1 || t > kNumTiles) t = 1;
+    *tx = TX[t];
+    *ty = TY[t];
+}
+
+int default_tile(const Geo &G, int st) {
+    (void)st;
+    if (G.nx >= 64 && G.ny >= 16 && (long)G.nx * G.ny * G.nz >= (8L << 20)) return 1;  // 64 x 16
+    if (G.nx >= 64) return 3;                 // 64 x 8
+    if (G.nx >= 32) return 4;                 // 32 x 8
+    return 6;                                 // 16 x 8
+}
+
+int default_zchunk(const Geo &G, int tile) {
+    int tx, ty;
+    tile_shape(tile, &tx, &ty);
+    const long cols = (long)((G.nx + tx - 1) / tx) * ((G.ny + ty - 1) / ty);
+    // about one workgroup per CU (a workgroup holds 5-12 waves) while
+    // keeping >= 8 planes per chunk, so the two planes recomputed at each
+    // chunk boundary stay a small overhead
+    long chunks = (256 + cols - 1) / cols;
+    long maxchunks = G.nz / 8;
+    if (maxchunks < 1) maxchunks = 1;
+    if (chunks > maxchunks) chunks = maxchunks;
+    if (chunks < 1) chunks = 1;
+    return (int)((G.nz + chunks - 1) / chunks);
+}
+
+// ------------------------------------------------------------ set-up
+
+__global__ void faces_from_cell_k(const double *__restrict__ eps, double *__restrict__ bx,
+                                  double *__restrict__ by, double *__restrict__ bz, Geo G) {
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const size_t nfx = (size_t)(nx + 1) * ny * nz, nfy = (size_t)nx * (ny + 1) * nz,
+                 nfz = (size_t)nx * ny * (nz + 1);
+    auto E = [&](int i, int j, int k) { return eps[((size_t)k * ny + j) * nx + i]; };
+    auto H = [](double p, double q) { return 2.0 * p * q / (p + q); };
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nfx + nfy + nfz;
+         t += (size_t)gridDim.x * blockDim.x) {
+        if (t < nfx) {
+            const int i = (int)(t % (nx + 1));
+            const size_t r = t / (nx + 1);
+            const int j = (int)(r % ny), k = (int)(r / ny);
+            bx[t] = i == 0 ? E(0, j, k) : (i == nx ? E(nx - 1, j, k) : H(E(i - 1, j, k), E(i, j, k)));
+        } else if (t < nfx + nfy) {
+            const size_t u = t - nfx;
+            const int i = (int)(u % nx);
+            const size_t r = u / nx;
+            const int j = (int)(r % (ny + 1)), k = (int)(r / (ny + 1));
+            by[u] = j == 0 ? E(i, 0, k) : (j == ny ? E(i, ny - 1, k) : H(E(i, j - 1, k), E(i, j, k)));
+        } else {
+            const size_t u = t - nfx - nfy;
+            const int i = (int)(u % nx);
+            const size_t r = u / nx;
+            const int j = (int)(r % ny), k = (int)(r / ny);
+            bz[u] = k == 0 ? E(i, j, 0) : (k == nz ? E(i, j, nz - 1) : H(E(i, j, k - 1), E(i, j, k)));
+        }
+    }
+}
+
+hipError_t faces_from_cell(hipStream_t s, const Geo &G, const double *eps, double *bx, double *by,
+                           double *bz) {
+    const size_t n = (size_t)(G.nx + 1) * G.ny * G.nz + (size_t)G.nx * (G.ny + 1) * G.nz +
+                     (size_t)G.nx * G.ny * (G.nz + 1);
+    size_t g = (n + 255) / 256;
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(faces_from_cell_k, dim3(g), dim3(256), 0, s, eps, bx, by, bz, G);
+    return hipGetLastError();
+}
+
+// coarse face = mean of the 4 fine faces it covers
+__global__ void coarsen_faces_k(const double *__restrict__ fbx, const double *__restrict__ fby,
+                                const double *__restrict__ fbz, Geo Gf, double *__restrict__ cbx,
+                                double *__restrict__ cby, double *__restrict__ cbz, Geo Gc) {
+    const int nx = Gc.nx, ny = Gc.ny, nz = Gc.nz;
+    const int fnx = Gf.nx, fny = Gf.ny;
+    const size_t nfx = (size_t)(nx + 1) * ny * nz, nfy = (size_t)nx * (ny + 1) * nz,
+                 nfz = (size_t)nx * ny * (nz + 1);
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nfx + nfy + nfz;
+         t += (size_t)gridDim.x * blockDim.x) {
+        if (t < nfx) {
+            const int i = (int)(t % (nx + 1));
+            const size_t r = t / (nx + 1);
+            const int j = (int)(r % ny), k = (int)(r / ny);
+            double s = 0.0;
+            for (int dk = 0; dk < 2; ++dk)
+                for (int dj = 0; dj < 2; ++dj)
+                    s += fbx[((size_t)(2 * k + dk) * fny + (2 * j + dj)) * (fnx + 1) + 2 * i];
+            cbx[t] = 0.25 * s;
+        } else if (t < nfx + nfy) {
+            const size_t u = t - nfx;
+            const int i = (int)(u % nx);
+            const size_t r = u / nx;
+            const int j = (int)(r % (ny + 1)), k = (int)(r / (ny + 1));
+            double s = 0.0;
+            for (int dk = 0; dk < 2; ++dk)
+                for (int di = 0; di < 2; ++di)
+                    s += fby[((size_t)(2 * k + dk) * (fny + 1) + 2 * j) * fnx + (2 * i + di)];
+            cby[u] = 0.25 * s;
+        } else {
+            const size_t u = t - nfx - nfy;
+            const int i = (int)(u % nx);
+            const size_t r = u / nx;
+            const int j = (int)(r % ny), k = (int)(r / ny);
+            double s = 0.0;
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di)
+                    s += fbz[((size_t)(2 * k) * fny + (2 * j + dj)) * fnx + (2 * i + di)];
+            cbz[u] = 0.25 * s;
+        }
+    }
+}
+
+hipError_t coarsen_faces(hipStream_t s, const Geo &Gf, const double *fbx, const double *fby,
+                         const double *fbz, const Geo &Gc, double *cbx, double *cby, double *cbz) {
+    const size_t n = (size_t)(Gc.nx + 1) * Gc.ny * Gc.nz + (size_t)Gc.nx * (Gc.ny + 1) * Gc.nz +
+                     (size_t)Gc.nx * Gc.ny * (Gc.nz + 1);
+    size_t g = (n + 255) / 256;
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(coarsen_faces_k, dim3(g), dim3(256), 0, s, fbx, fby, fbz, Gf, cbx, cby, cbz,
+                       Gc);
+    return hipGetLastError();
+}
+
+template <class T>
+__global__ void convert_k(const double *__restrict__ src, T *__restrict__ dst, size_t n) {
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x)
+        dst[t] = Num<T>::cv(typename Num<T>::C(src[t]));
+}
+
+hipError_t convert(hipStream_t s, const double *src, int st, void *dst, size_t n) {
+    size_t g = (n + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    switch (st) {
+        case ST_F64:
+            hipLaunchKernelGGL(convert_k<double>, dim3(g), dim3(256), 0, s, src, (double *)dst, n);
+            break;
+        case ST_F32:
+            hipLaunchKernelGGL(convert_k<float>, dim3(g), dim3(256), 0, s, src, (float *)dst, n);
+            break;
+        case ST_BF16:
+            hipLaunchKernelGGL(convert_k<bf16>, dim3(g), dim3(256), 0, s, src, (bf16 *)dst, n);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void count_bad_k(const double *__restrict__ x, size_t n, RedWs ws,
+                                                   int slot) {
+    double c = 0.0;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const double v = x[t];
+        if (!(v > 0.0) || !isfinite(v)) c += 1.0;
+    }
+    reduce2_finish<256>(c, 0.0, ws, slot, -1);
+}
+
+hipError_t count_bad(hipStream_t s, const double *x, size_t n, const RedWs &ws, int slot) {
+    size_t g = (n + 255) / 256;
+    if (g > (size_t)kMaxRedBlocks) g = kMaxRedBlocks;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(count_bad_k, dim3(g), dim3(256), 0, s, x, n, ws, slot);
+    return hipGetLastError();
+}
+
+// Zero fill by a kernel (a plain kernel node, safe inside captured graphs).
+__global__ void fill_zero_k(uint32_t *__restrict__ p, size_t nwords, uint16_t *tail, int has_tail,
+                            const int *__restrict__ done) {
+    if (done && *done) return;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nwords;
+         t += (size_t)gridDim.x * blockDim.x)
+        p[t] = 0u;
+    if (has_tail && blockIdx.x == 0 && threadIdx.x == 0) *tail = 0;
+}
+
+hipError_t fill_zero(hipStream_t s, void *p, size_t bytes, const int *done) {
+    if (bytes == 0) return hipSuccess;
+    const size_t nw = bytes / 4;
+    const int has_tail = (bytes % 4) != 0;
+    size_t g = (nw + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(fill_zero_k, dim3(g), dim3(256), 0, s, (uint32_t *)p, nw,
+                       (uint16_t *)((char *)p + nw * 4), has_tail, done);
+    return hipGetLastError();
+}
+
+__global__ void copy_f64_k(const double *__restrict__ a, double *__restrict__ b, size_t n,
+                           const int *__restrict__ done) {
+    if (done && *done) return;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x)
+        b[t] = a[t];
+}
+
+hipError_t copy_f64(hipStream_t s, const double *src, double *dst, size_t n, const int *done) {
+    size_t g = (n + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(copy_f64_k, dim3(g), dim3(256), 0, s, src, dst, n, done);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ FP64 residual
+
+template <int MODE>
+__global__ __launch_bounds__(256) void resid_out_k(const double *__restrict__ u,
+                                                   const double *__restrict__ b,
+                                                   const double *__restrict__ eps,
+                                                   const double *__restrict__ bx,
+                                                   const double *__restrict__ by,
+                                                   const double *__restrict__ bz, Geo G,
+                                                   double *__restrict__ r) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= G.nx || j >= G.ny) return;
+    r[((size_t)k * G.ny + j) * G.nx + i] = resid_global<double, MODE>(u, b, eps, bx, by, bz, G, i, j, k);
+}
+
+hipError_t resid_out(hipStream_t s, const Geo &G, const Coef &C, const double *u, const double *b,
+                     double *r) {
+    dim3 grid, block;
+    int kz;
+    brick_shape(G.nx, G.ny, G.nz, 0, &grid, &block, &kz);
+    const double *eps = (const double *)C.eps, *bx = (const double *)C.bx,
+                 *by = (const double *)C.by, *bz = (const double *)C.bz;
+    switch (C.mode) {
+        case COEF_CONST:
+            hipLaunchKernelGGL(resid_out_k<COEF_CONST>, grid, block, 0, s, u, b, eps, bx, by, bz, G, r);
+            break;
+        case COEF_CELL:
+            hipLaunchKernelGGL(resid_out_k<COEF_CELL>, grid, block, 0, s, u, b, eps, bx, by, bz, G, r);
+            break;
+        case COEF_FACE:
+            hipLaunchKernelGGL(resid_out_k<COEF_FACE>, grid, block, 0, s, u, b, eps, bx, by, bz, G, r);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ refinement
+// xn = x + e (FP64 + low precision), r = b - A xn in FP64, r stored in the
+// low-precision type, ||r||^2 accumulated in FP64.
+template <class TL, int MODE, bool HAS_E>
+__global__ __launch_bounds__(256) void ir_update_resid_k(const double *__restrict__ x,
+                                                         const TL *__restrict__ e,
+                                                         double *__restrict__ xout,
+                                                         const double *__restrict__ b,
+                                                         const double *__restrict__ eps, Geo G,
+                                                         TL *__restrict__ rl, RedWs ws, int slot,
+                                                         int kz, int ref_slot, double rtol2,
+                                                         int *__restrict__ done_out,
+                                                         const int *__restrict__ done_in) {
+    if (done_in && *done_in) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k0 = blockIdx.z * kz;
+    const int k1 = min(k0 + kz, G.nz);
+    const size_t sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
+    double sr = 0.0;
+    if (i < G.nx && j < G.ny) {
+        for (int k = k0; k < k1; ++k) {
+            const size_t p = (size_t)k * sz + (size_t)j * sy + i;
+            auto X = [&](size_t m) -> double {
+                if constexpr (HAS_E) return x[m] + (double)Num<TL>::ld(e[m]);
+                else return x[m];
+            };
+            auto nb = [&](int d) -> size_t {
+                return d == 0 ? p - 1 : d == 1 ? p + 1 : d == 2 ? p - sy : d == 3 ? p + sy : d == 4 ? p - sz : p + sz;
+            };
+            double eP = 1.0;
+            if constexpr (MODE == COEF_CELL) eP = eps[p];
+            double off, dg;
+            six_faces<double, MODE>(
+                G, i, j, k, eP, [&](int d) { return X(nb(d)); }, [&](int d) { return eps[nb(d)]; },
+                [&](int) { return 1.0; }, off, dg);
+            const double xp = X(p);
+            if constexpr (HAS_E) xout[p] = xp;
+            const double r = b[p] - G.a * xp - G.ih2 * (dg * xp - off);
+            rl[p] = Num<TL>::cv(typename Num<TL>::C(r));
+            sr += r * r;
+        }
+    }
+    reduce2_finish<256>(sr, 0.0, ws, slot, -1, ref_slot, rtol2, done_out);
+}
+
+template <class TL>
+static hipError_t ir_update_resid_T(hipStream_t s, const Geo &G, const Coef &C, const double *x,
+                                    const void *e, double *xout, const double *b, void *r_lp,
+                                    const RrCheck &k) {
+    const RedWs &ws = k.ws;
+    const int slot = k.slot;
+    dim3 g, blk;
+    int kz;
+    brick_shape(G.nx, G.ny, G.nz, kMaxRedBlocks, &g, &blk, &kz);
+    const double *eps = (const double *)C.eps;
+    const TL *el = (const TL *)e;
+    TL *rl = (TL *)r_lp;
+    if (C.mode == COEF_CELL) {
+        if (e)
+            hipLaunchKernelGGL((ir_update_resid_k<TL, COEF_CELL, true>), g, blk, 0, s, x, el,
+                               xout, b, eps, G, rl, ws, slot, kz, k.ref_slot, k.rtol2, k.done_out, k.done_in);
+        else
+            hipLaunchKernelGGL((ir_update_resid_k<TL, COEF_CELL, false>), g, blk, 0, s, x,
+                               el, xout, b, eps, G, rl, ws, slot, kz, k.ref_slot, k.rtol2, k.done_out, k.done_in);
+    } else if (C.mode == COEF_CONST) {
+        if (e)
+            hipLaunchKernelGGL((ir_update_resid_k<TL, COEF_CONST, true>), g, blk, 0, s, x,
+                               el, xout, b, eps, G, rl, ws, slot, kz, k.ref_slot, k.rtol2, k.done_out, k.done_in);
+        else
+            hipLaunchKernelGGL((ir_update_resid_k<TL, COEF_CONST, false>), g, blk, 0, s, x,
+                               el, xout, b, eps, G, rl, ws, slot, kz, k.ref_slot, k.rtol2, k.done_out, k.done_in);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t ir_update_resid(hipStream_t s, const Geo &G, const Coef &C, const double *x,
+                           const void *e, double *xout, const double *b, int stl, void *r_lp,
+                           const RrCheck &chk) {
+    switch (stl) {
+        case ST_F32: return ir_update_resid_T<float>(s, G, C, x, e, xout, b, r_lp, chk);
+        case ST_BF16: return ir_update_resid_T<bf16>(s, G, C, x, e, xout, b, r_lp, chk);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mg

@@ -1,0 +1,820 @@
+// Device templates of the cell-centred stencil kernels (smoother, residual,
+// restriction, prolongation, norms).  Included by one translation unit per
+// storage type.
+//
+// Operator of every level (second-order cell-centred finite volumes):
+//   (A u)_P = a u_P + h^-2 [ sum_interior beta_f (u_P - u_N)
+//                            + sum_Dirichlet 2 beta_b (u_P - g) ]
+// with beta_f the harmonic mean of the cell coefficients (finest level),
+// a stored face array (coarser levels) or 1, and beta_b the boundary
+// cell's own coefficient (or the stored boundary face).  A Neumann face
+// contributes nothing.  In terms of the per-cell sums
+//   off = sum_interior beta_f u_N + sum_Dirichlet 2 beta_b g
+//   dg  = sum_interior beta_f     + sum_Dirichlet 2 beta_b
+// a Gauss-Seidel update is u_P = (h^2 b_P + off) / (a h^2 + dg) and the
+// residual is b_P - a u_P - h^-2 (dg u_P - off).
+#pragma once
+
+#include <type_traits>
+
+#include "mg_internal.h"
+
+namespace mg {
+
+template <class T> struct Num;
+template <> struct Num<double> {
+    using C = double;
+    __device__ static __forceinline__ C ld(double v) { return v; }
+    __device__ static __forceinline__ double cv(C v) { return v; }
+};
+template <> struct Num<float> {
+    using C = float;
+    __device__ static __forceinline__ C ld(float v) { return v; }
+    __device__ static __forceinline__ float cv(C v) { return v; }
+};
+template <> struct Num<bf16> {
+    using C = float;
+    __device__ static __forceinline__ C ld(bf16 v) { return __bfloat162float(v); }
+    __device__ static __forceinline__ bf16 cv(C v) { return __float2bfloat16(v); }
+};
+
+template <class T> struct alignas(2 * sizeof(T)) Pair {
+    T v[2];
+};
+
+// Hardware hands workgroup w to XCD (w mod 8).  Give every XCD one
+// contiguous range of tiles so that tiles sharing halo planes share an L2.
+__device__ __forceinline__ int xcd_remap(int w, int n) {
+    constexpr int X = 8;
+    const int q = n / X, r = n % X;
+    const int xcd = w % X, pos = w / X;
+    return xcd * q + min(xcd, r) + pos;
+}
+
+// Workgroup barrier that orders LDS traffic only.  __syncthreads() also
+// fences global memory, which makes every wave wait for all of its
+// outstanding global loads (the register prefetch) at each barrier; the
+// stencil kernels never exchange data through global memory inside a
+// workgroup, so an LDS-scoped fence is sufficient.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Face coefficient arrays (FACE mode), see mg_internal.h for the layout.
+template <class T>
+__device__ __forceinline__ typename Num<T>::C face_x(const T *bx, const Geo &G, int i, int j, int k) {
+    return Num<T>::ld(bx[((size_t)k * G.ny + j) * (G.nx + 1) + i]);
+}
+template <class T>
+__device__ __forceinline__ typename Num<T>::C face_y(const T *by, const Geo &G, int i, int j, int k) {
+    return Num<T>::ld(by[((size_t)k * (G.ny + 1) + j) * G.nx + i]);
+}
+template <class T>
+__device__ __forceinline__ typename Num<T>::C face_z(const T *bz, const Geo &G, int i, int j, int k) {
+    return Num<T>::ld(bz[((size_t)k * G.ny + j) * G.nx + i]);
+}
+
+// Six-face sums (off, dg) of cell (i,j,k).  un(d), en(d), fb(d) give the
+// neighbour value, neighbour cell coefficient and stored face coefficient
+// in direction d = x-, x+, y-, y+, z-, z+; only the accessor matching MODE
+// is used.  SAFE: the accessors may be evaluated for every d, also across
+// the box boundary (LDS planes with a filled halo), so no branches are
+// needed; otherwise they are only evaluated for faces inside the box.
+// The sums live in locals (reference out-parameters that may alias would
+// otherwise be kept in scratch memory).
+template <class C, int MODE, bool SAFE = false, class UN, class EN, class FB>
+__device__ __forceinline__ void six_faces(const Geo &G, int i, int j, int k, C eP, UN un, EN en,
+                                          FB fb, C &off_out, C &dg_out) {
+    C off = C(0), dg = C(0);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const bool in = d == 0   ? i > 0
+                        : d == 1 ? i < G.nx - 1
+                        : d == 2 ? j > 0
+                        : d == 3 ? j < G.ny - 1
+                        : d == 4 ? k > 0
+                                 : k < G.nz - 1;
+        const bool dir = ((G.bcmask >> d) & 1) != 0;
+        C be_in, be_bd;
+        if constexpr (MODE == COEF_CONST) {
+            be_in = C(1);
+            be_bd = C(1);
+        } else if constexpr (MODE == COEF_CELL) {
+            C eN = eP;
+            if (SAFE || in) eN = en(d);
+            be_in = C(2) * eP * eN / (eP + eN);
+            be_bd = eP;
+        } else {
+            be_in = fb(d);
+            be_bd = be_in;
+        }
+        C uN = C(0);
+        if (SAFE || in) uN = un(d);
+        const C bnd = dir ? C(2) * be_bd : C(0);
+        off += in ? be_in * uN : bnd * C(G.g[d]);
+        dg += in ? be_in : bnd;
+    }
+    off_out = off;
+    dg_out = dg;
+}
+
+// Residual b - A u at cell (i,j,k), all operands read from global memory.
+template <class T, int MODE>
+__device__ __forceinline__ typename Num<T>::C resid_global(const T *__restrict__ u,
+                                                           const T *__restrict__ b,
+                                                           const T *__restrict__ eps,
+                                                           const T *__restrict__ bx,
+                                                           const T *__restrict__ by,
+                                                           const T *__restrict__ bz, const Geo &G,
+                                                           int i, int j, int k) {
+    using N = Num<T>;
+    using C = typename N::C;
+    const size_t sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
+    const size_t p = (size_t)k * sz + (size_t)j * sy + i;
+    auto nb = [&](int d) -> size_t {
+        return d == 0 ? p - 1 : d == 1 ? p + 1 : d == 2 ? p - sy : d == 3 ? p + sy : d == 4 ? p - sz : p + sz;
+    };
+    C eP = C(1);
+    if constexpr (MODE == COEF_CELL) eP = N::ld(eps[p]);
+    C off, dg;
+    six_faces<C, MODE>(
+        G, i, j, k, eP, [&](int d) { return N::ld(u[nb(d)]); },
+        [&](int d) { return N::ld(eps[nb(d)]); },
+        [&](int d) {
+            switch (d) {
+                case 0: return face_x(bx, G, i, j, k);
+                case 1: return face_x(bx, G, i + 1, j, k);
+                case 2: return face_y(by, G, i, j, k);
+                case 3: return face_y(by, G, i, j + 1, k);
+                case 4: return face_z(bz, G, i, j, k);
+                default: return face_z(bz, G, i, j, k + 1);
+            }
+        },
+        off, dg);
+    const C uP = N::ld(u[p]);
+    return N::ld(b[p]) - C(G.a) * uP - C(G.ih2) * (dg * uP - off);
+}
+
+// ---------------------------------------------------------------------
+// Fused red-black Gauss-Seidel sweep, column-pair form (out of place).
+//
+// A workgroup owns a TX x TY tile and marches up a chunk of z planes; each
+// thread owns one pair of adjacent x-columns (x, x+1) of the tile grown by a
+// 2-cell halo, so on every plane the pair holds exactly one red and one
+// black cell.  At step k the pair's red cell on plane k is updated (tile +
+// 1-cell ring) from old black values, and the black cell on plane k-1
+// (tile only) from new red values.  Vertical neighbours never leave the
+// thread's registers; in-plane neighbours are exchanged through LDS (one
+// plane of old u, two planes of new red values, two planes of the cell
+// coefficient).  u, b (and eps) stream in with one 16-byte load per array
+// and plane, PD planes ahead of use, and the compute phases issue no
+// global loads (except the stored faces of FACE mode), so a wait only ever
+// covers the oldest plane in flight.  Ring cells are recomputed by every
+// tile that needs them, from the same old values, so tiles never wait for
+// each other and the result equals a red sweep followed by a black sweep.
+template <class T, int MODE, int TX, int TY, bool ZIN, int PD>
+__global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void rbgs_col_k(
+    const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ b,
+    const T *__restrict__ eps, const T *__restrict__ fbx, const T *__restrict__ fby,
+    const T *__restrict__ fbz, Geo G, int cz, int tiles_x, int tiles_y, int nblk,
+    const int *__restrict__ done) {
+    if (done && *done) return;  // the solve has converged: nothing left to do
+    using N = Num<T>;
+    using C = typename N::C;
+    constexpr int PXW = (TX + 4) / 2;  // pairs per region row
+    constexpr int RX = TX + 4, RY = TY + 4;
+    constexpr bool CELL = (MODE == COEF_CELL);
+    __shared__ C s_u[RY][RX];
+    __shared__ C s_r[2][RY][RX];
+    __shared__ C s_e[CELL ? 2 : 1][CELL ? RY : 1][CELL ? RX : 1];
+
+    const int tid = threadIdx.x;
+    const int blk = xcd_remap(blockIdx.x, nblk);
+    const int tx = blk % tiles_x;
+    const int rest = blk / tiles_x;
+    const int ty = rest % tiles_y;
+    const int tc = rest / tiles_y;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tc * cz;
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int z1 = min(z0 + cz, nz);
+    const size_t plane = (size_t)nx * ny;
+    const C h2 = C(G.h2), ah2 = C(G.ah2);
+
+    const int ry = tid / PXW, pc = tid - ry * PXW;
+    const int lx = 2 * pc;                  // LDS column of the pair's first cell
+    const int x = lx - 2, y = ry - 2;       // tile coordinates of the pair
+    const int gx = x0 + x, gy = y0 + y;     // global coordinates of its first cell
+    const bool row_in = gy >= 0 && gy < ny;
+    const bool c0_in = row_in && gx >= 0 && gx < nx;
+    const bool c1_in = row_in && gx + 1 >= 0 && gx + 1 < nx;
+    const bool even_nx = (nx & 1) == 0;
+    const bool core = x >= 0 && x < TX && y >= 0 && y < TY;
+    const size_t rowoff = (size_t)(row_in ? gy : 0) * nx;
+
+    struct P2 { C v[2]; };
+    // load one pair of plane k (values outside the box are masked by the caller)
+    auto ld_pair = [&](const T *__restrict__ a, int k) -> P2 {
+        P2 r;
+        const bool kin = k >= 0 && k < nz;
+        if (even_nx) {
+            const size_t g = (kin && c0_in) ? (size_t)k * plane + rowoff + gx : 0;
+            const Pair<T> w = *reinterpret_cast<const Pair<T> *>(a + g);
+            r.v[0] = N::ld(w.v[0]);
+            r.v[1] = N::ld(w.v[1]);
+        } else {
+            const size_t base = (size_t)(kin ? k : 0) * plane + rowoff;
+            r.v[0] = N::ld(a[(kin && c0_in) ? base + gx : 0]);
+            r.v[1] = N::ld(a[(kin && c1_in) ? base + gx + 1 : 0]);
+        }
+        return r;
+    };
+    auto valid = [&](int k, int c) { return k >= 0 && k < nz && (c ? c1_in : c0_in); };
+    // select, not an index: a runtime index would force the pair into memory
+    auto pick = [](const P2 &p, int c) -> C { return c ? p.v[1] : p.v[0]; };
+
+    // current planes: u at k-1, k, k+1; b at k-1, k, k+1; eps at k-2..k+1
+    P2 um, u0, up, bm, b0, bp, em2, em, e0, ep;
+    // prefetch ring (plane p in slot (p - z0 - 1) mod PD); one named
+    // variable per slot so that the ring stays in registers
+    static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
+    P2 qu0, qu1, qu2, qu3, qb0, qb1, qb2, qb3, qe0, qe1, qe2, qe3;
+    auto QU = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qu0; else if constexpr (v == 1) return qu1;
+        else if constexpr (v == 2) return qu2; else return qu3;
+    };
+    auto QB = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qb0; else if constexpr (v == 1) return qb1;
+        else if constexpr (v == 2) return qb2; else return qb3;
+    };
+    auto QE = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qe0; else if constexpr (v == 1) return qe1;
+        else if constexpr (v == 2) return qe2; else return qe3;
+    };
+    auto masku = [&](P2 v, int k) { P2 r; r.v[0] = valid(k, 0) ? v.v[0] : C(0); r.v[1] = valid(k, 1) ? v.v[1] : C(0); return r; };
+    auto maske = [&](P2 v, int k) { P2 r; r.v[0] = valid(k, 0) ? v.v[0] : C(1); r.v[1] = valid(k, 1) ? v.v[1] : C(1); return r; };
+    auto issue = [&](int k, P2 &du, P2 &db, P2 &de) {
+        if constexpr (!ZIN) du = ld_pair(uin, k);
+        db = ld_pair(b, k);
+        if constexpr (CELL) de = ld_pair(eps, k);
+    };
+    {
+        P2 t0u, t0b, t0e, t1u, t1b, t1e, t2u, t2b, t2e, t3u, t3b, t3e;
+        issue(z0 - 3, t3u, t3b, t3e);
+        issue(z0 - 2, t0u, t0b, t0e);
+        issue(z0 - 1, t1u, t1b, t1e);
+        issue(z0, t2u, t2b, t2e);
+        issue(z0 + 1, qu0, qb0, qe0);
+        if constexpr (PD > 1) issue(z0 + 2, qu1, qb1, qe1);
+        if constexpr (PD > 2) issue(z0 + 3, qu2, qb2, qe2);
+        if constexpr (PD > 3) issue(z0 + 4, qu3, qb3, qe3);
+        P2 zero; zero.v[0] = zero.v[1] = C(0);
+        um = ZIN ? zero : masku(t0u, z0 - 2);
+        u0 = ZIN ? zero : masku(t1u, z0 - 1);
+        up = ZIN ? zero : masku(t2u, z0);
+        bm = masku(t0b, z0 - 2);
+        b0 = masku(t1b, z0 - 1);
+        bp = masku(t2b, z0);
+        if constexpr (CELL) {
+            em2 = maske(t3e, z0 - 3);
+            em = maske(t0e, z0 - 2);
+            e0 = maske(t1e, z0 - 1);
+            ep = maske(t2e, z0);
+        }
+    }
+    C rn_cur = C(0), rn_prev = C(0), rn_prev2 = C(0);  // new red values of planes k, k-1, k-2
+
+    auto step = [&](int k) {
+        // ---- publish plane k (old u, eps) for the in-plane neighbours
+        {
+            Pair<C> w;
+            w.v[0] = u0.v[0];
+            w.v[1] = u0.v[1];
+            *reinterpret_cast<Pair<C> *>(&s_u[ry][lx]) = w;
+            if constexpr (CELL) {
+                w.v[0] = e0.v[0];
+                w.v[1] = e0.v[1];
+                *reinterpret_cast<Pair<C> *>(&s_e[k & 1][ry][lx]) = w;
+            }
+        }
+        lds_barrier();
+        // ---- red cell of plane k (tile + 1-cell ring)
+        rn_prev2 = rn_prev;
+        rn_prev = rn_cur;
+        {
+            const int ro = (gy + k) & 1;  // red cell of the pair: x + ro
+            const int xr = x + ro;
+            const int lr = lx + ro;
+            const bool doit = k >= 0 && k < nz && xr >= -1 && xr <= TX && y >= -1 && y <= TY &&
+                              (ro ? c1_in : c0_in);
+            if (doit) {
+                const int gxr = gx + ro;
+                const C eP = CELL ? pick(e0, ro) : C(1);
+                C off, dg;
+                six_faces<C, MODE, true>(
+                    G, gxr, gy, k, eP,
+                    [&](int d) -> C {
+                        if constexpr (ZIN) return C(0);
+                        else return d == 0   ? (ro ? u0.v[0] : s_u[ry][lr - 1])
+                                    : d == 1 ? (ro ? s_u[ry][lr + 1] : u0.v[1])
+                                    : d == 2 ? s_u[ry - 1][lr]
+                                    : d == 3 ? s_u[ry + 1][lr]
+                                    : d == 4 ? pick(um, ro)
+                                             : pick(up, ro);
+                    },
+                    [&](int d) -> C {
+                        if constexpr (!CELL) return C(1);
+                        else return d == 0   ? (ro ? e0.v[0] : s_e[k & 1][ry][lr - 1])
+                                    : d == 1 ? (ro ? s_e[k & 1][ry][lr + 1] : e0.v[1])
+                                    : d == 2 ? s_e[k & 1][ry - 1][lr]
+                                    : d == 3 ? s_e[k & 1][ry + 1][lr]
+                                    : d == 4 ? pick(em, ro)
+                                             : pick(ep, ro);
+                    },
+                    [&](int d) -> C {
+                        return d == 0   ? face_x(fbx, G, gxr, gy, k)
+                               : d == 1 ? face_x(fbx, G, gxr + 1, gy, k)
+                               : d == 2 ? face_y(fby, G, gxr, gy, k)
+                               : d == 3 ? face_y(fby, G, gxr, gy + 1, k)
+                               : d == 4 ? face_z(fbz, G, gxr, gy, k)
+                                        : face_z(fbz, G, gxr, gy, k + 1);
+                    },
+                    off, dg);
+                rn_cur = (h2 * pick(b0, ro) + off) / (ah2 + dg);
+                s_r[k & 1][ry][lr] = rn_cur;
+            }
+        }
+        // ---- black cell of plane k-1 (tile only); write the pair
+        {
+            const int kb = k - 1;
+            const int ro = (gy + kb) & 1;  // red cell of the pair on plane kb
+            const int bo = 1 - ro;         // black cell
+            if (core && kb >= z0 && kb < z1 && (bo ? c1_in : c0_in)) {
+                const int gxb = gx + bo;
+                const int lb = lx + bo;
+                const C eP = CELL ? pick(em, bo) : C(1);
+                C off, dg;
+                six_faces<C, MODE, true>(
+                    G, gxb, gy, kb, eP,
+                    [&](int d) -> C {
+                        return d == 0   ? (bo ? rn_prev : s_r[kb & 1][ry][lb - 1])
+                               : d == 1 ? (bo ? s_r[kb & 1][ry][lb + 1] : rn_prev)
+                               : d == 2 ? s_r[kb & 1][ry - 1][lb]
+                               : d == 3 ? s_r[kb & 1][ry + 1][lb]
+                               : d == 4 ? rn_prev2
+                                        : rn_cur;
+                    },
+                    [&](int d) -> C {
+                        if constexpr (!CELL) return C(1);
+                        else return d == 0   ? (bo ? em.v[0] : s_e[kb & 1][ry][lb - 1])
+                                    : d == 1 ? (bo ? s_e[kb & 1][ry][lb + 1] : em.v[1])
+                                    : d == 2 ? s_e[kb & 1][ry - 1][lb]
+                                    : d == 3 ? s_e[kb & 1][ry + 1][lb]
+                                    : d == 4 ? pick(em2, bo)
+                                             : pick(e0, bo);
+                    },
+                    [&](int d) -> C {
+                        return d == 0   ? face_x(fbx, G, gxb, gy, kb)
+                               : d == 1 ? face_x(fbx, G, gxb + 1, gy, kb)
+                               : d == 2 ? face_y(fby, G, gxb, gy, kb)
+                               : d == 3 ? face_y(fby, G, gxb, gy + 1, kb)
+                               : d == 4 ? face_z(fbz, G, gxb, gy, kb)
+                                        : face_z(fbz, G, gxb, gy, kb + 1);
+                    },
+                    off, dg);
+                const C vb = (h2 * pick(bm, bo) + off) / (ah2 + dg);
+                const size_t gp = (size_t)kb * plane + rowoff + gx;
+                if (even_nx) {
+                    Pair<T> o;
+                    const T tb = N::cv(vb), tr = N::cv(rn_prev);
+                    o.v[0] = bo ? tr : tb;
+                    o.v[1] = bo ? tb : tr;
+                    *reinterpret_cast<Pair<T> *>(uout + gp) = o;
+                } else {
+                    uout[gp + bo] = N::cv(vb);
+                    if (ro ? c1_in : c0_in) uout[gp + ro] = N::cv(rn_prev);
+                }
+            } else if (core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
+                // odd nx: the pair's black cell lies outside the box
+                uout[(size_t)kb * plane + rowoff + gx + ro] = N::cv(rn_prev);
+            }
+        }
+        lds_barrier();
+    };
+
+    // shift in plane k+1 from ring slot S, refill the slot with k+1+PD, step k
+    auto iter = [&](auto S, int k) {
+        um = u0; u0 = up;
+        bm = b0; b0 = bp;
+        if constexpr (CELL) { em2 = em; em = e0; e0 = ep; }
+        if constexpr (!ZIN) up = masku(QU(S), k + 1);
+        bp = masku(QB(S), k + 1);
+        if constexpr (CELL) ep = maske(QE(S), k + 1);
+        if (k + 1 + PD <= z1 + 1) issue(k + 1 + PD, QU(S), QB(S), QE(S));
+        step(k);
+    };
+    step(z0 - 1);
+    for (int kk = z0; kk <= z1; kk += PD) {
+        iter(std::integral_constant<int, 0>{}, kk);
+        if constexpr (PD > 1) { if (kk + 1 > z1) break; iter(std::integral_constant<int, 1>{}, kk + 1); }
+        if constexpr (PD > 2) { if (kk + 2 > z1) break; iter(std::integral_constant<int, 2>{}, kk + 2); }
+        if constexpr (PD > 3) { if (kk + 3 > z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
+    }
+}
+
+// ---------------------------------------------------------------------
+// Residual + restriction (+ squared norm), column-pair streaming form.
+//
+// bc[K][J][I] = mean of the residuals b - A u of the 8 fine children.  A
+// thread owns the fine pair (2I, 2I+1) of one row of the tile grown by one
+// cell, marches up the planes of its chunk with u (and eps) streamed PD
+// planes ahead, exchanges in-plane neighbours through LDS, keeps vertical
+// ones in registers, and sums the pair's residuals over two planes; two
+// adjacent rows are then combined into the coarse value.  If slot >= 0 the
+// squared residual is also reduced (FP64, deterministic) into ws.result[slot]
+// and, with done_out, the convergence flag is set against
+// rtol2 * ws.result[ref_slot].
+template <class T, int MODE, int TX, int TY, int PD>
+__global__ __launch_bounds__((((TX + 4) / 2 * (TY + 2)) + 63) / 64 * 64) void rr_col_k(
+    const T *__restrict__ u, const T *__restrict__ b, const T *__restrict__ eps,
+    const T *__restrict__ fbx, const T *__restrict__ fby, const T *__restrict__ fbz, Geo G,
+    T *__restrict__ bc, int cz, int tiles_x, int tiles_y, int nblk, RedWs ws, int slot,
+    int ref_slot, double rtol2, int *__restrict__ done_out, const int *__restrict__ done_in) {
+    if (done_in && *done_in) return;
+    using N = Num<T>;
+    using C = typename N::C;
+    constexpr int PXW = (TX + 4) / 2;  // pairs per region row (1-cell halo, pair aligned)
+    constexpr int RX = TX + 4, RY = TY + 2;
+    constexpr int NTH = PXW * RY;
+    constexpr int NTP = (NTH + 63) / 64 * 64;
+    constexpr bool CELL = (MODE == COEF_CELL);
+    __shared__ C s_u[RY][RX];
+    __shared__ C s_e[CELL ? RY : 1][CELL ? RX : 1];
+    __shared__ C s_acc[RY][PXW];
+
+    const int tid = threadIdx.x;
+    const bool live = tid < NTH;
+    const int blk = xcd_remap(blockIdx.x, nblk);
+    const int tx = blk % tiles_x;
+    const int rest = blk / tiles_x;
+    const int ty = rest % tiles_y;
+    const int tc = rest / tiles_y;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tc * cz;
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int z1 = min(z0 + cz, nz);
+    const size_t plane = (size_t)nx * ny;
+    const int ncx = nx / 2, ncy = ny / 2;
+    const C ih2 = C(G.ih2), a = C(G.a);
+
+    const int ry = live ? tid / PXW : 0, pc = live ? tid - ry * PXW : 0;
+    const int lx = 2 * pc;             // LDS column of the pair's first cell
+    const int x = lx - 2, y = ry - 1;  // tile coordinates
+    const int gx = x0 + x, gy = y0 + y;
+    const bool row_in = live && gy >= 0 && gy < ny;
+    const bool c_in = row_in && gx >= 0 && gx < nx;  // nx is even here: pairs are all in or all out
+    const bool core = live && x >= 0 && x < TX && y >= 0 && y < TY && c_in;
+    const size_t rowoff = (size_t)(row_in ? gy : 0) * nx;
+
+    struct P2 { C v[2]; };
+    auto ld_pair = [&](const T *__restrict__ p, int k) -> P2 {
+        const bool kin = k >= 0 && k < nz;
+        const size_t g = (kin && c_in) ? (size_t)k * plane + rowoff + gx : 0;
+        const Pair<T> w = *reinterpret_cast<const Pair<T> *>(p + g);
+        P2 r;
+        r.v[0] = N::ld(w.v[0]);
+        r.v[1] = N::ld(w.v[1]);
+        return r;
+    };
+    auto vmask = [&](P2 v, int k, C fill) {
+        const bool ok = k >= 0 && k < nz && c_in;
+        P2 r;
+        r.v[0] = ok ? v.v[0] : fill;
+        r.v[1] = ok ? v.v[1] : fill;
+        return r;
+    };
+    P2 um, u0, up, e_m, e0, e_p, b0;
+    static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
+    P2 qu0, qu1, qu2, qu3, qe0, qe1, qe2, qe3, qb0, qb1, qb2, qb3;
+    auto QU = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qu0; else if constexpr (v == 1) return qu1;
+        else if constexpr (v == 2) return qu2; else return qu3;
+    };
+    auto QE = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qe0; else if constexpr (v == 1) return qe1;
+        else if constexpr (v == 2) return qe2; else return qe3;
+    };
+    auto QB = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qb0; else if constexpr (v == 1) return qb1;
+        else if constexpr (v == 2) return qb2; else return qb3;
+    };
+    // u/eps of plane p wait in slot (p - z0 - 2) mod PD; b of plane p in slot (p - z0 - 1) mod PD
+    auto issue = [&](int k, P2 &du, P2 &de) {
+        du = ld_pair(u, k);
+        if constexpr (CELL) de = ld_pair(eps, k);
+    };
+    {
+        P2 t0u, t0e, t1u, t1e, t2u, t2e, tb;
+        issue(z0 - 1, t0u, t0e);
+        issue(z0, t1u, t1e);
+        issue(z0 + 1, t2u, t2e);
+        tb = ld_pair(b, z0);
+        issue(z0 + 2, qu0, qe0);
+        qb0 = ld_pair(b, z0 + 1);
+        if constexpr (PD > 1) { issue(z0 + 3, qu1, qe1); qb1 = ld_pair(b, z0 + 2); }
+        if constexpr (PD > 2) { issue(z0 + 4, qu2, qe2); qb2 = ld_pair(b, z0 + 3); }
+        if constexpr (PD > 3) { issue(z0 + 5, qu3, qe3); qb3 = ld_pair(b, z0 + 4); }
+        um = vmask(t0u, z0 - 1, C(0));
+        u0 = vmask(t1u, z0, C(0));
+        up = vmask(t2u, z0 + 1, C(0));
+        b0 = vmask(tb, z0, C(0));
+        if constexpr (CELL) {
+            e_m = vmask(t0e, z0 - 1, C(1));
+            e0 = vmask(t1e, z0, C(1));
+            e_p = vmask(t2e, z0 + 1, C(1));
+        }
+    }
+    double nrm = 0.0;
+    C acc = C(0);
+    auto step = [&](int k) {
+        if (live) {
+            Pair<C> w;
+            w.v[0] = u0.v[0];
+            w.v[1] = u0.v[1];
+            *reinterpret_cast<Pair<C> *>(&s_u[ry][lx]) = w;
+            if constexpr (CELL) {
+                w.v[0] = e0.v[0];
+                w.v[1] = e0.v[1];
+                *reinterpret_cast<Pair<C> *>(&s_e[ry][lx]) = w;
+            }
+        }
+        lds_barrier();
+        if (core) {
+            C rr[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int lc = lx + c;
+                const int gxc = gx + c;
+                const C eP = CELL ? e0.v[c] : C(1);
+                C off, dg;
+                six_faces<C, MODE, true>(
+                    G, gxc, gy, k, eP,
+                    [&](int d) -> C {
+                        return d == 0   ? (c ? u0.v[0] : s_u[ry][lc - 1])
+                               : d == 1 ? (c ? s_u[ry][lc + 1] : u0.v[1])
+                               : d == 2 ? s_u[ry - 1][lc]
+                               : d == 3 ? s_u[ry + 1][lc]
+                               : d == 4 ? um.v[c]
+                                        : up.v[c];
+                    },
+                    [&](int d) -> C {
+                        if constexpr (!CELL) return C(1);
+                        else return d == 0   ? (c ? e0.v[0] : s_e[ry][lc - 1])
+                                    : d == 1 ? (c ? s_e[ry][lc + 1] : e0.v[1])
+                                    : d == 2 ? s_e[ry - 1][lc]
+                                    : d == 3 ? s_e[ry + 1][lc]
+                                    : d == 4 ? e_m.v[c]
+                                             : e_p.v[c];
+                    },
+                    [&](int d) -> C {
+                        return d == 0   ? face_x(fbx, G, gxc, gy, k)
+                               : d == 1 ? face_x(fbx, G, gxc + 1, gy, k)
+                               : d == 2 ? face_y(fby, G, gxc, gy, k)
+                               : d == 3 ? face_y(fby, G, gxc, gy + 1, k)
+                               : d == 4 ? face_z(fbz, G, gxc, gy, k)
+                                        : face_z(fbz, G, gxc, gy, k + 1);
+                    },
+                    off, dg);
+                const C uP = u0.v[c];
+                rr[c] = b0.v[c] - a * uP - ih2 * (dg * uP - off);
+            }
+            acc += rr[0] + rr[1];
+            nrm += (double)rr[0] * (double)rr[0] + (double)rr[1] * (double)rr[1];
+        }
+        if ((k - z0) & 1) {  // second fine plane of a coarse plane: combine rows
+            if (live) s_acc[ry][pc] = acc;
+            lds_barrier();
+            if (core && !(y & 1)) {
+                const C v = C(0.125) * (acc + s_acc[ry + 1][pc]);
+                const int I = gx >> 1, J = gy >> 1, K = k >> 1;
+                bc[((size_t)K * ncy + J) * ncx + I] = N::cv(v);
+            }
+            acc = C(0);
+        }
+        lds_barrier();
+    };
+    auto iter = [&](auto S, int k) {
+        um = u0; u0 = up;
+        if constexpr (CELL) { e_m = e0; e0 = e_p; }
+        up = vmask(QU(S), k + 1, C(0));
+        if constexpr (CELL) e_p = vmask(QE(S), k + 1, C(1));
+        b0 = vmask(QB(S), k, C(0));
+        if (k + 1 + PD < z1 + 1) { issue(k + 1 + PD, QU(S), QE(S)); QB(S) = ld_pair(b, k + PD); }
+        step(k);
+    };
+    step(z0);
+    for (int kk = z0 + 1; kk < z1; kk += PD) {
+        iter(std::integral_constant<int, 0>{}, kk);
+        if constexpr (PD > 1) { if (kk + 1 >= z1) break; iter(std::integral_constant<int, 1>{}, kk + 1); }
+        if constexpr (PD > 2) { if (kk + 2 >= z1) break; iter(std::integral_constant<int, 2>{}, kk + 2); }
+        if constexpr (PD > 3) { if (kk + 3 >= z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
+    }
+    if (slot >= 0) reduce2_finish<NTP>(nrm, 0.0, ws, slot, -1, ref_slot, rtol2, done_out);
+}
+
+// ---------------------------------------------------------------------
+// Element-wise kernels run on "bricks": blockDim (BX, BY) covers BX cells
+// (or coarse cells / pairs) along x and BY rows along y, blockIdx.z a run
+// of kz planes.  No integer division by grid sizes is needed.
+struct Brick {
+    int kz;  // planes per block along z
+};
+
+__device__ __forceinline__ int brick_id() {
+    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+__device__ __forceinline__ int brick_count() { return gridDim.x * gridDim.y * gridDim.z; }
+
+// ---------------------------------------------------------------------
+// Prolongation + correction: one thread per pair of fine cells (2I, 2I+1)
+// sharing a coarse x index.
+template <class T, class TC>
+__global__ __launch_bounds__(256) void prolong_k(T *__restrict__ u, const TC *__restrict__ e, Geo G,
+                                                 Geo Gc, const int *__restrict__ done) {
+    if (done && *done) return;
+    using C = typename Num<T>::C;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (I >= Gc.nx || j >= G.ny || k >= G.nz) return;
+    const int J = j >> 1, K = k >> 1;
+    const int sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+    // coarse value with ghost reflection (sign -1 across a Dirichlet face)
+    auto ev = [&](int ii, int jj, int kk) -> C {
+        C sg = C(1);
+        if (ii < 0) { ii = 0; if (Gc.bcmask & 1) sg = -sg; }
+        if (ii >= Gc.nx) { ii = Gc.nx - 1; if (Gc.bcmask & 2) sg = -sg; }
+        if (jj < 0) { jj = 0; if (Gc.bcmask & 4) sg = -sg; }
+        if (jj >= Gc.ny) { jj = Gc.ny - 1; if (Gc.bcmask & 8) sg = -sg; }
+        if (kk < 0) { kk = 0; if (Gc.bcmask & 16) sg = -sg; }
+        if (kk >= Gc.nz) { kk = Gc.nz - 1; if (Gc.bcmask & 32) sg = -sg; }
+        return sg * C(Num<TC>::ld(e[((size_t)kk * Gc.ny + jj) * Gc.nx + ii]));
+    };
+    C lo = C(0), mid = C(0), hi = C(0);
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const C w = (bb ? C(0.25) : C(0.75)) * (cc ? C(0.25) : C(0.75));
+            const int jj = J + bb * sj, kk = K + cc * sk;
+            lo += w * ev(I - 1, jj, kk);
+            mid += w * ev(I, jj, kk);
+            hi += w * ev(I + 1, jj, kk);
+        }
+    const size_t p = ((size_t)k * G.ny + j) * G.nx + 2 * I;
+    const C v0 = C(0.75) * mid + C(0.25) * lo;
+    const C v1 = C(0.75) * mid + C(0.25) * hi;
+    if ((G.nx & 1) == 0) {
+        Pair<T> o = *reinterpret_cast<const Pair<T> *>(u + p);
+        o.v[0] = Num<T>::cv(Num<T>::ld(o.v[0]) + v0);
+        o.v[1] = Num<T>::cv(Num<T>::ld(o.v[1]) + v1);
+        *reinterpret_cast<Pair<T> *>(u + p) = o;
+    } else {
+        u[p] = Num<T>::cv(Num<T>::ld(u[p]) + v0);
+        if (2 * I + 1 < G.nx) u[p + 1] = Num<T>::cv(Num<T>::ld(u[p + 1]) + v1);
+    }
+}
+
+// ---------------------------------------------------------------------
+// Deterministic block reduction of two FP64 sums, finished by the last
+// block to arrive (fixed summation order, counter reset for the next use).
+// If done != nullptr, the last block also sets *done = 1 when the first
+// sum is <= rtol2 * result[ref_slot] (squared residual against squared
+// right-hand side), else 0.
+template <int NT>
+__device__ __forceinline__ void reduce2_finish(double s0, double s1, const RedWs &ws, int slot,
+                                               int bslot, int ref_slot = -1, double rtol2 = 0.0,
+                                               int *done = nullptr) {
+    __shared__ double sh[2][NT / 64];
+    __shared__ bool last;
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int lane = tid & 63, w = tid >> 6;
+    const int bid = brick_id(), nb = brick_count();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s0 += __shfl_down(s0, o, 64);
+        s1 += __shfl_down(s1, o, 64);
+    }
+    if (lane == 0) {
+        sh[0][w] = s0;
+        sh[1][w] = s1;
+    }
+    __syncthreads();
+    double *part = ws.partials + (size_t)slot * kMaxRedBlocks * 2;
+    if (tid == 0) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int q = 0; q < NT / 64; ++q) {
+            a0 += sh[0][q];
+            a1 += sh[1][q];
+        }
+        __hip_atomic_store(&part[2 * bid], a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&part[2 * bid + 1], a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned t = atomicAdd(&ws.counter[slot], 1u);
+        last = (t == (unsigned)nb - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double a0 = 0.0, a1 = 0.0;
+    for (int q = tid; q < nb; q += NT) {
+        a0 += __hip_atomic_load(&part[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a1 += __hip_atomic_load(&part[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_down(a0, o, 64);
+        a1 += __shfl_down(a1, o, 64);
+    }
+    __syncthreads();
+    if (lane == 0) {
+        sh[0][w] = a0;
+        sh[1][w] = a1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int q = 0; q < NT / 64; ++q) {
+            t0 += sh[0][q];
+            t1 += sh[1][q];
+        }
+        ws.result[slot] = t0;
+        if (bslot >= 0) ws.result[bslot] = t1;
+        if (done) *done = (t0 <= rtol2 * ws.result[ref_slot]) ? 1 : 0;
+        ws.counter[slot] = 0u;
+    }
+}
+
+// ||b - A u||^2 and (optionally) ||b + boundary terms||^2 (brick with kz planes).
+template <class T, int MODE>
+__global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, const T *__restrict__ b,
+                                                     const T *__restrict__ eps,
+                                                     const T *__restrict__ bx,
+                                                     const T *__restrict__ by,
+                                                     const T *__restrict__ bz, Geo G, RedWs ws,
+                                                     int slot, int bslot, int kz, int ref_slot,
+                                                     double rtol2, int *__restrict__ done_out,
+                                                     const int *__restrict__ done_in) {
+    if (done_in && *done_in) return;
+    using N = Num<T>;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k0 = blockIdx.z * kz;
+    const int k1 = min(k0 + kz, G.nz);
+    double sr = 0.0, sb = 0.0;
+    if (i < G.nx && j < G.ny) {
+        for (int k = k0; k < k1; ++k) {
+            const size_t p = ((size_t)k * G.ny + j) * G.nx + i;
+            const double rv = (double)resid_global<T, MODE>(u, b, eps, bx, by, bz, G, i, j, k);
+            sr += rv * rv;
+            if (bslot >= 0) {
+                // b + h^-2 sum_Dirichlet 2 beta_b g  (boundary beta as in the operator)
+                double be = 1.0;
+                if constexpr (MODE == COEF_CELL) be = (double)N::ld(eps[p]);
+                double add = 0.0;
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                    const bool at = d == 0   ? i == 0
+                                    : d == 1 ? i == G.nx - 1
+                                    : d == 2 ? j == 0
+                                    : d == 3 ? j == G.ny - 1
+                                    : d == 4 ? k == 0
+                                             : k == G.nz - 1;
+                    if (at && ((G.bcmask >> d) & 1)) {
+                        double bf = be;
+                        if constexpr (MODE == COEF_FACE) {
+                            bf = d == 0   ? (double)face_x(bx, G, i, j, k)
+                                 : d == 1 ? (double)face_x(bx, G, i + 1, j, k)
+                                 : d == 2 ? (double)face_y(by, G, i, j, k)
+                                 : d == 3 ? (double)face_y(by, G, i, j + 1, k)
+                                 : d == 4 ? (double)face_z(bz, G, i, j, k)
+                                          : (double)face_z(bz, G, i, j, k + 1);
+                        }
+                        add += 2.0 * bf * G.g[d];
+                    }
+                }
+                const double bb = (double)N::ld(b[p]) + G.ih2 * add;
+                sb += bb * bb;
+            }
+        }
+    }
+    reduce2_finish<256>(sr, sb, ws, slot, bslot, ref_slot, rtol2, done_out);
+}
+
+}  // namespace mg

@@ -1,0 +1,288 @@
+// Bottom solver: one workgroup, all levels in LDS, FP64.
+//
+// The levels whose largest dimension is at most bottom_max (<= 16^3 cells)
+// are too small to fill the GPU, so one workgroup of 1024 threads keeps
+// their iterates and right-hand sides in LDS and runs the remaining part of
+// the V-cycle there: red-black Gauss-Seidel smoothing, residual
+// restriction, trilinear prolongation, and conjugate gradients on the
+// coarsest grid (the operator is symmetric positive definite).  The paper
+// pairs its red-black Gauss-Seidel multigrid with a Krylov bottom solver
+// (BiCGStab); CG is the Krylov method for the SPD case.
+#include "mg_stencil.cuh"
+
+namespace mg {
+
+namespace {
+
+constexpr int kNT = 1024;
+
+// off/dg of cell (i,j,k) at tail level l with operand array v (LDS).
+__device__ __forceinline__ void tail_terms(const TailDesc &D, int l, const double *v, int i, int j,
+                                           int k, bool with_g, double &off, double &dg) {
+    const TailLevel &L = D.L[l];
+    Geo G;
+    G.nx = L.nx;
+    G.ny = L.ny;
+    G.nz = L.nz;
+    G.bcmask = D.bcmask;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) G.g[d] = with_g ? D.g[d] : 0.0;
+    const int sy = L.nx, sz = L.nx * L.ny;
+    const int p = k * sz + j * sy + i;
+    auto un = [&](int d) -> double {
+        switch (d) {
+            case 0: return v[p - 1];
+            case 1: return v[p + 1];
+            case 2: return v[p - sy];
+            case 3: return v[p + sy];
+            case 4: return v[p - sz];
+            default: return v[p + sz];
+        }
+    };
+    auto en = [&](int) { return 1.0; };
+    if (D.mode == COEF_FACE) {
+        auto fb = [&](int d) -> double {
+            switch (d) {
+                case 0: return face_x(L.bx, G, i, j, k);
+                case 1: return face_x(L.bx, G, i + 1, j, k);
+                case 2: return face_y(L.by, G, i, j, k);
+                case 3: return face_y(L.by, G, i, j + 1, k);
+                case 4: return face_z(L.bz, G, i, j, k);
+                default: return face_z(L.bz, G, i, j, k + 1);
+            }
+        };
+        six_faces<double, COEF_FACE>(G, i, j, k, 1.0, un, en, fb, off, dg);
+    } else {
+        six_faces<double, COEF_CONST>(G, i, j, k, 1.0, un, en, [&](int) { return 1.0; }, off, dg);
+    }
+}
+
+__device__ __forceinline__ void decode(int idx, int nx, int ny, int &i, int &j, int &k) {
+    i = idx % nx;
+    const int r = idx / nx;
+    j = r % ny;
+    k = r / ny;
+}
+
+__device__ double block_sum(double v, double *red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNT / 64; ++q) t += red[q];
+    return t;
+}
+
+__device__ void gs_sweep(const TailDesc &D, int l, double *lds, bool with_g) {
+    const TailLevel &L = D.L[l];
+    double *u = lds + L.off_u;
+    const double *b = lds + L.off_b;
+    const int n = L.nx * L.ny * L.nz;
+    for (int colour = 0; colour < 2; ++colour) {
+        for (int idx = threadIdx.x; idx < n; idx += kNT) {
+            int i, j, k;
+            decode(idx, L.nx, L.ny, i, j, k);
+            if (((i + j + k) & 1) != colour) continue;
+            double off, dg;
+            tail_terms(D, l, u, i, j, k, with_g, off, dg);
+            u[idx] = (L.h2 * b[idx] + off) / (L.ah2 + dg);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ double tail_resid(const TailDesc &D, int l, const double *u,
+                                             const double *b, int idx, bool with_g) {
+    const TailLevel &L = D.L[l];
+    int i, j, k;
+    decode(idx, L.nx, L.ny, i, j, k);
+    double off, dg;
+    tail_terms(D, l, u, i, j, k, with_g, off, dg);
+    return b[idx] - (L.ah2 * u[idx] + dg * u[idx] - off) / L.h2;
+}
+
+__device__ void restrict_to(const TailDesc &D, int l, double *lds, bool with_g) {
+    const TailLevel &F = D.L[l], &Cc = D.L[l + 1];
+    const double *u = lds + F.off_u, *b = lds + F.off_b;
+    double *bc = lds + Cc.off_b, *uc = lds + Cc.off_u;
+    const int nc = Cc.nx * Cc.ny * Cc.nz;
+    for (int I = threadIdx.x; I < nc; I += kNT) {
+        int ci, cj, ck;
+        decode(I, Cc.nx, Cc.ny, ci, cj, ck);
+        double s = 0.0;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    const int idx = ((2 * ck + dz) * F.ny + (2 * cj + dy)) * F.nx + (2 * ci + dx);
+                    s += tail_resid(D, l, u, b, idx, with_g);
+                }
+        bc[I] = 0.125 * s;
+        uc[I] = 0.0;
+    }
+    __syncthreads();
+}
+
+__device__ void prolong_into(const TailDesc &D, int l, double *lds) {
+    const TailLevel &F = D.L[l], &Cc = D.L[l + 1];
+    double *u = lds + F.off_u;
+    const double *e = lds + Cc.off_u;
+    const int n = F.nx * F.ny * F.nz;
+    const int m = D.bcmask;
+    for (int idx = threadIdx.x; idx < n; idx += kNT) {
+        int i, j, k;
+        decode(idx, F.nx, F.ny, i, j, k);
+        const int I = i >> 1, J = j >> 1, K = k >> 1;
+        const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+        double v = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int bb = 0; bb < 2; ++bb)
+                for (int c = 0; c < 2; ++c) {
+                    int ii = I + a * si, jj = J + bb * sj, kk = K + c * sk;
+                    double sg = 1.0;
+                    if (ii < 0) { ii = 0; if (m & 1) sg = -sg; }
+                    if (ii >= Cc.nx) { ii = Cc.nx - 1; if (m & 2) sg = -sg; }
+                    if (jj < 0) { jj = 0; if (m & 4) sg = -sg; }
+                    if (jj >= Cc.ny) { jj = Cc.ny - 1; if (m & 8) sg = -sg; }
+                    if (kk < 0) { kk = 0; if (m & 16) sg = -sg; }
+                    if (kk >= Cc.nz) { kk = Cc.nz - 1; if (m & 32) sg = -sg; }
+                    const double w = (a ? 0.25 : 0.75) * (bb ? 0.25 : 0.75) * (c ? 0.25 : 0.75);
+                    v += w * sg * e[(kk * Cc.ny + jj) * Cc.nx + ii];
+                }
+        u[idx] += v;
+    }
+    __syncthreads();
+}
+
+// CG on level l: x = u_l (start), b_l is overwritten by the residual.
+__device__ void cg_solve(const TailDesc &D, int l, double *lds, double *red, bool with_g) {
+    const TailLevel &L = D.L[l];
+    double *x = lds + L.off_u;
+    double *r = lds + L.off_b;
+    double *p = lds + D.off_p;
+    double *q = lds + D.off_q;
+    const int n = L.nx * L.ny * L.nz;
+    // r = b - A x (boundary values only on the top level), p = r
+    for (int idx = threadIdx.x; idx < n; idx += kNT) q[idx] = tail_resid(D, l, x, r, idx, with_g);
+    __syncthreads();
+    double s = 0.0;
+    for (int idx = threadIdx.x; idx < n; idx += kNT) {
+        r[idx] = q[idx];
+        p[idx] = q[idx];
+        s += q[idx] * q[idx];
+    }
+    double rr = block_sum(s, red);
+    const double stop = D.cg_rtol * D.cg_rtol * rr;
+    for (int it = 0; it < D.cg_maxit && rr > stop && rr > 0.0; ++it) {
+        double pq = 0.0;
+        for (int idx = threadIdx.x; idx < n; idx += kNT) {
+            int i, j, k;
+            decode(idx, L.nx, L.ny, i, j, k);
+            double off, dg;
+            tail_terms(D, l, p, i, j, k, false, off, dg);
+            const double ap = (L.ah2 * p[idx] + dg * p[idx] - off) / L.h2;
+            q[idx] = ap;
+            pq += p[idx] * ap;
+        }
+        pq = block_sum(pq, red);
+        const double alpha = rr / pq;
+        double s2 = 0.0;
+        for (int idx = threadIdx.x; idx < n; idx += kNT) {
+            x[idx] += alpha * p[idx];
+            r[idx] -= alpha * q[idx];
+            s2 += r[idx] * r[idx];
+        }
+        const double rr_new = block_sum(s2, red);
+        const double beta = rr_new / rr;
+        rr = rr_new;
+        for (int idx = threadIdx.x; idx < n; idx += kNT) p[idx] = r[idx] + beta * p[idx];
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+template <class T>
+__global__ __launch_bounds__(kNT) void tail_k(TailDesc D, const T *__restrict__ b_in,
+                                              const T *u_in, T *u_out, int top_has_g,
+                                              const int *__restrict__ done) {
+    if (done && *done) return;
+    // u_in may alias u_out: every read of u_in precedes the barrier that
+    // precedes the first write of u_out.
+    __shared__ double lds[kTailLdsDoubles];
+    __shared__ double red[kNT / 64];
+    const TailLevel &L0 = D.L[0];
+    const int n0 = L0.nx * L0.ny * L0.nz;
+    for (int idx = threadIdx.x; idx < n0; idx += kNT) {
+        lds[L0.off_b + idx] = (double)Num<T>::ld(b_in[idx]);
+        lds[L0.off_u + idx] = u_in ? (double)Num<T>::ld(u_in[idx]) : 0.0;
+    }
+    __syncthreads();
+    const int c = D.nlev - 1;
+    if (c == 0) {
+        cg_solve(D, 0, lds, red, top_has_g != 0);
+    } else {
+        for (int cyc = 0; cyc < D.ncyc; ++cyc) {
+            for (int l = 0; l < c; ++l) {
+                const bool g = (l == 0) && top_has_g;
+                for (int s = 0; s < D.nu1; ++s) gs_sweep(D, l, lds, g);
+                restrict_to(D, l, lds, g);
+            }
+            cg_solve(D, c, lds, red, false);
+            __syncthreads();
+            for (int l = c - 1; l >= 0; --l) {
+                const bool g = (l == 0) && top_has_g;
+                prolong_into(D, l, lds);
+                for (int s = 0; s < D.nu2; ++s) gs_sweep(D, l, lds, g);
+            }
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < n0; idx += kNT)
+        u_out[idx] = Num<T>::cv(typename Num<T>::C(lds[L0.off_u + idx]));
+}
+
+bool tail_layout(TailDesc &D) {
+    int off = 0;
+    for (int l = 0; l < D.nlev; ++l) {
+        const int n = D.L[l].nx * D.L[l].ny * D.L[l].nz;
+        D.L[l].off_u = off;
+        off += n;
+        D.L[l].off_b = off;
+        off += n;
+    }
+    const TailLevel &C = D.L[D.nlev - 1];
+    const int nc = C.nx * C.ny * C.nz;
+    D.off_p = off;
+    off += nc;
+    D.off_q = off;
+    off += nc;
+    return off <= kTailLdsDoubles;
+}
+
+hipError_t tail_solve(hipStream_t s, int st, const TailDesc &D, const void *b_in, const void *u_in,
+                      void *u_out, const int *done) {
+    const int has_g = (D.g[0] != 0.0 || D.g[1] != 0.0 || D.g[2] != 0.0 || D.g[3] != 0.0 ||
+                       D.g[4] != 0.0 || D.g[5] != 0.0);
+    switch (st) {
+        case ST_F64:
+            hipLaunchKernelGGL(tail_k<double>, dim3(1), dim3(kNT), 0, s, D, (const double *)b_in,
+                               (const double *)u_in, (double *)u_out, has_g, done);
+            break;
+        case ST_F32:
+            hipLaunchKernelGGL(tail_k<float>, dim3(1), dim3(kNT), 0, s, D, (const float *)b_in,
+                               (const float *)u_in, (float *)u_out, has_g, done);
+            break;
+        case ST_BF16:
+            hipLaunchKernelGGL(tail_k<bf16>, dim3(1), dim3(kNT), 0, s, D, (const bf16 *)b_in,
+                               (const bf16 *)u_in, (bf16 *)u_out, has_g, done);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mg

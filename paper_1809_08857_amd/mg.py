@@ -1,0 +1,251 @@
+"""ctypes binding of the C ABI in include/mg.h (argument marshalling only).
+
+Every function has the name of the C entry point it calls.  Device arrays
+are passed as torch tensors (contiguous, float64, on the GPU); their data
+pointers and the current torch stream go straight to the library, which does
+all the work in its own HIP kernels.  There is no fallback: if libmg.so is
+missing or the GPU is absent the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmg.so")
+
+MG_OK, MG_NOT_CONVERGED = 0, 1
+MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_EDIVERGED = -1, -2, -3, -4
+MG_BC_DIRICHLET, MG_BC_NEUMANN = 0, 1
+MG_FP64, MG_FP32_IR, MG_BF16_IR = 0, 1, 2
+MG_GUESS = 1
+MG_NUM_TILES = 6
+
+PRECISIONS = {"fp64": MG_FP64, "fp32": MG_FP32_IR, "bf16": MG_BF16_IR}
+
+
+class MgDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("h", ctypes.c_double),
+                ("precision", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
+                ("bottom_max", ctypes.c_int), ("max_cycles", ctypes.c_int), ("rtol", ctypes.c_double)]
+
+
+class MgBcs(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int * 6), ("value", ctypes.c_double * 6)]
+
+
+class MgStats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("rel_res0", ctypes.c_double), ("rel_res", ctypes.c_double),
+                ("fell_back", ctypes.c_int), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree libmg.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1809_08857_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I, D = ctypes.c_int, ctypes.c_double
+    pI, pD = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "mg_desc_default": (None, [ctypes.POINTER(MgDesc), I, I, I, D]),
+        "mg_create": (I, [ctypes.POINTER(MgDesc), P, ctypes.POINTER(P)]),
+        "mg_set_coeffs": (I, [P, P, D, ctypes.POINTER(MgBcs)]),
+        "mg_solve": (I, [P, P, P, ctypes.c_uint, ctypes.POINTER(MgStats)]),
+        "mg_solve_batched": (I, [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.c_uint,
+                                 ctypes.POINTER(MgStats)]),
+        "mg_destroy": (I, [P]),
+        "mg_last_error": (ctypes.c_char_p, []),
+        "mg_residual": (I, [P, P, P, P, pD, pD]),
+        "mg_smooth": (I, [P, P, P, I]),
+        "mg_num_levels": (I, [P]),
+        "mg_level_dims": (I, [P, I, pI, pI, pI]),
+        "mg_set_tiling": (I, [P, I, I]),
+        "mg_tile_shape": (I, [I, pI, pI]),
+        "mg_autotune": (I, [P, I, pI, pI, pD]),
+        "mg_timing": (I, [P, I]),
+        "mg_timing_read": (I, [P, ctypes.POINTER(ctypes.c_long), pD, pD, ctypes.POINTER(ctypes.c_char_p)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous float64 CUDA tensors")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise MgError(rc, mg_last_error())
+    return rc
+
+
+def mg_last_error() -> str:
+    return load().mg_last_error().decode()
+
+
+def mg_desc_default(nx: int, ny: int, nz: int, h: float, **kw) -> MgDesc:
+    d = MgDesc()
+    load().mg_desc_default(ctypes.byref(d), nx, ny, nz, h)
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        setattr(d, k, v)
+    return d
+
+
+def make_bcs(types: Sequence, values: Sequence[float]) -> MgBcs:
+    """types: 'D'/'N' or MG_BC_* per face (x-, x+, y-, y+, z-, z+)."""
+    b = MgBcs()
+    for f in range(6):
+        t = types[f]
+        if isinstance(t, str):
+            t = MG_BC_DIRICHLET if t == "D" else MG_BC_NEUMANN
+        b.type[f] = t
+        b.value[f] = float(values[f])
+    return b
+
+
+def mg_create(desc: MgDesc, stream=None) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(load().mg_create(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(ctx)))
+    return ctx
+
+
+def mg_set_coeffs(ctx, eps, a: float, bcs: MgBcs) -> int:
+    return _check(load().mg_set_coeffs(ctx, _ptr(eps), float(a), ctypes.byref(bcs)))
+
+
+def mg_solve(ctx, f, x, flags: int = 0) -> Tuple[int, MgStats]:
+    st = MgStats()
+    rc = _check(load().mg_solve(ctx, _ptr(f), _ptr(x), flags, ctypes.byref(st)))
+    return rc, st
+
+
+def mg_solve_batched(ctxs: Sequence, fs: Sequence, xs: Sequence, flags: int = 0) -> Tuple[int, List[MgStats]]:
+    n = len(ctxs)
+    P = ctypes.c_void_p
+    carr = (P * n)(*[c.value if isinstance(c, P) else c for c in ctxs])
+    farr = (P * n)(*[_ptr(t) for t in fs])
+    xarr = (P * n)(*[_ptr(t) for t in xs])
+    st = (MgStats * n)()
+    rc = _check(load().mg_solve_batched(n, carr, farr, xarr, flags, st))
+    return rc, list(st)
+
+
+def mg_destroy(ctx) -> int:
+    return _check(load().mg_destroy(ctx))
+
+
+def mg_residual(ctx, f, x, r=None) -> Tuple[float, float]:
+    rn, bn = ctypes.c_double(), ctypes.c_double()
+    _check(load().mg_residual(ctx, _ptr(f), _ptr(x), _ptr(r), ctypes.byref(rn), ctypes.byref(bn)))
+    return rn.value, bn.value
+
+
+def mg_smooth(ctx, f, x, sweeps: int) -> int:
+    return _check(load().mg_smooth(ctx, _ptr(f), _ptr(x), sweeps))
+
+
+def mg_num_levels(ctx) -> int:
+    return load().mg_num_levels(ctx)
+
+
+def mg_level_dims(ctx, l: int) -> Tuple[int, int, int]:
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load().mg_level_dims(ctx, l, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def mg_set_tiling(ctx, tile: int, zchunk: int) -> int:
+    return _check(load().mg_set_tiling(ctx, tile, zchunk))
+
+
+def mg_tile_shape(t: int) -> Tuple[int, int]:
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(load().mg_tile_shape(t, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def mg_autotune(ctx, reps: int = 5) -> Tuple[int, int, float]:
+    t, z, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(load().mg_autotune(ctx, reps, ctypes.byref(t), ctypes.byref(z), ctypes.byref(us)))
+    return t.value, z.value, us.value
+
+
+def mg_timing(ctx, enable: int) -> int:
+    return _check(load().mg_timing(ctx, int(enable)))
+
+
+def mg_timing_read(ctx) -> Tuple[int, float, str, float]:
+    """(launches, total ms, kernel description, mean algorithmic bytes per launch)."""
+    n, ms, by, k = ctypes.c_long(), ctypes.c_double(), ctypes.c_double(), ctypes.c_char_p()
+    _check(load().mg_timing_read(ctx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(k)))
+    per = by.value / n.value if n.value else 0.0
+    return n.value, ms.value, (k.value or b"").decode(), per
+
+
+class Solver:
+    """Owns one context: create + set_coeffs on construction, destroy on close."""
+
+    def __init__(self, nx, ny, nz, h, *, eps=None, a=0.0, bc_types=("N",) * 6, bc_values=(0.0,) * 6,
+                 stream=None, **desc_kw):
+        self.desc = mg_desc_default(nx, ny, nz, h, **desc_kw)
+        self.ctx = mg_create(self.desc, stream)
+        try:
+            mg_set_coeffs(self.ctx, eps, a, make_bcs(bc_types, bc_values))
+        except Exception:
+            mg_destroy(self.ctx)
+            self.ctx = None
+            raise
+
+    def solve(self, f, x, flags: int = 0):
+        return mg_solve(self.ctx, f, x, flags)
+
+    def residual(self, f, x, r=None):
+        return mg_residual(self.ctx, f, x, r)
+
+    def close(self):
+        if self.ctx is not None:
+            mg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,81 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, every
+entry point declared in include/*.h is exported, and argument validation
+rejects bad descriptors before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1809_08857_amd import build as mgbuild
+from paper_1809_08857_amd import mg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    src = open(os.path.join(ROOT, "include", header)).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-zA-Z_][\w\s\*]*?\b((?:mg|mgl)_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mg.LIB_PATH):
+        mgbuild.build()
+    return mg.load()
+
+
+@pytest.mark.parametrize("header,libfile", [("mg.h", "libmg.so")])
+def test_every_declared_symbol_is_exported(header, libfile):
+    names = _declared(header)
+    assert len(names) >= 10
+    so = ctypes.CDLL(os.path.join(ROOT, "paper_1809_08857_amd", libfile))
+    missing = [n for n in names if not hasattr(so, n)]
+    assert not missing, missing
+
+
+def test_desc_default(lib):
+    d = mg.mg_desc_default(32, 16, 8, 0.5)
+    assert (d.nx, d.ny, d.nz, d.h) == (32, 16, 8, 0.5)
+    assert (d.precision, d.nu1, d.nu2, d.bottom_max, d.max_cycles) == (mg.MG_FP64, 2, 2, 16, 50)
+    assert d.rtol == 1e-10
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("h", 0.0), ("h", -1.0), ("precision", 7), ("nu1", -1),
+                                         ("nu2", 9), ("bottom_max", 1), ("bottom_max", 17), ("max_cycles", 0),
+                                         ("rtol", 0.0), ("rtol", 2.0)])
+def test_create_rejects_bad_desc(lib, field, value):
+    d = mg.mg_desc_default(32, 32, 32, 1 / 32)
+    setattr(d, field, value)
+    ctx = ctypes.c_void_p(123)
+    rc = lib.mg_create(ctypes.byref(d), None, ctypes.byref(ctx))
+    assert rc == mg.MG_EINVAL and ctx.value is None
+    assert mg.mg_last_error().startswith("mg_create")
+
+
+@pytest.mark.parametrize("dims", [(33, 32, 32), (34, 34, 34), (64, 48, 17)])
+def test_create_rejects_uncoarsenable_grid(lib, dims):
+    d = mg.mg_desc_default(*dims, 0.1)
+    ctx = ctypes.c_void_p()
+    assert lib.mg_create(ctypes.byref(d), None, ctypes.byref(ctx)) == mg.MG_EINVAL
+    assert "bottom_max" in mg.mg_last_error()
+
+
+def test_null_arguments(lib):
+    assert lib.mg_solve(None, None, None, 0, None) == mg.MG_EINVAL
+    assert lib.mg_set_coeffs(None, None, 0.0, None) == mg.MG_EINVAL
+    assert lib.mg_destroy(None) == mg.MG_OK
+    assert lib.mg_solve_batched(-1, None, None, None, 0, None) == mg.MG_EINVAL
+    assert lib.mg_residual(None, None, None, None, None, None) == mg.MG_EINVAL
+    assert lib.mg_num_levels(None) == 0
+
+
+def test_tile_shapes(lib):
+    shapes = [mg.mg_tile_shape(t) for t in range(1, mg.MG_NUM_TILES + 1)]
+    assert len(set(shapes)) == mg.MG_NUM_TILES
+    for tx, ty in shapes:
+        assert tx % 2 == 0 and tx * ty // 2 in (64, 128, 256, 512)
+    with pytest.raises(mg.MgError):
+        mg.mg_tile_shape(0)

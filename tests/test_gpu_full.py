@@ -1,0 +1,42 @@
+"""Parity at the benchmark's full size (256^3 streamer field update, seed 0)
+in the configuration bench.py times (default tiling, V(2,2), FP64; the
+potential to relative residual 1e-11, the photon groups to 1e-10).
+
+Every solve: the oracle recomputes the relative residual of the GPU result
+with its own operator.  The potential and the weakest-screened photon group
+(slowest to converge): the oracle also solves them in full and the two
+solutions must agree to 1e-9 relative L2."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import gpu_solve, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_1809_08857_amd import mg  # noqa: E402
+
+N = 256
+
+
+@pytest.fixture(scope="module")
+def problems():
+    return synth.streamer_set(N, seed=0)
+
+
+@pytest.mark.parametrize("which", range(4))
+def test_full_size(problems, which):
+    p = problems[which]
+    rtol = 1e-11 if p.a == 0.0 else 1e-10
+    print(f"full-size parity {p.name} rtol={rtol}", flush=True)
+    x, rc, st = gpu_solve(p, rtol=rtol)
+    print(st, flush=True)
+    assert rc == mg.MG_OK and st["rel_res"] <= rtol
+    _, rn, bn = oracle.residual(p, x)
+    assert rn / bn <= rtol * 1.001
+    if which in (0, 1):
+        ref, cycles, rel = oracle.solve_vcycle(p, rtol=1e-13, max_cycles=60)
+        print(f"oracle: {cycles} cycles to {rel:.2e}", flush=True)
+        assert rel <= 1e-12
+        assert rel_l2(x, ref) <= 1e-9

@@ -247,3 +247,29 @@ def test_p8_mesh_independent_cycles():
     counts = np.array(counts).reshape(3, 4)
     assert counts.max() <= 14, counts
     assert (counts.max(0) - counts.min(0)).max() <= 3, counts
+
+
+# ---------------------------------------------------------------- smoother
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_rbgs_black_residual_zero_after_sweep(seed):
+    """After a red-black sweep every black cell satisfies its own equation
+    (its neighbours, all red, do not change after it), while red cells in
+    general do not; a black-first sweep would show the opposite."""
+    p = synth.random_problem(9, 7, 6, seed)
+    rng = np.random.default_rng(seed)
+    u = oracle.rbgs(p, rng.standard_normal(p.shape), 1)
+    r, _, bn = oracle.residual(p, u)
+    k, j, i = np.indices(p.shape)
+    black = ((i + j + k) & 1) == 1
+    assert np.abs(r[black]).max() < 1e-12 * np.abs(r).max() + 1e-13 * bn
+    assert np.abs(r[~black]).max() > 1e-6 * np.abs(r).max()
+
+
+def test_rbgs_fixed_point_and_convergence():
+    p = synth.random_problem(8, 8, 8, 7)
+    ud = oracle.dense_solve(p)
+    assert _rel(oracle.rbgs(p, ud, 1), ud) < 1e-13
+    u = oracle.rbgs(p, np.zeros(p.shape), 400)
+    assert _rel(u, ud) < 1e-8
