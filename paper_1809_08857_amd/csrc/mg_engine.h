@@ -44,7 +44,7 @@ struct mg_ctx {
     mg_desc d{};
     hipStream_t stream = nullptr;
     int lp_store = -1;  // ST_F32 / ST_BF16 for refinement, -1 for MG_FP64
-    int nlev = 0, tail = 0;
+    int nlev = 0, tail = 0, tail0 = 0;  // tail: first level of the bottom solver
     mg::Level L[mg::kMaxLevels];
     bool has_eps = false;
     double *eps = nullptr;

@@ -119,7 +119,11 @@ void build_tail(const Ctx *c, TailDesc &D, bool with_g) {
     const TailLevel &Lc = D.L[D.nlev - 1];
     D.cg_maxit = 2 * Lc.nx * Lc.ny * Lc.nz + 50;
     D.cg_rtol = 1e-13;
-    tail_layout(D);
+    D.stage = 1;
+    if (!tail_layout(D)) {  // coefficients too large for LDS: read them from memory
+        D.stage = 0;
+        tail_layout(D);
+    }
 }
 
 // ------------------------------------------------------------ V-cycle
@@ -350,7 +354,11 @@ int mg_create(const mg_desc *d, void *hip_stream, mg_ctx **out) {
     const size_t n0 = c->L[0].n;
     c->xalt = (double *)dalloc(c, n0 * 8);
     ok &= c->xalt != nullptr;
-    for (int l = 1; l <= c->tail; ++l) {
+    // work arrays on every level: the bottom solver may start below the
+    // level chosen here (mg_set_coeffs moves it down when the staged
+    // coefficients of variable-permittivity operators do not fit in LDS)
+    c->tail0 = c->tail;
+    for (int l = 1; l < c->nlev; ++l) {
         Level &L = c->L[l];
         L.u = (double *)dalloc(c, L.n * 8);
         L.t = (double *)dalloc(c, L.n * 8);
@@ -359,7 +367,7 @@ int mg_create(const mg_desc *d, void *hip_stream, mg_ctx **out) {
     }
     if (c->lp_store >= 0) {
         const size_t es = store_size(c->lp_store);
-        for (int l = 0; l <= c->tail; ++l) {
+        for (int l = 0; l < c->nlev; ++l) {
             Level &L = c->L[l];
             L.ul = dalloc(c, L.n * es);
             L.tl = dalloc(c, L.n * es);
@@ -453,6 +461,15 @@ int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) 
                 CK(coarsen_faces(s, Gf, F.fbx, F.fby, F.fbz, G, L.fbx, L.fby, L.fbz));
             }
         }
+        // bottom level: the first whose staged coefficients fit in LDS
+        c->has_eps = true;
+        c->tail = c->tail0;
+        for (;;) {
+            TailDesc probe;
+            build_tail(c, probe, false);
+            if (probe.stage || c->tail == c->nlev - 1) break;
+            c->tail++;
+        }
         if (c->lp_store >= 0) {
             const size_t es = store_size(c->lp_store);
             if (!c->eps_lp) c->eps_lp = dalloc(c, n0 * es);
@@ -476,6 +493,7 @@ int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) 
         c->has_eps = true;
     } else {
         c->has_eps = false;
+        c->tail = c->tail0;
     }
     c->a = a;
     c->bcmask = mask;

@@ -148,7 +148,8 @@ struct TailLevel {
     int nx, ny, nz;
     double h2, ah2;
     const double *bx, *by, *bz;  // FACE arrays (FP64) or null (CONST)
-    int off_u, off_b;            // LDS offsets (doubles)
+    int off_u, off_b;            // LDS offsets (doubles) of iterate and right-hand side
+    int off_fx, off_fy, off_fz;  // LDS offsets of the staged face coefficients (FACE)
 };
 
 struct TailDesc {
@@ -160,6 +161,7 @@ struct TailDesc {
     int off_p, off_q;     // LDS offsets of the CG vectors of the coarsest
     int cg_maxit;
     double cg_rtol;
+    int stage;            // 1: FACE coefficients staged in LDS, 0: read from memory
     TailLevel L[kTailMaxLevels];
 };
 

@@ -51,6 +51,23 @@ __device__ __forceinline__ int xcd_remap(int w, int n) {
     return xcd * q + min(xcd, r) + pos;
 }
 
+// Quotients of the stencil kernels: the hardware reciprocal refined by
+// Newton steps (two for FP64, one for FP32), then one multiply.  The
+// divisors here are sums of positive coefficients (never zero, infinite or
+// denormal), so the special cases a full IEEE division handles cannot occur;
+// the result is within a few ulp of the rounded quotient.
+__device__ __forceinline__ double rcp_nr(double s) {
+    double r = __builtin_amdgcn_rcp(s);
+    r = fma(r, fma(-s, r, 1.0), r);
+    r = fma(r, fma(-s, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ float rcp_nr(float s) {
+    float r = __builtin_amdgcn_rcpf(s);
+    return fmaf(r, fmaf(-s, r, 1.0f), r);
+}
+template <class C> __device__ __forceinline__ C qdiv(C n, C d) { return n * rcp_nr(d); }
+
 // Workgroup barrier that orders LDS traffic only.  __syncthreads() also
 // fences global memory, which makes every wave wait for all of its
 // outstanding global loads (the register prefetch) at each barrier; the
@@ -104,7 +121,7 @@ __device__ __forceinline__ void six_faces(const Geo &G, int i, int j, int k, C e
         } else if constexpr (MODE == COEF_CELL) {
             C eN = eP;
             if (SAFE || in) eN = en(d);
-            be_in = C(2) * eP * eN / (eP + eN);
+            be_in = qdiv(C(2) * eP * eN, eP + eN);
             be_bd = eP;
         } else {
             be_in = fb(d);
@@ -344,7 +361,7 @@ __global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void rbgs_col_k(
                                         : face_z(fbz, G, gxr, gy, k + 1);
                     },
                     off, dg);
-                rn_cur = (h2 * pick(b0, ro) + off) / (ah2 + dg);
+                rn_cur = qdiv(h2 * pick(b0, ro) + off, ah2 + dg);
                 s_r[k & 1][ry][lr] = rn_cur;
             }
         }
@@ -386,7 +403,7 @@ __global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void rbgs_col_k(
                                         : face_z(fbz, G, gxb, gy, kb + 1);
                     },
                     off, dg);
-                const C vb = (h2 * pick(bm, bo) + off) / (ah2 + dg);
+                const C vb = qdiv(h2 * pick(bm, bo) + off, ah2 + dg);
                 const size_t gp = (size_t)kb * plane + rowoff + gx;
                 if (even_nx) {
                     Pair<T> o;

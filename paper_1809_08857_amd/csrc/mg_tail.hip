@@ -17,8 +17,9 @@ namespace {
 constexpr int kNT = 1024;
 
 // off/dg of cell (i,j,k) at tail level l with operand array v (LDS).
-__device__ __forceinline__ void tail_terms(const TailDesc &D, int l, const double *v, int i, int j,
-                                           int k, bool with_g, double &off, double &dg) {
+__device__ __forceinline__ void tail_terms(const TailDesc &D, int l, const double *lds,
+                                           const double *v, int i, int j, int k, bool with_g,
+                                           double &off, double &dg) {
     const TailLevel &L = D.L[l];
     Geo G;
     G.nx = L.nx;
@@ -41,14 +42,18 @@ __device__ __forceinline__ void tail_terms(const TailDesc &D, int l, const doubl
     };
     auto en = [&](int) { return 1.0; };
     if (D.mode == COEF_FACE) {
+        // face coefficients staged in LDS at the start of the kernel (or in memory)
+        const double *fx = D.stage ? lds + L.off_fx : L.bx;
+        const double *fy = D.stage ? lds + L.off_fy : L.by;
+        const double *fz = D.stage ? lds + L.off_fz : L.bz;
         auto fb = [&](int d) -> double {
             switch (d) {
-                case 0: return face_x(L.bx, G, i, j, k);
-                case 1: return face_x(L.bx, G, i + 1, j, k);
-                case 2: return face_y(L.by, G, i, j, k);
-                case 3: return face_y(L.by, G, i, j + 1, k);
-                case 4: return face_z(L.bz, G, i, j, k);
-                default: return face_z(L.bz, G, i, j, k + 1);
+                case 0: return face_x(fx, G, i, j, k);
+                case 1: return face_x(fx, G, i + 1, j, k);
+                case 2: return face_y(fy, G, i, j, k);
+                case 3: return face_y(fy, G, i, j + 1, k);
+                case 4: return face_z(fz, G, i, j, k);
+                default: return face_z(fz, G, i, j, k + 1);
             }
         };
         six_faces<double, COEF_FACE>(G, i, j, k, 1.0, un, en, fb, off, dg);
@@ -88,20 +93,21 @@ __device__ void gs_sweep(const TailDesc &D, int l, double *lds, bool with_g) {
             decode(idx, L.nx, L.ny, i, j, k);
             if (((i + j + k) & 1) != colour) continue;
             double off, dg;
-            tail_terms(D, l, u, i, j, k, with_g, off, dg);
+            tail_terms(D, l, lds, u, i, j, k, with_g, off, dg);
             u[idx] = (L.h2 * b[idx] + off) / (L.ah2 + dg);
         }
         __syncthreads();
     }
 }
 
-__device__ __forceinline__ double tail_resid(const TailDesc &D, int l, const double *u,
-                                             const double *b, int idx, bool with_g) {
+__device__ __forceinline__ double tail_resid(const TailDesc &D, int l, const double *lds,
+                                             const double *u, const double *b, int idx,
+                                             bool with_g) {
     const TailLevel &L = D.L[l];
     int i, j, k;
     decode(idx, L.nx, L.ny, i, j, k);
     double off, dg;
-    tail_terms(D, l, u, i, j, k, with_g, off, dg);
+    tail_terms(D, l, lds, u, i, j, k, with_g, off, dg);
     return b[idx] - (L.ah2 * u[idx] + dg * u[idx] - off) / L.h2;
 }
 
@@ -109,16 +115,20 @@ __device__ void restrict_to(const TailDesc &D, int l, double *lds, bool with_g) 
     const TailLevel &F = D.L[l], &Cc = D.L[l + 1];
     const double *u = lds + F.off_u, *b = lds + F.off_b;
     double *bc = lds + Cc.off_b, *uc = lds + Cc.off_u;
-    const int nc = Cc.nx * Cc.ny * Cc.nz;
-    for (int I = threadIdx.x; I < nc; I += kNT) {
+    const int nc = Cc.nx * Cc.ny * Cc.nz;  // <= 512
+    const int I = threadIdx.x;
+    if (I < nc) {
         int ci, cj, ck;
         decode(I, Cc.nx, Cc.ny, ci, cj, ck);
         double s = 0.0;
+#pragma unroll
         for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
             for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
                 for (int dx = 0; dx < 2; ++dx) {
                     const int idx = ((2 * ck + dz) * F.ny + (2 * cj + dy)) * F.nx + (2 * ci + dx);
-                    s += tail_resid(D, l, u, b, idx, with_g);
+                    s += tail_resid(D, l, lds, u, b, idx, with_g);
                 }
         bc[I] = 0.125 * s;
         uc[I] = 0.0;
@@ -138,8 +148,11 @@ __device__ void prolong_into(const TailDesc &D, int l, double *lds) {
         const int I = i >> 1, J = j >> 1, K = k >> 1;
         const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
         double v = 0.0;
+#pragma unroll
         for (int a = 0; a < 2; ++a)
+#pragma unroll
             for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     int ii = I + a * si, jj = J + bb * sj, kk = K + c * sk;
                     double sg = 1.0;
@@ -166,7 +179,7 @@ __device__ void cg_solve(const TailDesc &D, int l, double *lds, double *red, boo
     double *q = lds + D.off_q;
     const int n = L.nx * L.ny * L.nz;
     // r = b - A x (boundary values only on the top level), p = r
-    for (int idx = threadIdx.x; idx < n; idx += kNT) q[idx] = tail_resid(D, l, x, r, idx, with_g);
+    for (int idx = threadIdx.x; idx < n; idx += kNT) q[idx] = tail_resid(D, l, lds, x, r, idx, with_g);
     __syncthreads();
     double s = 0.0;
     for (int idx = threadIdx.x; idx < n; idx += kNT) {
@@ -182,7 +195,7 @@ __device__ void cg_solve(const TailDesc &D, int l, double *lds, double *red, boo
             int i, j, k;
             decode(idx, L.nx, L.ny, i, j, k);
             double off, dg;
-            tail_terms(D, l, p, i, j, k, false, off, dg);
+            tail_terms(D, l, lds, p, i, j, k, false, off, dg);
             const double ap = (L.ah2 * p[idx] + dg * p[idx] - off) / L.h2;
             q[idx] = ap;
             pq += p[idx] * ap;
@@ -216,6 +229,16 @@ __global__ __launch_bounds__(kNT) void tail_k(TailDesc D, const T *__restrict__ 
     __shared__ double red[kNT / 64];
     const TailLevel &L0 = D.L[0];
     const int n0 = L0.nx * L0.ny * L0.nz;
+    if (D.mode == COEF_FACE && D.stage) {
+        for (int l = 0; l < D.nlev; ++l) {
+            const TailLevel &L = D.L[l];
+            const int nfx = (L.nx + 1) * L.ny * L.nz, nfy = L.nx * (L.ny + 1) * L.nz,
+                      nfz = L.nx * L.ny * (L.nz + 1);
+            for (int q = threadIdx.x; q < nfx; q += kNT) lds[L.off_fx + q] = L.bx[q];
+            for (int q = threadIdx.x; q < nfy; q += kNT) lds[L.off_fy + q] = L.by[q];
+            for (int q = threadIdx.x; q < nfz; q += kNT) lds[L.off_fz + q] = L.bz[q];
+        }
+    }
     for (int idx = threadIdx.x; idx < n0; idx += kNT) {
         lds[L0.off_b + idx] = (double)Num<T>::ld(b_in[idx]);
         lds[L0.off_u + idx] = u_in ? (double)Num<T>::ld(u_in[idx]) : 0.0;
@@ -260,6 +283,17 @@ bool tail_layout(TailDesc &D) {
     off += nc;
     D.off_q = off;
     off += nc;
+    for (int l = 0; l < D.nlev; ++l) {
+        TailLevel &L = D.L[l];
+        L.off_fx = L.off_fy = L.off_fz = 0;
+        if (D.mode != COEF_FACE || !D.stage) continue;
+        L.off_fx = off;
+        off += (L.nx + 1) * L.ny * L.nz;
+        L.off_fy = off;
+        off += L.nx * (L.ny + 1) * L.nz;
+        L.off_fz = off;
+        off += L.nx * L.ny * (L.nz + 1);
+    }
     return off <= kTailLdsDoubles;
 }
 

@@ -213,3 +213,25 @@ def test_deterministic():
     x1, _, s1 = gpu_solve(p)
     x2, _, s2 = gpu_solve(p)
     assert np.array_equal(x1, x2) and s1["rel_res"] == s2["rel_res"]
+
+
+def test_autotune_keeps_parity():
+    p = synth.streamer_set(64, seed=5)[0]
+    rng = np.random.default_rng(9)
+    u0 = rng.standard_normal(p.shape)
+    ref = oracle.rbgs(p, u0, 1)
+    s = make_solver(p)
+    try:
+        tile, zc, us = mg.mg_autotune(s.ctx, 2)
+        print("autotune", tile, zc, us, flush=True)
+        assert 1 <= tile <= mg.MG_NUM_TILES and zc >= 1 and us > 0
+        x = dev(u0)
+        mg.mg_smooth(s.ctx, dev(p.f), x, 1)
+        got = x.cpu().numpy()
+        f = dev(p.f)
+        xs = torch.zeros(p.shape, dtype=torch.float64, device="cuda")
+        rc, st = s.solve(f, xs)
+        assert rc == mg.MG_OK
+    finally:
+        s.close()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
