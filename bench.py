@@ -1,16 +1,27 @@
 """Benchmark of the multigrid engine on one MI355X.
 
-Workload (one "step"): the four elliptic solves of one field update at
-256^3 — the variable-permittivity potential (dielectric slab + seeded
+Default workload (one "step"): the four elliptic solves of one field update
+at 256^3 — the variable-permittivity potential (dielectric slab + seeded
 streamer filament) and the three screened photon-group equations
-(kappa_i h = 0.05, 0.3, 1.5) — each from a zero guess to relative residual
-1e-10, in FP64 V-cycles.  Inputs are generated once on the host, copied to
-HBM, and stay resident; the timed region covers whole solves only.
+(kappa_i h = 0.05, 0.3, 1.5) — each from a zero guess, in FP64 V-cycles, to
+relative residual 1e-10 (the potential, whose error/residual ratio is
+~10-25, to 1e-11 so that it also agrees with the FP64 oracle to 1e-9).
+Inputs are generated once on the host, copied to HBM and stay resident; the
+timed region covers whole solves only.
 
-Prints one JSON line:  solves/s (value), DoF/s, ms per step, the roofline of
-the dominant kernel (the finest-level red-black smoother of the potential,
-timed live with HIP events inside the library) and the CPU oracle timed on
-a bounded sample.
+Other workloads (--workload):
+  mixed512   the same four solves at 512^3 in FP64, FP32-in-FP64 and
+             BF16-storage-in-FP64 refinement (value: the --precision one)
+  batched64  64 instances with axes drawn from {32,48,64,96,128}, four solves
+             each (256 solves), FP32-in-FP64 refinement: one fused batched
+             call (captured graphs) against a loop of single solves
+  learned128 the three photon-group solves at 128^3 from the learned initial
+             guess against the zero guess (needs trained weights)
+
+Prints one JSON line: solves/s (value), DoF/s, ms per step, the roofline of
+the dominant kernel (the finest-level red-black smoother of the first solve,
+timed live with HIP events inside the library) and the CPU oracle timed on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -25,6 +36,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "elliptic solves/s (Poisson+3 Helmholtz) & DoF/s at 256^3, rel-residual 1e-10"
 
 
 def parse():
@@ -32,18 +44,23 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--workload", default="streamer256", choices=["streamer256", "mixed512", "batched64", "learned128"])
+    ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     return ap.parse_args()
 
 
+def rtol_for(p):
+    return 1e-11 if p.a == 0.0 else 1e-10
+
+
 def cpu_baseline(n: int, seed: int):
     """The oracle as it stands: lexicographic Gauss-Seidel V(2,2) cycles on
-    the host, timed on the potential solve of the same 256^3 set (one solve:
-    a bounded sample of the four-solve step)."""
+    the host, timed on the potential solve of the same set (one solve: a
+    bounded sample of the four-solve step)."""
     import oracle
     import synth
     p = synth.streamer_set(n, seed=seed)[0]
@@ -51,9 +68,92 @@ def cpu_baseline(n: int, seed: int):
     t = time.perf_counter()
     _, cycles, rel = oracle.solve_vcycle(p, rtol=1e-10, max_cycles=50)
     dt = time.perf_counter() - t
-    return {"value": 1.0 / dt, "unit": "solves/s", "cores": oracle.threads(), "kind": "oracle",
+    return {"value": round(1.0 / dt, 4), "unit": "solves/s", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"1 of the 4 solves (potential, seed {seed}) at {n}^3, lexicographic GS V(2,2) "
                       f"to rel. residual 1e-10: {cycles} cycles, {dt:.1f} s"}
+
+
+def roofline(ctx):
+    from paper_1809_08857_amd import mg
+    launches, kern_ms, kname, bytes_per_launch = mg.mg_timing_read(ctx)
+    if launches <= 0:
+        return None
+    avg_s = kern_ms / launches / 1e3
+    achieved = bytes_per_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+            "avg_us": round(avg_s * 1e6, 2), "launches": launches,
+            "algorithmic_bytes_per_launch": bytes_per_launch}
+
+
+def make_solvers(probs, precision, autotune=False):
+    import torch
+    from paper_1809_08857_amd import mg
+    out = []
+    for p in probs:
+        eps = torch.from_numpy(p.eps).cuda() if p.eps is not None else None
+        s = mg.Solver(p.nx, p.ny, p.nz, p.h, eps=eps, a=p.a, bc_types=p.bc_types(), bc_values=p.bc_values(),
+                      precision=precision, rtol=rtol_for(p))
+        if autotune:
+            mg.mg_autotune(s.ctx, 3)
+        out.append(s)
+    return out
+
+
+def timed(step, steps, warmup, ctx=None):
+    import torch
+    from paper_1809_08857_amd import mg
+    for _ in range(warmup):
+        step()
+    if ctx is not None:
+        mg.mg_timing(ctx, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    roof = roofline(ctx) if ctx is not None else None
+    if ctx is not None:
+        mg.mg_timing(ctx, 0)
+    return dt, res, roof
+
+
+def run_set(n, seed, precision, steps, warmup, autotune):
+    """Four solves of one field update at n^3; returns (solves/s, ms/step, cycles, roofline)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1809_08857_amd import mg
+    probs = synth.streamer_set(n, seed=seed)
+    f_dev = torch.from_numpy(probs[0].f).cuda()  # the same source drives all four
+    solvers = make_solvers(probs, precision, autotune)
+    xs = [torch.zeros(p.shape, dtype=torch.float64, device="cuda") for p in probs]
+    torch.cuda.synchronize()
+
+    def step():
+        cyc = []
+        for s, x in zip(solvers, xs):
+            rc, st = s.solve(f_dev, x)
+            if rc != mg.MG_OK:
+                raise RuntimeError(f"solve did not converge: {st.as_dict()}")
+            cyc.append(st.cycles)
+        return cyc
+
+    dt, cycles, roof = timed(step, steps, warmup, solvers[0].ctx)
+    for s in solvers:
+        s.close()
+    del xs, f_dev
+    torch.cuda.empty_cache()
+    return 4 * steps / dt, dt / steps * 1e3, [int(c) for c in np.mean(np.array(cycles), axis=0).round()], roof
+
+
+def base_line(args, value, ms, cfg, dtype, roof, dof=None):
+    return {
+        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": cfg,
+        "dof_per_s": None if dof is None else round(dof, 1), "roofline": roof,
+    }
 
 
 def main():
@@ -64,87 +164,73 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
-
     import synth
     from paper_1809_08857_amd import mg
 
     torch.cuda.set_device(0)
-    n = args.n
-    probs = synth.streamer_set(n, seed=args.seed)
-    f_dev = torch.from_numpy(probs[0].f).cuda()  # the same source drives all four
-    ctxs, xs = [], []
-    for p in probs:
-        eps = torch.from_numpy(p.eps).cuda() if p.eps is not None else None
-        # the potential is solved one decade tighter: its error/residual
-        # ratio is ~10-25, and the 1e-9 agreement with the oracle must hold
-        rtol = 1e-11 if p.a == 0.0 else 1e-10
-        s = mg.Solver(p.nx, p.ny, p.nz, p.h, eps=eps, a=p.a, bc_types=p.bc_types(), bc_values=p.bc_values(),
-                      precision=args.precision, rtol=rtol)
-        ctxs.append(s)
-        xs.append(torch.zeros(p.shape, dtype=torch.float64, device="cuda"))
-        del eps
-    if args.autotune:
-        for s in ctxs:
-            mg.mg_autotune(s.ctx, 3)
-    torch.cuda.synchronize()
+    if args.workload == "streamer256":
+        n = args.n or 256
+        prec = args.precision or "fp64"
+        value, ms, cycles, roof = run_set(n, args.seed, prec, args.steps, args.warmup, args.autotune)
+        cfg = {"workload": f"streamer field update: potential (eps slab) + 3 photon groups at {n}^3, "
+                           f"zero guess to rel. residual 1e-10 (potential 1e-11)", "grid": [n, n, n],
+               "solves_per_step": 4, "precision": prec, "cycles_per_solve": cycles}
+        out = base_line(args, value, ms, cfg, "f64" if prec == "fp64" else f"f64+{prec}", roof, value * n**3)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(n, args.seed)
+    elif args.workload == "mixed512":
+        n = args.n or 512
+        prec = args.precision or "bf16"
+        res = {}
+        for pr in ("fp64", "fp32", "bf16"):
+            v, ms_, cyc, rf = run_set(n, args.seed, pr, args.steps, args.warmup, args.autotune)
+            res[pr] = {"solves_per_s": round(v, 3), "ms_per_step": round(ms_, 3), "cycles_per_solve": cyc,
+                       "roofline": rf}
+        value, ms = res[prec]["solves_per_s"], res[prec]["ms_per_step"]
+        cfg = {"workload": f"streamer field update at {n}^3, FP64 refinement around low-precision V-cycles",
+               "grid": [n, n, n], "solves_per_step": 4, "precision": prec, "by_precision": res}
+        out = base_line(args, value, ms, cfg, f"f64+{prec}" if prec != "fp64" else "f64", res[prec]["roofline"],
+                        value * n**3)
+    elif args.workload == "batched64":
+        prec = args.precision or "fp32"
+        dims = synth.batch_dims()
+        probs = []
+        for j, (nx, ny, nz) in enumerate(dims):
+            probs += synth.streamer_set(int(nx), int(ny), int(nz), seed=1000 + j)
+        cells = sum(p.cells for p in probs)
+        solvers = make_solvers(probs, prec)
+        fs = [torch.from_numpy(p.f).cuda() for p in probs]
+        xs = [torch.zeros(p.shape, dtype=torch.float64, device="cuda") for p in probs]
+        ctxs = [s.ctx for s in solvers]
 
-    def step():
-        cyc = []
-        for s, x in zip(ctxs, xs):
-            rc, st = s.solve(f_dev, x)
+        def bstep():
+            rc, st = mg.mg_solve_batched(ctxs, fs, xs)
             if rc != mg.MG_OK:
-                raise RuntimeError(f"solve did not converge: {st.as_dict()}")
-            cyc.append(st.cycles)
-        return cyc
+                raise RuntimeError("batched solve did not converge")
+            return max(s.cycles for s in st)
 
-    for _ in range(args.warmup):
-        step()
-    mg.mg_timing(ctxs[0].ctx, 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    cycles = []
-    for _ in range(args.steps):
-        cycles.append(step())
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    launches, kern_ms, kname, bytes_per_launch = mg.mg_timing_read(ctxs[0].ctx)
-    mg.mg_timing(ctxs[0].ctx, 0)
+        def lstep():
+            for s, f, x in zip(solvers, fs, xs):
+                rc, st = s.solve(f, x)
+                if rc != mg.MG_OK:
+                    raise RuntimeError("solve did not converge")
+            return 0
 
-    solves = 4 * args.steps
-    value = solves / dt
-    cells = n**3
-    roof = None
-    if launches > 0:
-        avg_s = kern_ms / launches / 1e3
-        achieved = bytes_per_launch / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
-                "avg_us": round(avg_s * 1e6, 2), "launches": launches,
-                "algorithmic_bytes_per_launch": bytes_per_launch}
-    out = {
-        "metric": "elliptic solves/s (Poisson+3 Helmholtz) & DoF/s at 256^3, rel-residual 1e-10",
-        "value": round(value, 3),
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else f"f64+{args.precision}",
-        "data": "synthetic",
-        "config": {"workload": f"streamer field update: potential (eps slab) + 3 photon groups at {n}^3, "
-                               f"zero guess to rel. residual 1e-10 (potential 1e-11)", "grid": [n, n, n],
-                   "solves_per_step": 4, "precision": args.precision,
-                   "cycles_per_solve": [int(c) for c in np.mean(np.array(cycles), axis=0).round()]},
-        "dof_per_s": round(value * cells, 1),
-        "roofline": roof,
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, args.seed)
-    for s in ctxs:
-        s.close()
+        dt_l, _, _ = timed(lstep, max(1, args.steps // 2), 1)
+        dt_b, cyc, _ = timed(bstep, args.steps, args.warmup)
+        value = len(probs) * args.steps / dt_b
+        loop_value = len(probs) * max(1, args.steps // 2) / dt_l
+        cfg = {"workload": "64 instances (axes from {32,48,64,96,128}, seed 4) x (potential + 3 photon groups), "
+                           "one batched call with captured graphs", "instances": 64, "solves_per_step": len(probs),
+               "cells_total": int(cells), "precision": prec, "max_steps": int(max(cyc)),
+               "loop_of_single_solves_solves_per_s": round(loop_value, 3)}
+        out = base_line(args, value, dt_b / args.steps * 1e3, cfg, f"f64+{prec}", None, value / 4 * cells / 64 * 4)
+        out["dof_per_s"] = round(cells * args.steps / dt_b, 1)
+        for s in solvers:
+            s.close()
+    else:
+        from paper_1809_08857_amd import learned
+        out = learned.bench_line(args)
     print(json.dumps(out), flush=True)
 
 

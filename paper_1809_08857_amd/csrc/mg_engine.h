@@ -54,6 +54,7 @@ struct mg_ctx {
     double g[6] = {0, 0, 0, 0, 0, 0};
     bool coeffs = false;
     unsigned version = 0;  // bumped by every mg_set_coeffs
+    unsigned long uid = 0;  // unique per context in the process
     double *xalt = nullptr;
     int *d_done = nullptr;             // device convergence flag of the running solve
     hipEvent_t ev_cyc[2] = {nullptr, nullptr};

@@ -6,6 +6,7 @@
 // a HIP kernel enqueued on the context's stream, and the host reads back
 // one residual norm per cycle to decide convergence.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdarg>
 #include <cmath>
@@ -306,7 +307,9 @@ int mg_create(const mg_desc *d, void *hip_stream, mg_ctx **out) {
     if (d->max_cycles < 1) return set_err(MG_EINVAL, "mg_create: max_cycles must be >= 1");
     if (!(d->rtol > 0.0) || !(d->rtol < 1.0)) return set_err(MG_EINVAL, "mg_create: rtol must be in (0,1)");
 
+    static std::atomic<unsigned long> next_uid{1};
     Ctx *c = new Ctx();
+    c->uid = next_uid++;
     c->d = *d;
     c->stream = (hipStream_t)hip_stream;
     c->lp_store = d->precision == MG_FP32_IR ? ST_F32 : (d->precision == MG_BF16_IR ? ST_BF16 : -1);

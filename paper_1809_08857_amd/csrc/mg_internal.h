@@ -171,4 +171,12 @@ hipError_t tail_solve(hipStream_t s, int st, const TailDesc &D, const void *b_in
                       void *u_out, const int *done = nullptr);
 bool tail_layout(TailDesc &D);  // assigns LDS offsets; false if it does not fit
 
+// Arrays of one problem of a batched bottom solve (zero start).
+struct TailIo {
+    const void *b;
+    void *u;
+    const int *done;
+};
+hipError_t tail_solve_batched(hipStream_t s, int st, const TailDesc *descs, const TailIo *io, int count);
+
 }  // namespace mg

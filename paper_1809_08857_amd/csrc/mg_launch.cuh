@@ -18,9 +18,6 @@ inline void coef_ptrs(const Coef &C, const T *&eps, const T *&bx, const T *&by, 
     bz = static_cast<const T *>(C.bz);
 }
 
-// Prefetch depth of the column-pair smoother (planes in flight per array).
-constexpr int kSmoothPD = 2;
-
 template <class T, int MODE, int TX, int TY>
 hipError_t smooth_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *uin, void *uout,
                        const void *b, bool zero_in, int cz, const int *done) {
@@ -30,14 +27,12 @@ hipError_t smooth_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *
     const int chunks = (G.nz + cz - 1) / cz;
     const int nblk = tiles_x * tiles_y * chunks;
     const dim3 grid(nblk), block((TX + 4) / 2 * (TY + 4));
+    SmoothArgs<T> A{static_cast<const T *>(uin), static_cast<T *>(uout), static_cast<const T *>(b), eps, bx,
+                    by, bz, G, cz, tiles_x, tiles_y, nblk, done};
     if (zero_in)
-        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, true, kSmoothPD>), grid, block, 0, s,
-                           static_cast<const T *>(uin), static_cast<T *>(uout),
-                           static_cast<const T *>(b), eps, bx, by, bz, G, cz, tiles_x, tiles_y, nblk, done);
+        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, true, kSmoothPD>), grid, block, 0, s, A);
     else
-        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, false, kSmoothPD>), grid, block, 0, s,
-                           static_cast<const T *>(uin), static_cast<T *>(uout),
-                           static_cast<const T *>(b), eps, bx, by, bz, G, cz, tiles_x, tiles_y, nblk, done);
+        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, false, kSmoothPD>), grid, block, 0, s, A);
     return hipGetLastError();
 }
 
@@ -81,12 +76,12 @@ hipError_t rr_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, c
     int cz = (int)((G.nz + chunks - 1) / chunks);
     cz += cz & 1;  // chunks hold whole coarse planes
     const int nblk = tiles_x * tiles_y * ((G.nz + cz - 1) / cz);
-    constexpr int NTH = ((TX + 4) / 2 * (TY + 2) + 63) / 64 * 64;
+    constexpr int NTH = rr_threads<TX, TY>();
     if (chk.slot >= 0 && nblk > kMaxRedBlocks) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((rr_col_k<T, MODE, TX, TY, kSmoothPD>), dim3(nblk), dim3(NTH), 0, s,
-                       static_cast<const T *>(u), static_cast<const T *>(b), eps, bx, by, bz, G,
-                       static_cast<T *>(bc), cz, tiles_x, tiles_y, nblk, chk.ws, chk.slot, chk.ref_slot,
-                       chk.rtol2, chk.done_out, chk.done_in);
+    RrArgs<T> A{static_cast<const T *>(u), static_cast<const T *>(b), eps, bx, by, bz, G,
+                static_cast<T *>(bc), cz, tiles_x, tiles_y, nblk, chk.ws, chk.slot, chk.ref_slot,
+                chk.rtol2, chk.done_out, chk.done_in};
+    hipLaunchKernelGGL((rr_col_k<T, MODE, TX, TY, kSmoothPD>), dim3(nblk), dim3(NTH), 0, s, A);
     return hipGetLastError();
 }
 

@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void count_bad_k(const double *__restrict__ x,
         const double v = x[t];
         if (!(v > 0.0) || !isfinite(v)) c += 1.0;
     }
-    reduce2_finish<256>(c, 0.0, ws, slot, -1);
+    reduce2_finish<256>(c, 0.0, ws, slot, -1, brick_id(), brick_count());
 }
 
 hipError_t count_bad(hipStream_t s, const double *x, size_t n, const RedWs &ws, int slot) {
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) void ir_update_resid_k(const double *__restric
             sr += r * r;
         }
     }
-    reduce2_finish<256>(sr, 0.0, ws, slot, -1, ref_slot, rtol2, done_out);
+    reduce2_finish<256>(sr, 0.0, ws, slot, -1, brick_id(), brick_count(), ref_slot, rtol2, done_out);
 }
 
 template <class TL>

@@ -21,6 +21,9 @@
 
 namespace mg {
 
+// Prefetch depth of the column-pair kernels (planes in flight per array).
+constexpr int kSmoothPD = 2;
+
 template <class T> struct Num;
 template <> struct Num<double> {
     using C = double;
@@ -77,6 +80,95 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// ---------------------------------------------------------------------
+// Element-wise kernels run on "bricks": blockDim (BX, BY) covers BX cells
+// (or coarse cells / pairs) along x and BY rows along y, blockIdx.z a run
+// of kz planes.  No integer division by grid sizes is needed.
+struct Brick {
+    int kz;  // planes per block along z
+};
+
+__device__ __forceinline__ int brick_id() {
+    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+__device__ __forceinline__ int brick_count() { return gridDim.x * gridDim.y * gridDim.z; }
+
+// ---------------------------------------------------------------------
+// Prolongation + correction: one thread per pair of fine cells (2I, 2I+1)
+// sharing a coarse x index.
+// ---------------------------------------------------------------------
+// Deterministic block reduction of two FP64 sums, finished by the last
+// block to arrive (fixed summation order, counter reset for the next use).
+// If done != nullptr, the last block also sets *done = 1 when the first
+// sum is <= rtol2 * result[ref_slot] (squared residual against squared
+// right-hand side), else 0.
+template <int NT>
+__device__ __forceinline__ void reduce2_finish(double s0, double s1, const RedWs &ws, int slot,
+                                               int bslot, int bid, int nb, int ref_slot = -1,
+                                               double rtol2 = 0.0, int *done = nullptr) {
+    __shared__ double sh[2][NT / 64];
+    __shared__ bool last;
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s0 += __shfl_down(s0, o, 64);
+        s1 += __shfl_down(s1, o, 64);
+    }
+    if (lane == 0) {
+        sh[0][w] = s0;
+        sh[1][w] = s1;
+    }
+    __syncthreads();
+    double *part = ws.partials + (size_t)slot * kMaxRedBlocks * 2;
+    if (tid == 0) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int q = 0; q < NT / 64; ++q) {
+            a0 += sh[0][q];
+            a1 += sh[1][q];
+        }
+        __hip_atomic_store(&part[2 * bid], a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&part[2 * bid + 1], a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned t = atomicAdd(&ws.counter[slot], 1u);
+        last = (t == (unsigned)nb - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double a0 = 0.0, a1 = 0.0;
+    for (int q = tid; q < nb; q += NT) {
+        a0 += __hip_atomic_load(&part[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a1 += __hip_atomic_load(&part[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_down(a0, o, 64);
+        a1 += __shfl_down(a1, o, 64);
+    }
+    __syncthreads();
+    if (lane == 0) {
+        sh[0][w] = a0;
+        sh[1][w] = a1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int q = 0; q < NT / 64; ++q) {
+            t0 += sh[0][q];
+            t1 += sh[1][q];
+        }
+        ws.result[slot] = t0;
+        if (bslot >= 0) ws.result[bslot] = t1;
+        if (done) {
+            // the reference may be the right-hand side norm reduced in this same pass
+            const double ref = (bslot >= 0 && ref_slot == bslot) ? t1 : ws.result[ref_slot];
+            *done = (t0 <= rtol2 * ref) ? 1 : 0;
+        }
+        ws.counter[slot] = 0u;
+    }
 }
 
 // Face coefficient arrays (FACE mode), see mg_internal.h for the layout.
@@ -191,24 +283,44 @@ __device__ __forceinline__ typename Num<T>::C resid_global(const T *__restrict__
 // covers the oldest plane in flight.  Ring cells are recomputed by every
 // tile that needs them, from the same old values, so tiles never wait for
 // each other and the result equals a red sweep followed by a black sweep.
+template <class T> struct SmoothArgs {
+    const T *uin;
+    T *uout;
+    const T *b;
+    const T *eps;
+    const T *fbx, *fby, *fbz;
+    Geo G;
+    int cz, tiles_x, tiles_y, nblk;
+    const int *done;
+};
+
+// LDS elements (of the compute type) used by one smoother workgroup.
+template <int MODE, int TX, int TY> constexpr int smooth_lds() {
+    return (3 + (MODE == COEF_CELL ? 2 : 0)) * (TY + 4) * (TX + 4);
+}
+
 template <class T, int MODE, int TX, int TY, bool ZIN, int PD>
-__global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void rbgs_col_k(
-    const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ b,
-    const T *__restrict__ eps, const T *__restrict__ fbx, const T *__restrict__ fby,
-    const T *__restrict__ fbz, Geo G, int cz, int tiles_x, int tiles_y, int nblk,
-    const int *__restrict__ done) {
-    if (done && *done) return;  // the solve has converged: nothing left to do
+__device__ __forceinline__ void rbgs_col_body(const SmoothArgs<T> &A, const int blk,
+                                              typename Num<T>::C *smem) {
     using N = Num<T>;
     using C = typename N::C;
     constexpr int PXW = (TX + 4) / 2;  // pairs per region row
     constexpr int RX = TX + 4, RY = TY + 4;
     constexpr bool CELL = (MODE == COEF_CELL);
-    __shared__ C s_u[RY][RX];
-    __shared__ C s_r[2][RY][RX];
-    __shared__ C s_e[CELL ? 2 : 1][CELL ? RY : 1][CELL ? RX : 1];
+    C(*s_u)[RX] = reinterpret_cast<C(*)[RX]>(smem);
+    C(*s_r)[RY][RX] = reinterpret_cast<C(*)[RY][RX]>(smem + RY * RX);
+    C(*s_e)[RY][RX] = reinterpret_cast<C(*)[RY][RX]>(smem + 3 * RY * RX);
+    const T *__restrict__ uin = A.uin;
+    T *__restrict__ uout = A.uout;
+    const T *__restrict__ b = A.b;
+    const T *__restrict__ eps = A.eps;
+    const T *__restrict__ fbx = A.fbx;
+    const T *__restrict__ fby = A.fby;
+    const T *__restrict__ fbz = A.fbz;
+    const Geo &G = A.G;
+    const int cz = A.cz, tiles_x = A.tiles_x, tiles_y = A.tiles_y;
 
     const int tid = threadIdx.x;
-    const int blk = xcd_remap(blockIdx.x, nblk);
     const int tx = blk % tiles_x;
     const int rest = blk / tiles_x;
     const int ty = rest % tiles_y;
@@ -443,6 +555,13 @@ __global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void rbgs_col_k(
     }
 }
 
+template <class T, int MODE, int TX, int TY, bool ZIN, int PD>
+__global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void rbgs_col_k(SmoothArgs<T> A) {
+    if (A.done && *A.done) return;  // the solve has converged: nothing left to do
+    __shared__ typename Num<T>::C smem[smooth_lds<MODE, TX, TY>()];
+    rbgs_col_body<T, MODE, TX, TY, ZIN, PD>(A, xcd_remap(blockIdx.x, A.nblk), smem);
+}
+
 // ---------------------------------------------------------------------
 // Residual + restriction (+ squared norm), column-pair streaming form.
 //
@@ -455,13 +574,28 @@ __global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void rbgs_col_k(
 // squared residual is also reduced (FP64, deterministic) into ws.result[slot]
 // and, with done_out, the convergence flag is set against
 // rtol2 * ws.result[ref_slot].
+template <class T> struct RrArgs {
+    const T *u;
+    const T *b;
+    const T *eps;
+    const T *fbx, *fby, *fbz;
+    Geo G;
+    T *bc;
+    int cz, tiles_x, tiles_y, nblk;
+    RedWs ws;
+    int slot, ref_slot;
+    double rtol2;
+    int *done_out;
+    const int *done_in;
+};
+
+template <int MODE, int TX, int TY> constexpr int rr_lds() {
+    return (1 + (MODE == COEF_CELL ? 1 : 0)) * (TY + 2) * (TX + 4) + (TY + 2) * ((TX + 4) / 2);
+}
+template <int TX, int TY> constexpr int rr_threads() { return (((TX + 4) / 2 * (TY + 2)) + 63) / 64 * 64; }
+
 template <class T, int MODE, int TX, int TY, int PD>
-__global__ __launch_bounds__((((TX + 4) / 2 * (TY + 2)) + 63) / 64 * 64) void rr_col_k(
-    const T *__restrict__ u, const T *__restrict__ b, const T *__restrict__ eps,
-    const T *__restrict__ fbx, const T *__restrict__ fby, const T *__restrict__ fbz, Geo G,
-    T *__restrict__ bc, int cz, int tiles_x, int tiles_y, int nblk, RedWs ws, int slot,
-    int ref_slot, double rtol2, int *__restrict__ done_out, const int *__restrict__ done_in) {
-    if (done_in && *done_in) return;
+__device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, typename Num<T>::C *smem) {
     using N = Num<T>;
     using C = typename N::C;
     constexpr int PXW = (TX + 4) / 2;  // pairs per region row (1-cell halo, pair aligned)
@@ -469,13 +603,21 @@ __global__ __launch_bounds__((((TX + 4) / 2 * (TY + 2)) + 63) / 64 * 64) void rr
     constexpr int NTH = PXW * RY;
     constexpr int NTP = (NTH + 63) / 64 * 64;
     constexpr bool CELL = (MODE == COEF_CELL);
-    __shared__ C s_u[RY][RX];
-    __shared__ C s_e[CELL ? RY : 1][CELL ? RX : 1];
-    __shared__ C s_acc[RY][PXW];
+    C(*s_u)[RX] = reinterpret_cast<C(*)[RX]>(smem);
+    C(*s_e)[RX] = reinterpret_cast<C(*)[RX]>(smem + RY * RX);
+    C(*s_acc)[PXW] = reinterpret_cast<C(*)[PXW]>(smem + (CELL ? 2 : 1) * RY * RX);
+    const T *__restrict__ u = A.u;
+    const T *__restrict__ b = A.b;
+    const T *__restrict__ eps = A.eps;
+    const T *__restrict__ fbx = A.fbx;
+    const T *__restrict__ fby = A.fby;
+    const T *__restrict__ fbz = A.fbz;
+    T *__restrict__ bc = A.bc;
+    const Geo &G = A.G;
+    const int cz = A.cz, tiles_x = A.tiles_x, tiles_y = A.tiles_y;
 
     const int tid = threadIdx.x;
     const bool live = tid < NTH;
-    const int blk = xcd_remap(blockIdx.x, nblk);
     const int tx = blk % tiles_x;
     const int rest = blk / tiles_x;
     const int ty = rest % tiles_y;
@@ -642,33 +784,21 @@ __global__ __launch_bounds__((((TX + 4) / 2 * (TY + 2)) + 63) / 64 * 64) void rr
         if constexpr (PD > 2) { if (kk + 2 >= z1) break; iter(std::integral_constant<int, 2>{}, kk + 2); }
         if constexpr (PD > 3) { if (kk + 3 >= z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
     }
-    if (slot >= 0) reduce2_finish<NTP>(nrm, 0.0, ws, slot, -1, ref_slot, rtol2, done_out);
+    if (A.slot >= 0)
+        reduce2_finish<NTP>(nrm, 0.0, A.ws, A.slot, -1, blk, A.nblk, A.ref_slot, A.rtol2, A.done_out);
 }
 
-// ---------------------------------------------------------------------
-// Element-wise kernels run on "bricks": blockDim (BX, BY) covers BX cells
-// (or coarse cells / pairs) along x and BY rows along y, blockIdx.z a run
-// of kz planes.  No integer division by grid sizes is needed.
-struct Brick {
-    int kz;  // planes per block along z
-};
-
-__device__ __forceinline__ int brick_id() {
-    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+template <class T, int MODE, int TX, int TY, int PD>
+__global__ __launch_bounds__((rr_threads<TX, TY>())) void rr_col_k(RrArgs<T> A) {
+    if (A.done_in && *A.done_in) return;
+    __shared__ typename Num<T>::C smem[rr_lds<MODE, TX, TY>()];
+    rr_col_body<T, MODE, TX, TY, PD>(A, xcd_remap(blockIdx.x, A.nblk), smem);
 }
-__device__ __forceinline__ int brick_count() { return gridDim.x * gridDim.y * gridDim.z; }
 
-// ---------------------------------------------------------------------
-// Prolongation + correction: one thread per pair of fine cells (2I, 2I+1)
-// sharing a coarse x index.
 template <class T, class TC>
-__global__ __launch_bounds__(256) void prolong_k(T *__restrict__ u, const TC *__restrict__ e, Geo G,
-                                                 Geo Gc, const int *__restrict__ done) {
-    if (done && *done) return;
+__device__ __forceinline__ void prolong_body(T *__restrict__ u, const TC *__restrict__ e, const Geo &G,
+                                             const Geo &Gc, const int I, const int j, const int k) {
     using C = typename Num<T>::C;
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
     if (I >= Gc.nx || j >= G.ny || k >= G.nz) return;
     const int J = j >> 1, K = k >> 1;
     const int sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
@@ -708,74 +838,12 @@ __global__ __launch_bounds__(256) void prolong_k(T *__restrict__ u, const TC *__
     }
 }
 
-// ---------------------------------------------------------------------
-// Deterministic block reduction of two FP64 sums, finished by the last
-// block to arrive (fixed summation order, counter reset for the next use).
-// If done != nullptr, the last block also sets *done = 1 when the first
-// sum is <= rtol2 * result[ref_slot] (squared residual against squared
-// right-hand side), else 0.
-template <int NT>
-__device__ __forceinline__ void reduce2_finish(double s0, double s1, const RedWs &ws, int slot,
-                                               int bslot, int ref_slot = -1, double rtol2 = 0.0,
-                                               int *done = nullptr) {
-    __shared__ double sh[2][NT / 64];
-    __shared__ bool last;
-    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-    const int lane = tid & 63, w = tid >> 6;
-    const int bid = brick_id(), nb = brick_count();
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        s0 += __shfl_down(s0, o, 64);
-        s1 += __shfl_down(s1, o, 64);
-    }
-    if (lane == 0) {
-        sh[0][w] = s0;
-        sh[1][w] = s1;
-    }
-    __syncthreads();
-    double *part = ws.partials + (size_t)slot * kMaxRedBlocks * 2;
-    if (tid == 0) {
-        double a0 = 0.0, a1 = 0.0;
-        for (int q = 0; q < NT / 64; ++q) {
-            a0 += sh[0][q];
-            a1 += sh[1][q];
-        }
-        __hip_atomic_store(&part[2 * bid], a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&part[2 * bid + 1], a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned t = atomicAdd(&ws.counter[slot], 1u);
-        last = (t == (unsigned)nb - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double a0 = 0.0, a1 = 0.0;
-    for (int q = tid; q < nb; q += NT) {
-        a0 += __hip_atomic_load(&part[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a1 += __hip_atomic_load(&part[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        a0 += __shfl_down(a0, o, 64);
-        a1 += __shfl_down(a1, o, 64);
-    }
-    __syncthreads();
-    if (lane == 0) {
-        sh[0][w] = a0;
-        sh[1][w] = a1;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double t0 = 0.0, t1 = 0.0;
-        for (int q = 0; q < NT / 64; ++q) {
-            t0 += sh[0][q];
-            t1 += sh[1][q];
-        }
-        ws.result[slot] = t0;
-        if (bslot >= 0) ws.result[bslot] = t1;
-        if (done) *done = (t0 <= rtol2 * ws.result[ref_slot]) ? 1 : 0;
-        ws.counter[slot] = 0u;
-    }
+template <class T, class TC>
+__global__ __launch_bounds__(256) void prolong_k(T *__restrict__ u, const TC *__restrict__ e, Geo G,
+                                                 Geo Gc, const int *__restrict__ done) {
+    if (done && *done) return;
+    prolong_body<T, TC>(u, e, G, Gc, blockIdx.x * blockDim.x + threadIdx.x,
+                        blockIdx.y * blockDim.y + threadIdx.y, blockIdx.z);
 }
 
 // ||b - A u||^2 and (optionally) ||b + boundary terms||^2 (brick with kz planes).
@@ -831,7 +899,7 @@ __global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, co
             }
         }
     }
-    reduce2_finish<256>(sr, sb, ws, slot, bslot, ref_slot, rtol2, done_out);
+    reduce2_finish<256>(sr, sb, ws, slot, bslot, brick_id(), brick_count(), ref_slot, rtol2, done_out);
 }
 
 }  // namespace mg

@@ -218,15 +218,12 @@ __device__ void cg_solve(const TailDesc &D, int l, double *lds, double *red, boo
 
 }  // namespace
 
+// Bottom solve of one problem by the calling workgroup (kNT threads).
 template <class T>
-__global__ __launch_bounds__(kNT) void tail_k(TailDesc D, const T *__restrict__ b_in,
-                                              const T *u_in, T *u_out, int top_has_g,
-                                              const int *__restrict__ done) {
-    if (done && *done) return;
+__device__ void tail_body(const TailDesc &D, const T *__restrict__ b_in, const T *u_in, T *u_out,
+                          int top_has_g, double *lds, double *red) {
     // u_in may alias u_out: every read of u_in precedes the barrier that
     // precedes the first write of u_out.
-    __shared__ double lds[kTailLdsDoubles];
-    __shared__ double red[kNT / 64];
     const TailLevel &L0 = D.L[0];
     const int n0 = L0.nx * L0.ny * L0.nz;
     if (D.mode == COEF_FACE && D.stage) {
@@ -266,6 +263,38 @@ __global__ __launch_bounds__(kNT) void tail_k(TailDesc D, const T *__restrict__ 
     __syncthreads();
     for (int idx = threadIdx.x; idx < n0; idx += kNT)
         u_out[idx] = Num<T>::cv(typename Num<T>::C(lds[L0.off_u + idx]));
+}
+
+template <class T>
+__global__ __launch_bounds__(kNT) void tail_k(TailDesc D, const T *__restrict__ b_in, const T *u_in,
+                                              T *u_out, int top_has_g, const int *__restrict__ done) {
+    if (done && *done) return;
+    __shared__ double lds[kTailLdsDoubles];
+    __shared__ double red[kNT / 64];
+    tail_body<T>(D, b_in, u_in, u_out, top_has_g, lds, red);
+}
+
+// Batched bottom solves: workgroup w solves problem w (descriptors and
+// arrays per problem, problems that have converged are skipped).
+template <class T>
+__global__ __launch_bounds__(kNT) void tail_batched_k(const TailDesc *__restrict__ descs,
+                                                      const TailIo *__restrict__ io) {
+    const TailIo &q = io[blockIdx.x];
+    if (q.done && *q.done) return;
+    __shared__ double lds[kTailLdsDoubles];
+    __shared__ double red[kNT / 64];
+    tail_body<T>(descs[blockIdx.x], static_cast<const T *>(q.b), nullptr, static_cast<T *>(q.u), 0, lds, red);
+}
+
+hipError_t tail_solve_batched(hipStream_t s, int st, const TailDesc *descs, const TailIo *io, int count) {
+    if (count <= 0) return hipSuccess;
+    switch (st) {
+        case ST_F64: hipLaunchKernelGGL(tail_batched_k<double>, dim3(count), dim3(kNT), 0, s, descs, io); break;
+        case ST_F32: hipLaunchKernelGGL(tail_batched_k<float>, dim3(count), dim3(kNT), 0, s, descs, io); break;
+        case ST_BF16: hipLaunchKernelGGL(tail_batched_k<bf16>, dim3(count), dim3(kNT), 0, s, descs, io); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 bool tail_layout(TailDesc &D) {

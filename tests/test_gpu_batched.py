@@ -1,0 +1,95 @@
+"""Batched solves (one launch per V-cycle phase over many problems, captured
+hipGraph replays): every problem of a mixed-size batch must match its own
+single-problem solve of the same precision (the iterates do not depend on
+tiling or batching, so they agree to rounding of the stopping test) and the
+CPU oracle to 1e-9 relative L2."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import dev, make_solver, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_1809_08857_amd import mg  # noqa: E402
+
+
+def _batch_problems(n_inst, sizes, seed):
+    rng = np.random.default_rng(seed)
+    dims = rng.choice(np.asarray(sizes), size=(n_inst, 3))
+    probs = []
+    for j, (nx, ny, nz) in enumerate(dims):
+        probs += synth.streamer_set(int(nx), int(ny), int(nz), seed=100 + j)
+    return probs
+
+
+def _rtol(p):
+    return 1e-11 if p.a == 0.0 else 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batched_matches_single_and_oracle(prec):
+    probs = _batch_problems(4, (32, 48, 64), seed=7)
+    print("batch dims", [(p.nx, p.ny, p.nz) for p in probs[::4]], flush=True)
+    solvers = [make_solver(p, precision=prec, rtol=_rtol(p)) for p in probs]
+    try:
+        fs = [dev(p.f) for p in probs]
+        xs = [torch.zeros(p.shape, dtype=torch.float64, device="cuda") for p in probs]
+        # two batched solves in a row: the second replays the cached plan's graphs
+        for rep in range(2):
+            for x in xs:
+                x.fill_(123.0)
+            rc, stats = mg.mg_solve_batched([s.ctx for s in solvers], fs, xs)
+            torch.cuda.synchronize()
+            assert rc == mg.MG_OK, [st.as_dict() for st in stats]
+            for p, st in zip(probs, stats):
+                assert st.rel_res <= _rtol(p), (p.name, st.as_dict())
+        xb = [x.cpu().numpy() for x in xs]
+        for p, s, f, x_b, st in zip(probs, solvers, fs, xb, stats):
+            xsng = torch.zeros(p.shape, dtype=torch.float64, device="cuda")
+            rc1, st1 = s.solve(f, xsng)
+            assert rc1 == mg.MG_OK
+            x_s = xsng.cpu().numpy()
+            print(p.name, st.cycles, st1.cycles, rel_l2(x_b, x_s), flush=True)
+            if st.cycles == st1.cycles:
+                assert rel_l2(x_b, x_s) <= 1e-12
+            _, rn, bn = oracle.residual(p, x_b)
+            assert rn / bn <= _rtol(p) * 1.001
+            assert rel_l2(x_b, oracle.solve_reference(p)) <= 1e-9
+    finally:
+        for s in solvers:
+            s.close()
+
+
+def test_batched_guess_fallback_and_fp64_loop():
+    probs = _batch_problems(2, (32, 48), seed=3)
+    refs = [oracle.solve_reference(p) for p in probs]
+    solvers = [make_solver(p, precision="fp32", rtol=_rtol(p)) for p in probs]
+    try:
+        fs = [dev(p.f) for p in probs]
+        rng = np.random.default_rng(1)
+        guesses = []
+        for k, (p, r) in enumerate(zip(probs, refs)):
+            g = r * (1 + 1e-3) if k % 2 == 0 else 1e6 * rng.standard_normal(p.shape)
+            guesses.append(dev(g))
+        rc, stats = mg.mg_solve_batched([s.ctx for s in solvers], fs, guesses, mg.MG_GUESS)
+        assert rc == mg.MG_OK
+        for k, (p, r, x, st) in enumerate(zip(probs, refs, guesses, stats)):
+            assert st.fell_back == (0 if k % 2 == 0 else 1)
+            assert rel_l2(x.cpu().numpy(), r) <= 1e-9
+    finally:
+        for s in solvers:
+            s.close()
+    # FP64 batches run problem by problem on the single-problem path
+    solvers = [make_solver(p, rtol=_rtol(p)) for p in probs]
+    try:
+        fs = [dev(p.f) for p in probs]
+        xs = [torch.zeros(p.shape, dtype=torch.float64, device="cuda") for p in probs]
+        rc, stats = mg.mg_solve_batched([s.ctx for s in solvers], fs, xs)
+        assert rc == mg.MG_OK
+        for p, r, x in zip(probs, refs, xs):
+            assert rel_l2(x.cpu().numpy(), r) <= 1e-9
+    finally:
+        for s in solvers:
+            s.close()
