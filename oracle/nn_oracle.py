@@ -217,28 +217,38 @@ def check_shape(shape: Tuple[int, int, int]) -> None:
         raise ValueError("every grid axis must be a positive multiple of 8 (three 2x coarsenings)")
 
 
-def forward(theta: np.ndarray, x: np.ndarray) -> Tuple[np.ndarray, Dict[str, np.ndarray]]:
+def forward(theta: np.ndarray, x: np.ndarray, rnd=None) -> Tuple[np.ndarray, Dict[str, np.ndarray]]:
     """Network output y [z,y,x,3] for the scaled input x [z,y,x] (or [z,y,x,1]);
-    returns (y, activations)."""
+    returns (y, activations).
+
+    ``rnd`` (optional) rounds every stored tensor — the scaled input and
+    each layer's activation — to a storage format (e.g. ``bf16_round``),
+    the arithmetic itself staying FP64; None keeps everything in FP64."""
     check_shape(x.shape[:3])
     p = unflatten(theta)
-    acts = {"x": x.reshape(x.shape[:3] + (1,)).astype(np.float64)}
+    keep = rnd if rnd is not None else (lambda a: a)
+    acts = {"x": keep(x.reshape(x.shape[:3] + (1,)).astype(np.float64))}
     for name, ins in GRAPH:
         inp = np.concatenate([acts[i] for i in ins], axis=3) if len(ins) > 1 else acts[ins[0]]
         W, b = p[name]
         if KIND[name] == "head":
             acts[name] = inp @ W.T + b
         else:
-            acts[name] = np.maximum(_FWD[KIND[name]](inp, W, b), 0.0)
+            acts[name] = keep(np.maximum(_FWD[KIND[name]](inp, W, b), 0.0))
     return acts["head"], acts
 
 
 def loss_and_grad(theta: np.ndarray, x: np.ndarray, target: np.ndarray,
-                  want_dx: bool = False):
+                  want_dx: bool = False, rnd=None):
     """MSE loss L = mean over cells and the 3 channels of (y - target)^2, and
     dL/dtheta (flat, same layout as theta) by reverse-mode differentiation.
-    With want_dx also dL/dx."""
-    y, acts = forward(theta, x)
+    With want_dx also dL/dx.
+
+    ``rnd`` (optional, see ``forward``) also rounds every stored gradient of
+    a layer output: each consumer's contribution is masked by the layer's
+    ReLU and rounded, and a second contribution is added to the stored
+    first one and the sum rounded again."""
+    y, acts = forward(theta, x, rnd)
     p = unflatten(theta)
     diff = y - target
     loss = float(np.mean(diff * diff))
@@ -261,7 +271,11 @@ def loss_and_grad(theta: np.ndarray, x: np.ndarray, target: np.ndarray,
             c = acts[i].shape[3]
             part = gin[..., c0:c0 + c]
             c0 += c
-            g_act[i] = g_act[i] + part if i in g_act else part
+            if rnd is not None and i != "x":
+                part = rnd(part * (acts[i] > 0.0))
+                g_act[i] = rnd(g_act[i] + part) if i in g_act else part
+            else:
+                g_act[i] = g_act[i] + part if i in g_act else part
     gx = g_act.get("x")
     flat = flatten(grads)
     return (loss, flat, gx) if want_dx else (loss, flat)

@@ -1,7 +1,7 @@
 """Compile the HIP sources of the engine into in-tree shared libraries for
 gfx950 with hipcc (no JIT cache, no torch extension machinery).
 
-    python -m paper_1809_08857_amd.build        # builds libmg.so
+    python -m paper_1809_08857_amd.build        # builds libmg.so and libmgl.so
 """
 from __future__ import annotations
 
@@ -29,6 +29,7 @@ FLAGS = [
 LIBS = {
     "libmg.so": ["mg_kern_f64.hip", "mg_kern_f32.hip", "mg_kern_bf16.hip", "mg_misc.hip",
                  "mg_tail.hip", "mg_engine.hip", "mg_batched.hip", "mg_autotune.hip"],
+    "libmgl.so": ["nn_kernels.hip", "nn_net.hip"],
 }
 
 

@@ -1,0 +1,709 @@
+// Device kernels of the learned initial guess: a 3D convolutional U-net in
+// bfloat16 with FP32 accumulation on the CDNA4 matrix cores
+// (v_mfma_f32_16x16x32_bf16), its backward pass and its optimiser.
+//
+// Convolutions are implicit GEMMs.  One MFMA computes a 16x16 tile
+// D[co][v] += W[co][k] X[k][v] over 32 reduction indices k = (tap, input
+// channel): the weights are the A operand (16 output channels, k
+// contiguous per row), the activations the B operand (16 cells along x,
+// eight consecutive channels of one cell per lane = one 16-byte load from
+// the channels-last tensor).  The result layout gives each lane four
+// consecutive output channels of one cell, so the epilogue stores 8 bytes
+// per lane and a row of 16 cells is written contiguously.
+//
+// The input gradient of a convolution is again a convolution (transposed
+// weights; mirrored taps for 3x3x3, DOWN2 <-> UP2 for the strided pair), so
+// conv_k serves the forward and the backward data pass.  The weight
+// gradient reduces over cells: wgrad_k puts cells on the reduction axis and
+// gathers eight cells of one channel per lane from the channels-last
+// tensors.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "nn_internal.h"
+
+namespace nn {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float bf2f(unsigned b) { return __uint_as_float((b & 0xffffu) << 16); }
+
+// float -> bfloat16, round to nearest, ties to even (NaN kept quiet)
+__device__ __forceinline__ unsigned f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// bfloat16 pattern > 0 (NaN excluded)
+__device__ __forceinline__ bool bf_pos(unsigned b) { return !(b & 0x8000u) && (b & 0x7fffu) && (b & 0x7fffu) <= 0x7f80u; }
+
+__device__ __forceinline__ u32x4 ld16(const bf16_t *p) { return *reinterpret_cast<const u32x4 *>(p); }
+
+__device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                    0, 0, 0);
+}
+
+__device__ __forceinline__ u32x4 pack8(const unsigned (&e)[8]) {
+    u32x4 r;
+    r.x = e[0] | (e[1] << 16);
+    r.y = e[2] | (e[3] << 16);
+    r.z = e[4] | (e[5] << 16);
+    r.w = e[6] | (e[7] << 16);
+    return r;
+}
+
+// ------------------------------------------------------------------ conv
+// Block: 4 waves; wave w owns output row y = 4*blockIdx.y + w and NT rows
+// z = NT*blockIdx.z' + 0..NT-1 of a 16-cell x segment, for all COUT output
+// channels (MT = COUT/16 tiles).  UP2 tiles the coarse input grid and
+// spends blockIdx.z on the 8 output parities as well.
+template <int GEOM, int COUT, int NT>
+__global__ __launch_bounds__(256) void conv_k(ConvArgs a) {
+    constexpr int MT = COUT / 16;
+    constexpr int T = GEOM == G_SAME3 ? 27 : (GEOM == G_DOWN2 ? 8 : 1);  // taps summed per output
+    constexpr int WT = GEOM == G_SAME3 ? 27 : 8;                          // taps per weight row
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int cin = a.ca + a.cb;
+    const int K = T * cin;
+    const int nchunk = (K + 31) >> 5;
+    int tnx, tny, tnz;
+    if (GEOM == G_UP2) {
+        tnx = a.inx, tny = a.iny, tnz = a.inz;
+    } else {
+        tnx = a.onx, tny = a.ony, tnz = a.onz;
+    }
+    int bz = blockIdx.z, par = 0;
+    if (GEOM == G_UP2) {
+        const int nzb = (tnz + NT - 1) / NT;
+        par = bz / nzb;
+        bz -= par * nzb;
+    }
+    const int x = blockIdx.x * 16 + col;
+    const int y = blockIdx.y * 4 + wave;
+    const int z0 = bz * NT;
+    const bool colok = x < tnx && y < tny;
+
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+
+    for (int c = 0; c < nchunk; ++c) {
+        const int k0 = c * 32 + grp * 8;
+        const bool kok = k0 < K;
+        const int tap = kok ? k0 / cin : 0;
+        const int ci = k0 - tap * cin;
+        const bf16_t *src;
+        int cs, cl;
+        if (ci < a.ca) {
+            src = a.srcA, cs = a.ca, cl = ci;
+        } else {
+            src = a.srcB, cs = a.cb, cl = ci - a.ca;
+        }
+        int dx = 0, dy = 0, dz = 0;
+        if (GEOM == G_SAME3) {
+            dz = tap / 9 - 1;
+            dy = (tap / 3) % 3 - 1;
+            dx = tap % 3 - 1;
+        } else if (GEOM == G_DOWN2) {
+            dz = tap >> 2;
+            dy = (tap >> 1) & 1;
+            dx = tap & 1;
+        }
+        const int wt = GEOM == G_UP2 ? par : tap;
+        u32x4 A[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int co = m * 16 + col;
+            A[m] = kok ? ld16(a.w + ((size_t)co * WT + wt) * cin + ci) : zero;
+        }
+        u32x4 B[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int z = z0 + n;
+            bool ok = kok && colok && z < tnz;
+            int sx, sy, sz;
+            if (GEOM == G_SAME3) {
+                sx = x + dx, sy = y + dy, sz = z + dz;
+                ok = ok && sx >= 0 && sx < a.inx && sy >= 0 && sy < a.iny && sz >= 0 && sz < a.inz;
+            } else if (GEOM == G_DOWN2) {
+                sx = 2 * x + dx, sy = 2 * y + dy, sz = 2 * z + dz;
+            } else {
+                sx = x, sy = y, sz = z;
+            }
+            B[n] = ok ? ld16(src + (((size_t)sz * a.iny + sy) * a.inx + sx) * cs + cl) : zero;
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[m][n] = mfma(A[m], B[n], acc[m][n]);
+    }
+
+    int px = 0, py = 0, pz = 0;
+    if (GEOM == G_UP2) {
+        pz = par >> 2;
+        py = (par >> 1) & 1;
+        px = par & 1;
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int z = z0 + n;
+        if (!colok || z >= tnz) continue;
+        int ox = x, oy = y, oz = z;
+        if (GEOM == G_UP2) ox = 2 * x + px, oy = 2 * y + py, oz = 2 * z + pz;
+        const size_t ov = ((size_t)oz * a.ony + oy) * a.onx + ox;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int co = m * 16 + grp * 4;
+            float v[4] = {acc[m][n].x, acc[m][n].y, acc[m][n].z, acc[m][n].w};
+            if (a.bias) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] += a.bias[co + r];
+            }
+            if (a.relu) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
+            }
+            bf16_t *d;
+            const bf16_t *mk;
+            int cd, cc, ac;
+            if (co < a.da) {
+                d = a.dstA, cd = a.da, cc = co, mk = a.maskA, ac = a.accA;
+            } else {
+                d = a.dstB, cd = a.db, cc = co - a.da, mk = a.maskB, ac = a.accB;
+            }
+            const size_t off = ov * cd + cc;
+            if (mk) {
+                const u32x2 mm = *reinterpret_cast<const u32x2 *>(mk + off);
+                if (!bf_pos(mm.x)) v[0] = 0.f;
+                if (!bf_pos(mm.x >> 16)) v[1] = 0.f;
+                if (!bf_pos(mm.y)) v[2] = 0.f;
+                if (!bf_pos(mm.y >> 16)) v[3] = 0.f;
+            }
+            if (ac) {
+                const u32x2 o = *reinterpret_cast<const u32x2 *>(d + off);
+                v[0] += bf2f(o.x);
+                v[1] += bf2f(o.x >> 16);
+                v[2] += bf2f(o.y);
+                v[3] += bf2f(o.y >> 16);
+            }
+            u32x2 st;
+            st.x = f2bf(v[0]) | (f2bf(v[1]) << 16);
+            st.y = f2bf(v[2]) | (f2bf(v[3]) << 16);
+            *reinterpret_cast<u32x2 *>(d + off) = st;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- wgrad
+// dW[co][t][ci] = sum_q G(q, t)[co] X(q, t)[ci] with
+//   SAME3: q over the output grid, G = g[q],      X = x[q + o_t]
+//   DOWN2: q over the coarse output, G = g[q],    X = x[2q + t]
+//   UP2  : q over the coarse input,  G = g[2q+t], X = x[q]
+// as D[co][ci] += A[co][q] B[q][ci] with 32 cells q per MFMA.  Block:
+// input-channel tile blockIdx.x (16 channels) x cell slice blockIdx.y;
+// wave w owns taps w, w+4, ...  Each block writes its partial sums.
+template <int GEOM, int MT>
+__global__ __launch_bounds__(256) void wgrad_k(WgradArgs a, int steps_per_slice) {
+    constexpr int T = GEOM == G_SAME3 ? 27 : 8;
+    constexpr int TW = (T + 3) / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int cin = a.ca + a.cb;
+    const int cout = MT * 16;
+    const int ci = blockIdx.x * 16 + col;
+    const bool ciok = ci < cin;
+    const bf16_t *xs;
+    int cs, cl;
+    if (ci < a.ca) {
+        xs = a.xA, cs = a.ca, cl = ci;
+    } else {
+        xs = a.xB, cs = a.cb, cl = ci - a.ca;
+    }
+    unsigned qnx, qny, qnz;
+    if (GEOM == G_UP2) {
+        qnx = a.xnx, qny = a.xny, qnz = a.xnz;
+    } else {
+        qnx = a.gnx, qny = a.gny, qnz = a.gnz;
+    }
+    const unsigned qplane = qnx * qny;
+    const unsigned nq = qplane * qnz;
+    const unsigned nsteps = (nq + 31) / 32;
+    const unsigned st0 = blockIdx.y * (unsigned)steps_per_slice;
+    const unsigned st1 = min(st0 + (unsigned)steps_per_slice, nsteps);
+
+    f32x4 acc[MT][TW];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < TW; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (unsigned step = st0; step < st1; ++step) {
+        int qx[8], qy[8], qz[8];
+        bool qok[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const unsigned q = step * 32 + grp * 8 + j;
+            qok[j] = q < nq;
+            const unsigned qq = qok[j] ? q : 0;
+            const unsigned z = qq / qplane, r = qq - z * qplane;
+            const unsigned yy = r / qnx;
+            qz[j] = z, qy[j] = yy, qx[j] = r - yy * qnx;
+        }
+        u32x4 A[MT], B;
+        if (GEOM != G_UP2) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                unsigned e[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const size_t q = ((size_t)qz[j] * qny + qy[j]) * qnx + qx[j];
+                    e[j] = qok[j] ? a.g[q * cout + m * 16 + col] : 0u;
+                }
+                A[m] = pack8(e);
+            }
+        } else {
+            unsigned e[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const size_t q = ((size_t)qz[j] * qny + qy[j]) * qnx + qx[j];
+                e[j] = (qok[j] && ciok) ? xs[q * cs + cl] : 0u;
+            }
+            B = pack8(e);
+        }
+#pragma unroll
+        for (int tw = 0; tw < TW; ++tw) {
+            const int t = wave + 4 * tw;
+            if (t >= T) break;
+            if (GEOM == G_SAME3) {
+                const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+                unsigned e[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int sx = qx[j] + dx, sy = qy[j] + dy, sz = qz[j] + dz;
+                    const bool ok = qok[j] && ciok && sx >= 0 && sx < a.xnx && sy >= 0 && sy < a.xny && sz >= 0 &&
+                                    sz < a.xnz;
+                    e[j] = ok ? xs[(((size_t)sz * a.xny + sy) * a.xnx + sx) * cs + cl] : 0u;
+                }
+                B = pack8(e);
+            } else if (GEOM == G_DOWN2) {
+                const int tz = t >> 2, ty = (t >> 1) & 1, tx = t & 1;
+                unsigned e[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const size_t s = (((size_t)(2 * qz[j] + tz) * a.xny + 2 * qy[j] + ty) * a.xnx + 2 * qx[j] + tx);
+                    e[j] = (qok[j] && ciok) ? xs[s * cs + cl] : 0u;
+                }
+                B = pack8(e);
+            } else {
+                const int tz = t >> 2, ty = (t >> 1) & 1, tx = t & 1;
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    unsigned e[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const size_t s = (((size_t)(2 * qz[j] + tz) * a.gny + 2 * qy[j] + ty) * a.gnx + 2 * qx[j] + tx);
+                        e[j] = qok[j] ? a.g[s * cout + m * 16 + col] : 0u;
+                    }
+                    A[m] = pack8(e);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[m][tw] = mfma(A[m], B, acc[m][tw]);
+        }
+    }
+    if (!ciok) return;
+    float *P = a.partials + (size_t)blockIdx.y * cout * T * cin;
+#pragma unroll
+    for (int tw = 0; tw < TW; ++tw) {
+        const int t = wave + 4 * tw;
+        if (t >= T) break;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const float v[4] = {acc[m][tw].x, acc[m][tw].y, acc[m][tw].z, acc[m][tw].w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = m * 16 + grp * 4 + r;
+                P[((size_t)co * T + t) * cin + ci] = v[r];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ reductions
+__global__ __launch_bounds__(256) void bias_grad_k(const bf16_t *g, unsigned cells, int c, float *partials,
+                                                   unsigned cells_per_slice) {
+    __shared__ float red[256];
+    const int tid = threadIdx.x;
+    const int ch = tid % c, sub = tid / c, nsub = 256 / c;
+    const unsigned v0 = blockIdx.x * cells_per_slice;
+    const unsigned v1 = min(v0 + cells_per_slice, cells);
+    float s = 0.f;
+    for (unsigned v = v0 + sub; v < v1; v += nsub) s += bf2f(g[(size_t)v * c + ch]);
+    red[tid] = s;
+    __syncthreads();
+    if (tid < c) {
+        float t = 0.f;
+        for (int k = 0; k < nsub; ++k) t += red[k * c + tid];
+        partials[(size_t)blockIdx.x * c + tid] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_k(const float *P, int nslice, int n, int stride, int cinp,
+                                                int cin_real, float *out, int accumulate) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int ci = i % cinp;
+    if (ci >= cin_real) return;
+    float s = 0.f;
+    for (int j = 0; j < nslice; ++j) s += P[(size_t)j * stride + i];
+    const size_t o = (size_t)(i / cinp) * cin_real + ci;
+    out[o] = accumulate ? out[o] + s : s;
+}
+
+__global__ __launch_bounds__(256) void maxabs_k(const double *x, size_t n, unsigned long long *out) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) m = fmax(m, fabs(x[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    // non-negative doubles order like their bit patterns
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+__global__ __launch_bounds__(256) void prep_input_k(const double *s, size_t n, const double *sigma, bf16_t *x8) {
+    const size_t i = blockIdx.x * 256ull + threadIdx.x;
+    if (i >= n) return;
+    const double sg = *sigma;
+    const double v = sg > 0.0 ? s[i] / sg : s[i];
+    u32x4 w = {f2bf((float)v), 0u, 0u, 0u};
+    *reinterpret_cast<u32x4 *>(x8 + i * 8) = w;
+}
+
+__device__ __forceinline__ void load16ch(const bf16_t *a, size_t v, float (&x)[16]) {
+    const u32x4 p0 = ld16(a + v * 16), p1 = ld16(a + v * 16 + 8);
+    const unsigned w[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        x[2 * k] = bf2f(w[k]);
+        x[2 * k + 1] = bf2f(w[k] >> 16);
+    }
+}
+
+struct Coef3 {
+    double c[3];
+};
+
+__global__ __launch_bounds__(256) void head_predict_k(const bf16_t *a, size_t n, const float *wh, const float *bh,
+                                                      const double *sigma, Coef3 coef, double *g0, double *g1,
+                                                      double *g2) {
+    const size_t v = blockIdx.x * 256ull + threadIdx.x;
+    if (v >= n) return;
+    float x[16];
+    load16ch(a, v, x);
+    float y[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        float s = bh[i];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) s = fmaf(wh[i * 16 + c], x[c], s);
+        y[i] = s;
+    }
+    const double sg = *sigma > 0.0 ? *sigma : 1.0;
+    g0[v] = sg * coef.c[0] * (double)y[0];
+    g1[v] = sg * coef.c[1] * (double)y[1];
+    g2[v] = sg * coef.c[2] * (double)y[2];
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+constexpr int kHeadRed = 52;  // dW[3][16], db[3], sum of squared errors
+
+__global__ __launch_bounds__(256) void head_train_k(const bf16_t *a, size_t n, const float *wh, const float *bh,
+                                                    const float *t, bf16_t *ga, float *partials) {
+    __shared__ float red[4][kHeadRed];
+    const size_t v = blockIdx.x * 256ull + threadIdx.x;
+    const bool ok = v < n;
+    float x[16], gy[3], sse = 0.f;
+    if (ok) {
+        load16ch(a, v, x);
+        const float k = 2.f / (3.f * (float)n);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            float s = bh[i];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) s = fmaf(wh[i * 16 + c], x[c], s);
+            const float d = s - t[v * 3 + i];
+            sse = fmaf(d, d, sse);
+            gy[i] = k * d;
+        }
+        unsigned w[8];
+#pragma unroll
+        for (int c = 0; c < 16; c += 2) {
+            float q0 = wh[c] * gy[0] + wh[16 + c] * gy[1] + wh[32 + c] * gy[2];
+            float q1 = wh[c + 1] * gy[0] + wh[17 + c] * gy[1] + wh[33 + c] * gy[2];
+            if (!(x[c] > 0.f)) q0 = 0.f;
+            if (!(x[c + 1] > 0.f)) q1 = 0.f;
+            w[c / 2] = f2bf(q0) | (f2bf(q1) << 16);
+        }
+        *reinterpret_cast<u32x4 *>(ga + v * 16) = u32x4{w[0], w[1], w[2], w[3]};
+        *reinterpret_cast<u32x4 *>(ga + v * 16 + 8) = u32x4{w[4], w[5], w[6], w[7]};
+    } else {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) x[c] = 0.f;
+        gy[0] = gy[1] = gy[2] = 0.f;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const float s = wave_sum(gy[i] * x[c]);
+            if (lane == 0) red[wave][i * 16 + c] = s;
+        }
+        const float s = wave_sum(gy[i]);
+        if (lane == 0) red[wave][48 + i] = s;
+    }
+    const float s = wave_sum(sse);
+    if (lane == 0) red[wave][51] = s;
+    __syncthreads();
+    if (threadIdx.x < kHeadRed) {
+        const int k = threadIdx.x;
+        partials[(size_t)blockIdx.x * kHeadRed + k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+    }
+}
+
+__global__ __launch_bounds__(256) void make_target_k(const double *p0, const double *p1, const double *p2, size_t n,
+                                                     Coef3 k2, Coef3 scale, const double *sigma, float *t,
+                                                     unsigned *maxbits) {
+    const size_t v = blockIdx.x * 256ull + threadIdx.x;
+    const double sg = *sigma > 0.0 ? *sigma : 1.0;
+    float m[3] = {0.f, 0.f, 0.f};
+    if (v < n) {
+        const double ps[3] = {p0[v], p1[v], p2[v]};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float tv = (float)(k2.c[i] * ps[i] / (sg * scale.c[i]));
+            t[v * 3 + i] = tv;
+            m[i] = fabsf(tv);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        float r = m[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) r = fmaxf(r, __shfl_xor(r, o, 64));
+        if ((threadIdx.x & 63) == 0) atomicMax(maxbits + i, __float_as_uint(r));
+    }
+}
+
+__global__ __launch_bounds__(256) void adam_k(float *theta, float *m, float *v, const float *g, size_t n, float gscale,
+                                              float lr, float b1, float b2, float eps, float c1, float c2) {
+    const size_t i = blockIdx.x * 256ull + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i] * gscale;
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void pack_fwd_k(const float *W, int cout, int T, int cin, int cinp, bf16_t *wf) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= cout * T * cinp) return;
+    const int ci = i % cinp, ct = i / cinp;
+    wf[i] = ci < cin ? (bf16_t)f2bf(W[(size_t)ct * cin + ci]) : (bf16_t)0;
+}
+
+__global__ __launch_bounds__(256) void pack_bwd_k(const float *W, int cout, int T, int cin, int mirror, bf16_t *wd) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= cout * T * cin) return;
+    // wd[ci][t'][co]
+    const int co = i % cout, r = i / cout, tp = r % T, ci = r / T;
+    const int t = mirror ? T - 1 - tp : tp;
+    wd[i] = (bf16_t)f2bf(W[((size_t)co * T + t) * cin + ci]);
+}
+
+__global__ __launch_bounds__(256) void fill_zero_k(unsigned *p, size_t nw) {
+    for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < nw; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void bf16_to_f32_k(const bf16_t *s, float *d, size_t n) {
+    const size_t i = blockIdx.x * 256ull + threadIdx.x;
+    if (i < n) d[i] = bf2f(s[i]);
+}
+
+inline unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
+
+template <int GEOM, int COUT>
+hipError_t conv_launch(hipStream_t s, const ConvArgs &a) {
+    constexpr int NT = COUT >= 128 ? 2 : 4;
+    int tnx = a.onx, tny = a.ony, tnz = a.onz;
+    if (GEOM == G_UP2) tnx = a.inx, tny = a.iny, tnz = a.inz;
+    dim3 grid((tnx + 15) / 16, (tny + 3) / 4, ((tnz + NT - 1) / NT) * (GEOM == G_UP2 ? 8 : 1));
+    conv_k<GEOM, COUT, NT><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int GEOM>
+hipError_t conv_geom(hipStream_t s, const ConvArgs &a) {
+    switch (a.da + a.db) {
+        case 16: return conv_launch<GEOM, 16>(s, a);
+        case 32: return conv_launch<GEOM, 32>(s, a);
+        case 64: return conv_launch<GEOM, 64>(s, a);
+        case 128: return conv_launch<GEOM, 128>(s, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int GEOM>
+hipError_t wgrad_geom(hipStream_t s, const WgradArgs &a) {
+    const int cin = a.ca + a.cb;
+    size_t q = GEOM == G_UP2 ? (size_t)a.xnx * a.xny * a.xnz : (size_t)a.gnx * a.gny * a.gnz;
+    const unsigned nsteps = (unsigned)((q + 31) / 32);
+    const int sps = (int)((nsteps + a.nslice - 1) / a.nslice);
+    dim3 grid((cin + 15) / 16, a.nslice);
+    switch (a.cout) {
+        case 16: wgrad_k<GEOM, 1><<<grid, 256, 0, s>>>(a, sps); break;
+        case 32: wgrad_k<GEOM, 2><<<grid, 256, 0, s>>>(a, sps); break;
+        case 64: wgrad_k<GEOM, 4><<<grid, 256, 0, s>>>(a, sps); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t conv(hipStream_t s, int geom, const ConvArgs &a) {
+    if ((a.ca & 7) || (a.cb & 7) || (a.da & 3) || (a.db & 3)) return hipErrorInvalidValue;
+    switch (geom) {
+        case G_SAME3: return conv_geom<G_SAME3>(s, a);
+        case G_DOWN2: return conv_geom<G_DOWN2>(s, a);
+        case G_UP2: return conv_geom<G_UP2>(s, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int wgrad_slices(int geom, int qcells, int cin, int cout, size_t max_floats) {
+    const int nsteps = (qcells + 31) / 32;
+    const int ctiles = (cin + 15) / 16;
+    int ns = 1024 / ctiles;
+    if (ns < 1) ns = 1;
+    if (ns > nsteps) ns = nsteps;
+    const size_t per = (size_t)cout * geom_taps(geom) * cin;
+    while (ns > 1 && (size_t)ns * per > max_floats) ns /= 2;
+    // every slice must own at least one step
+    const int sps = (nsteps + ns - 1) / ns;
+    return (nsteps + sps - 1) / sps;
+}
+
+hipError_t wgrad(hipStream_t s, int geom, const WgradArgs &a) {
+    if ((a.ca & 7) || (a.cb & 7) || a.nslice < 1) return hipErrorInvalidValue;
+    switch (geom) {
+        case G_SAME3: return wgrad_geom<G_SAME3>(s, a);
+        case G_DOWN2: return wgrad_geom<G_DOWN2>(s, a);
+        case G_UP2: return wgrad_geom<G_UP2>(s, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t bias_grad(hipStream_t s, const bf16_t *g, size_t cells, int c, float *partials, int nslice) {
+    if (c <= 0 || 256 % c) return hipErrorInvalidValue;
+    const unsigned cps = (unsigned)((cells + nslice - 1) / nslice);
+    bias_grad_k<<<nslice, 256, 0, s>>>(g, (unsigned)cells, c, partials, cps);
+    return hipGetLastError();
+}
+
+hipError_t reduce_partials(hipStream_t s, const float *partials, int nslice, int n, int stride, int cinp,
+                           int cin_real, float *out, int accumulate) {
+    reduce_k<<<nblk(n), 256, 0, s>>>(partials, nslice, n, stride, cinp, cin_real, out, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t maxabs(hipStream_t s, const double *x, size_t n, double *out) {
+    unsigned g = nblk(n);
+    if (g > 1024) g = 1024;
+    maxabs_k<<<g, 256, 0, s>>>(x, n, reinterpret_cast<unsigned long long *>(out));
+    return hipGetLastError();
+}
+
+hipError_t prep_input(hipStream_t s, const double *src, size_t n, const double *sigma, bf16_t *x8) {
+    prep_input_k<<<nblk(n), 256, 0, s>>>(src, n, sigma, x8);
+    return hipGetLastError();
+}
+
+hipError_t head_predict(hipStream_t s, const bf16_t *a, size_t n, const float *wh, const float *bh,
+                        const double *sigma, const double coef[3], double *g0, double *g1, double *g2) {
+    Coef3 c{{coef[0], coef[1], coef[2]}};
+    head_predict_k<<<nblk(n), 256, 0, s>>>(a, n, wh, bh, sigma, c, g0, g1, g2);
+    return hipGetLastError();
+}
+
+int head_train_blocks(size_t n) { return (int)nblk(n); }
+
+hipError_t head_train(hipStream_t s, const bf16_t *a, size_t n, const float *wh, const float *bh, const float *t,
+                      bf16_t *ga, float *partials) {
+    head_train_k<<<nblk(n), 256, 0, s>>>(a, n, wh, bh, t, ga, partials);
+    return hipGetLastError();
+}
+
+hipError_t make_target(hipStream_t s, const double *psi0, const double *psi1, const double *psi2, size_t n,
+                       const double kappa2[3], const double scale[3], const double *sigma, float *t,
+                       unsigned *maxbits) {
+    Coef3 k{{kappa2[0], kappa2[1], kappa2[2]}}, c{{scale[0], scale[1], scale[2]}};
+    make_target_k<<<nblk(n), 256, 0, s>>>(psi0, psi1, psi2, n, k, c, sigma, t, maxbits);
+    return hipGetLastError();
+}
+
+hipError_t adam(hipStream_t s, float *theta, float *m, float *v, const float *g, size_t n, float gscale, float lr,
+                float beta1, float beta2, float eps, int step) {
+    const float c1 = (float)(1.0 - std::pow((double)beta1, step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+    adam_k<<<nblk(n), 256, 0, s>>>(theta, m, v, g, n, gscale, lr, beta1, beta2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t pack_weights(hipStream_t s, int geom, const float *W, int cout, int cin, int cinp, bf16_t *wf,
+                        bf16_t *wd) {
+    const int T = geom_taps(geom);
+    pack_fwd_k<<<nblk((size_t)cout * T * cinp), 256, 0, s>>>(W, cout, T, cin, cinp, wf);
+    if (wd) pack_bwd_k<<<nblk((size_t)cout * T * cin), 256, 0, s>>>(W, cout, T, cin, geom == G_SAME3, wd);
+    return hipGetLastError();
+}
+
+hipError_t fill_zero(hipStream_t s, void *p, size_t bytes) {
+    if (bytes & 3) return hipErrorInvalidValue;
+    const size_t nw = bytes / 4;
+    unsigned g = nblk(nw);
+    if (g > 4096) g = 4096;
+    if (g == 0) return hipSuccess;
+    fill_zero_k<<<g, 256, 0, s>>>(static_cast<unsigned *>(p), nw);
+    return hipGetLastError();
+}
+
+hipError_t bf16_to_f32(hipStream_t s, const bf16_t *src, float *dst, size_t n) {
+    bf16_to_f32_k<<<nblk(n), 256, 0, s>>>(src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace nn

@@ -27,7 +27,7 @@ def lib():
     return mg.load()
 
 
-@pytest.mark.parametrize("header,libfile", [("mg.h", "libmg.so")])
+@pytest.mark.parametrize("header,libfile", [("mg.h", "libmg.so"), ("mgl.h", "libmgl.so")])
 def test_every_declared_symbol_is_exported(header, libfile):
     names = _declared(header)
     assert len(names) >= 10
@@ -79,3 +79,31 @@ def test_tile_shapes(lib):
         assert tx % 2 == 0 and tx * ty // 2 in (64, 128, 256, 512)
     with pytest.raises(mg.MgError):
         mg.mg_tile_shape(0)
+
+
+def test_learned_guess_parameter_count_matches_the_oracle():
+    """The flat parameter layout is an interface shared by the library and
+    the oracle: both must count the same parameters."""
+    from oracle import nn_oracle
+    from paper_1809_08857_amd import learned
+    if not os.path.exists(learned.LIB_PATH):
+        mgbuild.build()
+    assert learned.mgl_num_params() == nn_oracle.num_params()
+
+
+@pytest.mark.parametrize("dims", [(12, 16, 16), (16, 16, 4), (0, 8, 8), (8, 8, 20)])
+def test_learned_guess_rejects_grids_that_do_not_coarsen(dims):
+    from paper_1809_08857_amd import learned
+    lib = learned.load()
+    out = ctypes.c_void_p(5)
+    rc = lib.mgl_create(ctypes.byref(learned.MglDesc(*dims)), None, ctypes.byref(out))
+    assert rc == mg.MG_EINVAL and out.value is None
+    assert learned.mgl_last_error().startswith("mgl_create")
+
+
+def test_learned_guess_null_arguments():
+    from paper_1809_08857_amd import learned
+    lib = learned.load()
+    assert lib.mgl_set_params(None, None, 0) == mg.MG_EINVAL
+    assert lib.mgl_predict(None, None, None, None) == mg.MG_EINVAL
+    assert lib.mgl_destroy(None) == mg.MG_OK

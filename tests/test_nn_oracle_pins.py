@@ -180,3 +180,23 @@ def test_prediction_scales_with_the_source():
 def test_rejects_grids_that_do_not_coarsen_three_times():
     with pytest.raises(ValueError):
         nn.forward(nn.init_params(0), np.zeros((8, 12, 16)))
+
+
+def test_storage_rounding_option():
+    """rnd = identity reproduces the plain FP64 pass bit for bit; with
+    bfloat16 rounding every stored activation is a bfloat16 value and the
+    loss moves by no more than the storage precision allows."""
+    rng = np.random.default_rng(12)
+    theta = nn.init_params(3)
+    x = rng.random((8, 8, 8))
+    t = rng.standard_normal((8, 8, 8, 3))
+    l0, g0 = nn.loss_and_grad(theta, x, t)
+    l1, g1 = nn.loss_and_grad(theta, x, t, rnd=lambda a: a)
+    assert l0 == l1 and np.array_equal(g0, g1)
+    _, acts = nn.forward(theta, x, rnd=nn.bf16_round)
+    for k, a in acts.items():
+        if k != "head":
+            assert np.array_equal(a, nn.bf16_round(a)), k
+    l2, g2 = nn.loss_and_grad(theta, x, t, rnd=nn.bf16_round)
+    assert abs(l2 - l0) <= 1e-2 * l0
+    assert np.linalg.norm(g2 - g0) <= 0.1 * np.linalg.norm(g0)
