@@ -82,10 +82,16 @@ enum { MG_FP64 = 0, MG_FP32_IR = 1, MG_BF16_IR = 2 };
 
 /* mg_solve flags */
 enum {
-    MG_GUESS = 1u /* x holds an initial guess.  It is kept only if its
-                     residual does not exceed that of the zero guess
-                     (||b - A x|| <= ||b||); otherwise x is zeroed and
-                     stats.fell_back = 1. */
+    MG_GUESS = 1u /* x holds an initial guess.  It is kept only if, after
+                     the nu1 pre-smoothing sweeps that open every cycle
+                     (FP64, finest level), its residual does not exceed
+                     that of the zero guess: ||b - A S(x)|| <= ||b||.
+                     Otherwise the solve starts from zero and
+                     stats.fell_back = 1.  (Grids handled by the bottom
+                     solver alone, or nu1 = 0: the raw residual
+                     ||b - A x|| is compared.)  stats.rel_res0 is the raw
+                     relative residual of the guess (1 after a
+                     fallback). */
 };
 
 typedef struct {
@@ -146,7 +152,8 @@ int mg_solve(mg_ctx *c, const double *f_dev, double *x_dev, unsigned flags, mg_s
  * the whole batch is one kernel launch over a work list of tiles, the
  * cycle is captured once into a hipGraph and replayed, and converged
  * problems are skipped on the device.  f_dev[i], x_dev[i] as in mg_solve
- * for context c[i]; st (optional) receives count entries. */
+ * for context c[i]; st (optional) receives count entries.  With MG_GUESS
+ * each guess is judged on its raw residual (||b - A x|| <= ||b||). */
 int mg_solve_batched(int count, mg_ctx *const *c, const double *const *f_dev,
                      double *const *x_dev, unsigned flags, mg_stats *st);
 

@@ -536,7 +536,13 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
         if (st) *st = S;
         return MG_OK;
     }
-    if ((flags & MG_GUESS) && rn > bn) {
+    // A guess is judged at its first convergence test, after the nu1
+    // pre-smoothing sweeps that open every cycle (they remove the
+    // cell-scale noise that the operator would otherwise magnify), against
+    // the residual of the zero guess, ||b||.  Without a multigrid hierarchy
+    // or pre-smoothing the raw residual is compared.
+    const bool judge = (flags & MG_GUESS) && c->tail > 0 && c->d.nu1 > 0;
+    if ((flags & MG_GUESS) && !judge && rn > bn) {
         CK(fill_zero(s, x, n0 * 8));
         S.fell_back = 1;
         rn = bn;
@@ -627,7 +633,30 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
         return MG_OK;
     };
 
+    if (judge && lowp) {
+        // the FP64 pre-smoothing of the guess (the low-precision cycles
+        // start from a residual)
+        int zc;
+        const int tile = tile_for(c, G0, ST_F64, 0, &zc);
+        for (int q = 0; q < c->d.nu1; ++q) {
+            CK(smooth(s, ST_F64, G0, C0, cur, oth, f, false, tile, zc));
+            std::swap(cur, oth);
+        }
+    }
     if ((rc = check(0))) return rc;
+    if (judge) {
+        CK(hipEventSynchronize(c->ev_cyc[0]));
+        const double rel_s = std::sqrt(c->h_pin[SLOT_CYC]) / bn;
+        if (!(rel_s <= 1.0)) {  // worse than the zero guess (or not finite): start from zero
+            CK(fill_zero(s, x, n0 * 8));
+            CK(fill_zero(s, done, sizeof(int)));
+            cur = x;
+            oth = c->xalt;
+            S.fell_back = 1;
+            S.rel_res0 = 1.0;
+            if ((rc = check(0))) return rc;
+        }
+    }
     double *at_check[2] = {cur, nullptr};
     int cycles = 0;
     double rel = S.rel_res0;

@@ -65,11 +65,13 @@ struct WgradArgs {
     int nslice;
 };
 hipError_t wgrad(hipStream_t s, int geom, const WgradArgs &a);
-// number of slices wgrad() uses for a layer (the partials buffer holds
-// nslice * cout * T * cin floats)
-int wgrad_slices(int geom, int qcells, int cin, int cout, size_t max_floats);
+// number of slices wgrad() uses for a layer whose reduction runs over a
+// qx*qy*qz grid (the output grid, or the coarse input grid for UP2); the
+// partials buffer holds nslice * cout * T * cin floats
+int wgrad_slices(int geom, int qx, int qy, int qz, int cin, int cout, size_t max_floats);
 
-// Bias gradient: partials[slice][c] = sum over the slice's cells of g[.][c].
+// Bias gradient: partials[slice][c] = sum over the slice's cells of g[.][c]
+// (c = 16, 32 or 64).
 hipError_t bias_grad(hipStream_t s, const bf16_t *g, size_t cells, int c, float *partials, int nslice);
 
 // out[map(i)] (+)= sum_j partials[j * stride + i] for i < n, summed in slice
@@ -77,8 +79,11 @@ hipError_t bias_grad(hipStream_t s, const bf16_t *g, size_t cells, int c, float 
 // i % cinp >= cin_real dropped (so a channel-padded weight gradient
 // [cout][T][cinp] lands in its unpadded layout; cinp = cin_real = n for a
 // plain vector).
+// More than kReduceGroups slices are first summed in kReduceGroups groups
+// into work (kReduceGroups * n floats), then the groups in order.
+constexpr int kReduceGroups = 64;
 hipError_t reduce_partials(hipStream_t s, const float *partials, int nslice, int n, int stride, int cinp,
-                           int cin_real, float *out, int accumulate);
+                           int cin_real, float *out, int accumulate, float *work);
 
 // max |s| over n FP64 values into *out (FP64); *out must hold 0 or less.
 hipError_t maxabs(hipStream_t s, const double *x, size_t n, double *out);

@@ -60,6 +60,55 @@ __device__ __forceinline__ u32x4 pack8(const unsigned (&e)[8]) {
     return r;
 }
 
+// Epilogue of one lane: output channels co..co+3 of output cell ov.
+__device__ __forceinline__ void store4(const ConvArgs &a, size_t ov, int co, f32x4 acc) {
+    float v[4] = {acc.x, acc.y, acc.z, acc.w};
+    if (a.bias) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] += a.bias[co + r];
+    }
+    if (a.relu) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
+    }
+    bf16_t *d;
+    const bf16_t *mk;
+    int cd, cc, ac;
+    if (co < a.da) {
+        d = a.dstA, cd = a.da, cc = co, mk = a.maskA, ac = a.accA;
+    } else {
+        d = a.dstB, cd = a.db, cc = co - a.da, mk = a.maskB, ac = a.accB;
+    }
+    const size_t off = ov * cd + cc;
+    if (mk) {
+        const u32x2 mm = *reinterpret_cast<const u32x2 *>(mk + off);
+        if (!bf_pos(mm.x)) v[0] = 0.f;
+        if (!bf_pos(mm.x >> 16)) v[1] = 0.f;
+        if (!bf_pos(mm.y)) v[2] = 0.f;
+        if (!bf_pos(mm.y >> 16)) v[3] = 0.f;
+    }
+    if (ac) {
+        const u32x2 o = *reinterpret_cast<const u32x2 *>(d + off);
+        v[0] += bf2f(o.x);
+        v[1] += bf2f(o.x >> 16);
+        v[2] += bf2f(o.y);
+        v[3] += bf2f(o.y >> 16);
+    }
+    u32x2 st;
+    st.x = f2bf(v[0]) | (f2bf(v[1]) << 16);
+    st.y = f2bf(v[2]) | (f2bf(v[3]) << 16);
+    *reinterpret_cast<u32x2 *>(d + off) = st;
+}
+
+// Hardware block w of n -> logical block, so that each of the 8 XCDs (which
+// receive blocks round-robin) works on one contiguous range of tiles and
+// the halos its tiles share stay in its own L2.
+__device__ __forceinline__ int xcd_order(int w, int n) {
+    const int q = n / 8, r = n % 8;
+    const int xcd = w % 8, pos = w / 8;
+    return xcd * q + min(xcd, r) + pos;
+}
+
 // ------------------------------------------------------------------ conv
 // Block: 4 waves; wave w owns output row y = 4*blockIdx.y + w and NT rows
 // z = NT*blockIdx.z' + 0..NT-1 of a 16-cell x segment, for all COUT output
@@ -164,45 +213,200 @@ __global__ __launch_bounds__(256) void conv_k(ConvArgs a) {
         if (GEOM == G_UP2) ox = 2 * x + px, oy = 2 * y + py, oz = 2 * z + pz;
         const size_t ov = ((size_t)oz * a.ony + oy) * a.onx + ox;
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const int co = m * 16 + grp * 4;
-            float v[4] = {acc[m][n].x, acc[m][n].y, acc[m][n].z, acc[m][n].w};
-            if (a.bias) {
+        for (int m = 0; m < MT; ++m) store4(a, ov, m * 16 + grp * 4, acc[m][n]);
+    }
+}
+
+// 3x3x3 convolution with the input tile staged in LDS.  Block: output tile
+// of 16 x RY x RZ cells (x fastest); wave w owns rows r = w, w+4, ... of
+// the RY*RZ rows of 16 cells, for all COUT output channels.  The input
+// channels are staged CC at a time: the (18) x (RY+2) x (RZ+2) halo tile,
+// zero outside the grid, with a per-cell stride of VS bfloat16 (16-byte
+// units odd, so the 16 cells a lane group reads hit distinct banks).  Each
+// MFMA takes its B operand (8 channels of one cell per lane) from LDS and
+// its A operand (16 output channels x 8 taps/channels) from the weights.
+template <int COUT, int CC, int RY, int RZ>
+__global__ __launch_bounds__(256) void conv3_lds_k(ConvArgs a) {
+    constexpr int MT = COUT / 16;
+    constexpr int RPW = RY * RZ / 4;
+    constexpr int HX = 18, HY = RY + 2, HZ = RZ + 2;
+    constexpr int NV = HX * HY * HZ;
+    constexpr int G8 = CC / 8;                      // 8-channel groups per cell
+    constexpr int VS = (G8 % 2 == 0) ? CC + 8 : CC; // LDS stride per cell
+    constexpr int GPT = G8 < 4 ? G8 : 4;            // lane groups per tap
+    constexpr int TPC = 4 / GPT;                    // taps per K-chunk of 32
+    constexpr int CPT = G8 / GPT;                   // K-chunks per tap
+    __shared__ __align__(16) bf16_t tile[NV * VS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int cin = a.ca + a.cb;
+    const int ntx = (a.onx + 15) / 16, nty = (a.ony + RY - 1) / RY, ntz = (a.onz + RZ - 1) / RZ;
+    const int b = xcd_order(blockIdx.x, ntx * nty * ntz);
+    const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
+    const int x0 = bx * 16, y0 = by * RY, z0 = bz * RZ;
+
+    f32x4 acc[MT][RPW];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] += a.bias[co + r];
-            }
-            if (a.relu) {
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
+        for (int r = 0; r < RPW; ++r) acc[m][r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    // this lane's tap offset within a K-chunk and channel offset within a tap
+    const int tsub = grp / GPT;
+    const int cl = (grp % GPT) * 8;
+
+    for (int cb = 0; cb < cin; cb += CC) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < NV * G8; i += 256) {
+            const int v = i / G8, q = i - v * G8;
+            const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            u32x4 val = zero;
+            if (gx >= 0 && gx < a.inx && gy >= 0 && gy < a.iny && gz >= 0 && gz < a.inz) {
+                const int ci = cb + q * 8;
+                const size_t cell = ((size_t)gz * a.iny + gy) * a.inx + gx;
+                val = ci < a.ca ? ld16(a.srcA + cell * a.ca + ci) : ld16(a.srcB + cell * a.cb + (ci - a.ca));
             }
-            bf16_t *d;
-            const bf16_t *mk;
-            int cd, cc, ac;
-            if (co < a.da) {
-                d = a.dstA, cd = a.da, cc = co, mk = a.maskA, ac = a.accA;
-            } else {
-                d = a.dstB, cd = a.db, cc = co - a.da, mk = a.maskB, ac = a.accB;
-            }
-            const size_t off = ov * cd + cc;
-            if (mk) {
-                const u32x2 mm = *reinterpret_cast<const u32x2 *>(mk + off);
-                if (!bf_pos(mm.x)) v[0] = 0.f;
-                if (!bf_pos(mm.x >> 16)) v[1] = 0.f;
-                if (!bf_pos(mm.y)) v[2] = 0.f;
-                if (!bf_pos(mm.y >> 16)) v[3] = 0.f;
-            }
-            if (ac) {
-                const u32x2 o = *reinterpret_cast<const u32x2 *>(d + off);
-                v[0] += bf2f(o.x);
-                v[1] += bf2f(o.x >> 16);
-                v[2] += bf2f(o.y);
-                v[3] += bf2f(o.y >> 16);
-            }
-            u32x2 st;
-            st.x = f2bf(v[0]) | (f2bf(v[1]) << 16);
-            st.y = f2bf(v[2]) | (f2bf(v[3]) << 16);
-            *reinterpret_cast<u32x2 *>(d + off) = st;
+            *reinterpret_cast<u32x4 *>(tile + v * VS + q * 8) = val;
         }
+        __syncthreads();
+#pragma unroll 1
+        for (int t0 = 0; t0 < 27; t0 += TPC) {
+            const int tap = t0 + tsub;
+            const bool tok = tap < 27;
+            const int tq = tok ? tap : 0;
+            const int dz = tq / 9, dy = (tq / 3) % 3, dx = tq % 3;  // offsets + 1
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int ch = c * 32 + cl;  // channel within the staged block
+                u32x4 A[MT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    A[m] = tok ? ld16(a.w + ((size_t)(m * 16 + col) * 27 + tq) * cin + cb + ch) : zero;
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) {
+                    const int row = wave + 4 * r;
+                    const int ry = row % RY, rz = row / RY;
+                    const int v = ((rz + dz) * HY + (ry + dy)) * HX + col + dx;
+                    const u32x4 B = tok ? *reinterpret_cast<const u32x4 *>(tile + v * VS + ch) : zero;
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) acc[m][r] = mfma(A[m], B, acc[m][r]);
+                }
+            }
+        }
+    }
+    const int ox = x0 + col;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const int row = wave + 4 * r;
+        const int oy = y0 + row % RY, oz = z0 + row / RY;
+        if (ox >= a.onx || oy >= a.ony || oz >= a.onz) continue;
+        const size_t ov = ((size_t)oz * a.ony + oy) * a.onx + ox;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) store4(a, ov, m * 16 + grp * 4, acc[m][r]);
+    }
+}
+
+// LDS byte offset (in cells) of tap t in the halo tile, taps (dz,dy,dx)+1.
+template <int HX, int HY>
+__device__ __forceinline__ constexpr int tap_off(int t) {
+    return ((t / 9) * HY + (t / 3) % 3) * HX + t % 3;
+}
+
+// 3x3x3 convolution, weights resident in registers.  As conv3_lds_k, but
+// the waves split the output channels into WM groups (wave w: channel
+// tiles of group w % WM, rows w / WM, w / WM + 4/WM, ...), and each wave
+// loads its whole A operand for the staged channel block (NCH K-chunks)
+// into registers before the K loop, which is fully unrolled so that every
+// LDS address is a per-row base plus a compile-time offset.
+template <int COUT, int CC, int RY, int RZ, int WM>
+__global__ __launch_bounds__(256) void conv3_reg_k(ConvArgs a) {
+    constexpr int MT = COUT / 16;
+    constexpr int MTW = MT / WM;                    // channel tiles per wave
+    constexpr int WR = 4 / WM;                      // wave groups along rows
+    constexpr int RW = RY * RZ / WR;                // rows per wave
+    constexpr int HX = 18, HY = RY + 2, HZ = RZ + 2;
+    constexpr int NV = HX * HY * HZ;
+    constexpr int G8 = CC / 8;
+    constexpr int VS = (G8 % 2 == 0) ? CC + 8 : CC;
+    constexpr int GPT = G8 < 4 ? G8 : 4;            // lane groups per tap
+    constexpr int TPC = 4 / GPT;                    // taps per K-chunk
+    constexpr int NCH = (27 + TPC - 1) / TPC;       // K-chunks per staged block
+    static_assert(G8 <= 4, "staged channel block must fit one K-chunk per tap");
+    __shared__ __align__(16) bf16_t tile[NV * VS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int wm = wave % WM, wr = wave / WM;
+    const int cin = a.ca + a.cb;
+    const int ntx = (a.onx + 15) / 16, nty = (a.ony + RY - 1) / RY, ntz = (a.onz + RZ - 1) / RZ;
+    const int b = xcd_order(blockIdx.x, ntx * nty * ntz);
+    const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
+    const int x0 = bx * 16, y0 = by * RY, z0 = bz * RZ;
+    const int tsub = grp / GPT;
+    const int cl = (grp % GPT) * 8;
+
+    f32x4 acc[MTW][RW];
+#pragma unroll
+    for (int m = 0; m < MTW; ++m)
+#pragma unroll
+        for (int r = 0; r < RW; ++r) acc[m][r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    int rbase[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int row = wr + WR * r;
+        rbase[r] = ((row / RY) * HY + row % RY) * HX + col;
+    }
+
+    for (int cb = 0; cb < cin; cb += CC) {
+        u32x4 A[NCH][MTW];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int tap = c * TPC + tsub;
+#pragma unroll
+            for (int m = 0; m < MTW; ++m) {
+                const int co = (wm * MTW + m) * 16 + col;
+                A[c][m] = tap < 27 ? ld16(a.w + ((size_t)co * 27 + tap) * cin + cb + cl) : zero;
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < NV * G8; i += 256) {
+            const int v = i / G8, q = i - v * G8;
+            const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            u32x4 val = zero;
+            if (gx >= 0 && gx < a.inx && gy >= 0 && gy < a.iny && gz >= 0 && gz < a.inz) {
+                const int ci = cb + q * 8;
+                const size_t cell = ((size_t)gz * a.iny + gy) * a.inx + gx;
+                val = ci < a.ca ? ld16(a.srcA + cell * a.ca + ci) : ld16(a.srcB + cell * a.cb + (ci - a.ca));
+            }
+            *reinterpret_cast<u32x4 *>(tile + v * VS + q * 8) = val;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            // this lane's tap in chunk c (past the last tap: any cell, A is 0)
+            int off = tap_off<HX, HY>(c * TPC < 27 ? c * TPC : 26);
+#pragma unroll
+            for (int k = 1; k < TPC; ++k)
+                if (tsub == k) off = tap_off<HX, HY>(c * TPC + k < 27 ? c * TPC + k : 26);
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const u32x4 B = *reinterpret_cast<const u32x4 *>(tile + (rbase[r] + off) * VS + cl);
+#pragma unroll
+                for (int m = 0; m < MTW; ++m) acc[m][r] = mfma(A[c][m], B, acc[m][r]);
+            }
+        }
+    }
+    const int ox = x0 + col;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int row = wr + WR * r;
+        const int oy = y0 + row % RY, oz = z0 + row / RY;
+        if (ox >= a.onx || oy >= a.ony || oz >= a.onz) continue;
+        const size_t ov = ((size_t)oz * a.ony + oy) * a.onx + ox;
+#pragma unroll
+        for (int m = 0; m < MTW; ++m) store4(a, ov, (wm * MTW + m) * 16 + grp * 4, acc[m][r]);
     }
 }
 
@@ -341,23 +545,149 @@ __global__ __launch_bounds__(256) void wgrad_k(WgradArgs a, int steps_per_slice)
     }
 }
 
+// Weight gradient of a 3x3x3 convolution with both operands staged in LDS.
+// Block: input-channel tile blockIdx.x (16 channels) x a contiguous range
+// of 16x4x4 output tiles (blockIdx.y).  Per tile the input halo (18x6x6
+// cells x 16 channels, zero outside the grid) and the output gradient
+// (256 cells x COUT channels) are staged with 16-byte loads; each MFMA then
+// reduces 32 cells of the tile, whose values the lanes gather from LDS
+// (8 cells of one channel per lane).  Wave w owns taps w, w+4, ...
+template <int MT>
+__global__ __launch_bounds__(256) void wgrad3_lds_k(WgradArgs a, int tiles_per_block) {
+    constexpr int COUT = MT * 16;
+    constexpr int TW = 7;
+    constexpr int HX = 18, HY = 6, HZ = 6, NV = HX * HY * HZ;
+    constexpr int XS = 24;         // bf16 per staged input cell (16 channels + pad)
+    constexpr int GS = COUT + 8;   // bf16 per staged gradient cell
+    __shared__ __align__(16) bf16_t xt[NV * XS];
+    __shared__ __align__(16) bf16_t gt[256 * GS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int cin = a.ca + a.cb;
+    const int c0 = blockIdx.x * 16;
+    const int ntx = (a.gnx + 15) / 16, nty = (a.gny + 3) / 4, ntz = (a.gnz + 3) / 4;
+    const int ntiles = ntx * nty * ntz;
+    const int tb0 = blockIdx.y * tiles_per_block, tb1 = min(tb0 + tiles_per_block, ntiles);
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+
+    f32x4 acc[MT][TW];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < TW; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int tb = tb0; tb < tb1; ++tb) {
+        const int bx = tb % ntx, by = (tb / ntx) % nty, bz = tb / (ntx * nty);
+        const int x0 = bx * 16, y0 = by * 4, z0 = bz * 4;
+        __syncthreads();
+        for (int i = threadIdx.x; i < NV * 2; i += 256) {
+            const int v = i >> 1, q = i & 1;
+            const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            const int c = c0 + q * 8;
+            u32x4 val = zero;
+            if (c < cin && gx >= 0 && gx < a.xnx && gy >= 0 && gy < a.xny && gz >= 0 && gz < a.xnz) {
+                const size_t cell = ((size_t)gz * a.xny + gy) * a.xnx + gx;
+                val = c < a.ca ? ld16(a.xA + cell * a.ca + c) : ld16(a.xB + cell * a.cb + (c - a.ca));
+            }
+            *reinterpret_cast<u32x4 *>(xt + v * XS + q * 8) = val;
+        }
+        for (int i = threadIdx.x; i < 256 * (COUT / 8); i += 256) {
+            const int v = i / (COUT / 8), q = i % (COUT / 8);
+            const int gx = x0 + (v & 15), gy = y0 + ((v >> 4) & 3), gz = z0 + (v >> 6);
+            u32x4 val = zero;
+            if (gx < a.gnx && gy < a.gny && gz < a.gnz)
+                val = ld16(a.g + (((size_t)gz * a.gny + gy) * a.gnx + gx) * COUT + q * 8);
+            *reinterpret_cast<u32x4 *>(gt + v * GS + q * 8) = val;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int step = 0; step < 8; ++step) {
+            const int row = step * 2 + (grp >> 1);   // 0..15 = (ly, lz)
+            const int ly = row & 3, lz = row >> 2;
+            const int lx0 = (grp & 1) * 8;
+            u32x4 A[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                unsigned e[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) e[j] = gt[(row * 16 + lx0 + j) * GS + m * 16 + col];
+                A[m] = pack8(e);
+            }
+#pragma unroll
+            for (int tw = 0; tw < TW; ++tw) {
+                const int t = wave + 4 * tw;
+                if (t >= 27) break;
+                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+                const int base = ((lz + dz) * HY + (ly + dy)) * HX + lx0 + dx;
+                unsigned e[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) e[j] = xt[(base + j) * XS + col];
+                const u32x4 B = pack8(e);
+#pragma unroll
+                for (int m = 0; m < MT; ++m) acc[m][tw] = mfma(A[m], B, acc[m][tw]);
+            }
+        }
+    }
+    const int ci = c0 + col;
+    if (ci >= cin) return;
+    float *P = a.partials + (size_t)blockIdx.y * COUT * 27 * cin;
+#pragma unroll
+    for (int tw = 0; tw < TW; ++tw) {
+        const int t = wave + 4 * tw;
+        if (t >= 27) break;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const float v[4] = {acc[m][tw].x, acc[m][tw].y, acc[m][tw].z, acc[m][tw].w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) P[((size_t)(m * 16 + grp * 4 + r) * 27 + t) * cin + ci] = v[r];
+        }
+    }
+}
+
 // ------------------------------------------------------------ reductions
-__global__ __launch_bounds__(256) void bias_grad_k(const bf16_t *g, unsigned cells, int c, float *partials,
+// Bias gradient: each thread keeps one 8-channel group (256 is a multiple
+// of C/8) and reads 16 bytes per cell, so a block sweeps its cells with
+// coalesced loads; the groups are then summed through LDS.
+template <int C>
+__global__ __launch_bounds__(256) void bias_grad_k(const bf16_t *g, unsigned cells, float *partials,
                                                    unsigned cells_per_slice) {
-    __shared__ float red[256];
+    constexpr int G8 = C / 8;
+    __shared__ float red[256][9];
     const int tid = threadIdx.x;
-    const int ch = tid % c, sub = tid / c, nsub = 256 / c;
     const unsigned v0 = blockIdx.x * cells_per_slice;
     const unsigned v1 = min(v0 + cells_per_slice, cells);
-    float s = 0.f;
-    for (unsigned v = v0 + sub; v < v1; v += nsub) s += bf2f(g[(size_t)v * c + ch]);
-    red[tid] = s;
-    __syncthreads();
-    if (tid < c) {
-        float t = 0.f;
-        for (int k = 0; k < nsub; ++k) t += red[k * c + tid];
-        partials[(size_t)blockIdx.x * c + tid] = t;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (v1 > v0) {
+        const size_t k0 = (size_t)v0 * G8, k1 = (size_t)v1 * G8;
+        for (size_t k = k0 + tid; k < k1; k += 256) {
+            const u32x4 w = ld16(g + k * 8);
+            s[0] += bf2f(w.x), s[1] += bf2f(w.x >> 16), s[2] += bf2f(w.y), s[3] += bf2f(w.y >> 16);
+            s[4] += bf2f(w.z), s[5] += bf2f(w.z >> 16), s[6] += bf2f(w.w), s[7] += bf2f(w.w >> 16);
+        }
     }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[tid][e] = s[e];
+    __syncthreads();
+    if (tid < C) {
+        const int grp = tid / 8, e = tid % 8;
+        float t = 0.f;
+        for (int k = grp; k < 256; k += G8) t += red[k][e];
+        partials[(size_t)blockIdx.x * C + tid] = t;
+    }
+}
+
+// First level of the partial-sum reduction: group blockIdx.y of `groups`
+// sums its share of the slices (in slice order).
+__global__ __launch_bounds__(256) void reduce1_k(const float *P, int nslice, int n, int stride, int groups,
+                                                 float *out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int per = (nslice + groups - 1) / groups;
+    const int j0 = blockIdx.y * per, j1 = min(j0 + per, nslice);
+    float s = 0.f;
+    for (int j = j0; j < j1; ++j) s += P[(size_t)j * stride + i];
+    out[(size_t)blockIdx.y * n + i] = s;
 }
 
 __global__ __launch_bounds__(256) void reduce_k(const float *P, int nslice, int n, int stride, int cinp,
@@ -565,6 +895,56 @@ hipError_t conv_launch(hipStream_t s, const ConvArgs &a) {
     return hipGetLastError();
 }
 
+template <int COUT, int CC, int RY, int RZ>
+hipError_t lds_launch(hipStream_t s, const ConvArgs &a) {
+    const int nb = ((a.onx + 15) / 16) * ((a.ony + RY - 1) / RY) * ((a.onz + RZ - 1) / RZ);
+    conv3_lds_k<COUT, CC, RY, RZ><<<nb, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int COUT, int CC, int RY, int RZ>
+hipError_t reg_launch(hipStream_t s, const ConvArgs &a) {
+    constexpr int WM = COUT >= 64 ? 4 : COUT / 16;
+    const int nb = ((a.onx + 15) / 16) * ((a.ony + RY - 1) / RY) * ((a.onz + RZ - 1) / RZ);
+    conv3_reg_k<COUT, CC, RY, RZ, WM><<<nb, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// Tile: 16 x 4 x 4 cells on grids with enough tiles to fill the chip,
+// 16 x 2 x 2 on small grids.  Up to 64 output channels the weights of a
+// wave fit in registers (conv3_reg_k); 128 takes conv3_lds_k.
+template <int COUT, int CC>
+hipError_t lds_tile(hipStream_t s, const ConvArgs &a) {
+    const long tiles44 = (long)((a.onx + 15) / 16) * ((a.ony + 3) / 4) * ((a.onz + 3) / 4);
+    if constexpr (COUT <= 64) {
+        if (tiles44 >= 1024) return reg_launch<COUT, CC, 4, 4>(s, a);
+        return reg_launch<COUT, CC, 2, 2>(s, a);
+    } else {
+        if (tiles44 >= 1024) return lds_launch<COUT, CC, 4, 4>(s, a);
+        return lds_launch<COUT, CC, 2, 2>(s, a);
+    }
+}
+
+template <int COUT>
+hipError_t lds_cc(hipStream_t s, const ConvArgs &a) {
+    const int cin = a.ca + a.cb;
+    if (cin == 8) return lds_tile<COUT, 8>(s, a);
+    if (cin == 16) return lds_tile<COUT, 16>(s, a);
+    if (cin % 32 == 0 && a.ca % 8 == 0) return lds_tile<COUT, 32>(s, a);
+    return hipErrorInvalidValue;
+}
+
+hipError_t conv_same3(hipStream_t s, const ConvArgs &a) {
+    if (a.inx != a.onx || a.iny != a.ony || a.inz != a.onz) return hipErrorInvalidValue;
+    switch (a.da + a.db) {
+        case 16: return lds_cc<16>(s, a);
+        case 32: return lds_cc<32>(s, a);
+        case 64: return lds_cc<64>(s, a);
+        case 128: return lds_cc<128>(s, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int GEOM>
 hipError_t conv_geom(hipStream_t s, const ConvArgs &a) {
     switch (a.da + a.db) {
@@ -574,6 +954,20 @@ hipError_t conv_geom(hipStream_t s, const ConvArgs &a) {
         case 128: return conv_launch<GEOM, 128>(s, a);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t wgrad_same3(hipStream_t s, const WgradArgs &a) {
+    const int cin = a.ca + a.cb;
+    const int ntiles = ((a.gnx + 15) / 16) * ((a.gny + 3) / 4) * ((a.gnz + 3) / 4);
+    const int tpb = (ntiles + a.nslice - 1) / a.nslice;
+    dim3 grid((cin + 15) / 16, a.nslice);
+    switch (a.cout) {
+        case 16: wgrad3_lds_k<1><<<grid, 256, 0, s>>>(a, tpb); break;
+        case 32: wgrad3_lds_k<2><<<grid, 256, 0, s>>>(a, tpb); break;
+        case 64: wgrad3_lds_k<4><<<grid, 256, 0, s>>>(a, tpb); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <int GEOM>
@@ -597,15 +991,17 @@ hipError_t wgrad_geom(hipStream_t s, const WgradArgs &a) {
 hipError_t conv(hipStream_t s, int geom, const ConvArgs &a) {
     if ((a.ca & 7) || (a.cb & 7) || (a.da & 3) || (a.db & 3)) return hipErrorInvalidValue;
     switch (geom) {
-        case G_SAME3: return conv_geom<G_SAME3>(s, a);
+        case G_SAME3: return conv_same3(s, a);
         case G_DOWN2: return conv_geom<G_DOWN2>(s, a);
         case G_UP2: return conv_geom<G_UP2>(s, a);
         default: return hipErrorInvalidValue;
     }
 }
 
-int wgrad_slices(int geom, int qcells, int cin, int cout, size_t max_floats) {
-    const int nsteps = (qcells + 31) / 32;
+int wgrad_slices(int geom, int qx, int qy, int qz, int cin, int cout, size_t max_floats) {
+    // work units: 16x4x4 tiles (SAME3) or steps of 32 cells
+    const int nsteps = geom == G_SAME3 ? ((qx + 15) / 16) * ((qy + 3) / 4) * ((qz + 3) / 4)
+                                       : (int)(((size_t)qx * qy * qz + 31) / 32);
     const int ctiles = (cin + 15) / 16;
     int ns = 1024 / ctiles;
     if (ns < 1) ns = 1;
@@ -620,7 +1016,7 @@ int wgrad_slices(int geom, int qcells, int cin, int cout, size_t max_floats) {
 hipError_t wgrad(hipStream_t s, int geom, const WgradArgs &a) {
     if ((a.ca & 7) || (a.cb & 7) || a.nslice < 1) return hipErrorInvalidValue;
     switch (geom) {
-        case G_SAME3: return wgrad_geom<G_SAME3>(s, a);
+        case G_SAME3: return wgrad_same3(s, a);
         case G_DOWN2: return wgrad_geom<G_DOWN2>(s, a);
         case G_UP2: return wgrad_geom<G_UP2>(s, a);
         default: return hipErrorInvalidValue;
@@ -628,15 +1024,24 @@ hipError_t wgrad(hipStream_t s, int geom, const WgradArgs &a) {
 }
 
 hipError_t bias_grad(hipStream_t s, const bf16_t *g, size_t cells, int c, float *partials, int nslice) {
-    if (c <= 0 || 256 % c) return hipErrorInvalidValue;
     const unsigned cps = (unsigned)((cells + nslice - 1) / nslice);
-    bias_grad_k<<<nslice, 256, 0, s>>>(g, (unsigned)cells, c, partials, cps);
+    switch (c) {
+        case 16: bias_grad_k<16><<<nslice, 256, 0, s>>>(g, (unsigned)cells, partials, cps); break;
+        case 32: bias_grad_k<32><<<nslice, 256, 0, s>>>(g, (unsigned)cells, partials, cps); break;
+        case 64: bias_grad_k<64><<<nslice, 256, 0, s>>>(g, (unsigned)cells, partials, cps); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 hipError_t reduce_partials(hipStream_t s, const float *partials, int nslice, int n, int stride, int cinp,
-                           int cin_real, float *out, int accumulate) {
-    reduce_k<<<nblk(n), 256, 0, s>>>(partials, nslice, n, stride, cinp, cin_real, out, accumulate);
+                           int cin_real, float *out, int accumulate, float *work) {
+    if (nslice > kReduceGroups && work) {
+        reduce1_k<<<dim3(nblk(n), kReduceGroups), 256, 0, s>>>(partials, nslice, n, stride, kReduceGroups, work);
+        reduce_k<<<nblk(n), 256, 0, s>>>(work, kReduceGroups, n, n, cinp, cin_real, out, accumulate);
+    } else {
+        reduce_k<<<nblk(n), 256, 0, s>>>(partials, nslice, n, stride, cinp, cin_real, out, accumulate);
+    }
     return hipGetLastError();
 }
 

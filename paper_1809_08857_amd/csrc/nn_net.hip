@@ -123,7 +123,7 @@ struct mgl_net {
     bf16_t *x8 = nullptr;
     double *sigma = nullptr;       // [0]: max|s| (FP64)
     unsigned *maxbits = nullptr;   // 3 float bit patterns
-    float *wpart = nullptr, *bpart = nullptr, *hpart = nullptr;
+    float *wpart = nullptr, *bpart = nullptr, *hpart = nullptr, *rwork = nullptr;
     float *lossacc = nullptr;
     int wslices[kLayers] = {}, bslices[kLayers] = {};
     double scale[3] = {1.0, 1.0, 1.0};
@@ -209,8 +209,8 @@ int head_backward(mgl_net *n, const float *t, bool want_grad) {
     CK(head_train(st, n->act[19], n0, n->theta + kOff.w[kHeadLayer], n->theta + kOff.b[kHeadLayer], t, n->gact[19],
                   n->hpart));
     if (want_grad)  // dW[3][16] then db[3]: contiguous in the parameter vector
-        CK(reduce_partials(st, n->hpart, nb, 51, kHeadRed, 51, 51, n->grad + kOff.w[kHeadLayer], 1));
-    CK(reduce_partials(st, n->hpart + 51, nb, 1, kHeadRed, 1, 1, n->lossacc, 1));
+        CK(reduce_partials(st, n->hpart, nb, 51, kHeadRed, 51, 51, n->grad + kOff.w[kHeadLayer], 1, n->rwork));
+    CK(reduce_partials(st, n->hpart + 51, nb, 1, kHeadRed, 1, 1, n->lossacc, 1, n->rwork));
     return MG_OK;
 }
 
@@ -236,10 +236,10 @@ int backward(mgl_net *n) {
         const int cinp = ca + cb;
         const int T = taps(L);
         const int cnt = L.cout * T * cinp;
-        CK(reduce_partials(st, n->wpart, w.nslice, cnt, cnt, cinp, L.cin, n->grad + kOff.w[l], 1));
+        CK(reduce_partials(st, n->wpart, w.nslice, cnt, cnt, cinp, L.cin, n->grad + kOff.w[l], 1, n->rwork));
         // bias gradient
         CK(bias_grad(st, n->gact[l], n->cells(L.lout), L.cout, n->bpart, n->bslices[l]));
-        CK(reduce_partials(st, n->bpart, n->bslices[l], L.cout, L.cout, L.cout, L.cout, n->grad + kOff.b[l], 1));
+        CK(reduce_partials(st, n->bpart, n->bslices[l], L.cout, L.cout, L.cout, L.cout, n->grad + kOff.b[l], 1, n->rwork));
         if (L.inA == kInput) continue;
         // input gradient, masked by the ReLU of each producing layer
         ConvArgs a{};
@@ -300,7 +300,7 @@ int mgl_create(const mgl_desc *d, void *hip_stream, mgl_net **out) {
     n->m = (float *)A(P * 4);
     n->v = (float *)A(P * 4);
     n->grad = (float *)A(P * 4);
-    size_t wmax = 0;
+    size_t wmax = 0, nmax = 52;
     int bmax = 0;
     for (int l = 0; l < kLayers; ++l) {
         const LayerDef &L = kNet[l];
@@ -311,9 +311,11 @@ int mgl_create(const mgl_desc *d, void *hip_stream, mgl_net **out) {
         if (l > 0) n->wd[l] = (bf16_t *)A((size_t)L.cout * T * L.cin * 2);
         n->act[l] = (bf16_t *)A(n->cells(L.lout) * L.cout * 2);
         n->gact[l] = (bf16_t *)A(n->cells(L.lout) * L.cout * 2);
-        const size_t qcells = L.geom == G_UP2 ? n->cells(L.lin) : n->cells(L.lout);
-        n->wslices[l] = wgrad_slices(L.geom, (int)qcells, cinp, L.cout, kMaxPartialFloats);
+        int qx, qy, qz;
+        n->dims(L.geom == G_UP2 ? L.lin : L.lout, qx, qy, qz);
+        n->wslices[l] = wgrad_slices(L.geom, qx, qy, qz, cinp, L.cout, kMaxPartialFloats);
         wmax = std::max(wmax, (size_t)n->wslices[l] * L.cout * T * cinp);
+        nmax = std::max(nmax, (size_t)L.cout * T * cinp);
         size_t bs = n->cells(L.lout) / 2048;
         n->bslices[l] = (int)std::min<size_t>(1024, std::max<size_t>(1, bs));
         bmax = std::max(bmax, n->bslices[l] * L.cout);
@@ -325,6 +327,7 @@ int mgl_create(const mgl_desc *d, void *hip_stream, mgl_net **out) {
     n->wpart = (float *)A(wmax * 4);
     n->bpart = (float *)A((size_t)bmax * 4);
     n->hpart = (float *)A((size_t)head_train_blocks(n->cells(0)) * kHeadRed * 4);
+    n->rwork = (float *)A(nmax * kReduceGroups * 4);
     if (!ok) {
         mgl_destroy(n);
         return set_err(MG_ENOMEM, "mgl_create: device allocation failed");

@@ -72,24 +72,54 @@ def _close_bf16(got, ref, what):
     assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} off, worst {np.abs(got - ref).max():.3e}"
 
 
-@pytest.fixture(scope="module")
-def case():
-    """One forward + backward (gradients only) on a ragged 16x8x24 grid."""
-    shape = (24, 8, 16)  # [z][y][x]: levels 24x8x16 .. 3x1x2
-    theta = _params(11)
-    s = _source(shape, 3)
-    rng = np.random.default_rng(4)
+def _run_case(shape, pseed, sseed, tseed):
+    theta = _params(pseed)
+    s = _source(shape, sseed)
+    rng = np.random.default_rng(tseed)
     target = rng.standard_normal(shape + (3,)) * 0.1
     net = L.mgl_create(shape[2], shape[1], shape[0])
     L.mgl_set_params(net, theta.astype(np.float32))
     sd = dev(s)
     td = torch.from_numpy(target.astype(np.float32)).cuda()
     loss = L.mgl_train_step(net, [sd], [td])
-    out = dict(theta=theta, s=s, target=target, loss=loss, acts=_gpu_acts(net),
-               gacts={n: L.mgl_read_tensor(net, 1, i).astype(np.float64) for i, n in enumerate(NAMES[:-1])},
-               grads=L.mgl_get_grads(net).astype(np.float64), net=net)
+    return dict(theta=theta, s=s, target=target, loss=loss, acts=_gpu_acts(net),
+                gacts={n: L.mgl_read_tensor(net, 1, i).astype(np.float64) for i, n in enumerate(NAMES[:-1])},
+                grads=L.mgl_get_grads(net).astype(np.float64), net=net)
+
+
+@pytest.fixture(scope="module")
+def case():
+    """One forward + backward (gradients only) on a ragged 16x8x24 grid
+    (levels 16x8x24 .. 2x1x3: small tiles, partial tiles on every axis)."""
+    out = _run_case((24, 8, 16), 11, 3, 4)
     yield out
-    L.mgl_destroy(net)
+    L.mgl_destroy(out["net"])
+
+
+@pytest.fixture(scope="module")
+def case_big():
+    """128x64x32: the finest level takes the large-tile path."""
+    out = _run_case((32, 64, 128), 12, 5, 6)
+    yield out
+    L.mgl_destroy(out["net"])
+
+
+BIG_LAYERS = ["e0a", "e0b", "d0", "u0", "c0a", "c0b"]
+
+
+@pytest.mark.parametrize("name", BIG_LAYERS)
+def test_forward_layer_large_tiles(case_big, name):
+    test_forward_layer(case_big, name)
+
+
+@pytest.mark.parametrize("name", ["e0a", "e0b", "u0", "c0a"])
+def test_input_gradient_large_tiles(case_big, name):
+    test_input_gradient(case_big, name)
+
+
+@pytest.mark.parametrize("name", ["e0a", "e0b", "c0a", "c0b", "head"])
+def test_weight_gradient_large_tiles(case_big, name):
+    test_weight_gradient(case_big, name)
 
 
 def test_input_scaling(case):
