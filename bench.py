@@ -16,7 +16,7 @@ Other workloads (--workload):
              each (256 solves), FP32-in-FP64 refinement: one fused batched
              call (captured graphs) against a loop of single solves
   learned128 the three photon-group solves at 128^3 from the learned initial
-             guess against the zero guess (needs trained weights)
+             guess (U-net inference included) against the zero guess
 
 Prints one JSON line: solves/s (value), DoF/s, ms per step, the roofline of
 the dominant kernel (the finest-level red-black smoother of the first solve,
@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="streamer256", choices=["streamer256", "mixed512", "batched64", "learned128"])
+    ap.add_argument("--workload", default="streamer256",
+                    choices=["streamer256", "mixed512", "batched64", "learned128", "copycal"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16"])
@@ -73,6 +74,41 @@ def cpu_baseline(n: int, seed: int):
                       f"to rel. residual 1e-10: {cycles} cycles, {dt:.1f} s"}
 
 
+# HBM traffic of the smoother measured by rocprofv3 counters (FETCH_SIZE,
+# WRITE_SIZE, scaled by a copy-kernel calibration); valid only while the
+# smoother's sources hash to the value recorded with the counters.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rbgs_col_k_streamer256_traffic.txt")
+SMOOTHER_SOURCES = ["paper_1809_08857_amd/csrc/mg_stencil.cuh", "paper_1809_08857_amd/csrc/mg_launch.cuh",
+                    "paper_1809_08857_amd/csrc/mg_kern_f64.hip", "paper_1809_08857_amd/csrc/mg_internal.h"]
+
+
+def smoother_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in SMOOTHER_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None (no summary, another kernel, or sources changed since)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256_16") != smoother_source_hash() or kv.get("kernel") != kernel:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def roofline(ctx):
     from paper_1809_08857_amd import mg
     launches, kern_ms, kname, bytes_per_launch = mg.mg_timing_read(ctx)
@@ -81,9 +117,23 @@ def roofline(ctx):
     avg_s = kern_ms / launches / 1e3
     achieved = bytes_per_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname), "kernel": kname,
             "avg_us": round(avg_s * 1e6, 2), "launches": launches,
             "algorithmic_bytes_per_launch": bytes_per_launch}
+
+
+def copy_calibration(args):
+    """A plain device-to-device copy of a known size (torch's copy kernel),
+    to calibrate the FETCH_SIZE / WRITE_SIZE counters against bytes."""
+    import torch
+    nbytes = 512 << 20
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(max(1, args.steps)):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"workload": "copycal", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+            "copies": max(1, args.steps)}
 
 
 def make_solvers(probs, precision, autotune=False):
@@ -154,6 +204,109 @@ def base_line(args, value, ms, cfg, dtype, roof, dof=None):
         "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": cfg,
         "dof_per_s": None if dof is None else round(dof, 1), "roofline": roof,
     }
+
+
+def unet_flops(n: int) -> float:
+    """Multiply-adds x 2 of one forward pass of the U-net at n^3 (the 1x1
+    head included; the input layer counted at its one real channel)."""
+    layers = [  # (kind, cin, cout, level of the output grid)
+        ("c", 1, 16, 0), ("c", 16, 16, 0), ("d", 16, 32, 1), ("c", 32, 32, 1), ("c", 32, 32, 1),
+        ("d", 32, 64, 2), ("c", 64, 64, 2), ("c", 64, 64, 2), ("d", 64, 64, 3), ("c", 64, 64, 3),
+        ("c", 64, 64, 3), ("u", 64, 64, 2), ("c", 128, 64, 2), ("c", 64, 64, 2), ("u", 64, 32, 1),
+        ("c", 64, 32, 1), ("c", 32, 32, 1), ("u", 32, 16, 0), ("c", 32, 16, 0), ("c", 16, 16, 0),
+        ("h", 16 + 27, 3, 0)]
+    taps = {"c": 27, "d": 8, "u": 1, "h": 1}
+    return sum(2.0 * taps[k] * ci * co * (n >> l) ** 3 for k, ci, co, l in layers)
+
+
+def learned_line(args):
+    """Learned initial guess at n^3: per step one test source s, the U-net
+    prediction of the three photon-group fields, then the three FP64
+    solves from those guesses (fallback to zero judged by the engine),
+    against the three solves from zero.  Sources are resident on the GPU."""
+    import numpy as np
+    import torch
+    from synth.problems import filament_source
+    from paper_1809_08857_amd import learned as L
+    from paper_1809_08857_amd import mg
+    from paper_1809_08857_amd.train_guess import helmholtz_solvers, TEST_SEED0
+    n = args.n or 128
+    wpath = os.path.join(L.WEIGHTS_DIR, f"unet{n}.mglw")
+    if not os.path.exists(wpath):
+        raise SystemExit(f"no trained weights at {wpath} (train them with paper_1809_08857_amd.train_guess)")
+    prec = args.precision or "fp64"
+    solvers, k2 = helmholtz_solvers(n, prec)
+    net = L.mgl_create(n, n, n)
+    L.mgl_load(net, wpath)
+    nsrc = 8
+    srcs = [torch.from_numpy(filament_source(n, n, n, TEST_SEED0 + k)).cuda() for k in range(nsrc)]
+    xs = [torch.zeros((n, n, n), dtype=torch.float64, device="cuda") for _ in range(3)]
+    it = {"k": 0}
+    stats = {"plain": [], "learned": [], "fell_back": 0}
+
+    def plain_step():
+        s = srcs[it["k"] % nsrc]
+        it["k"] += 1
+        cyc = []
+        for sv, x in zip(solvers, xs):
+            rc, st = sv.solve(s, x)
+            if rc != mg.MG_OK:
+                raise RuntimeError(f"plain solve failed: {st.as_dict()}")
+            cyc.append(st.cycles)
+        stats["plain"].append(cyc)
+
+    def learned_step():
+        s = srcs[it["k"] % nsrc]
+        it["k"] += 1
+        L.mgl_predict(net, s, k2, xs)
+        cyc = []
+        for sv, x in zip(solvers, xs):
+            rc, st = sv.solve(s, x, mg.MG_GUESS)
+            if rc != mg.MG_OK:
+                raise RuntimeError(f"learned solve failed: {st.as_dict()}")
+            cyc.append(st.cycles)
+            stats["fell_back"] += st.fell_back
+        stats["learned"].append(cyc)
+
+    dt_p, _, _ = timed(plain_step, args.steps, args.warmup)
+    stats["plain"] = stats["plain"][args.warmup:]
+    stats["fell_back"] = 0
+    dt_l, _, _ = timed(learned_step, args.steps, args.warmup)
+    learned_cycles = list(stats["learned"][args.warmup:])
+    nfb = stats["fell_back"]
+    _, _, roof = timed(learned_step, 2, 0, solvers[0].ctx)  # the smoother's roofline, timed apart
+    stats["fell_back"], stats["learned"] = nfb, learned_cycles
+    # inference alone
+    gs = [torch.empty_like(xs[0]) for _ in range(3)]
+    for _ in range(3):
+        L.mgl_predict(net, srcs[0], k2, gs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        L.mgl_predict(net, srcs[0], k2, gs)
+    torch.cuda.synchronize()
+    inf_ms = (time.perf_counter() - t0) / reps * 1e3
+    cp = np.mean(np.array(stats["plain"]), axis=0)
+    cl = np.mean(np.array(stats["learned"]), axis=0)
+    value = 3 * args.steps / dt_l
+    plain_value = 3 * args.steps / dt_p
+    fl = unet_flops(n)
+    cfg = {"workload": f"3 photon-group solves (kappa h = 0.05, 0.3, 1.5) at {n}^3 per step, FP64 V-cycles to "
+                       f"rel. residual 1e-10, started from the U-net guess (fallback to zero judged after "
+                       f"pre-smoothing); sources: filament seeds {TEST_SEED0}..{TEST_SEED0 + nsrc - 1}",
+           "grid": [n, n, n], "solves_per_step": 3, "precision": prec,
+           "plain_solves_per_s": round(plain_value, 3), "speedup_vs_plain": round(value / plain_value, 4),
+           "cycles_per_solve_plain": [round(float(c), 2) for c in cp],
+           "cycles_per_solve_learned": [round(float(c), 2) for c in cl],
+           "cycles_saved_per_step": round(float(cp.sum() - cl.sum()), 2),
+           "fallbacks": stats["fell_back"], "inference_ms": round(inf_ms, 3),
+           "inference_tflops": round(fl / (inf_ms * 1e-3) / 1e12, 1), "inference_gflop": round(fl / 1e9, 1)}
+    out = base_line(args, value, dt_l / args.steps * 1e3, cfg, "f64+bf16", roof, value * n**3)
+    for sv in solvers:
+        sv.close()
+    L.mgl_destroy(net)
+    return out
 
 
 def main():
@@ -228,9 +381,10 @@ def main():
         out["dof_per_s"] = round(cells * args.steps / dt_b, 1)
         for s in solvers:
             s.close()
+    elif args.workload == "copycal":
+        out = copy_calibration(args)
     else:
-        from paper_1809_08857_amd import learned
-        out = learned.bench_line(args)
+        out = learned_line(args)
     print(json.dumps(out), flush=True)
 
 

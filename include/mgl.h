@@ -18,17 +18,21 @@
  *   level 3 (n/8)  b3a conv3 64->64, b3b conv3 64->64, u2 up2 64->64
  *   level 2        c2a conv3 (64+64)->64, c2b conv3 64->64, u1 up2 64->32
  *   level 1        c1a conv3 (32+32)->32, c1b conv3 32->32, u0 up2 32->16
- *   level 0        c0a conv3 (16+16)->16, c0b conv3 16->16, head 1x1 16->3
+ *   level 0        c0a conv3 (16+16)->16, c0b conv3 16->16,
+ *                  head: linear map of (c0b's 16 channels, x at the 27 taps
+ *                  of the cell) -> 3
  * conv3 = 3x3x3 cross-correlation with zero padding, down2 = 2x2x2
  * stride-2 cross-correlation, up2 = its transpose, (a+b) = concatenation
  * (upsampled channels first); every layer but the head adds a bias and
  * applies ReLU.  Input x = s / max|s|; outputs y_i are in units of scale_i:
- * kappa_i^2 Psi_i = max|s| * scale_i * y_i.
+ * kappa_i^2 Psi_i = max|s| * scale_i * y_i.  The head's direct 3x3x3 path
+ * from x (FP32) carries the local part of the fields past the bfloat16
+ * network.
  *
  * Parameters: one flat FP32 vector, the layers in the order above, each as
  * W[cout][tap][cin] (C order; taps t = (dz+1)*9 + (dy+1)*3 + (dx+1) for
  * conv3 with offset (dz,dy,dx), t = tz*4 + ty*2 + tx for down2/up2; the
- * head is W[3][16]) followed by b[cout].  mgl_num_params() gives its
+ * head is W[3][16 + 27]) followed by b[cout].  mgl_num_params() gives its
  * length.  The FP32 vector is the master copy; the kernels use bfloat16
  * copies of the weights (FP32 biases and head).
  *

@@ -21,18 +21,22 @@ The paper itself has no network; its architecture is fixed here:
     level 1        c1a conv3 64->32, c1b conv3 32->32
                    u0  up2 32->16, concat skip0
     level 0        c0a conv3 32->16, c0b conv3 16->16
-                   head 1x1 16->3 (no activation)
+                   head: linear map of (c0b's 16 channels, the 27 values
+                   of the scaled input x around the cell) -> 3
 
 Every layer except the head adds a bias and applies ReLU.  conv3 is a
 3x3x3 cross-correlation with zero padding; down2 is a 2x2x2 stride-2
 cross-correlation; up2 is its transpose (each fine cell 2V+t receives
-W[:, t, :] @ x[V]).  Concatenation puts the upsampled channels first.
+W[:, t, :] @ x[V]).  Concatenation puts the upsampled channels first.  The
+head's direct path from x (a 3x3x3 stencil, zero padding) lets the local
+part of the screened fields bypass the network.
 
 Tensors are channels-last ``[z][y][x][c]``.  Weights of a layer are
 ``W[cout][tap][cin]`` with taps ``t = (dz+1)*9 + (dy+1)*3 + (dx+1)`` for
 conv3 (offset (dz,dy,dx)) and ``t = tz*4 + ty*2 + tx`` for down2/up2; the
-head is ``W[3][16]``.  The flat parameter vector lists the layers in the
-order above, each as W (C order) followed by b.
+head is ``W[3][16 + 27]`` (c0b channels, then x at taps 0..26).  The flat
+parameter vector lists the layers in the order above, each as W (C order)
+followed by b.
 
 Input and output scaling: x = s / max|s|; the network output y_i is in
 units of ``scale_i`` so that the predicted field is
@@ -53,7 +57,7 @@ LAYERS: List[Tuple[str, str, int, int]] = [
     ("b3a", "conv3", 64, 64), ("b3b", "conv3", 64, 64), ("u2", "up2", 64, 64),
     ("c2a", "conv3", 128, 64), ("c2b", "conv3", 64, 64), ("u1", "up2", 64, 32),
     ("c1a", "conv3", 64, 32), ("c1b", "conv3", 32, 32), ("u0", "up2", 32, 16),
-    ("c0a", "conv3", 32, 16), ("c0b", "conv3", 16, 16), ("head", "head", 16, 3),
+    ("c0a", "conv3", 32, 16), ("c0b", "conv3", 16, 16), ("head", "head", 16 + 27, 3),
 ]
 NTAPS = {"conv3": 27, "down2": 8, "up2": 8}
 
@@ -194,6 +198,12 @@ def up2_wgrad(x: np.ndarray, gy: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     return gW, gy.reshape(-1, co).sum(axis=0)
 
 
+def head_features(a: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """Input of the head: c0b's channels, then x at the 27 taps of the cell."""
+    taps = [_shifted(x, dz, dy, dx) for dz, dy, dx in _offsets3()]
+    return np.concatenate([a] + taps, axis=3)
+
+
 _FWD = {"conv3": conv3, "down2": down2, "up2": up2}
 _DGRAD = {"conv3": conv3_dgrad, "down2": down2_dgrad, "up2": up2_dgrad}
 _WGRAD = {"conv3": conv3_wgrad, "down2": down2_wgrad, "up2": up2_wgrad}
@@ -227,12 +237,14 @@ def forward(theta: np.ndarray, x: np.ndarray, rnd=None) -> Tuple[np.ndarray, Dic
     check_shape(x.shape[:3])
     p = unflatten(theta)
     keep = rnd if rnd is not None else (lambda a: a)
-    acts = {"x": keep(x.reshape(x.shape[:3] + (1,)).astype(np.float64))}
+    x1 = x.reshape(x.shape[:3] + (1,)).astype(np.float64)
+    acts = {"x": keep(x1), "x_head": x1}
     for name, ins in GRAPH:
         inp = np.concatenate([acts[i] for i in ins], axis=3) if len(ins) > 1 else acts[ins[0]]
         W, b = p[name]
         if KIND[name] == "head":
-            acts[name] = inp @ W.T + b
+            acts["head_in"] = head_features(inp, acts["x_head"])
+            acts[name] = acts["head_in"] @ W.T + b
         else:
             acts[name] = keep(np.maximum(_FWD[KIND[name]](inp, W, b), 0.0))
     return acts["head"], acts
@@ -260,8 +272,15 @@ def loss_and_grad(theta: np.ndarray, x: np.ndarray, target: np.ndarray,
         W, _ = p[name]
         kind = KIND[name]
         if kind == "head":
-            grads[name] = (g.reshape(-1, 3).T @ inp.reshape(-1, inp.shape[3]), g.reshape(-1, 3).sum(axis=0))
-            gin = g @ W
+            hin = acts["head_in"]
+            grads[name] = (g.reshape(-1, 3).T @ hin.reshape(-1, hin.shape[3]), g.reshape(-1, 3).sum(axis=0))
+            c16 = inp.shape[3]
+            gin = g @ W[:, :c16]
+            # the direct path: x at tap t of cell v feeds y(v)
+            gx = np.zeros(acts["x"].shape)
+            for t, (dz, dy, dx) in enumerate(_offsets3()):
+                gx += _shifted(g @ W[:, c16 + t:c16 + t + 1], -dz, -dy, -dx)
+            g_act["x"] = g_act["x"] + gx if "x" in g_act else gx
         else:
             g = g * (acts[name] > 0.0)   # through the ReLU of this layer
             grads[name] = _WGRAD[kind](inp, g)

@@ -90,16 +90,26 @@ hipError_t maxabs(hipStream_t s, const double *x, size_t n, double *out);
 // x8[v][0] = bf16(s[v] / *sigma) (1 if *sigma == 0), x8[v][1..7] = 0.
 hipError_t prep_input(hipStream_t s, const double *src, size_t n, const double *sigma, bf16_t *x8);
 
-// Head (1x1 convolution 16 -> 3, FP32 weights wh[3][16], bias bh[3]).
+// Head: y = wh f + bh with FP32 weights wh[3][kHeadIn], bias bh[3], and
+// features f = (16 channels of a, then x = s / sigma at the 27 taps of the
+// cell, FP32, zero outside the grid).
+constexpr int kHeadIn = 16 + 27;
+constexpr int kHeadRed = 3 * kHeadIn + 3 + 1;  // dW, db, sum of squared errors
 // Prediction: guess_i[v] = sigma * coef_i * y_i[v]   (FP64 out)
-hipError_t head_predict(hipStream_t s, const bf16_t *a, size_t n, const float *wh, const float *bh,
-                        const double *sigma, const double coef[3], double *g0, double *g1, double *g2);
+hipError_t head_predict(hipStream_t s, const bf16_t *a, const double *src, int nx, int ny, int nz, const float *wh,
+                        const float *bh, const double *sigma, const double coef[3], double *g0, double *g1,
+                        double *g2);
 // Training: mean-squared error against t[v][3]; writes the masked input
-// gradient ga[v][16] (bf16) and per-block partials of (dW[3][16], db[3],
-// sum of squared errors) = 52 floats per block.
+// gradient ga[v][16] (bf16) and per-block partials of (dW, db, sum of
+// squared errors), kHeadRed floats per block.
 int head_train_blocks(size_t n);
-hipError_t head_train(hipStream_t s, const bf16_t *a, size_t n, const float *wh, const float *bh,
-                      const float *t, bf16_t *ga, float *partials);
+hipError_t head_train(hipStream_t s, const bf16_t *a, const double *src, int nx, int ny, int nz, const float *wh,
+                      const float *bh, const double *sigma, const float *t, bf16_t *ga, float *partials);
+// First layer (1 -> 16 channels, 3x3x3): out = ReLU(b + W x) with x the
+// bfloat16-rounded s / sigma and W the bfloat16 weights wf[16][27][8]
+// (channel 0 used), FP32 arithmetic.
+hipError_t conv_in(hipStream_t s, const double *src, int nx, int ny, int nz, const double *sigma, const bf16_t *wf,
+                   const float *bias, bf16_t *out);
 
 // Targets: t[v][i] = kappa2_i psi_i[v] / (*sigma * scale_i) (FP32), and
 // max_i |t| into maxbits[i] (as float bit patterns; must start at 0).

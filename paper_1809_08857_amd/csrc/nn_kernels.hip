@@ -739,22 +739,47 @@ struct Coef3 {
     double c[3];
 };
 
-__global__ __launch_bounds__(256) void head_predict_k(const bf16_t *a, size_t n, const float *wh, const float *bh,
-                                                      const double *sigma, Coef3 coef, double *g0, double *g1,
-                                                      double *g2) {
+struct Grid3 {
+    int nx, ny, nz;
+};
+
+// Features of the head at cell v: c0b's 16 channels, then the scaled input
+// x = s / sigma (FP32) at the 27 taps of the cell (0 outside the grid).
+__device__ __forceinline__ void head_features(const bf16_t *a, const double *s, double inv, Grid3 g, size_t v,
+                                              float (&f)[kHeadIn]) {
+    float x16[16];
+    load16ch(a, v, x16);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) f[c] = x16[c];
+    const int px = (int)(v % g.nx);
+    const size_t r = v / g.nx;
+    const int py = (int)(r % g.ny), pz = (int)(r / g.ny);
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const int qx = px + dx, qy = py + dy, qz = pz + dz;
+        const bool in = qx >= 0 && qx < g.nx && qy >= 0 && qy < g.ny && qz >= 0 && qz < g.nz;
+        f[16 + t] = in ? (float)(s[((size_t)qz * g.ny + qy) * g.nx + qx] * inv) : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void head_predict_k(const bf16_t *a, const double *s, Grid3 g, const float *wh,
+                                                      const float *bh, const double *sigma, Coef3 coef, double *g0,
+                                                      double *g1, double *g2) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
     const size_t v = blockIdx.x * 256ull + threadIdx.x;
     if (v >= n) return;
-    float x[16];
-    load16ch(a, v, x);
+    const double sg = *sigma > 0.0 ? *sigma : 1.0;
+    float f[kHeadIn];
+    head_features(a, s, 1.0 / sg, g, v, f);
     float y[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        float s = bh[i];
+        float acc = bh[i];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) s = fmaf(wh[i * 16 + c], x[c], s);
-        y[i] = s;
+        for (int c = 0; c < kHeadIn; ++c) acc = fmaf(wh[i * kHeadIn + c], f[c], acc);
+        y[i] = acc;
     }
-    const double sg = *sigma > 0.0 ? *sigma : 1.0;
     g0[v] = sg * coef.c[0] * (double)y[0];
     g1[v] = sg * coef.c[1] * (double)y[1];
     g2[v] = sg * coef.c[2] * (double)y[2];
@@ -766,60 +791,99 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-constexpr int kHeadRed = 52;  // dW[3][16], db[3], sum of squared errors
-
-__global__ __launch_bounds__(256) void head_train_k(const bf16_t *a, size_t n, const float *wh, const float *bh,
-                                                    const float *t, bf16_t *ga, float *partials) {
+__global__ __launch_bounds__(256) void head_train_k(const bf16_t *a, const double *s, Grid3 g, const float *wh,
+                                                    const float *bh, const double *sigma, const float *t, bf16_t *ga,
+                                                    float *partials) {
     __shared__ float red[4][kHeadRed];
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
     const size_t v = blockIdx.x * 256ull + threadIdx.x;
     const bool ok = v < n;
-    float x[16], gy[3], sse = 0.f;
+    float f[kHeadIn], gy[3], sse = 0.f;
     if (ok) {
-        load16ch(a, v, x);
+        const double sg = *sigma > 0.0 ? *sigma : 1.0;
+        head_features(a, s, 1.0 / sg, g, v, f);
         const float k = 2.f / (3.f * (float)n);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            float s = bh[i];
+            float acc = bh[i];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) s = fmaf(wh[i * 16 + c], x[c], s);
-            const float d = s - t[v * 3 + i];
+            for (int c = 0; c < kHeadIn; ++c) acc = fmaf(wh[i * kHeadIn + c], f[c], acc);
+            const float d = acc - t[v * 3 + i];
             sse = fmaf(d, d, sse);
             gy[i] = k * d;
         }
         unsigned w[8];
 #pragma unroll
         for (int c = 0; c < 16; c += 2) {
-            float q0 = wh[c] * gy[0] + wh[16 + c] * gy[1] + wh[32 + c] * gy[2];
-            float q1 = wh[c + 1] * gy[0] + wh[17 + c] * gy[1] + wh[33 + c] * gy[2];
-            if (!(x[c] > 0.f)) q0 = 0.f;
-            if (!(x[c + 1] > 0.f)) q1 = 0.f;
+            float q0 = wh[c] * gy[0] + wh[kHeadIn + c] * gy[1] + wh[2 * kHeadIn + c] * gy[2];
+            float q1 = wh[c + 1] * gy[0] + wh[kHeadIn + c + 1] * gy[1] + wh[2 * kHeadIn + c + 1] * gy[2];
+            if (!(f[c] > 0.f)) q0 = 0.f;
+            if (!(f[c + 1] > 0.f)) q1 = 0.f;
             w[c / 2] = f2bf(q0) | (f2bf(q1) << 16);
         }
         *reinterpret_cast<u32x4 *>(ga + v * 16) = u32x4{w[0], w[1], w[2], w[3]};
         *reinterpret_cast<u32x4 *>(ga + v * 16 + 8) = u32x4{w[4], w[5], w[6], w[7]};
     } else {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) x[c] = 0.f;
+        for (int c = 0; c < kHeadIn; ++c) f[c] = 0.f;
         gy[0] = gy[1] = gy[2] = 0.f;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            const float s = wave_sum(gy[i] * x[c]);
-            if (lane == 0) red[wave][i * 16 + c] = s;
+        for (int c = 0; c < kHeadIn; ++c) {
+            const float r = wave_sum(gy[i] * f[c]);
+            if (lane == 0) red[wave][i * kHeadIn + c] = r;
         }
-        const float s = wave_sum(gy[i]);
-        if (lane == 0) red[wave][48 + i] = s;
+        const float r = wave_sum(gy[i]);
+        if (lane == 0) red[wave][3 * kHeadIn + i] = r;
     }
-    const float s = wave_sum(sse);
-    if (lane == 0) red[wave][51] = s;
+    const float r = wave_sum(sse);
+    if (lane == 0) red[wave][kHeadRed - 1] = r;
     __syncthreads();
-    if (threadIdx.x < kHeadRed) {
-        const int k = threadIdx.x;
+    for (int k = threadIdx.x; k < kHeadRed; k += 256)
         partials[(size_t)blockIdx.x * kHeadRed + k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+}
+
+// First layer (1 input channel -> 16): direct FP32 products of the
+// bfloat16-rounded scaled input x = s / sigma at the 27 taps with the
+// bfloat16 weights wf[16][27][8] (channel 0), + bias, ReLU.  One thread per
+// cell; the neighbours of s come through the caches.
+__global__ __launch_bounds__(256) void conv_in_k(const double *s, Grid3 g, const double *sigma, const bf16_t *wf,
+                                                 const float *bias, bf16_t *out) {
+    __shared__ float w[16 * 27];
+    for (int i = threadIdx.x; i < 16 * 27; i += 256) w[i] = bf2f(wf[i * 8]);
+    __syncthreads();
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t v = blockIdx.x * 256ull + threadIdx.x;
+    if (v >= n) return;
+    const double sg = *sigma;
+    const int px = (int)(v % g.nx);
+    const size_t r = v / g.nx;
+    const int py = (int)(r % g.ny), pz = (int)(r / g.ny);
+    float xt[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const int qx = px + dx, qy = py + dy, qz = pz + dz;
+        const bool in = qx >= 0 && qx < g.nx && qy >= 0 && qy < g.ny && qz >= 0 && qz < g.nz;
+        const double sv = in ? s[((size_t)qz * g.ny + qy) * g.nx + qx] : 0.0;
+        xt[t] = bf2f(f2bf((float)(sg > 0.0 ? sv / sg : sv)));
     }
+    unsigned pk[8];
+#pragma unroll
+    for (int c = 0; c < 16; c += 2) {
+        float y0 = bias[c], y1 = bias[c + 1];
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+            y0 = fmaf(w[c * 27 + t], xt[t], y0);
+            y1 = fmaf(w[(c + 1) * 27 + t], xt[t], y1);
+        }
+        pk[c / 2] = f2bf(fmaxf(y0, 0.f)) | (f2bf(fmaxf(y1, 0.f)) << 16);
+    }
+    *reinterpret_cast<u32x4 *>(out + v * 16) = u32x4{pk[0], pk[1], pk[2], pk[3]};
+    *reinterpret_cast<u32x4 *>(out + v * 16 + 8) = u32x4{pk[4], pk[5], pk[6], pk[7]};
 }
 
 __global__ __launch_bounds__(256) void make_target_k(const double *p0, const double *p1, const double *p2, size_t n,
@@ -911,12 +975,14 @@ hipError_t reg_launch(hipStream_t s, const ConvArgs &a) {
 }
 
 // Tile: 16 x 4 x 4 cells on grids with enough tiles to fill the chip,
-// 16 x 2 x 2 on small grids.  Up to 64 output channels the weights of a
-// wave fit in registers (conv3_reg_k); 128 takes conv3_lds_k.
+// 16 x 2 x 2 on small grids.  With 32 or 64 output channels the weights of
+// a wave stay in registers (conv3_reg_k); with 16 (one channel tile, the
+// weights a small L1-resident set) and 128 conv3_lds_k keeps more waves
+// in flight.
 template <int COUT, int CC>
 hipError_t lds_tile(hipStream_t s, const ConvArgs &a) {
     const long tiles44 = (long)((a.onx + 15) / 16) * ((a.ony + 3) / 4) * ((a.onz + 3) / 4);
-    if constexpr (COUT <= 64) {
+    if constexpr (COUT == 32 || COUT == 64) {
         if (tiles44 >= 1024) return reg_launch<COUT, CC, 4, 4>(s, a);
         return reg_launch<COUT, CC, 2, 2>(s, a);
     } else {
@@ -1057,18 +1123,28 @@ hipError_t prep_input(hipStream_t s, const double *src, size_t n, const double *
     return hipGetLastError();
 }
 
-hipError_t head_predict(hipStream_t s, const bf16_t *a, size_t n, const float *wh, const float *bh,
-                        const double *sigma, const double coef[3], double *g0, double *g1, double *g2) {
+hipError_t head_predict(hipStream_t s, const bf16_t *a, const double *src, int nx, int ny, int nz, const float *wh,
+                        const float *bh, const double *sigma, const double coef[3], double *g0, double *g1,
+                        double *g2) {
     Coef3 c{{coef[0], coef[1], coef[2]}};
-    head_predict_k<<<nblk(n), 256, 0, s>>>(a, n, wh, bh, sigma, c, g0, g1, g2);
+    const size_t n = (size_t)nx * ny * nz;
+    head_predict_k<<<nblk(n), 256, 0, s>>>(a, src, Grid3{nx, ny, nz}, wh, bh, sigma, c, g0, g1, g2);
     return hipGetLastError();
 }
 
 int head_train_blocks(size_t n) { return (int)nblk(n); }
 
-hipError_t head_train(hipStream_t s, const bf16_t *a, size_t n, const float *wh, const float *bh, const float *t,
-                      bf16_t *ga, float *partials) {
-    head_train_k<<<nblk(n), 256, 0, s>>>(a, n, wh, bh, t, ga, partials);
+hipError_t head_train(hipStream_t s, const bf16_t *a, const double *src, int nx, int ny, int nz, const float *wh,
+                      const float *bh, const double *sigma, const float *t, bf16_t *ga, float *partials) {
+    const size_t n = (size_t)nx * ny * nz;
+    head_train_k<<<nblk(n), 256, 0, s>>>(a, src, Grid3{nx, ny, nz}, wh, bh, sigma, t, ga, partials);
+    return hipGetLastError();
+}
+
+hipError_t conv_in(hipStream_t s, const double *src, int nx, int ny, int nz, const double *sigma, const bf16_t *wf,
+                   const float *bias, bf16_t *out) {
+    const size_t n = (size_t)nx * ny * nz;
+    conv_in_k<<<nblk(n), 256, 0, s>>>(src, Grid3{nx, ny, nz}, sigma, wf, bias, out);
     return hipGetLastError();
 }
 

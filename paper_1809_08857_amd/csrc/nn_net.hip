@@ -44,7 +44,6 @@ constexpr int kInput = -1; // input index: the scaled source
 constexpr int kNone = -2;  // no second input
 constexpr int kLayers = 21;
 constexpr int kHeadLayer = 20;
-constexpr int kHeadRed = 52;
 constexpr size_t kMaxPartialFloats = size_t(32) << 20;
 
 struct LayerDef {
@@ -76,7 +75,7 @@ const LayerDef kNet[kLayers] = {
     {G_UP2, 32, 16, 16, kNone, 1, 0},       // u0
     {G_SAME3, 32, 16, 17, 1, 0, 0},         // c0a = conv(u0 | e0b)
     {G_SAME3, 16, 16, 18, kNone, 0, 0},     // c0b
-    {kHead, 16, 3, 19, kNone, 0, 0},        // head
+    {kHead, kHeadIn, 3, 19, kNone, 0, 0},   // head: c0b's 16 channels + x at 27 taps
 };
 
 int taps(const LayerDef &L) { return L.geom == kHead ? 1 : geom_taps(L.geom); }
@@ -178,13 +177,16 @@ void inputs(const mgl_net *n, int l, const bf16_t *&a, int &ca, const bf16_t *&b
     }
 }
 
-int forward(mgl_net *n, const double *s) {
+// Forward pass; with_x8 also writes the padded input tensor that the
+// weight gradient of the first layer reads.
+int forward(mgl_net *n, const double *s, bool with_x8) {
     hipStream_t st = n->stream;
     const size_t n0 = n->cells(0);
     CK(fill_zero(st, n->sigma, 8));
     CK(maxabs(st, s, n0, n->sigma));
-    CK(prep_input(st, s, n0, n->sigma, n->x8));
-    for (int l = 0; l < kLayers; ++l) {
+    if (with_x8) CK(prep_input(st, s, n0, n->sigma, n->x8));
+    CK(conv_in(st, s, n->nx, n->ny, n->nz, n->sigma, n->wf[0], n->theta + kOff.b[0], n->act[0]));
+    for (int l = 1; l < kLayers; ++l) {
         const LayerDef &L = kNet[l];
         if (L.geom == kHead) continue;
         ConvArgs a{};
@@ -202,15 +204,16 @@ int forward(mgl_net *n, const double *s) {
 }
 
 // head loss and gradient of one sample; sse accumulates into lossacc
-int head_backward(mgl_net *n, const float *t, bool want_grad) {
+int head_backward(mgl_net *n, const double *s, const float *t, bool want_grad) {
     hipStream_t st = n->stream;
     const size_t n0 = n->cells(0);
     const int nb = head_train_blocks(n0);
-    CK(head_train(st, n->act[19], n0, n->theta + kOff.w[kHeadLayer], n->theta + kOff.b[kHeadLayer], t, n->gact[19],
-                  n->hpart));
-    if (want_grad)  // dW[3][16] then db[3]: contiguous in the parameter vector
-        CK(reduce_partials(st, n->hpart, nb, 51, kHeadRed, 51, 51, n->grad + kOff.w[kHeadLayer], 1, n->rwork));
-    CK(reduce_partials(st, n->hpart + 51, nb, 1, kHeadRed, 1, 1, n->lossacc, 1, n->rwork));
+    constexpr int nwb = 3 * kHeadIn + 3;  // dW then db: contiguous in the parameter vector
+    CK(head_train(st, n->act[19], s, n->nx, n->ny, n->nz, n->theta + kOff.w[kHeadLayer],
+                  n->theta + kOff.b[kHeadLayer], n->sigma, t, n->gact[19], n->hpart));
+    if (want_grad)
+        CK(reduce_partials(st, n->hpart, nb, nwb, kHeadRed, nwb, nwb, n->grad + kOff.w[kHeadLayer], 1, n->rwork));
+    CK(reduce_partials(st, n->hpart + nwb, nb, 1, kHeadRed, 1, 1, n->lossacc, 1, n->rwork));
     return MG_OK;
 }
 
@@ -300,7 +303,7 @@ int mgl_create(const mgl_desc *d, void *hip_stream, mgl_net **out) {
     n->m = (float *)A(P * 4);
     n->v = (float *)A(P * 4);
     n->grad = (float *)A(P * 4);
-    size_t wmax = 0, nmax = 52;
+    size_t wmax = 0, nmax = kHeadRed;
     int bmax = 0;
     for (int l = 0; l < kLayers; ++l) {
         const LayerDef &L = kNet[l];
@@ -450,8 +453,8 @@ int mgl_train_step(mgl_net *n, int count, const double *const *s, const float *c
     CK(fill_zero(st, n->grad, kOff.total * 4));
     CK(fill_zero(st, n->lossacc, 4));
     for (int k = 0; k < count; ++k) {
-        if (int rc = forward(n, s[k])) return rc;
-        if (int rc = head_backward(n, t[k], true)) return rc;
+        if (int rc = forward(n, s[k], true)) return rc;
+        if (int rc = head_backward(n, s[k], t[k], true)) return rc;
         if (int rc = backward(n)) return rc;
     }
     if (opt && opt->lr > 0.f) {
@@ -474,8 +477,8 @@ int mgl_eval_loss(mgl_net *n, const double *s, const float *t, double *loss) {
     if (!s || !t || !loss) return set_err(MG_EINVAL, "mgl_eval_loss: null argument");
     hipStream_t st = n->stream;
     CK(fill_zero(st, n->lossacc, 4));
-    if (int rc = forward(n, s)) return rc;
-    if (int rc = head_backward(n, t, false)) return rc;
+    if (int rc = forward(n, s, false)) return rc;
+    if (int rc = head_backward(n, s, t, false)) return rc;
     float l;
     CK(hipMemcpyAsync(&l, n->lossacc, 4, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
@@ -493,9 +496,9 @@ int mgl_predict(mgl_net *n, const double *s, const double kappa2[3], double *con
             return set_err(MG_EINVAL, "mgl_predict: kappa2[%d] must be finite and > 0", i);
         coef[i] = n->scale[i] / kappa2[i];
     }
-    if (int rc = forward(n, s)) return rc;
-    CK(head_predict(n->stream, n->act[19], n->cells(0), n->theta + kOff.w[kHeadLayer], n->theta + kOff.b[kHeadLayer],
-                    n->sigma, coef, guess[0], guess[1], guess[2]));
+    if (int rc = forward(n, s, false)) return rc;
+    CK(head_predict(n->stream, n->act[19], s, n->nx, n->ny, n->nz, n->theta + kOff.w[kHeadLayer],
+                    n->theta + kOff.b[kHeadLayer], n->sigma, coef, guess[0], guess[1], guess[2]));
     return MG_OK;
 }
 

@@ -136,13 +136,21 @@ def test_forward_layer(case, name):
     _close_bf16(case["acts"][name], ref, name)
 
 
+def _head_in(case):
+    """The head's features as the kernel forms them: c0b's bfloat16 channels
+    and x = s / max|s| in FP32 at the 27 taps."""
+    s = case["s"]
+    x = (s / np.abs(s).max()).astype(np.float32).astype(np.float64)[..., None]
+    return nn.head_features(case["acts"]["c0b"], x)
+
+
 def test_head_gradient(case):
     p = nn.unflatten(case["theta"])
     W, b = p["head"]
     a = case["acts"]["c0b"]
-    y = a @ W.astype(np.float32).astype(np.float64).T + b
+    y = _head_in(case) @ W.T + b
     gy = 2.0 * (y - case["target"].astype(np.float32)) / y.size
-    ga = (gy @ W) * (a > 0)
+    ga = (gy @ W[:, :16]) * (a > 0)
     _close_bf16(case["gacts"]["c0b"], nn.bf16_round(ga), "head input gradient")
     loss = float(np.mean((y - case["target"].astype(np.float32)) ** 2))
     assert abs(case["loss"] - loss) <= 1e-5 * loss
@@ -195,9 +203,10 @@ def test_weight_gradient(case, name):
     if name == "head":
         p = nn.unflatten(case["theta"])
         W, b = p["head"]
-        y = inp @ W.T + b
+        hin = _head_in(case)
+        y = hin @ W.T + b
         g = 2.0 * (y - case["target"].astype(np.float32)) / y.size
-        rW, rb = g.reshape(-1, 3).T @ inp.reshape(-1, 16), g.reshape(-1, 3).sum(axis=0)
+        rW, rb = g.reshape(-1, 3).T @ hin.reshape(-1, hin.shape[3]), g.reshape(-1, 3).sum(axis=0)
         tol = 1e-4
     else:
         g = case["gacts"][name]

@@ -195,7 +195,7 @@ def test_storage_rounding_option():
     assert l0 == l1 and np.array_equal(g0, g1)
     _, acts = nn.forward(theta, x, rnd=nn.bf16_round)
     for k, a in acts.items():
-        if k != "head":
+        if k not in ("head", "head_in", "x_head"):  # the head and its direct x path stay FP64
             assert np.array_equal(a, nn.bf16_round(a)), k
     l2, g2 = nn.loss_and_grad(theta, x, t, rnd=nn.bf16_round)
     assert abs(l2 - l0) <= 1e-2 * l0
