@@ -68,6 +68,8 @@ struct mg_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev;  // start/stop pairs
     std::vector<double> ev_bytes;
+    std::vector<int> ev_step;  // pipeline step of each timed launch (-1: outside a solve)
+    int cur_step = -1;         // check(k) = 2k, advance(k) = 2k + 1
     int ev_used = 0;
     long t_launches = 0;
     double t_ms = 0.0, t_bytes = 0.0;
@@ -89,7 +91,9 @@ void fp64_view(Ctx *c, std::vector<LvView> &V, const double *f, double *x);
 void lowp_view(Ctx *c, std::vector<LvView> &V);
 int read_results(Ctx *c, int n);
 void batch_release(Ctx *c);
-int timing_flush(Ctx *c);
+// Adds the timed launches to the totals; launches of pipeline steps after
+// max_step (enqueued ahead and skipped once the solve converged) are dropped.
+int timing_flush(Ctx *c, int max_step = 1 << 30);
 hipError_t timed_smooth(Ctx *c, int l, const LvView &W, bool zin, int tile, int zc, const int *done = nullptr);
 
 }  // namespace mg

@@ -232,6 +232,7 @@ hipError_t timed_smooth(Ctx *c, int l, const LvView &W, bool zin, int tile, int 
     const double es = (double)store_size(W.st);
     const int arrays = (zin ? 0 : 1) + 1 + (W.C.mode == COEF_CELL ? 1 : 0) + 1;
     c->ev_bytes[c->ev_used / 2] = (double)W.n * es * arrays;
+    c->ev_step[c->ev_used / 2] = c->cur_step;
     c->ev_used += 2;
     if (c->t_kernel.empty()) {
         int tx, ty;
@@ -245,10 +246,11 @@ hipError_t timed_smooth(Ctx *c, int l, const LvView &W, bool zin, int tile, int 
     return hipSuccess;
 }
 
-int timing_flush(Ctx *c) {
+int timing_flush(Ctx *c, int max_step) {
     if (!c->timing || c->ev_used == 0) return MG_OK;
     CK(hipStreamSynchronize(c->stream));
     for (int q = 0; q + 1 < c->ev_used; q += 2) {
+        if (c->ev_step[q / 2] > max_step) continue;
         float ms = 0.f;
         CK(hipEventElapsedTime(&ms, c->ev[q], c->ev[q + 1]));
         c->t_ms += ms;
@@ -574,6 +576,7 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
     if (lowp) lowp_view(c, V);
     else fp64_view(c, V, f, x);
     auto check = [&](int cyc) -> int {
+        c->cur_step = 2 * cyc;
         chk.slot = SLOT_CYC + (cyc & 1);
         if (lowp) {
             // FP64 residual of the starting iterate, cast into the inner
@@ -602,6 +605,7 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
         return MG_OK;
     };
     auto advance = [&](int cyc) -> int {
+        c->cur_step = 2 * cyc + 1;
         if (lowp) {
             // inner low-precision V-cycle on A e = r, then x += e (the check
             // of the next step computes the new residual from x and e)
@@ -688,7 +692,8 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
     // the iterate that passed the test may sit in the spare buffer
     if (final_x != x) CK(copy_f64(s, final_x, x, n0));
     CK(hipStreamSynchronize(s));
-    if ((rc = timing_flush(c))) return rc;
+    c->cur_step = -1;
+    if ((rc = timing_flush(c, 2 * cycles))) return rc;
     S.cycles = cycles;
     S.rel_res = rel;
     S.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -769,6 +774,7 @@ int mg_timing(mg_ctx *c, int enable) {
         c->ev.resize(1024);
         for (auto &e : c->ev) CK(hipEventCreate(&e));
         c->ev_bytes.resize(512);
+        c->ev_step.resize(512);
     }
     c->timing = enable != 0;
     c->ev_used = 0;
