@@ -102,7 +102,7 @@ hipError_t head_predict(hipStream_t s, const bf16_t *a, const double *src, int n
 // Training: mean-squared error against t[v][3]; writes the masked input
 // gradient ga[v][16] (bf16) and per-block partials of (dW, db, sum of
 // squared errors), kHeadRed floats per block.
-int head_train_blocks(size_t n);
+int head_train_blocks(int nx, int ny, int nz);
 hipError_t head_train(hipStream_t s, const bf16_t *a, const double *src, int nx, int ny, int nz, const float *wh,
                       const float *bh, const double *sigma, const float *t, bf16_t *ga, float *partials);
 // First layer (1 -> 16 channels, 3x3x3): out = ReLU(b + W x) with x the

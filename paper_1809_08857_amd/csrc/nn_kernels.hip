@@ -743,35 +743,57 @@ struct Grid3 {
     int nx, ny, nz;
 };
 
-// Features of the head at cell v: c0b's 16 channels, then the scaled input
-// x = s / sigma (FP32) at the 27 taps of the cell (0 outside the grid).
-__device__ __forceinline__ void head_features(const bf16_t *a, const double *s, double inv, Grid3 g, size_t v,
+// Blocks of the input-side kernels (first layer, head): 256 threads on a
+// 64 x 4 tile of one z plane.  The scaled input x = s / sigma of the tile
+// and its one-cell halo on planes z-1, z, z+1 is staged in LDS (0 outside
+// the grid), optionally rounded to bfloat16.
+constexpr int kInTX = 64, kInTY = 4;
+struct InTile {
+    float v[3][kInTY + 2][kInTX + 2];
+};
+
+__device__ __forceinline__ void stage_input(const double *s, Grid3 g, double sg, bool round_bf16, InTile &t) {
+    const int x0 = blockIdx.x * kInTX, y0 = blockIdx.y * kInTY, z = blockIdx.z;
+    constexpr int N = 3 * (kInTY + 2) * (kInTX + 2);
+    for (int i = threadIdx.x; i < N; i += 256) {
+        const int hx = i % (kInTX + 2), r = i / (kInTX + 2);
+        const int hy = r % (kInTY + 2), hz = r / (kInTY + 2);
+        const int qx = x0 + hx - 1, qy = y0 + hy - 1, qz = z + hz - 1;
+        float v = 0.f;
+        if (qx >= 0 && qx < g.nx && qy >= 0 && qy < g.ny && qz >= 0 && qz < g.nz) {
+            const double sv = s[((size_t)qz * g.ny + qy) * g.nx + qx];
+            v = (float)(sg > 0.0 ? sv / sg : sv);
+            if (round_bf16) v = bf2f(f2bf(v));
+        }
+        t.v[hz][hy][hx] = v;
+    }
+    __syncthreads();
+}
+
+// Features of the head at this thread's cell: c0b's 16 channels, then x at
+// the 27 taps (from the staged tile).
+__device__ __forceinline__ void head_features(const bf16_t *a, size_t v, const InTile &t, int lx, int ly,
                                               float (&f)[kHeadIn]) {
     float x16[16];
     load16ch(a, v, x16);
 #pragma unroll
     for (int c = 0; c < 16; ++c) f[c] = x16[c];
-    const int px = (int)(v % g.nx);
-    const size_t r = v / g.nx;
-    const int py = (int)(r % g.ny), pz = (int)(r / g.ny);
 #pragma unroll
-    for (int t = 0; t < 27; ++t) {
-        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-        const int qx = px + dx, qy = py + dy, qz = pz + dz;
-        const bool in = qx >= 0 && qx < g.nx && qy >= 0 && qy < g.ny && qz >= 0 && qz < g.nz;
-        f[16 + t] = in ? (float)(s[((size_t)qz * g.ny + qy) * g.nx + qx] * inv) : 0.f;
-    }
+    for (int q = 0; q < 27; ++q) f[16 + q] = t.v[q / 9][ly + (q / 3) % 3][lx + q % 3];
 }
 
 __global__ __launch_bounds__(256) void head_predict_k(const bf16_t *a, const double *s, Grid3 g, const float *wh,
                                                       const float *bh, const double *sigma, Coef3 coef, double *g0,
                                                       double *g1, double *g2) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t v = blockIdx.x * 256ull + threadIdx.x;
-    if (v >= n) return;
+    __shared__ InTile tile;
     const double sg = *sigma > 0.0 ? *sigma : 1.0;
+    stage_input(s, g, sg, false, tile);
+    const int lx = threadIdx.x % kInTX, ly = threadIdx.x / kInTX;
+    const int px = blockIdx.x * kInTX + lx, py = blockIdx.y * kInTY + ly, pz = blockIdx.z;
+    if (px >= g.nx || py >= g.ny) return;
+    const size_t v = ((size_t)pz * g.ny + py) * g.nx + px;
     float f[kHeadIn];
-    head_features(a, s, 1.0 / sg, g, v, f);
+    head_features(a, v, tile, lx, ly, f);
     float y[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -795,13 +817,17 @@ __global__ __launch_bounds__(256) void head_train_k(const bf16_t *a, const doubl
                                                     const float *bh, const double *sigma, const float *t, bf16_t *ga,
                                                     float *partials) {
     __shared__ float red[4][kHeadRed];
+    __shared__ InTile tile;
     const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t v = blockIdx.x * 256ull + threadIdx.x;
-    const bool ok = v < n;
+    const double sg0 = *sigma > 0.0 ? *sigma : 1.0;
+    stage_input(s, g, sg0, false, tile);
+    const int lx = threadIdx.x % kInTX, ly = threadIdx.x / kInTX;
+    const int px = blockIdx.x * kInTX + lx, py = blockIdx.y * kInTY + ly, pz = blockIdx.z;
+    const bool ok = px < g.nx && py < g.ny;
+    const size_t v = ok ? ((size_t)pz * g.ny + py) * g.nx + px : 0;
     float f[kHeadIn], gy[3], sse = 0.f;
     if (ok) {
-        const double sg = *sigma > 0.0 ? *sigma : 1.0;
-        head_features(a, s, 1.0 / sg, g, v, f);
+        head_features(a, v, tile, lx, ly, f);
         const float k = 2.f / (3.f * (float)n);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -842,43 +868,36 @@ __global__ __launch_bounds__(256) void head_train_k(const bf16_t *a, const doubl
     const float r = wave_sum(sse);
     if (lane == 0) red[wave][kHeadRed - 1] = r;
     __syncthreads();
+    const size_t bid = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
     for (int k = threadIdx.x; k < kHeadRed; k += 256)
-        partials[(size_t)blockIdx.x * kHeadRed + k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+        partials[bid * kHeadRed + k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
 }
 
 // First layer (1 input channel -> 16): direct FP32 products of the
-// bfloat16-rounded scaled input x = s / sigma at the 27 taps with the
-// bfloat16 weights wf[16][27][8] (channel 0), + bias, ReLU.  One thread per
-// cell; the neighbours of s come through the caches.
+// bfloat16-rounded scaled input x = s / sigma at the 27 taps (staged in LDS)
+// with the bfloat16 weights wf[16][27][8] (channel 0), + bias, ReLU.  One
+// thread per cell.
 __global__ __launch_bounds__(256) void conv_in_k(const double *s, Grid3 g, const double *sigma, const bf16_t *wf,
                                                  const float *bias, bf16_t *out) {
     __shared__ float w[16 * 27];
+    __shared__ InTile tile;
     for (int i = threadIdx.x; i < 16 * 27; i += 256) w[i] = bf2f(wf[i * 8]);
-    __syncthreads();
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t v = blockIdx.x * 256ull + threadIdx.x;
-    if (v >= n) return;
-    const double sg = *sigma;
-    const int px = (int)(v % g.nx);
-    const size_t r = v / g.nx;
-    const int py = (int)(r % g.ny), pz = (int)(r / g.ny);
+    stage_input(s, g, *sigma, true, tile);
+    const int lx = threadIdx.x % kInTX, ly = threadIdx.x / kInTX;
+    const int px = blockIdx.x * kInTX + lx, py = blockIdx.y * kInTY + ly, pz = blockIdx.z;
+    if (px >= g.nx || py >= g.ny) return;
+    const size_t v = ((size_t)pz * g.ny + py) * g.nx + px;
     float xt[27];
 #pragma unroll
-    for (int t = 0; t < 27; ++t) {
-        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-        const int qx = px + dx, qy = py + dy, qz = pz + dz;
-        const bool in = qx >= 0 && qx < g.nx && qy >= 0 && qy < g.ny && qz >= 0 && qz < g.nz;
-        const double sv = in ? s[((size_t)qz * g.ny + qy) * g.nx + qx] : 0.0;
-        xt[t] = bf2f(f2bf((float)(sg > 0.0 ? sv / sg : sv)));
-    }
+    for (int q = 0; q < 27; ++q) xt[q] = tile.v[q / 9][ly + (q / 3) % 3][lx + q % 3];
     unsigned pk[8];
 #pragma unroll
     for (int c = 0; c < 16; c += 2) {
         float y0 = bias[c], y1 = bias[c + 1];
 #pragma unroll
-        for (int t = 0; t < 27; ++t) {
-            y0 = fmaf(w[c * 27 + t], xt[t], y0);
-            y1 = fmaf(w[(c + 1) * 27 + t], xt[t], y1);
+        for (int q = 0; q < 27; ++q) {
+            y0 = fmaf(w[c * 27 + q], xt[q], y0);
+            y1 = fmaf(w[(c + 1) * 27 + q], xt[q], y1);
         }
         pk[c / 2] = f2bf(fmaxf(y0, 0.f)) | (f2bf(fmaxf(y1, 0.f)) << 16);
     }
@@ -1123,28 +1142,30 @@ hipError_t prep_input(hipStream_t s, const double *src, size_t n, const double *
     return hipGetLastError();
 }
 
+inline dim3 in_grid(int nx, int ny, int nz) { return dim3((nx + kInTX - 1) / kInTX, (ny + kInTY - 1) / kInTY, nz); }
+
 hipError_t head_predict(hipStream_t s, const bf16_t *a, const double *src, int nx, int ny, int nz, const float *wh,
                         const float *bh, const double *sigma, const double coef[3], double *g0, double *g1,
                         double *g2) {
     Coef3 c{{coef[0], coef[1], coef[2]}};
-    const size_t n = (size_t)nx * ny * nz;
-    head_predict_k<<<nblk(n), 256, 0, s>>>(a, src, Grid3{nx, ny, nz}, wh, bh, sigma, c, g0, g1, g2);
+    head_predict_k<<<in_grid(nx, ny, nz), 256, 0, s>>>(a, src, Grid3{nx, ny, nz}, wh, bh, sigma, c, g0, g1, g2);
     return hipGetLastError();
 }
 
-int head_train_blocks(size_t n) { return (int)nblk(n); }
+int head_train_blocks(int nx, int ny, int nz) {
+    const dim3 g = in_grid(nx, ny, nz);
+    return (int)(g.x * g.y * g.z);
+}
 
 hipError_t head_train(hipStream_t s, const bf16_t *a, const double *src, int nx, int ny, int nz, const float *wh,
                       const float *bh, const double *sigma, const float *t, bf16_t *ga, float *partials) {
-    const size_t n = (size_t)nx * ny * nz;
-    head_train_k<<<nblk(n), 256, 0, s>>>(a, src, Grid3{nx, ny, nz}, wh, bh, sigma, t, ga, partials);
+    head_train_k<<<in_grid(nx, ny, nz), 256, 0, s>>>(a, src, Grid3{nx, ny, nz}, wh, bh, sigma, t, ga, partials);
     return hipGetLastError();
 }
 
 hipError_t conv_in(hipStream_t s, const double *src, int nx, int ny, int nz, const double *sigma, const bf16_t *wf,
                    const float *bias, bf16_t *out) {
-    const size_t n = (size_t)nx * ny * nz;
-    conv_in_k<<<nblk(n), 256, 0, s>>>(src, Grid3{nx, ny, nz}, sigma, wf, bias, out);
+    conv_in_k<<<in_grid(nx, ny, nz), 256, 0, s>>>(src, Grid3{nx, ny, nz}, sigma, wf, bias, out);
     return hipGetLastError();
 }
 

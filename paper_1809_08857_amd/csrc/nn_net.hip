@@ -207,7 +207,7 @@ int forward(mgl_net *n, const double *s, bool with_x8) {
 int head_backward(mgl_net *n, const double *s, const float *t, bool want_grad) {
     hipStream_t st = n->stream;
     const size_t n0 = n->cells(0);
-    const int nb = head_train_blocks(n0);
+    const int nb = head_train_blocks(n->nx, n->ny, n->nz);
     constexpr int nwb = 3 * kHeadIn + 3;  // dW then db: contiguous in the parameter vector
     CK(head_train(st, n->act[19], s, n->nx, n->ny, n->nz, n->theta + kOff.w[kHeadLayer],
                   n->theta + kOff.b[kHeadLayer], n->sigma, t, n->gact[19], n->hpart));
@@ -329,7 +329,7 @@ int mgl_create(const mgl_desc *d, void *hip_stream, mgl_net **out) {
     n->lossacc = (float *)A(64);
     n->wpart = (float *)A(wmax * 4);
     n->bpart = (float *)A((size_t)bmax * 4);
-    n->hpart = (float *)A((size_t)head_train_blocks(n->cells(0)) * kHeadRed * 4);
+    n->hpart = (float *)A((size_t)head_train_blocks(n->nx, n->ny, n->nz) * kHeadRed * 4);
     n->rwork = (float *)A(nmax * kReduceGroups * 4);
     if (!ok) {
         mgl_destroy(n);
