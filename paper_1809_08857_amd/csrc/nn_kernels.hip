@@ -383,19 +383,31 @@ __global__ __launch_bounds__(256) void conv3_reg_k(ConvArgs a) {
             *reinterpret_cast<u32x4 *>(tile + v * VS + q * 8) = val;
         }
         __syncthreads();
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
+        // B operands of chunk c + 1 are read before the products of chunk c
+        auto fetchB = [&](int c, u32x4 (&B)[RW]) {
             // this lane's tap in chunk c (past the last tap: any cell, A is 0)
             int off = tap_off<HX, HY>(c * TPC < 27 ? c * TPC : 26);
 #pragma unroll
             for (int k = 1; k < TPC; ++k)
                 if (tsub == k) off = tap_off<HX, HY>(c * TPC + k < 27 ? c * TPC + k : 26);
 #pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                const u32x4 B = *reinterpret_cast<const u32x4 *>(tile + (rbase[r] + off) * VS + cl);
+            for (int r = 0; r < RW; ++r) B[r] = *reinterpret_cast<const u32x4 *>(tile + (rbase[r] + off) * VS + cl);
+        };
+        u32x4 Bn[RW];
+        fetchB(0, Bn);
 #pragma unroll
-                for (int m = 0; m < MTW; ++m) acc[m][r] = mfma(A[c][m], B, acc[m][r]);
-            }
+        for (int c = 0; c < NCH; ++c) {
+            u32x4 Bc[RW];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) Bc[r] = Bn[r];
+            if (c + 1 < NCH) fetchB(c + 1, Bn);
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int m = 0; m < MTW; ++m) acc[m][r] = mfma(A[c][m], Bc[r], acc[m][r]);
+            // keep the order: next chunk's LDS reads, then this chunk's MFMAs
+            if (c + 1 < NCH) __builtin_amdgcn_sched_group_barrier(0x100, RW, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, RW * MTW, 0);
         }
     }
     const int ox = x0 + col;
