@@ -89,9 +89,9 @@ enum {
                      Otherwise the solve starts from zero and
                      stats.fell_back = 1.  (Grids handled by the bottom
                      solver alone, or nu1 = 0: the raw residual
-                     ||b - A x|| is compared.)  stats.rel_res0 is the raw
-                     relative residual of the guess (1 after a
-                     fallback). */
+                     ||b - A x|| is compared.)  stats.rel_res0 is the
+                     relative residual of the guess at that test (1
+                     after a fallback). */
 };
 
 typedef struct {
@@ -114,7 +114,8 @@ typedef struct {
 
 typedef struct {
     int cycles;        /* V-cycles (or refinement steps) performed */
-    double rel_res0;   /* ||b - A x0|| / ||b|| of the starting iterate */
+    double rel_res0;   /* ||b - A x0|| / ||b|| of the starting iterate
+                          (1 for a zero start; for MG_GUESS see there) */
     double rel_res;    /* final ||b - A x|| / ||b|| (FP64) */
     int fell_back;     /* 1 if an MG_GUESS was rejected */
     double ms;         /* wall time of the call */
@@ -143,7 +144,9 @@ int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc);
 /* Solve A x = b with b = f + boundary terms.  f_dev and x_dev are device
  * arrays of nx*ny*nz FP64 values; f_dev is read only; x_dev receives the
  * solution (without MG_GUESS its input content is ignored).  st may be
- * NULL. */
+ * NULL.  A non-finite f is MG_EINVAL; a non-finite guess is rejected like
+ * any other guess worse than zero (MG_EINVAL where the raw residual is
+ * compared). */
 int mg_solve(mg_ctx *c, const double *f_dev, double *x_dev, unsigned flags, mg_stats *st);
 
 /* Solve `count` independent problems (contexts may differ in size and

@@ -94,6 +94,10 @@ void batch_release(Ctx *c);
 // Adds the timed launches to the totals; launches of pipeline steps after
 // max_step (enqueued ahead and skipped once the solve converged) are dropped.
 int timing_flush(Ctx *c, int max_step = 1 << 30);
+
+// ||b||^2 of the finest-level FP64 problem (b = f + boundary terms) into
+// ws.result[slot] (mg_misc.hip); level 0 is CONST or CELL.
+hipError_t norm2_b(hipStream_t s, const Geo &G, const Coef &C, const double *f, const RedWs &ws, int slot);
 hipError_t timed_smooth(Ctx *c, int l, const LvView &W, bool zin, int tile, int zc, const int *done = nullptr);
 
 }  // namespace mg

@@ -524,12 +524,24 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
     int *done = c->d_done;
     int rc;
     // ||b|| and the residual of the starting iterate
+    // A guess is judged at its first convergence test, after the nu1
+    // pre-smoothing sweeps that open every cycle (they remove the
+    // cell-scale noise that the operator would otherwise magnify), against
+    // the residual of the zero guess, ||b||.  Without a multigrid hierarchy
+    // or pre-smoothing the raw residual is compared.
+    const bool judge = (flags & MG_GUESS) && c->tail > 0 && c->d.nu1 > 0;
+    const bool raw_guess = (flags & MG_GUESS) && !judge;
     if (!(flags & MG_GUESS)) CK(fill_zero(s, x, n0 * 8));
     CK(fill_zero(s, done, sizeof(int)));
-    CK(norm2_resid(s, ST_F64, G0, C0, x, f, c->ws, SLOT_R0, SLOT_B));
+    if (raw_guess) {
+        CK(norm2_resid(s, ST_F64, G0, C0, x, f, c->ws, SLOT_R0, SLOT_B));
+    } else {
+        // zero start: ||b - A 0|| = ||b||; a judged guess is tested later
+        CK(norm2_b(s, G0, C0, f, c->ws, SLOT_B));
+    }
     if ((rc = read_results(c, 2))) return rc;
     const double bn = std::sqrt(c->h_pin[SLOT_B]);
-    double rn = std::sqrt(c->h_pin[SLOT_R0]);
+    double rn = raw_guess ? std::sqrt(c->h_pin[SLOT_R0]) : bn;
     if (!std::isfinite(bn) || !std::isfinite(rn))
         return set_err(MG_EINVAL, "mg_solve: right-hand side or initial guess is not finite");
     if (bn == 0.0) {
@@ -538,20 +550,14 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
         if (st) *st = S;
         return MG_OK;
     }
-    // A guess is judged at its first convergence test, after the nu1
-    // pre-smoothing sweeps that open every cycle (they remove the
-    // cell-scale noise that the operator would otherwise magnify), against
-    // the residual of the zero guess, ||b||.  Without a multigrid hierarchy
-    // or pre-smoothing the raw residual is compared.
-    const bool judge = (flags & MG_GUESS) && c->tail > 0 && c->d.nu1 > 0;
-    if ((flags & MG_GUESS) && !judge && rn > bn) {
+    if (raw_guess && rn > bn) {
         CK(fill_zero(s, x, n0 * 8));
         S.fell_back = 1;
         rn = bn;
     }
     S.rel_res0 = rn / bn;
     const double rtol = c->d.rtol;
-    if (S.rel_res0 <= rtol) {
+    if (!judge && S.rel_res0 <= rtol) {
         CK(hipStreamSynchronize(s));
         S.rel_res = S.rel_res0;
         if (st) *st = S;
@@ -659,6 +665,8 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
             S.fell_back = 1;
             S.rel_res0 = 1.0;
             if ((rc = check(0))) return rc;
+        } else {
+            S.rel_res0 = rel_s;
         }
     }
     double *at_check[2] = {cur, nullptr};

@@ -59,6 +59,60 @@ hipError_t norm2_resid(hipStream_t s, int st, const Geo &G, const Coef &C, const
     return hipErrorInvalidValue;
 }
 
+// ||b||^2 with b = f + h^-2 sum_Dirichlet 2 beta g (the relative-residual
+// reference, and the residual of a zero iterate): one read of f per cell,
+// beta (cell coefficient, or 1) only on boundary cells.  Brick of kz
+// planes per block, loads of four planes in flight.
+template <bool CELL>
+__global__ __launch_bounds__(256) void norm2_b_k(const double *__restrict__ f, const double *__restrict__ eps, Geo G,
+                                                 RedWs ws, int slot, int kz) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k0 = blockIdx.z * kz;
+    const int k1 = min(k0 + kz, G.nz);
+    double sb = 0.0;
+    if (i < G.nx && j < G.ny) {
+        const size_t plane = (size_t)G.nx * G.ny, col = (size_t)j * G.nx + i;
+        const bool side = i == 0 || i == G.nx - 1 || j == 0 || j == G.ny - 1;
+        auto term = [&](int k) -> double {
+            const size_t p = (size_t)k * plane + col;
+            double v = f[p];
+            if (side || k == 0 || k == G.nz - 1) {
+                const double be = CELL ? eps[p] : 1.0;
+                double add = 0.0;
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                    const bool at = d == 0 ? i == 0 : d == 1 ? i == G.nx - 1 : d == 2 ? j == 0
+                                  : d == 3 ? j == G.ny - 1 : d == 4 ? k == 0 : k == G.nz - 1;
+                    if (at && ((G.bcmask >> d) & 1)) add += 2.0 * be * G.g[d];
+                }
+                v += G.ih2 * add;
+            }
+            return v * v;
+        };
+        int k = k0;
+        for (; k + 4 <= k1; k += 4) {
+            const double t0 = term(k), t1 = term(k + 1), t2 = term(k + 2), t3 = term(k + 3);
+            sb += (t0 + t1) + (t2 + t3);
+        }
+        for (; k < k1; ++k) sb += term(k);
+    }
+    reduce2_finish<256>(0.0, sb, ws, slot, slot, brick_id(), brick_count());
+}
+
+hipError_t norm2_b(hipStream_t s, const Geo &G, const Coef &C, const double *f, const RedWs &ws, int slot) {
+    dim3 grid, block;
+    int kz;
+    brick_shape(G.nx, G.ny, G.nz, kMaxRedBlocks, &grid, &block, &kz);
+    if (C.mode == COEF_CELL)
+        hipLaunchKernelGGL((norm2_b_k<true>), grid, block, 0, s, f, (const double *)C.eps, G, ws, slot, kz);
+    else if (C.mode == COEF_CONST)
+        hipLaunchKernelGGL((norm2_b_k<false>), grid, block, 0, s, f, nullptr, G, ws, slot, kz);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 void tile_shape(int t, int *tx, int *ty) {
     static const int TX[kNumTiles + 1] = {0, 64, 128, 64, 32, 32, 16};
     static const int TY[kNumTiles + 1] = {0, 16, 8, 8, 8, 4, 8};

@@ -40,3 +40,40 @@ def test_full_size(problems, which):
         print(f"oracle: {cycles} cycles to {rel:.2e}", flush=True)
         assert rel <= 1e-12
         assert rel_l2(x, ref) <= 1e-9
+
+
+N_MIXED = 512
+
+
+@pytest.fixture(scope="module")
+def problems512():
+    return synth.streamer_set(N_MIXED, seed=0)
+
+
+@pytest.fixture(scope="module")
+def oracle_helm2_512(problems512):
+    """The oracle's own solution of the strongly screened photon group at
+    512^3 (the one whose oracle solve finishes in about a minute)."""
+    ref, cycles, rel = oracle.solve_vcycle(problems512[3], rtol=1e-13, max_cycles=60)
+    assert rel <= 1e-12
+    return ref
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("which", range(4))
+def test_mixed_precision_512(problems512, oracle_helm2_512, prec, which):
+    """The 512^3 mixed-precision configuration bench.py times: every solve
+    reaches its tolerance by the oracle's own residual; the strongly
+    screened photon group also matches the oracle's solution to 1e-9."""
+    p = problems512[which]
+    rtol = 1e-11 if p.a == 0.0 else 1e-10
+    print(f"512^3 {prec} {p.name}", flush=True)
+    x, rc, st = gpu_solve(p, precision=prec, rtol=rtol)
+    print(st, flush=True)
+    assert rc == mg.MG_OK and st["rel_res"] <= rtol
+    _, rn, bn = oracle.residual(p, x)
+    assert rn / bn <= rtol * 1.001
+    if which == 3:
+        err = rel_l2(x, oracle_helm2_512)
+        print(f"error vs oracle {err:.2e}", flush=True)
+        assert err <= 1e-9
