@@ -92,9 +92,10 @@ def smoother_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, algorithmic_bytes: float):
     """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None (no summary, another kernel, or sources changed since)."""
+    or None (no summary, another kernel or grid size, or sources changed
+    since)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -105,6 +106,8 @@ def measured_traffic(kernel: str):
     if kv.get("source_sha256_16") != smoother_source_hash() or kv.get("kernel") != kernel:
         return None
     try:
+        if float(kv["algorithmic_bytes_per_launch"]) != float(algorithmic_bytes):
+            return None
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -118,7 +121,7 @@ def roofline(ctx):
     avg_s = kern_ms / launches / 1e3
     achieved = bytes_per_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname), "kernel": kname,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname, bytes_per_launch), "kernel": kname,
             "avg_us": round(avg_s * 1e6, 2), "launches": launches,
             "algorithmic_bytes_per_launch": bytes_per_launch}
 

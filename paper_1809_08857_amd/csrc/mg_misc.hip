@@ -440,7 +440,7 @@ __global__ __launch_bounds__(TX *TY) void ir_col_k(const double *__restrict__ x,
             if (lx == 0 || lx == TX - 1) se[q][ly + 1][sxl] = ehx0;
             if (ly == 0 || ly == TY - 1) se[q][syl][lx + 1] = ehy0;
         }
-        __syncthreads();
+        lds_barrier();
         if (inc) {
             auto un = [&](int d) -> double {
                 switch (d) {
