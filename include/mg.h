@@ -95,7 +95,8 @@ enum {
 };
 
 typedef struct {
-    int nx, ny, nz;  /* cells per axis, >= 1 each */
+    int nx, ny, nz;  /* cells per axis, >= 1 each; nx*ny <= 2^28 and
+                        nx*ny*nz <= 4e9 */
     double h;        /* cell side, > 0 */
     int precision;   /* MG_FP64 | MG_FP32_IR | MG_BF16_IR */
     int nu1, nu2;    /* red-black Gauss-Seidel sweeps before/after the
@@ -136,7 +137,7 @@ int mg_create(const mg_desc *d, void *hip_stream, mg_ctx **out);
 /* Set the operator: eps_dev = device array of nx*ny*nz cell coefficients
  * (beta; NULL means beta = 1), copied into library storage; a >= 0 the
  * screening coefficient kappa^2; bc the six face conditions.  Errors
- * (MG_EINVAL): eps not finite or not > 0 (checked on the device), a < 0
+ * (MG_EINVAL): eps outside (0, 1e100] (checked on the device), a < 0
  * or not finite, an unknown face type, or a singular operator (a == 0 and
  * no Dirichlet face). */
 int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc);

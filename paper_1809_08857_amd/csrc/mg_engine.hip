@@ -299,6 +299,8 @@ int mg_create(const mg_desc *d, void *hip_stream, mg_ctx **out) {
                        d->ny, d->nz);
     if ((double)d->nx * d->ny * d->nz > 4.0e9)
         return set_err(MG_EINVAL, "mg_create: grid too large");
+    if ((double)d->nx * d->ny > (double)kMaxPlaneCells)
+        return set_err(MG_EINVAL, "mg_create: an x-y plane may hold at most 2^28 cells");
     if (!(d->h > 0.0) || !std::isfinite(d->h)) return set_err(MG_EINVAL, "mg_create: h must be > 0");
     if (d->precision < MG_FP64 || d->precision > MG_BF16_IR)
         return set_err(MG_EINVAL, "mg_create: unknown precision %d", d->precision);
@@ -446,7 +448,7 @@ int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) 
         int rc = read_results(c, 1);
         if (rc) return rc;
         if (c->h_pin[0] != 0.0)
-            return set_err(MG_EINVAL, "mg_set_coeffs: %.0f coefficient entries are not finite and > 0",
+            return set_err(MG_EINVAL, "mg_set_coeffs: %.0f coefficient entries are not in (0, 1e100]",
                            c->h_pin[0]);
         // face coefficients of every level (level 0 only while coarsening,
         // unless the bottom solver starts at level 0)

@@ -50,6 +50,12 @@ struct RedWs {
     double *result;     // result slots
 };
 constexpr int kMaxRedBlocks = 2048;
+// Largest accepted cell coefficient (the smoothers encode Dirichlet box
+// faces with a coefficient of 2^400 that must dominate every cell's).
+constexpr double kMaxCellCoef = 1e100;
+// Largest x-y plane (cells): the stencil kernels address a plane with
+// 32-bit byte offsets from a per-plane base.
+constexpr long kMaxPlaneCells = 1L << 28;
 constexpr int kRedSlots = 8;
 
 // Fused convergence test of a residual pass: reduce ||r||^2 into

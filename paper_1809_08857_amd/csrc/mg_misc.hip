@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void count_bad_k(const double *__restrict__ x,
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (size_t)gridDim.x * blockDim.x) {
         const double v = x[t];
-        if (!(v > 0.0) || !isfinite(v)) c += 1.0;
+        if (!(v > 0.0 && v <= kMaxCellCoef)) c += 1.0;
     }
     reduce2_finish<256>(c, 0.0, ws, slot, -1, brick_id(), brick_count());
 }

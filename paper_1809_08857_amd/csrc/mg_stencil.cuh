@@ -294,14 +294,322 @@ template <class T> struct SmoothArgs {
     const int *done;
 };
 
-// LDS elements (of the compute type) used by one smoother workgroup.
+// LDS elements (of the compute type) used by one smoother workgroup:
+// region planes of old u and of new red values (two), and for cell
+// coefficients one plane of eps and three planes each of x and y faces.
 template <int MODE, int TX, int TY> constexpr int smooth_lds() {
-    return (3 + (MODE == COEF_CELL ? 2 : 0)) * (TY + 4) * (TX + 4);
+    return (MODE == COEF_CELL ? 10 : 3) * (TY + 4) * (TX + 4);
+}
+
+// Harmonic-mean face coefficient 2 a b / (a + b) of two cell coefficients.
+// With a zero coefficient beyond a Neumann face it gives 0; with kBigCoef
+// beyond a Dirichlet face it gives 2 eP to rounding (the ghost-cell term of
+// that face) for every eP <= kMaxCellCoef, and never overflows.
+template <class C> __device__ __forceinline__ C fma_c(C a, C b, C c) {
+    if constexpr (sizeof(C) == 8) return fma(a, b, c);
+    else return fmaf(a, b, c);
+}
+// Select between two values.  (A conditional over two lvalues selects an
+// address, which keeps the variables in private memory.)
+template <class C> __device__ __forceinline__ C csel(bool c, C a, C b) { return c ? a : b; }
+
+template <class C> __device__ __forceinline__ C harm_face(C a, C b) {
+    return qdiv<C>((a + a) * b, a + b);
+}
+// 2^400 (FP64) and 2^60 (FP32 compute of the low-precision copies, where
+// the coefficients stay below 2^36 for a rounding-exact boundary term).
+template <class C> constexpr C kBigCoef = sizeof(C) == 8 ? C(0x1p400) : C(0x1p60f);
+
+// ---------------------------------------------------------------------
+// The same sweep for cell coefficients (harmonic-mean faces).  Every face
+// joins a red and a black cell, so each face coefficient is formed once per
+// sweep and read by both of its cells: at step k the pair forms the x and
+// y faces of plane k+1 (from its own eps and an LDS plane of eps) into one
+// of three LDS face planes (plane k+1 being formed, plane k for the red
+// cells, plane k-1 for the black cells) and the two vertical faces between
+// planes k and k+1 in registers.  Box faces take no branches: an outside
+// cell carries u = the boundary value of the box face it lies beyond and a
+// coefficient (0 beyond a Neumann face, kBigCoef beyond a Dirichlet face)
+// for which harm_face yields that face's term.
+template <class T, int TX, int TY, bool ZIN, int PD>
+__device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int blk,
+                                               typename Num<T>::C *smem) {
+    using N = Num<T>;
+    using C = typename N::C;
+    constexpr int PXW = (TX + 4) / 2;  // pairs per region row
+    constexpr int RX = TX + 4, RY = TY + 4, PL = RX * RY;
+    C(*s_u)[RX] = reinterpret_cast<C(*)[RX]>(smem);                  // old u, plane k
+    C(*s_e)[RX] = reinterpret_cast<C(*)[RX]>(smem + PL);             // eps, plane k+1
+    C(*s_r)[RY][RX] = reinterpret_cast<C(*)[RY][RX]>(smem + 2 * PL);  // new red u, by plane parity
+    // s_fx[q][y][c]: face between cells c and c+1 of row y; s_fy[q][y][c]:
+    // face between rows y and y+1 of column c; q = plane mod 3
+    C(*s_fx)[RY][RX] = reinterpret_cast<C(*)[RY][RX]>(smem + 4 * PL);
+    C(*s_fy)[RY][RX] = reinterpret_cast<C(*)[RY][RX]>(smem + 7 * PL);
+    const T *__restrict__ uin = A.uin;
+    T *__restrict__ uout = A.uout;
+    const T *__restrict__ b = A.b;
+    const T *__restrict__ eps = A.eps;
+    const Geo &G = A.G;
+    const int cz = A.cz, tiles_x = A.tiles_x, tiles_y = A.tiles_y;
+
+    const int tid = threadIdx.x;
+    const int tx = blk % tiles_x;
+    const int rest = blk / tiles_x;
+    const int ty = rest % tiles_y;
+    const int tc = rest / tiles_y;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tc * cz;
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int z1 = min(z0 + cz, nz);
+    const size_t plane = (size_t)nx * ny;
+    const C h2 = C(G.h2), ah2 = C(G.ah2);
+
+    const int ry = tid / PXW, pc = tid - ry * PXW;
+    const int lx = 2 * pc;                  // LDS column of the pair's first cell
+    const int x = lx - 2, y = ry - 2;       // tile coordinates of the pair
+    const int gx = x0 + x, gy = y0 + y;     // global coordinates of its first cell
+    const bool row_in = gy >= 0 && gy < ny;
+    const bool c0_in = row_in && gx >= 0 && gx < nx;
+    const bool c1_in = row_in && gx + 1 >= 0 && gx + 1 < nx;
+    const bool even_nx = (nx & 1) == 0;
+    const bool core = x >= 0 && x < TX && y >= 0 && y < TY;
+    const size_t rowoff = (size_t)(row_in ? gy : 0) * nx;
+    const int lx2 = min(lx + 2, RX - 2);    // next pair (clamped: its face is never read)
+    const int ry1 = min(ry + 1, RY - 1);    // next row (clamped likewise)
+
+    // values carried by cells outside the box: u = boundary value and the
+    // face-encoding coefficient of the box face beyond which the cell lies
+    // (x faces first; a cell outside in x and y is never read)
+    const C big = kBigCoef<C>;
+    auto side = [&](int c) -> int {
+        const int g = gx + c;
+        return g < 0 ? 0 : g >= nx ? 1 : gy < 0 ? 2 : gy >= ny ? 3 : 4;
+    };
+    auto bval = [&](int d) -> C {
+        return d == 0 ? C(G.g[0]) : d == 1 ? C(G.g[1]) : d == 2 ? C(G.g[2]) : d == 3 ? C(G.g[3]) : C(0);
+    };
+    auto bcoef = [&](int d) -> C { return d < 4 && ((G.bcmask >> d) & 1) ? big : C(0); };
+    const int sd0 = side(0), sd1 = side(1);
+    const C gout0 = bval(sd0), gout1 = bval(sd1), eout0 = bcoef(sd0), eout1 = bcoef(sd1);
+    const C gz_lo = C(G.g[4]), gz_hi = C(G.g[5]);
+    const C ez_lo = ((G.bcmask >> 4) & 1) ? big : C(0), ez_hi = ((G.bcmask >> 5) & 1) ? big : C(0);
+
+    // byte offsets of the pair's cells within a plane (0 outside the box)
+    // and the byte offset of plane k: loads and stores take a uniform
+    // plane base plus a 32-bit lane offset
+    const uint32_t lb0 = (uint32_t)((c0_in ? rowoff + gx : 0) * sizeof(T));
+    const uint32_t lb1 = (uint32_t)((c1_in ? rowoff + gx + 1 : 0) * sizeof(T));
+    auto plane_at = [&](int k) -> size_t { return (size_t)min(max(k, 0), nz - 1) * plane * sizeof(T); };
+
+    struct P2 { C v[2]; };
+    // one pair of plane k (a plane outside the box reads the nearest one;
+    // the caller masks what it uses)
+    auto ld_pair = [&](const T *__restrict__ a, int k) -> P2 {
+        const char *pk = reinterpret_cast<const char *>(a) + plane_at(k);
+        P2 r;
+        if (even_nx) {
+            const Pair<T> w = *reinterpret_cast<const Pair<T> *>(pk + lb0);
+            r.v[0] = N::ld(w.v[0]);
+            r.v[1] = N::ld(w.v[1]);
+        } else {
+            r.v[0] = N::ld(*reinterpret_cast<const T *>(pk + lb0));
+            r.v[1] = N::ld(*reinterpret_cast<const T *>(pk + lb1));
+        }
+        return r;
+    };
+    auto pick = [](const P2 &p, int c) -> C { return csel<C>(c, p.v[1], p.v[0]); };
+    // cells outside the box take their boundary values; plane k outside the
+    // box: the z face values (cells also outside in x or y are never read)
+    auto mask = [&](P2 v, int k, C out0, C out1, C zlo, C zhi) -> P2 {
+        const bool kin = k >= 0 && k < nz;
+        const C zv = csel<C>(k < 0, zlo, zhi);
+        P2 r;
+        r.v[0] = csel<C>(kin && c0_in, v.v[0], csel<C>(kin, out0, zv));
+        r.v[1] = csel<C>(kin && c1_in, v.v[1], csel<C>(kin, out1, zv));
+        return r;
+    };
+    auto masku = [&](P2 v, int k) { return mask(v, k, gout0, gout1, gz_lo, gz_hi); };
+    auto maske = [&](P2 v, int k) { return mask(v, k, eout0, eout1, ez_lo, ez_hi); };
+
+    // current planes: u at k-1, k, k+1; b at k-1, k, k+1 (values outside the
+    // box are never used); eps at k, k+1; vertical faces of the pair between
+    // planes k-2|k-1 (zA), k-1|k (zB), k|k+1 (zC)
+    P2 um, u0, up, bm, b0, bp, e0, ep, zA, zB, zC;
+    static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
+    P2 qu0, qu1, qu2, qu3, qb0, qb1, qb2, qb3, qe0, qe1, qe2, qe3;
+    auto QU = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qu0; else if constexpr (v == 1) return qu1;
+        else if constexpr (v == 2) return qu2; else return qu3;
+    };
+    auto QB = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qb0; else if constexpr (v == 1) return qb1;
+        else if constexpr (v == 2) return qb2; else return qb3;
+    };
+    auto QE = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qe0; else if constexpr (v == 1) return qe1;
+        else if constexpr (v == 2) return qe2; else return qe3;
+    };
+    auto issue = [&](int k, P2 &du, P2 &db, P2 &de) {
+        if constexpr (!ZIN) du = ld_pair(uin, k);
+        db = ld_pair(b, k);
+        de = ld_pair(eps, k);
+    };
+    auto vface = [&](const P2 &lo, const P2 &hi) {
+        P2 r;
+        r.v[0] = harm_face(lo.v[0], hi.v[0]);
+        r.v[1] = harm_face(lo.v[1], hi.v[1]);
+        return r;
+    };
+    // x and y faces of plane kp from the pair's eps e and the LDS plane s_e
+    auto form_faces = [&](int kp, const P2 &e) __attribute__((always_inline)) {
+        const int q = (kp + 3) % 3;
+        const Pair<C> en = *reinterpret_cast<const Pair<C> *>(&s_e[ry1][lx]);
+        Pair<C> w;
+        w.v[0] = harm_face(e.v[0], e.v[1]);
+        w.v[1] = harm_face(e.v[1], s_e[ry][lx2]);
+        *reinterpret_cast<Pair<C> *>(&s_fx[q][ry][lx]) = w;
+        w.v[0] = harm_face(e.v[0], en.v[0]);
+        w.v[1] = harm_face(e.v[1], en.v[1]);
+        *reinterpret_cast<Pair<C> *>(&s_fy[q][ry][lx]) = w;
+    };
+    auto put_e = [&](const P2 &e) {
+        Pair<C> w;
+        w.v[0] = e.v[0];
+        w.v[1] = e.v[1];
+        *reinterpret_cast<Pair<C> *>(&s_e[ry][lx]) = w;
+    };
+    P2 zero;
+    zero.v[0] = zero.v[1] = C(0);
+    {
+        P2 t0u, t0b, t0e, t1u, t1b, t1e, t2u, t2b, t2e;
+        issue(z0 - 2, t0u, t0b, t0e);
+        issue(z0 - 1, t1u, t1b, t1e);
+        issue(z0, t2u, t2b, t2e);
+        issue(z0 + 1, qu0, qb0, qe0);
+        if constexpr (PD > 1) issue(z0 + 2, qu1, qb1, qe1);
+        if constexpr (PD > 2) issue(z0 + 3, qu2, qb2, qe2);
+        if constexpr (PD > 3) issue(z0 + 4, qu3, qb3, qe3);
+        um = masku(ZIN ? zero : t0u, z0 - 2);
+        u0 = masku(ZIN ? zero : t1u, z0 - 1);
+        up = masku(ZIN ? zero : t2u, z0);
+        bm = t0b;
+        b0 = t1b;
+        bp = t2b;
+        const P2 em = maske(t0e, z0 - 2);
+        e0 = maske(t1e, z0 - 1);
+        ep = maske(t2e, z0);
+        // faces of plane z0-1 and the vertical faces below it
+        put_e(e0);
+        lds_barrier();
+        form_faces(z0 - 1, e0);
+        zB = vface(em, e0);
+        lds_barrier();
+    }
+    C rn_cur = C(0), rn_prev = C(0), rn_prev2 = C(0);  // new red values of planes k, k-1, k-2
+
+    auto step = [&](int k) __attribute__((always_inline)) {
+        zC = vface(e0, ep);
+        {
+            Pair<C> w;
+            w.v[0] = u0.v[0];
+            w.v[1] = u0.v[1];
+            *reinterpret_cast<Pair<C> *>(&s_u[ry][lx]) = w;
+        }
+        put_e(ep);
+        lds_barrier();
+        form_faces(k + 1, ep);
+        // ---- red cell of plane k (tile + 1-cell ring)
+        rn_prev2 = rn_prev;
+        rn_prev = rn_cur;
+        {
+            const int ro = (gy + k) & 1;  // red cell of the pair: x + ro
+            const int xr = x + ro;
+            const int lr = lx + ro;
+            const bool kin = k >= 0 && k < nz;
+            const bool ring = xr >= -1 && xr <= TX && y >= -1 && y <= TY;
+            C rv = csel<C>(kin, csel<C>(ro, gout1, gout0), csel<C>(k < 0, gz_lo, gz_hi));
+            if (kin && ring && (ro ? c1_in : c0_in)) {
+                const int q = (k + 3) % 3;
+                const C fL = s_fx[q][ry][lr - 1], fR = s_fx[q][ry][lr];
+                const C fD = s_fy[q][ry - 1][lr], fU = s_fy[q][ry][lr];
+                const C fzm = pick(zB, ro), fzp = pick(zC, ro);
+                C off = fL * s_u[ry][lr - 1];
+                off = fma_c<C>(fR, s_u[ry][lr + 1], off);
+                off = fma_c<C>(fD, s_u[ry - 1][lr], off);
+                off = fma_c<C>(fU, s_u[ry + 1][lr], off);
+                off = fma_c<C>(fzm, pick(um, ro), off);
+                off = fma_c<C>(fzp, pick(up, ro), off);
+                const C dg = ((fL + fR) + (fD + fU)) + (fzm + fzp);
+                rv = qdiv<C>(fma_c<C>(h2, pick(b0, ro), off), ah2 + dg);
+            }
+            if (ring) s_r[k & 1][ry][lr] = rv;
+            rn_cur = rv;
+        }
+        // ---- black cell of plane k-1 (tile only); write the pair
+        {
+            const int kb = k - 1;
+            const int ro = (gy + kb) & 1;  // red cell of the pair on plane kb
+            const int bo = 1 - ro;         // black cell
+            if (core && kb >= z0 && kb < z1 && (bo ? c1_in : c0_in)) {
+                const int lb = lx + bo;
+                const int q = (kb + 3) % 3;
+                const C fL = s_fx[q][ry][lb - 1], fR = s_fx[q][ry][lb];
+                const C fD = s_fy[q][ry - 1][lb], fU = s_fy[q][ry][lb];
+                const C fzm = pick(zA, bo), fzp = pick(zB, bo);
+                C off = fL * s_r[kb & 1][ry][lb - 1];
+                off = fma_c<C>(fR, s_r[kb & 1][ry][lb + 1], off);
+                off = fma_c<C>(fD, s_r[kb & 1][ry - 1][lb], off);
+                off = fma_c<C>(fU, s_r[kb & 1][ry + 1][lb], off);
+                off = fma_c<C>(fzm, rn_prev2, off);
+                off = fma_c<C>(fzp, rn_cur, off);
+                const C dg = ((fL + fR) + (fD + fU)) + (fzm + fzp);
+                const C vb = qdiv<C>(fma_c<C>(h2, pick(bm, bo), off), ah2 + dg);
+                char *pk = reinterpret_cast<char *>(uout) + plane_at(kb);
+                if (even_nx) {
+                    Pair<T> o;
+                    const T tb = N::cv(vb), tr = N::cv(rn_prev);
+                    o.v[0] = bo ? tr : tb;
+                    o.v[1] = bo ? tb : tr;
+                    *reinterpret_cast<Pair<T> *>(pk + lb0) = o;
+                } else {
+                    *reinterpret_cast<T *>(pk + (bo ? lb1 : lb0)) = N::cv(vb);
+                    if (ro ? c1_in : c0_in) *reinterpret_cast<T *>(pk + (ro ? lb1 : lb0)) = N::cv(rn_prev);
+                }
+            } else if (core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
+                // odd nx: the pair's black cell lies outside the box
+                char *pk = reinterpret_cast<char *>(uout) + plane_at(kb);
+                *reinterpret_cast<T *>(pk + (ro ? lb1 : lb0)) = N::cv(rn_prev);
+            }
+        }
+        lds_barrier();
+    };
+
+    // shift in plane k+1 from ring slot S, refill the slot with k+1+PD, step k
+    auto iter = [&](auto S, int k) __attribute__((always_inline)) {
+        um = u0; u0 = up;
+        bm = b0; b0 = bp;
+        e0 = ep;
+        zA = zB; zB = zC;
+        up = masku(ZIN ? zero : QU(S), k + 1);
+        bp = QB(S);
+        ep = maske(QE(S), k + 1);
+        if (k + 1 + PD <= z1 + 1) issue(k + 1 + PD, QU(S), QB(S), QE(S));
+        step(k);
+    };
+    step(z0 - 1);
+    for (int kk = z0; kk <= z1; kk += PD) {
+        iter(std::integral_constant<int, 0>{}, kk);
+        if constexpr (PD > 1) { if (kk + 1 > z1) break; iter(std::integral_constant<int, 1>{}, kk + 1); }
+        if constexpr (PD > 2) { if (kk + 2 > z1) break; iter(std::integral_constant<int, 2>{}, kk + 2); }
+        if constexpr (PD > 3) { if (kk + 3 > z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
+    }
 }
 
 template <class T, int MODE, int TX, int TY, bool ZIN, int PD>
-__device__ __forceinline__ void rbgs_col_body(const SmoothArgs<T> &A, const int blk,
-                                              typename Num<T>::C *smem) {
+__device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int blk,
+                                               typename Num<T>::C *smem) {
     using N = Num<T>;
     using C = typename N::C;
     constexpr int PXW = (TX + 4) / 2;  // pairs per region row
@@ -553,6 +861,13 @@ __device__ __forceinline__ void rbgs_col_body(const SmoothArgs<T> &A, const int 
         if constexpr (PD > 2) { if (kk + 2 > z1) break; iter(std::integral_constant<int, 2>{}, kk + 2); }
         if constexpr (PD > 3) { if (kk + 3 > z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
     }
+}
+
+template <class T, int MODE, int TX, int TY, bool ZIN, int PD>
+__device__ __forceinline__ void rbgs_col_body(const SmoothArgs<T> &A, const int blk,
+                                              typename Num<T>::C *smem) {
+    if constexpr (MODE == COEF_CELL) rbgs_cell_body<T, TX, TY, ZIN, PD>(A, blk, smem);
+    else rbgs_pair_body<T, MODE, TX, TY, ZIN, PD>(A, blk, smem);
 }
 
 template <class T, int MODE, int TX, int TY, bool ZIN, int PD>

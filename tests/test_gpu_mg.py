@@ -97,6 +97,40 @@ def test_smoother_every_tile_variant(tile, zchunk):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+_BC_PATTERNS = [
+    (("D", 0.3), ("D", -0.7), ("D", 0.5), ("D", -0.2), ("D", 0.9), ("D", -0.4)),
+    (("N", 0.0), ("N", 0.0), ("N", 0.0), ("N", 0.0), ("N", 0.0), ("D", 0.6)),
+    (("D", 0.8), ("N", 0.0), ("N", 0.0), ("D", -0.5), ("D", 0.1), ("N", 0.0)),
+    (("N", 0.0), ("D", -0.9), ("D", 0.4), ("N", 0.0), ("N", 0.0), ("D", 0.7)),
+]
+
+
+@pytest.mark.parametrize("pattern", range(len(_BC_PATTERNS)))
+@pytest.mark.parametrize("dims,wide", [((56, 20, 36), False), ((15, 13, 11), False), ((64, 40, 24), True)])
+def test_smoother_boundary_faces(pattern, dims, wide):
+    """Cell coefficients against each kind of box face on every side: the
+    sweep encodes Dirichlet and Neumann faces in the values of the cells
+    outside the box.  Several tiles with a ragged tail, an odd nx, and
+    coefficients spread over twelve decades."""
+    p = synth.random_problem(*dims, 40 + pattern, bc=_BC_PATTERNS[pattern], a=0.0)
+    if wide:
+        rng = np.random.default_rng(pattern)
+        p = Problem(p.nx, p.ny, p.nz, p.h, p.a, p.f, np.exp(rng.uniform(np.log(1e-6), np.log(1e6), p.shape)),
+                    p.bc, p.name + "_wide")
+    print(f"smoother boundary faces: {p.name} {p.bc}", flush=True)
+    rng = np.random.default_rng(200 + pattern)
+    u0 = rng.standard_normal(p.shape)
+    ref = oracle.rbgs(p, u0, 1)
+    s = make_solver(p)
+    try:
+        x = dev(u0)
+        mg.mg_smooth(s.ctx, dev(p.f), x, 1)
+        got = x.cpu().numpy()
+    finally:
+        s.close()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 def _manufactured_exact(n):
     h = 1.0 / n
     c = (np.arange(n) + 0.5) * h
@@ -190,6 +224,9 @@ def test_invalid_inputs_rejected():
         mg.Solver(p.nx, p.ny, p.nz, p.h, eps=dev(eps), a=0.0, bc_types=p.bc_types(), bc_values=p.bc_values())
     assert e.value.code == mg.MG_EINVAL
     eps[3, 4, 5] = np.nan
+    with pytest.raises(mg.MgError):
+        mg.Solver(p.nx, p.ny, p.nz, p.h, eps=dev(eps), a=0.0, bc_types=p.bc_types(), bc_values=p.bc_values())
+    eps[3, 4, 5] = 1e101  # above the largest accepted coefficient (1e100)
     with pytest.raises(mg.MgError):
         mg.Solver(p.nx, p.ny, p.nz, p.h, eps=dev(eps), a=0.0, bc_types=p.bc_types(), bc_values=p.bc_values())
     s = make_solver(p)
