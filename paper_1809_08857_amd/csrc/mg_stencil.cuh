@@ -45,6 +45,31 @@ template <class T> struct alignas(2 * sizeof(T)) Pair {
     T v[2];
 };
 
+// Store a pair with the non-temporal hint: the sweep's output is not read
+// again by the same launch, so it should not displace the halo planes that
+// neighbouring workgroups are still reading from L2.
+template <class T> __device__ __forceinline__ void store_pair_nt(T *p, T a, T b) {
+    if constexpr (std::is_same<T, double>::value) {
+        typedef double v2 __attribute__((ext_vector_type(2)));
+        v2 w;
+        w.x = a;
+        w.y = b;
+        __builtin_nontemporal_store(w, reinterpret_cast<v2 *>(p));
+    } else if constexpr (std::is_same<T, float>::value) {
+        typedef float v2 __attribute__((ext_vector_type(2)));
+        v2 w;
+        w.x = a;
+        w.y = b;
+        __builtin_nontemporal_store(w, reinterpret_cast<v2 *>(p));
+    } else {
+        static_assert(sizeof(T) == 2, "16-bit storage type");
+        uint16_t ua, ub;
+        __builtin_memcpy(&ua, &a, 2);
+        __builtin_memcpy(&ub, &b, 2);
+        __builtin_nontemporal_store((uint32_t)ua | ((uint32_t)ub << 16), reinterpret_cast<uint32_t *>(p));
+    }
+}
+
 // Hardware hands workgroup w to XCD (w mod 8).  Give every XCD one
 // contiguous range of tiles so that tiles sharing halo planes share an L2.
 __device__ __forceinline__ int xcd_remap(int w, int n) {
@@ -401,6 +426,8 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
     auto plane_at = [&](int k) -> size_t { return (size_t)min(max(k, 0), nz - 1) * plane * sizeof(T); };
 
     struct P2 { C v[2]; };
+    P2 zero;
+    zero.v[0] = zero.v[1] = C(0);
     // one pair of plane k (a plane outside the box reads the nearest one;
     // the caller masks what it uses)
     auto ld_pair = [&](const T *__restrict__ a, int k) -> P2 {
@@ -453,7 +480,8 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
     };
     auto issue = [&](int k, P2 &du, P2 &db, P2 &de) {
         if constexpr (!ZIN) du = ld_pair(uin, k);
-        db = ld_pair(b, k);
+        db = zero;  // b is used on the tile and its ring only
+        if (y >= -1 && y <= TY) db = ld_pair(b, k);
         de = ld_pair(eps, k);
     };
     auto vface = [&](const P2 &lo, const P2 &hi) {
@@ -480,8 +508,6 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
         w.v[1] = e.v[1];
         *reinterpret_cast<Pair<C> *>(&s_e[ry][lx]) = w;
     };
-    P2 zero;
-    zero.v[0] = zero.v[1] = C(0);
     {
         P2 t0u, t0b, t0e, t1u, t1b, t1e, t2u, t2b, t2e;
         issue(z0 - 2, t0u, t0b, t0e);
@@ -568,11 +594,8 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
                 const C vb = qdiv<C>(fma_c<C>(h2, pick(bm, bo), off), ah2 + dg);
                 char *pk = reinterpret_cast<char *>(uout) + plane_at(kb);
                 if (even_nx) {
-                    Pair<T> o;
                     const T tb = N::cv(vb), tr = N::cv(rn_prev);
-                    o.v[0] = bo ? tr : tb;
-                    o.v[1] = bo ? tb : tr;
-                    *reinterpret_cast<Pair<T> *>(pk + lb0) = o;
+                    store_pair_nt(reinterpret_cast<T *>(pk + lb0), bo ? tr : tb, bo ? tb : tr);
                 } else {
                     *reinterpret_cast<T *>(pk + (bo ? lb1 : lb0)) = N::cv(vb);
                     if (ro ? c1_in : c0_in) *reinterpret_cast<T *>(pk + (ro ? lb1 : lb0)) = N::cv(rn_prev);
@@ -596,6 +619,214 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
         bp = QB(S);
         ep = maske(QE(S), k + 1);
         if (k + 1 + PD <= z1 + 1) issue(k + 1 + PD, QU(S), QB(S), QE(S));
+        step(k);
+    };
+    step(z0 - 1);
+    for (int kk = z0; kk <= z1; kk += PD) {
+        iter(std::integral_constant<int, 0>{}, kk);
+        if constexpr (PD > 1) { if (kk + 1 > z1) break; iter(std::integral_constant<int, 1>{}, kk + 1); }
+        if constexpr (PD > 2) { if (kk + 2 > z1) break; iter(std::integral_constant<int, 2>{}, kk + 2); }
+        if constexpr (PD > 3) { if (kk + 3 > z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
+    }
+}
+
+// ---------------------------------------------------------------------
+// The same sweep for beta = 1.  Every interior face has weight 1, so a cell
+// outside the box carries the boundary term of the box face it lies beyond
+// (2 g for Dirichlet, 0 for Neumann) and each cell's diagonal sum is fixed
+// by its position: no per-face branches or selects remain.
+template <class T, int TX, int TY, bool ZIN, int PD>
+__device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const int blk,
+                                                typename Num<T>::C *smem) {
+    using N = Num<T>;
+    using C = typename N::C;
+    constexpr int PXW = (TX + 4) / 2;  // pairs per region row
+    constexpr int RX = TX + 4, RY = TY + 4, PL = RX * RY;
+    C(*s_u)[RX] = reinterpret_cast<C(*)[RX]>(smem);                  // old u, plane k
+    C(*s_r)[RY][RX] = reinterpret_cast<C(*)[RY][RX]>(smem + PL);      // new red u, by plane parity
+    const T *__restrict__ uin = A.uin;
+    T *__restrict__ uout = A.uout;
+    const T *__restrict__ b = A.b;
+    const Geo &G = A.G;
+    const int cz = A.cz, tiles_x = A.tiles_x, tiles_y = A.tiles_y;
+
+    const int tid = threadIdx.x;
+    const int tx = blk % tiles_x;
+    const int rest = blk / tiles_x;
+    const int ty = rest % tiles_y;
+    const int tc = rest / tiles_y;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tc * cz;
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int z1 = min(z0 + cz, nz);
+    const size_t plane = (size_t)nx * ny;
+    const C h2 = C(G.h2), ah2 = C(G.ah2);
+
+    const int ry = tid / PXW, pc = tid - ry * PXW;
+    const int lx = 2 * pc;                  // LDS column of the pair's first cell
+    const int x = lx - 2, y = ry - 2;       // tile coordinates of the pair
+    const int gx = x0 + x, gy = y0 + y;     // global coordinates of its first cell
+    const bool row_in = gy >= 0 && gy < ny;
+    const bool c0_in = row_in && gx >= 0 && gx < nx;
+    const bool c1_in = row_in && gx + 1 >= 0 && gx + 1 < nx;
+    const bool even_nx = (nx & 1) == 0;
+    const bool core = x >= 0 && x < TX && y >= 0 && y < TY;
+    const size_t rowoff = (size_t)(row_in ? gy : 0) * nx;
+
+    // box faces: weight in the diagonal (2 Dirichlet, 0 Neumann) and the
+    // value carried by the cells beyond them
+    auto fw = [&](int d) -> C { return ((G.bcmask >> d) & 1) ? C(2) : C(0); };
+    auto hv = [&](int d) -> C { return ((G.bcmask >> d) & 1) ? C(2) * C(G.g[d]) : C(0); };
+    auto halo = [&](int c) -> C {
+        const int g = gx + c;
+        return g < 0 ? hv(0) : g >= nx ? hv(1) : gy < 0 ? hv(2) : gy >= ny ? hv(3) : C(0);
+    };
+    auto dg_xy = [&](int c) -> C {
+        const int g = gx + c;
+        return (g > 0 ? C(1) : fw(0)) + (g < nx - 1 ? C(1) : fw(1)) + (gy > 0 ? C(1) : fw(2)) +
+               (gy < ny - 1 ? C(1) : fw(3));
+    };
+    const C hout0 = halo(0), hout1 = halo(1), dxy0 = dg_xy(0), dxy1 = dg_xy(1);
+    const C hz_lo = hv(4), hz_hi = hv(5), wz_lo = fw(4), wz_hi = fw(5);
+    auto dg_z = [&](int k) -> C { return csel<C>(k > 0, C(1), wz_lo) + csel<C>(k < nz - 1, C(1), wz_hi); };
+
+    const uint32_t lb0 = (uint32_t)((c0_in ? rowoff + gx : 0) * sizeof(T));
+    const uint32_t lb1 = (uint32_t)((c1_in ? rowoff + gx + 1 : 0) * sizeof(T));
+    auto plane_at = [&](int k) -> size_t { return (size_t)min(max(k, 0), nz - 1) * plane * sizeof(T); };
+
+    struct P2 { C v[2]; };
+    P2 zero;
+    zero.v[0] = zero.v[1] = C(0);
+    auto ld_pair = [&](const T *__restrict__ a, int k) -> P2 {
+        const char *pk = reinterpret_cast<const char *>(a) + plane_at(k);
+        P2 r;
+        if (even_nx) {
+            const Pair<T> w = *reinterpret_cast<const Pair<T> *>(pk + lb0);
+            r.v[0] = N::ld(w.v[0]);
+            r.v[1] = N::ld(w.v[1]);
+        } else {
+            r.v[0] = N::ld(*reinterpret_cast<const T *>(pk + lb0));
+            r.v[1] = N::ld(*reinterpret_cast<const T *>(pk + lb1));
+        }
+        return r;
+    };
+    auto pick = [](const P2 &p, int c) -> C { return csel<C>(c, p.v[1], p.v[0]); };
+    auto masku = [&](P2 v, int k) -> P2 {
+        const bool kin = k >= 0 && k < nz;
+        const C zv = csel<C>(k < 0, hz_lo, hz_hi);
+        P2 r;
+        r.v[0] = csel<C>(kin && c0_in, v.v[0], csel<C>(kin, hout0, zv));
+        r.v[1] = csel<C>(kin && c1_in, v.v[1], csel<C>(kin, hout1, zv));
+        return r;
+    };
+
+    // current planes: u at k-1, k, k+1 (outside cells carry their boundary
+    // term); b at k-1, k, k+1 (never used outside the box)
+    P2 um, u0, up, bm, b0, bp;
+    static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
+    P2 qu0, qu1, qu2, qu3, qb0, qb1, qb2, qb3;
+    auto QU = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qu0; else if constexpr (v == 1) return qu1;
+        else if constexpr (v == 2) return qu2; else return qu3;
+    };
+    auto QB = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qb0; else if constexpr (v == 1) return qb1;
+        else if constexpr (v == 2) return qb2; else return qb3;
+    };
+    auto issue = [&](int k, P2 &du, P2 &db) {
+        if constexpr (!ZIN) du = ld_pair(uin, k);
+        db = zero;  // b is used on the tile and its ring only
+        if (y >= -1 && y <= TY) db = ld_pair(b, k);
+    };
+    {
+        P2 t0u, t0b, t1u, t1b, t2u, t2b;
+        issue(z0 - 2, t0u, t0b);
+        issue(z0 - 1, t1u, t1b);
+        issue(z0, t2u, t2b);
+        issue(z0 + 1, qu0, qb0);
+        if constexpr (PD > 1) issue(z0 + 2, qu1, qb1);
+        if constexpr (PD > 2) issue(z0 + 3, qu2, qb2);
+        if constexpr (PD > 3) issue(z0 + 4, qu3, qb3);
+        if constexpr (ZIN) {
+            um = masku(zero, z0 - 2);
+            u0 = masku(zero, z0 - 1);
+            up = masku(zero, z0);
+        } else {
+            um = masku(t0u, z0 - 2);
+            u0 = masku(t1u, z0 - 1);
+            up = masku(t2u, z0);
+        }
+        bm = t0b;
+        b0 = t1b;
+        bp = t2b;
+    }
+    C rn_cur = C(0), rn_prev = C(0), rn_prev2 = C(0);  // new red values of planes k, k-1, k-2
+
+    auto step = [&](int k) __attribute__((always_inline)) {
+        {
+            Pair<C> w;
+            w.v[0] = u0.v[0];
+            w.v[1] = u0.v[1];
+            *reinterpret_cast<Pair<C> *>(&s_u[ry][lx]) = w;
+        }
+        lds_barrier();
+        // ---- red cell of plane k (tile + 1-cell ring)
+        rn_prev2 = rn_prev;
+        rn_prev = rn_cur;
+        {
+            const int ro = (gy + k) & 1;  // red cell of the pair: x + ro
+            const int xr = x + ro;
+            const int lr = lx + ro;
+            const bool kin = k >= 0 && k < nz;
+            const bool ring = xr >= -1 && xr <= TX && y >= -1 && y <= TY;
+            C rv = csel<C>(kin, csel<C>(ro, hout1, hout0), csel<C>(k < 0, hz_lo, hz_hi));
+            if (kin && ring && (ro ? c1_in : c0_in)) {
+                const C off = ((s_u[ry][lr - 1] + s_u[ry][lr + 1]) + (s_u[ry - 1][lr] + s_u[ry + 1][lr])) +
+                              (pick(um, ro) + pick(up, ro));
+                const C dg = csel<C>(ro, dxy1, dxy0) + dg_z(k);
+                rv = qdiv<C>(fma_c<C>(h2, pick(b0, ro), off), ah2 + dg);
+            }
+            if (ring) s_r[k & 1][ry][lr] = rv;
+            rn_cur = rv;
+        }
+        // ---- black cell of plane k-1 (tile only); write the pair
+        {
+            const int kb = k - 1;
+            const int ro = (gy + kb) & 1;  // red cell of the pair on plane kb
+            const int bo = 1 - ro;         // black cell
+            if (core && kb >= z0 && kb < z1 && (bo ? c1_in : c0_in)) {
+                const int lb = lx + bo;
+                const C off = ((s_r[kb & 1][ry][lb - 1] + s_r[kb & 1][ry][lb + 1]) +
+                               (s_r[kb & 1][ry - 1][lb] + s_r[kb & 1][ry + 1][lb])) +
+                              (rn_prev2 + rn_cur);
+                const C dg = csel<C>(bo, dxy1, dxy0) + dg_z(kb);
+                const C vb = qdiv<C>(fma_c<C>(h2, pick(bm, bo), off), ah2 + dg);
+                char *pk = reinterpret_cast<char *>(uout) + plane_at(kb);
+                if (even_nx) {
+                    const T tb = N::cv(vb), tr = N::cv(rn_prev);
+                    store_pair_nt(reinterpret_cast<T *>(pk + lb0), bo ? tr : tb, bo ? tb : tr);
+                } else {
+                    *reinterpret_cast<T *>(pk + (bo ? lb1 : lb0)) = N::cv(vb);
+                    if (ro ? c1_in : c0_in) *reinterpret_cast<T *>(pk + (ro ? lb1 : lb0)) = N::cv(rn_prev);
+                }
+            } else if (core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
+                // odd nx: the pair's black cell lies outside the box
+                char *pk = reinterpret_cast<char *>(uout) + plane_at(kb);
+                *reinterpret_cast<T *>(pk + (ro ? lb1 : lb0)) = N::cv(rn_prev);
+            }
+        }
+        lds_barrier();
+    };
+
+    // shift in plane k+1 from ring slot S, refill the slot with k+1+PD, step k
+    auto iter = [&](auto S, int k) __attribute__((always_inline)) {
+        um = u0; u0 = up;
+        bm = b0; b0 = bp;
+        if constexpr (ZIN) up = masku(zero, k + 1);
+        else up = masku(QU(S), k + 1);
+        bp = QB(S);
+        if (k + 1 + PD <= z1 + 1) issue(k + 1 + PD, QU(S), QB(S));
         step(k);
     };
     step(z0 - 1);
@@ -867,6 +1098,7 @@ template <class T, int MODE, int TX, int TY, bool ZIN, int PD>
 __device__ __forceinline__ void rbgs_col_body(const SmoothArgs<T> &A, const int blk,
                                               typename Num<T>::C *smem) {
     if constexpr (MODE == COEF_CELL) rbgs_cell_body<T, TX, TY, ZIN, PD>(A, blk, smem);
+    else if constexpr (MODE == COEF_CONST) rbgs_const_body<T, TX, TY, ZIN, PD>(A, blk, smem);
     else rbgs_pair_body<T, MODE, TX, TY, ZIN, PD>(A, blk, smem);
 }
 
