@@ -18,6 +18,7 @@ from .oracle import (  # noqa: F401
     solve_cg,
     solve_vcycle,
     rbgs,
+    prolong_add,
     solve_reference,
     dense_matrix,
     dense_solve,

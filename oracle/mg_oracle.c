@@ -511,6 +511,20 @@ void orc_rbgs(int nx, int ny, int nz, double h, double a, const double *eps, con
     level_free(&L);
 }
 
+/* u (2nxc x 2nyc x 2nzc) += P e, the trilinear prolongation of the coarse
+ * field e (nxc x nyc x nzc) with the coarse level's face types bct, as one
+ * V-cycle applies it to the coarse correction. */
+void orc_prolong_add(int nxc, int nyc, int nzc, const int *bct, const double *e, double *u) {
+    orc_level C, F;
+    memset(&C, 0, sizeof C);
+    memset(&F, 0, sizeof F);
+    C.nx = nxc; C.ny = nyc; C.nz = nzc;
+    F.nx = 2 * nxc; F.ny = 2 * nyc; F.nz = 2 * nzc;
+    memcpy(C.bc_type, bct, 6 * sizeof(int));
+    memcpy(F.bc_type, bct, 6 * sizeof(int));
+    prolong_add(&C, e, &F, u);
+}
+
 /* Threads the oracle's parallel loops use (1 without OpenMP). */
 int orc_threads(void) {
 #ifdef _OPENMP

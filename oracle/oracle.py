@@ -65,6 +65,8 @@ def _load():
             lib.orc_rbgs.restype = None
             lib.orc_threads.argtypes = []
             lib.orc_threads.restype = c_int
+            lib.orc_prolong_add.argtypes = [c_int, c_int, c_int, ip, dp, dp]
+            lib.orc_prolong_add.restype = None
             lib.orc_num_levels.argtypes = [c_int, c_int, c_int, c_int]
             lib.orc_num_levels.restype = c_int
             _lib = lib
@@ -167,6 +169,21 @@ def solve_reference(p, rtol: float = 1e-13) -> np.ndarray:
     if rel > rtol:
         u, _, rel = solve_cg(p, rtol=rtol, u0=u)
     return u
+
+
+def prolong_add(e: np.ndarray, u: np.ndarray, bc_types: Sequence[str]) -> np.ndarray:
+    """u + P e: cell-centred trilinear prolongation of the coarse field e
+    (shape (nzc, nyc, nxc)) onto the fine grid of twice its size per axis,
+    ghost values reflected across the box faces (negated at Dirichlet faces,
+    where the correction vanishes)."""
+    lib = _load()
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    nzc, nyc, nxc = e.shape
+    out = np.array(u, dtype=np.float64, copy=True, order="C")
+    assert out.shape == (2 * nzc, 2 * nyc, 2 * nxc)
+    bct = np.array([DIRICHLET if t == "D" else NEUMANN for t in bc_types], dtype=np.int32)
+    lib.orc_prolong_add(nxc, nyc, nzc, _ip(bct), _dp(e), _dp(out))
+    return out
 
 
 def threads() -> int:

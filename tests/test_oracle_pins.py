@@ -273,3 +273,45 @@ def test_rbgs_fixed_point_and_convergence():
     assert _rel(oracle.rbgs(p, ud, 1), ud) < 1e-13
     u = oracle.rbgs(p, np.zeros(p.shape), 400)
     assert _rel(u, ud) < 1e-8
+
+
+# ------------------------------------------------------ prolongation pins
+# Trilinear cell-centred prolongation (weights 3/4 and 1/4 per axis, ghost
+# values reflected across the box faces, negated at Dirichlet faces).
+
+
+def test_prolong_preserves_constants_with_neumann_faces():
+    e = np.full((3, 5, 4), 2.5)
+    u = oracle.prolong_add(e, np.zeros((6, 10, 8)), ["N"] * 6)
+    assert np.allclose(u, 2.5, rtol=0, atol=1e-15)
+
+
+def test_prolong_reproduces_linear_fields_inside():
+    """Away from the faces the interpolation is exact for linear fields, on
+    a box with three different extents and three different slopes (a
+    swapped axis or a wrong weight breaks it)."""
+    nzc, nyc, nxc = 4, 5, 6
+    H = 0.2
+    Zc, Yc, Xc = np.meshgrid(*[(np.arange(n) + 0.5) * H for n in (nzc, nyc, nxc)], indexing="ij")
+    lin = lambda x, y, z: 0.3 + 1.7 * x - 0.9 * y + 2.3 * z  # noqa: E731
+    e = lin(Xc, Yc, Zc)
+    u0 = np.random.default_rng(5).standard_normal((2 * nzc, 2 * nyc, 2 * nxc))
+    u = oracle.prolong_add(e, u0, ["N", "D", "N", "D", "D", "N"])
+    Zf, Yf, Xf = np.meshgrid(*[(np.arange(2 * n) + 0.5) * H / 2 for n in (nzc, nyc, nxc)], indexing="ij")
+    inner = (slice(1, -1),) * 3
+    assert np.allclose((u - u0)[inner], lin(Xf, Yf, Zf)[inner], rtol=0, atol=1e-13)
+
+
+def test_prolong_dirichlet_ghost_halves_boundary_cells():
+    """A constant correction c next to a Dirichlet face: the ghost is -c, so a
+    fine cell touching one face gets c/2, an edge cell c/4, a corner c/8."""
+    c = 3.0
+    u = oracle.prolong_add(np.full((3, 3, 3), c), np.zeros((6, 6, 6)), ["D"] * 6)
+    assert u[3, 3, 3] == pytest.approx(c)
+    assert u[3, 3, 0] == pytest.approx(c / 2) and u[3, 0, 3] == pytest.approx(c / 2)
+    assert u[0, 3, 3] == pytest.approx(c / 2)
+    assert u[3, 0, 5] == pytest.approx(c / 4)
+    assert u[0, 0, 0] == pytest.approx(c / 8) and u[5, 5, 5] == pytest.approx(c / 8)
+    # a Neumann face reflects without a sign: the same cell keeps c
+    u = oracle.prolong_add(np.full((3, 3, 3), c), np.zeros((6, 6, 6)), ["N", "D", "D", "D", "D", "D"])
+    assert u[3, 3, 0] == pytest.approx(c) and u[3, 3, 5] == pytest.approx(c / 2)
