@@ -181,6 +181,13 @@ int mg_residual(mg_ctx *c, const double *f_dev, const double *x_dev, double *r_d
  * then black) of the finest-level equation to x_dev in place, FP64. */
 int mg_smooth(mg_ctx *c, const double *f_dev, double *x_dev, int sweeps);
 
+/* u_dev (level l) += P e_dev (level l+1): the cell-centred trilinear
+ * prolongation of a coarse correction, ghost values reflected across the
+ * box faces and negated at Dirichlet faces (paper Sec. 2, the V-cycle's
+ * interpolation step), FP64.  Dimensions from mg_level_dims; requires
+ * 0 <= l < mg_num_levels - 1. */
+int mg_prolong_add(mg_ctx *c, int l, const double *e_dev, double *u_dev);
+
 /* Number of levels and the dimensions of level l (0 = finest). */
 int mg_num_levels(const mg_ctx *c);
 int mg_level_dims(const mg_ctx *c, int l, int *nx, int *ny, int *nz);

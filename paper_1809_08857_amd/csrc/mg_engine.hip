@@ -753,6 +753,16 @@ int mg_smooth(mg_ctx *c, const double *f_dev, double *x_dev, int sweeps) {
     return MG_OK;
 }
 
+int mg_prolong_add(mg_ctx *c, int l, const double *e_dev, double *u_dev) {
+    if (!c || !e_dev || !u_dev) return set_err(MG_EINVAL, "mg_prolong_add: null argument");
+    if (l < 0 || l >= c->nlev - 1) return set_err(MG_EINVAL, "mg_prolong_add: level %d has no coarser level", l);
+    hipStream_t s = c->stream;
+    const Geo G = level_geo(c, l, false), Gc = level_geo(c, l + 1, false);
+    CK(prolong_add(s, ST_F64, G, u_dev, ST_F64, Gc, e_dev, nullptr));
+    CK(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
 int mg_num_levels(const mg_ctx *c) { return c ? c->nlev : 0; }
 
 int mg_level_dims(const mg_ctx *c, int l, int *nx, int *ny, int *nz) {

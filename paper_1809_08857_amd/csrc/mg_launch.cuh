@@ -108,11 +108,19 @@ hipError_t resid_restrict_T(hipStream_t s, const Geo &G, const Coef &Cf, const v
 
 template <class T>
 hipError_t prolong_T(hipStream_t s, const Geo &G, void *u, const Geo &Gc, const void *e, const int *done) {
-    dim3 grid, block;
-    int kz;
-    brick_shape(Gc.nx, G.ny, G.nz, 0, &grid, &block, &kz);
-    hipLaunchKernelGGL((prolong_k<T, T>), grid, block, 0, s, static_cast<T *>(u),
-                       static_cast<const T *>(e), G, Gc, done);
+    if ((G.nx | G.ny | G.nz) & 1 || Gc.nx * 2 != G.nx || Gc.ny * 2 != G.ny || Gc.nz * 2 != G.nz)
+        return hipErrorInvalidValue;
+    constexpr int BX = 64, BY = 4;
+    const long cols = (long)((Gc.nx + BX - 1) / BX) * ((G.ny + BY - 1) / BY);
+    // about 2048 workgroups, chunks of an even number of fine planes
+    long chunks = (2048 + cols - 1) / cols;
+    if (chunks > G.nz / 2) chunks = G.nz / 2;
+    if (chunks < 1) chunks = 1;
+    int kz = (int)((G.nz + chunks - 1) / chunks);
+    kz += kz & 1;
+    const dim3 grid((Gc.nx + BX - 1) / BX, (G.ny + BY - 1) / BY, (G.nz + kz - 1) / kz), block(BX, BY);
+    hipLaunchKernelGGL((prolong_col_k<T, BX, BY>), grid, block, 0, s, static_cast<T *>(u),
+                       static_cast<const T *>(e), G, Gc, kz, done);
     return hipGetLastError();
 }
 

@@ -1393,6 +1393,79 @@ __global__ __launch_bounds__(256) void prolong_k(T *__restrict__ u, const TC *__
                         blockIdx.y * blockDim.y + threadIdx.y, blockIdx.z);
 }
 
+// Prolongation, column form: u += P e on a level whose axes are all even.
+// A thread owns the fine pair (2I, 2I+1) of fine row j and marches up a
+// chunk of fine planes (even start).  The trilinear weights are separable:
+// each coarse plane is first combined across its two rows (J and J + sj,
+// weights 3/4, 1/4) into three values, for coarse columns I-1, I, I+1,
+// which stay in registers for both fine planes that read that coarse plane
+// (plane K serves fine planes 2K-1 .. 2K+2).  Ghost values outside the box
+// reflect the boundary cell, negated across a Dirichlet face; the signs of
+// the x and y ghosts are fixed per thread, those of the z ghosts per plane.
+template <class T, int BX, int BY>
+__global__ __launch_bounds__(BX *BY) void prolong_col_k(T *__restrict__ u, const T *__restrict__ e, Geo G,
+                                                        Geo Gc, int kz, const int *__restrict__ done) {
+    if (done && *done) return;
+    using N = Num<T>;
+    using C = typename N::C;
+    const int I = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    if (I >= Gc.nx || j >= G.ny) return;  // no barrier follows
+    const int k0 = blockIdx.z * kz, k1 = min(k0 + kz, G.nz);
+    const int ncx = Gc.nx, ncy = Gc.ny, ncz = Gc.nz;
+    const int J = j >> 1;
+    int J2 = J + ((j & 1) ? 1 : -1);
+    C sy = C(1);
+    if (J2 < 0) { J2 = 0; if (Gc.bcmask & 4) sy = C(-1); }
+    if (J2 >= ncy) { J2 = ncy - 1; if (Gc.bcmask & 8) sy = C(-1); }
+    int Im = I - 1, Ip = I + 1;
+    C sxm = C(1), sxp = C(1);
+    if (Im < 0) { Im = 0; if (Gc.bcmask & 1) sxm = C(-1); }
+    if (Ip >= ncx) { Ip = ncx - 1; if (Gc.bcmask & 2) sxp = C(-1); }
+    const size_t cplane = (size_t)ncx * ncy;
+    const size_t r1 = (size_t)J * ncx, r2 = (size_t)J2 * ncx;
+    const C wy2 = C(0.25) * sy;
+
+    struct R3 { C m, c, p; };
+    // coarse plane Kc combined across its two rows (and its ghost sign)
+    auto rows = [&](int Kc) -> R3 {
+        C sz = C(1);
+        if (Kc < 0) { Kc = 0; if (Gc.bcmask & 16) sz = C(-1); }
+        if (Kc >= ncz) { Kc = ncz - 1; if (Gc.bcmask & 32) sz = C(-1); }
+        const T *pl = e + (size_t)Kc * cplane;
+        R3 r;
+        r.m = sz * sxm * fma_c<C>(C(0.75), N::ld(pl[r1 + Im]), wy2 * N::ld(pl[r2 + Im]));
+        r.c = sz * fma_c<C>(C(0.75), N::ld(pl[r1 + I]), wy2 * N::ld(pl[r2 + I]));
+        r.p = sz * sxp * fma_c<C>(C(0.75), N::ld(pl[r1 + Ip]), wy2 * N::ld(pl[r2 + Ip]));
+        return r;
+    };
+    const size_t fplane = (size_t)G.nx * G.ny;
+    T *urow = u + (size_t)j * G.nx + 2 * I;
+    // fine plane k from coarse planes K = k/2 (weight 3/4) and its z
+    // neighbour o (1/4), then along x
+    auto apply = [&](int k, const R3 &w0, const R3 &o) {
+        const C cm = fma_c<C>(C(0.75), w0.m, C(0.25) * o.m);
+        const C cc = fma_c<C>(C(0.75), w0.c, C(0.25) * o.c);
+        const C cp = fma_c<C>(C(0.75), w0.p, C(0.25) * o.p);
+        const C v0 = fma_c<C>(C(0.75), cc, C(0.25) * cm);
+        const C v1 = fma_c<C>(C(0.75), cc, C(0.25) * cp);
+        Pair<T> *q = reinterpret_cast<Pair<T> *>(urow + (size_t)k * fplane);
+        Pair<T> w = *q;
+        w.v[0] = N::cv(N::ld(w.v[0]) + v0);
+        w.v[1] = N::cv(N::ld(w.v[1]) + v1);
+        *q = w;
+    };
+    const int K0 = k0 >> 1;
+    R3 wm = rows(K0 - 1), w0 = rows(K0);
+    for (int K = K0; 2 * K < k1; ++K) {
+        const R3 wp = rows(K + 1);
+        apply(2 * K, w0, wm);
+        if (2 * K + 1 < k1) apply(2 * K + 1, w0, wp);
+        wm = w0;
+        w0 = wp;
+    }
+}
+
 // ||b - A u||^2 and (optionally) ||b + boundary terms||^2 (brick with kz planes).
 template <class T, int MODE>
 __global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, const T *__restrict__ b,

@@ -74,6 +74,7 @@ def load() -> ctypes.CDLL:
         "mg_last_error": (ctypes.c_char_p, []),
         "mg_residual": (I, [P, P, P, P, pD, pD]),
         "mg_smooth": (I, [P, P, P, I]),
+        "mg_prolong_add": (I, [P, I, P, P]),
         "mg_num_levels": (I, [P]),
         "mg_level_dims": (I, [P, I, pI, pI, pI]),
         "mg_set_tiling": (I, [P, I, I]),
@@ -179,6 +180,10 @@ def mg_residual(ctx, f, x, r=None) -> Tuple[float, float]:
 
 def mg_smooth(ctx, f, x, sweeps: int) -> int:
     return _check(load().mg_smooth(ctx, _ptr(f), _ptr(x), sweeps))
+
+
+def mg_prolong_add(ctx, l: int, e, u) -> int:
+    return _check(load().mg_prolong_add(ctx, l, _ptr(e), _ptr(u)))
 
 
 def mg_num_levels(ctx) -> int:

@@ -131,6 +131,33 @@ def test_smoother_boundary_faces(pattern, dims, wide):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("pattern", range(len(_BC_PATTERNS)))
+def test_prolongation_parity(pattern):
+    """u += P e at every level of a ragged three-level hierarchy (each face
+    type on each side) against the oracle's prolongation."""
+    p = synth.random_problem(56, 20, 36, 50 + pattern, bc=_BC_PATTERNS[pattern], a=0.0)
+    s = make_solver(p)
+    try:
+        nlev = mg.mg_num_levels(s.ctx)
+        assert nlev >= 3
+        rng = np.random.default_rng(300 + pattern)
+        for lev in range(nlev - 1):
+            fx, fy, fz = mg.mg_level_dims(s.ctx, lev)
+            cx, cy, cz = mg.mg_level_dims(s.ctx, lev + 1)
+            print(f"prolongation {p.name} level {lev}: {cx}x{cy}x{cz} -> {fx}x{fy}x{fz}", flush=True)
+            e = rng.standard_normal((cz, cy, cx))
+            u0 = rng.standard_normal((fz, fy, fx))
+            ref = oracle.prolong_add(e, u0, p.bc_types())
+            u = dev(u0)
+            mg.mg_prolong_add(s.ctx, lev, dev(e), u)
+            got = u.cpu().numpy()
+            assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max(), lev
+        with pytest.raises(mg.MgError):
+            mg.mg_prolong_add(s.ctx, nlev - 1, dev(np.zeros(1)), dev(np.zeros(1)))
+    finally:
+        s.close()
+
+
 def _manufactured_exact(n):
     h = 1.0 / n
     c = (np.arange(n) + 0.5) * h
