@@ -7,7 +7,9 @@ streamer filament) and the three screened photon-group equations
 relative residual 1e-10 (the potential, whose error/residual ratio is
 ~10-25, to 1e-11 so that it also agrees with the FP64 oracle to 1e-9).
 Inputs are generated once on the host, copied to HBM and stay resident; the
-timed region covers whole solves only.
+timed region covers whole solves only.  The four equations are independent:
+each has its own context and HIP stream and the four solves of a step run at
+once from four host threads (--sequential: one after another).
 
 Other workloads (--workload):
   mixed512   the same four solves at 512^3 in FP64, FP32-in-FP64 and
@@ -21,8 +23,11 @@ Other workloads (--workload):
 Prints one JSON line: solves/s (value), DoF/s, ms per step, the roofline of
 the dominant kernel (the finest-level red-black smoother of the photon-group
 solves, which takes the largest share of the step; timed live with HIP
-events inside the library; the potential's smoother is reported beside it)
-and the CPU oracle timed on a bounded sample.
+events inside the library, in a sequential pass of the same steps that
+follows the timed one, because launches of concurrent streams interleave on
+the CUs and an event pair would then time other streams' work too; the
+potential's smoother is reported beside it) and the CPU oracle timed on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -52,6 +57,8 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--sequential", action="store_true",
+                    help="issue the four solves of a step one after another (default: four streams at once)")
     return ap.parse_args()
 
 
@@ -140,14 +147,14 @@ def copy_calibration(args):
             "copies": max(1, args.steps)}
 
 
-def make_solvers(probs, precision, autotune=False):
+def make_solvers(probs, precision, autotune=False, streams=None):
     import torch
     from paper_1809_08857_amd import mg
     out = []
-    for p in probs:
+    for q, p in enumerate(probs):
         eps = torch.from_numpy(p.eps).cuda() if p.eps is not None else None
         s = mg.Solver(p.nx, p.ny, p.nz, p.h, eps=eps, a=p.a, bc_types=p.bc_types(), bc_values=p.bc_values(),
-                      precision=precision, rtol=rtol_for(p))
+                      precision=precision, rtol=rtol_for(p), stream=None if streams is None else streams[q])
         if autotune:
             mg.mg_autotune(s.ctx, 3)
         out.append(s)
@@ -177,39 +184,59 @@ def timed(step, steps, warmup, ctx=None):
     return dt, res, roof
 
 
-def run_set(n, seed, precision, steps, warmup, autotune):
-    """Four solves of one field update at n^3; returns (solves/s, ms/step, cycles, roofline)."""
+def run_set(n, seed, precision, steps, warmup, autotune, concurrent=True):
+    """Four solves of one field update at n^3.  The four equations are
+    independent, so by default each has its own context on its own HIP
+    stream and the four solves of a step run from four host threads at once:
+    the coarse levels and the one-workgroup bottom solves of one equation
+    then share the GPU with the others' work.  A second, sequential pass of
+    the same steps (solves one after another) follows; the finest-level
+    smoothers are timed live in that pass, where their launches do not
+    interleave with another stream's.  Returns (solves/s, ms/step, cycles,
+    roofline, sequential solves/s, sequential ms/step)."""
     import numpy as np
     import torch
     import synth
+    from concurrent.futures import ThreadPoolExecutor
     from paper_1809_08857_amd import mg
     probs = synth.streamer_set(n, seed=seed)
     f_dev = torch.from_numpy(probs[0].f).cuda()  # the same source drives all four
-    solvers = make_solvers(probs, precision, autotune)
+    streams = [torch.cuda.Stream() for _ in probs] if concurrent else None
+    solvers = make_solvers(probs, precision, autotune, streams)
     xs = [torch.zeros(p.shape, dtype=torch.float64, device="cuda") for p in probs]
     torch.cuda.synchronize()
 
-    def step():
-        cyc = []
-        for s, x in zip(solvers, xs):
-            rc, st = s.solve(f_dev, x)
-            if rc != mg.MG_OK:
-                raise RuntimeError(f"solve did not converge: {st.as_dict()}")
-            cyc.append(st.cycles)
-        return cyc
+    def solve_one(q):
+        rc, st = solvers[q].solve(f_dev, xs[q])
+        if rc != mg.MG_OK:
+            raise RuntimeError(f"solve did not converge: {st.as_dict()}")
+        return st.cycles
 
+    def step_seq():
+        return [solve_one(q) for q in range(len(solvers))]
+
+    dt = cycles = None
+    if concurrent:
+        with ThreadPoolExecutor(len(solvers)) as pool:
+            dt, cycles, _ = timed(lambda: list(pool.map(solve_one, range(len(solvers)))), steps, warmup)
     # the finest-level smoother of the first photon group (beta = 1: the
     # kernel with the largest share of the step) and of the potential
-    # (cell permittivity) are timed live
-    dt, cycles, roofs = timed(step, steps, warmup, [solvers[1].ctx, solvers[0].ctx])
+    # (cell permittivity), timed live in the sequential pass
+    dt_s, cycles_s, roofs = timed(step_seq, steps, warmup, [solvers[1].ctx, solvers[0].ctx])
+    if not concurrent:
+        dt, cycles = dt_s, cycles_s
     for s in solvers:
         s.close()
     del xs, f_dev
     torch.cuda.empty_cache()
     roof = roofs[0]
-    if roof is not None and roofs[1] is not None:
-        roof = dict(roof, other_smoother=roofs[1])
-    return 4 * steps / dt, dt / steps * 1e3, [int(c) for c in np.mean(np.array(cycles), axis=0).round()], roof
+    if roof is not None:
+        roof = dict(roof, timed_in="the sequential pass of the same steps (solves one after another)")
+        if roofs[1] is not None:
+            roof["other_smoother"] = roofs[1]
+    nsol = len(probs)
+    return (nsol * steps / dt, dt / steps * 1e3, [int(c) for c in np.mean(np.array(cycles), axis=0).round()],
+            roof, nsol * steps / dt_s, dt_s / steps * 1e3)
 
 
 def base_line(args, value, ms, cfg, dtype, roof, dof=None):
@@ -339,10 +366,13 @@ def main():
     if args.workload == "streamer256":
         n = args.n or 256
         prec = args.precision or "fp64"
-        value, ms, cycles, roof = run_set(n, args.seed, prec, args.steps, args.warmup, args.autotune)
+        value, ms, cycles, roof, seq_v, seq_ms = run_set(n, args.seed, prec, args.steps, args.warmup,
+                                                         args.autotune, not args.sequential)
         cfg = {"workload": f"streamer field update: potential (eps slab) + 3 photon groups at {n}^3, "
                            f"zero guess to rel. residual 1e-10 (potential 1e-11)", "grid": [n, n, n],
-               "solves_per_step": 4, "precision": prec, "cycles_per_solve": cycles}
+               "solves_per_step": 4, "precision": prec, "cycles_per_solve": cycles,
+               "solves_in_flight": 1 if args.sequential else 4,
+               "sequential_pass": {"solves_per_s": round(seq_v, 3), "ms_per_step": round(seq_ms, 3)}}
         out = base_line(args, value, ms, cfg, "f64" if prec == "fp64" else f"f64+{prec}", roof, value * n**3)
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(n, args.seed)
@@ -351,12 +381,15 @@ def main():
         prec = args.precision or "bf16"
         res = {}
         for pr in ("fp64", "fp32", "bf16"):
-            v, ms_, cyc, rf = run_set(n, args.seed, pr, args.steps, args.warmup, args.autotune)
+            v, ms_, cyc, rf, sv, sms = run_set(n, args.seed, pr, args.steps, args.warmup, args.autotune,
+                                                not args.sequential)
             res[pr] = {"solves_per_s": round(v, 3), "ms_per_step": round(ms_, 3), "cycles_per_solve": cyc,
+                       "sequential_pass": {"solves_per_s": round(sv, 3), "ms_per_step": round(sms, 3)},
                        "roofline": rf}
         value, ms = res[prec]["solves_per_s"], res[prec]["ms_per_step"]
         cfg = {"workload": f"streamer field update at {n}^3, FP64 refinement around low-precision V-cycles",
-               "grid": [n, n, n], "solves_per_step": 4, "precision": prec, "by_precision": res}
+               "grid": [n, n, n], "solves_per_step": 4, "precision": prec,
+               "solves_in_flight": 1 if args.sequential else 4, "by_precision": res}
         out = base_line(args, value, ms, cfg, f"f64+{prec}" if prec != "fp64" else "f64", res[prec]["roofline"],
                         value * n**3)
     elif args.workload == "batched64":

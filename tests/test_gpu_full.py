@@ -42,6 +42,37 @@ def test_full_size(problems, which):
         assert rel_l2(x, ref) <= 1e-9
 
 
+def test_concurrent_streams_match_sequential(problems):
+    """The bench's configuration: the four solves of the step on four HIP
+    streams from four host threads at once.  Each context's work is
+    independent and every reduction has a fixed order, so the results equal
+    the solves run one after another bit for bit, and the oracle's residual
+    of each meets its tolerance."""
+    from concurrent.futures import ThreadPoolExecutor
+    from tests.gpu_util import dev, make_solver
+    streams = [torch.cuda.Stream() for _ in problems]
+    solvers = [make_solver(p, rtol=1e-11 if p.a == 0.0 else 1e-10, stream=st) for p, st in zip(problems, streams)]
+    try:
+        f = dev(problems[0].f)
+        seq = [torch.zeros(p.shape, dtype=torch.float64, device="cuda") for p in problems]
+        par = [torch.zeros(p.shape, dtype=torch.float64, device="cuda") for p in problems]
+        torch.cuda.synchronize()
+        for s, x in zip(solvers, seq):
+            assert s.solve(f, x)[0] == mg.MG_OK
+        print("sequential done; concurrent:", flush=True)
+        with ThreadPoolExecutor(4) as pool:
+            rcs = list(pool.map(lambda q: solvers[q].solve(f, par[q])[0], range(4)))
+        torch.cuda.synchronize()
+        assert rcs == [mg.MG_OK] * 4
+        for p, a, b in zip(problems, seq, par):
+            assert torch.equal(a, b), p.name
+            _, rn, bn = oracle.residual(p, b.cpu().numpy())
+            assert rn / bn <= (1e-11 if p.a == 0.0 else 1e-10) * 1.001
+    finally:
+        for s in solvers:
+            s.close()
+
+
 N_MIXED = 512
 
 
