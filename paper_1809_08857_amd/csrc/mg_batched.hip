@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "mg_engine.h"
+#include "mg_ir.cuh"
 #include "mg_stencil.cuh"
 
 namespace mg {
@@ -62,7 +63,7 @@ template <class TL> struct BIr {
     int slot, bslot, ref_slot;
     double rtol2;
     int *done;
-    int gx, gy, kz, nblk;
+    int gx, gy, kz, nblk;  // column-kernel tiles in x and y, planes per z chunk, workgroups
     int has_e, zero_x;
 };
 
@@ -114,59 +115,28 @@ __global__ __launch_bounds__(kBX *kBY) void b_prolong_k(const BProlong<T> *__res
     prolong_body<T, T>(it.u, it.e, it.G, it.Gc, bx * kBX + threadIdx.x, by * kBY + threadIdx.y, bz);
 }
 
-template <class TL, int MODE>
-__device__ __forceinline__ void b_ir_body(const BIr<TL> &it, int blk) {
-    const Geo &G = it.G;
-    const int bx = blk % it.gx, rest = blk / it.gx;
-    const int by = rest % it.gy, bz = rest / it.gy;
-    const int i = bx * kBX + threadIdx.x, j = by * kBY + threadIdx.y;
-    const int k0 = bz * it.kz, k1 = min(k0 + it.kz, G.nz);
-    const size_t sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
-    double sr = 0.0, sb = 0.0;
-    if (i < G.nx && j < G.ny) {
-        for (int k = k0; k < k1; ++k) {
-            const size_t p = (size_t)k * sz + (size_t)j * sy + i;
-            auto X = [&](size_t m) -> double {
-                if (it.zero_x) return 0.0;
-                return it.has_e ? it.x[m] + (double)Num<TL>::ld(it.e[m]) : it.x[m];
-            };
-            auto nb = [&](int d) -> size_t {
-                return d == 0 ? p - 1 : d == 1 ? p + 1 : d == 2 ? p - sy : d == 3 ? p + sy : d == 4 ? p - sz : p + sz;
-            };
-            double eP = 1.0;
-            if constexpr (MODE == COEF_CELL) eP = it.eps[p];
-            double off, dg;
-            six_faces<double, MODE>(
-                G, i, j, k, eP, [&](int d) { return X(nb(d)); }, [&](int d) { return it.eps[nb(d)]; },
-                [&](int) { return 1.0; }, off, dg);
-            const double xp = X(p);
-            if (it.has_e) it.xout[p] = xp;
-            if (it.zero_x) it.xout[p] = 0.0;
-            const double rv = it.f[p] - G.a * xp - G.ih2 * (dg * xp - off);
-            it.rl[p] = Num<TL>::cv(typename Num<TL>::C(rv));
-            sr += rv * rv;
-            if (it.bslot >= 0) {  // ||f + boundary terms||^2
-                double add = 0.0;
-                const bool at[6] = {i == 0, i == G.nx - 1, j == 0, j == G.ny - 1, k == 0, k == G.nz - 1};
-#pragma unroll
-                for (int d = 0; d < 6; ++d)
-                    if (at[d] && ((G.bcmask >> d) & 1)) add += 2.0 * eP * G.g[d];
-                const double bb = it.f[p] + G.ih2 * add;
-                sb += bb * bb;
-            }
-        }
-    }
-    reduce2_finish<kBX * kBY>(sr, sb, it.ws, it.slot, it.bslot, blk, it.nblk, it.ref_slot, it.rtol2, it.done);
-}
+// FP64 refinement pass of every problem: the single engine's column kernel
+// body, one workgroup per (problem, tile and z chunk).
+constexpr int kIrTX = 64, kIrTY = 4;
 
 template <class TL>
-__global__ __launch_bounds__(kBX *kBY) void b_ir_k(const BIr<TL> *__restrict__ items,
-                                                   const WorkRef *__restrict__ work, int check_done) {
+__global__ __launch_bounds__(kIrTX *kIrTY) void b_ir_k(const BIr<TL> *__restrict__ items,
+                                                       const WorkRef *__restrict__ work, int check_done) {
     const WorkRef r = work[blockIdx.x];
     const BIr<TL> it = items[r.item];
     if (check_done && it.done && *it.done) return;
-    if (it.mode == COEF_CELL) b_ir_body<TL, COEF_CELL>(it, r.blk);
-    else b_ir_body<TL, COEF_CONST>(it, r.blk);
+#define MG_B_IR(MODE, HE)                                                                                     \
+    ir_col_body<TL, MODE, HE, kIrTX, kIrTY>(it.x, it.e, it.xout, it.f, it.eps, it.G, it.rl, it.ws, it.slot,   \
+                                            it.bslot, it.kz, it.gx, it.gy, r.blk, it.nblk, it.ref_slot,       \
+                                            it.rtol2, it.done, it.zero_x != 0)
+    if (it.mode == COEF_CELL) {
+        if (it.has_e) MG_B_IR(COEF_CELL, true);
+        else MG_B_IR(COEF_CELL, false);
+    } else {
+        if (it.has_e) MG_B_IR(COEF_CONST, true);
+        else MG_B_IR(COEF_CONST, false);
+    }
+#undef MG_B_IR
 }
 
 // ------------------------------------------------------------ plan
@@ -232,7 +202,7 @@ hipError_t launch_phase_st(hipStream_t s, const Launch &L, char *base, int st) {
 template <class TL>
 hipError_t launch_ir(hipStream_t s, char *base, size_t items, size_t work, int nwork, bool check_done) {
     if (nwork <= 0) return hipSuccess;
-    hipLaunchKernelGGL(b_ir_k<TL>, dim3(nwork), dim3(kBX, kBY), 0, s,
+    hipLaunchKernelGGL(b_ir_k<TL>, dim3(nwork), dim3(kIrTX * kIrTY), 0, s,
                        reinterpret_cast<const BIr<TL> *>(base + items), reinterpret_cast<const WorkRef *>(base + work),
                        check_done ? 1 : 0);
     return hipGetLastError();
@@ -456,6 +426,20 @@ static int build_plan(BatchPlan *P, int count, mg_ctx *const *c, const double *c
     {
         std::vector<BIr<TL>> it[4];
         std::vector<WorkRef> work;
+        // Workgroups of the whole pass: about 32 per CU, shared out by cell
+        // count.  Each workgroup ends with an atomic on its problem's
+        // counter, and a problem's workgroups run side by side, so many
+        // short workgroups would serialise on those counters.
+        int cus = 256;
+        {
+            int dev = 0, v = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                cus = v;
+        }
+        double cells_all = 0.0;
+        for (int i = 0; i < count; ++i) cells_all += (double)c[i]->L[0].n;
+        const double budget = 32.0 * cus;
         for (int i = 0; i < count; ++i) {
             Ctx *ci = c[i];
             const Geo G0 = level_geo(ci, 0, true);
@@ -470,15 +454,19 @@ static int build_plan(BatchPlan *P, int count, mg_ctx *const *c, const double *c
             b.ref_slot = 1;
             b.rtol2 = ci->d.rtol * ci->d.rtol;
             b.done = P->flags + i;
-            b.gx = (G0.nx + kBX - 1) / kBX;
-            b.gy = (G0.ny + kBY - 1) / kBY;
-            const int room = std::max(1, kMaxRedBlocks / (b.gx * b.gy));
-            const int gz = std::min(G0.nz, room);
+            // tiles of the column kernel and z chunks, at most kMaxRedBlocks per problem
+            b.gx = (G0.nx + kIrTX - 1) / kIrTX;
+            b.gy = (G0.ny + kIrTY - 1) / kIrTY;
+            const int cols = b.gx * b.gy;
+            const int room = std::max(1, kMaxRedBlocks / cols);
+            const double want = budget * (double)ci->L[0].n / cells_all;
+            const int gz = std::max(1, std::min({G0.nz, room, (int)std::ceil(want / cols)}));
             b.kz = (G0.nz + gz - 1) / gz;
             b.nblk = b.gx * b.gy * ((G0.nz + b.kz - 1) / b.kz);
             if (b.nblk > kMaxRedBlocks)
                 return set_err(MG_EINVAL, "mg_solve_batched: problem %d is too wide for the batched "
-                                          "refinement pass (nx*ny > %d)", i, kMaxRedBlocks * kBX * kBY);
+                                          "refinement pass (more than %d tiles of %dx%d per plane)", i,
+                               kMaxRedBlocks, kIrTX, kIrTY);
             b.has_e = 1;
             b.zero_x = 0;
             b.bslot = -1;

@@ -1,5 +1,6 @@
 // Set-up kernels, FP64 refinement kernels and the storage-type dispatch of
 // the stencil launchers.
+#include "mg_ir.cuh"
 #include "mg_stencil.cuh"
 
 namespace mg {
@@ -363,15 +364,6 @@ hipError_t resid_out(hipStream_t s, const Geo &G, const Coef &C, const double *u
 }
 
 // ------------------------------------------------------------ refinement
-// xn = x + e (FP64 + low precision), r = b - A xn in FP64, r stored in the
-// low-precision type, ||r||^2 accumulated in FP64.
-//
-// Block: a TX x TY tile of columns (one thread each) marching up a chunk of
-// z planes.  xn (and eps) of planes k-1, k, k+1 stay in the thread's
-// registers, loaded one step ahead of use; the in-plane neighbours of
-// plane k come from an LDS plane with a one-cell halo (two buffers by plane
-// parity, so one barrier per plane).  Edge threads also carry the halo cell
-// beyond their edge; neighbours outside the box are never read.
 template <class TL, int MODE, bool HAS_E, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void ir_col_k(const double *__restrict__ x, const TL *__restrict__ e,
                                                    double *__restrict__ xout, const double *__restrict__ b,
@@ -380,106 +372,8 @@ __global__ __launch_bounds__(TX *TY) void ir_col_k(const double *__restrict__ x,
                                                    int nblk, int ref_slot, double rtol2, int *__restrict__ done_out,
                                                    const int *__restrict__ done_in) {
     if (done_in && *done_in) return;
-    constexpr bool CELL = (MODE == COEF_CELL);
-    __shared__ double su[2][TY + 2][TX + 2];
-    __shared__ double se[CELL ? 2 : 1][CELL ? TY + 2 : 1][CELL ? TX + 2 : 1];
-    const int blk = xcd_remap(blockIdx.x, nblk);
-    const int tx = blk % tiles_x, rest = blk / tiles_x;
-    const int ty = rest % tiles_y, tc = rest / tiles_y;
-    const int x0 = tx * TX, y0 = ty * TY, z0 = tc * cz;
-    const int nx = G.nx, ny = G.ny, nz = G.nz;
-    const int z1 = min(z0 + cz, nz);
-    const size_t plane = (size_t)nx * ny;
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int i = x0 + lx, j = y0 + ly;
-    const bool inc = i < nx && j < ny;
-    const size_t col = inc ? (size_t)j * nx + i : 0;
-    // halo roles: x-edge threads carry (i -/+ 1, j), y-edge threads (i, j -/+ 1)
-    const int hxi = lx == 0 ? i - 1 : (lx == TX - 1 ? i + 1 : -1);
-    const int hyj = ly == 0 ? j - 1 : (ly == TY - 1 ? j + 1 : -1);
-    const bool hx = hxi >= 0 && hxi < nx && j < ny;
-    const bool hy = hyj >= 0 && hyj < ny && i < nx;
-    const size_t colx = hx ? (size_t)j * nx + hxi : 0;
-    const size_t coly = hy ? (size_t)hyj * nx + i : 0;
-    const int sxl = lx == 0 ? 0 : TX + 1, syl = ly == 0 ? 0 : TY + 1;
-
-    auto X = [&](size_t m) -> double {
-        if constexpr (HAS_E) return x[m] + (double)Num<TL>::ld(e[m]);
-        else return x[m];
-    };
-    auto ldx = [&](bool ok, size_t c, int k) -> double {
-        return (ok && k >= 0 && k < nz) ? X((size_t)k * plane + c) : 0.0;
-    };
-    auto lde = [&](bool ok, size_t c, int k) -> double {
-        if constexpr (CELL) return (ok && k >= 0 && k < nz) ? eps[(size_t)k * plane + c] : 1.0;
-        else return 1.0;
-    };
-    // own column: planes k-1, k, k+1 and the prefetch k+2; halo: k and k+1
-    double um = ldx(inc, col, z0 - 1), u0 = ldx(inc, col, z0), up = ldx(inc, col, z0 + 1), uq;
-    double em = lde(inc, col, z0 - 1), e0 = lde(inc, col, z0), ep = lde(inc, col, z0 + 1), eq;
-    double hx0 = ldx(hx, colx, z0), hy0 = ldx(hy, coly, z0), hx1, hy1;
-    double ehx0 = lde(hx, colx, z0), ehy0 = lde(hy, coly, z0), ehx1, ehy1;
-    double b0 = (inc && z0 < nz) ? b[(size_t)z0 * plane + col] : 0.0, b1;
-    double sr = 0.0;
-    for (int k = z0; k < z1; ++k) {
-        // loads for the next step
-        uq = ldx(inc, col, k + 2);
-        eq = lde(inc, col, k + 2);
-        hx1 = ldx(hx, colx, k + 1);
-        hy1 = ldx(hy, coly, k + 1);
-        ehx1 = lde(hx, colx, k + 1);
-        ehy1 = lde(hy, coly, k + 1);
-        b1 = (inc && k + 1 < z1) ? b[(size_t)(k + 1) * plane + col] : 0.0;
-        // publish plane k
-        const int q = k & 1;
-        su[q][ly + 1][lx + 1] = u0;
-        if (lx == 0 || lx == TX - 1) su[q][ly + 1][sxl] = hx0;
-        if (ly == 0 || ly == TY - 1) su[q][syl][lx + 1] = hy0;
-        if constexpr (CELL) {
-            se[q][ly + 1][lx + 1] = e0;
-            if (lx == 0 || lx == TX - 1) se[q][ly + 1][sxl] = ehx0;
-            if (ly == 0 || ly == TY - 1) se[q][syl][lx + 1] = ehy0;
-        }
-        lds_barrier();
-        if (inc) {
-            auto un = [&](int d) -> double {
-                switch (d) {
-                    case 0: return su[q][ly + 1][lx];
-                    case 1: return su[q][ly + 1][lx + 2];
-                    case 2: return su[q][ly][lx + 1];
-                    case 3: return su[q][ly + 2][lx + 1];
-                    case 4: return um;
-                    default: return up;
-                }
-            };
-            auto en = [&](int d) -> double {
-                if constexpr (CELL) {
-                    switch (d) {
-                        case 0: return se[q][ly + 1][lx];
-                        case 1: return se[q][ly + 1][lx + 2];
-                        case 2: return se[q][ly][lx + 1];
-                        case 3: return se[q][ly + 2][lx + 1];
-                        case 4: return em;
-                        default: return ep;
-                    }
-                } else {
-                    return 1.0;
-                }
-            };
-            double off, dg;
-            six_faces<double, MODE>(G, i, j, k, CELL ? e0 : 1.0, un, en, [&](int) { return 1.0; }, off, dg);
-            const size_t p = (size_t)k * plane + col;
-            if constexpr (HAS_E) xout[p] = u0;
-            const double r = b0 - G.a * u0 - G.ih2 * (dg * u0 - off);
-            rl[p] = Num<TL>::cv(typename Num<TL>::C(r));
-            sr += r * r;
-        }
-        um = u0, u0 = up, up = uq;
-        em = e0, e0 = ep, ep = eq;
-        hx0 = hx1, hy0 = hy1, ehx0 = ehx1, ehy0 = ehy1;
-        b0 = b1;
-    }
-    reduce2_finish<TX * TY>(sr, 0.0, ws, slot, -1, blk, nblk, ref_slot, rtol2, done_out);
+    ir_col_body<TL, MODE, HAS_E, TX, TY>(x, e, xout, b, eps, G, rl, ws, slot, -1, cz, tiles_x, tiles_y,
+                                         xcd_remap(blockIdx.x, nblk), nblk, ref_slot, rtol2, done_out, false);
 }
 
 template <class TL>
