@@ -136,7 +136,7 @@ int tile_for(const Ctx *c, const Geo &G, int st, int l, int *zc) {
         z = (st == ST_F64) ? c->zc64 : c->zc_lp;
     }
     if (t <= 0) t = default_tile(G, st);
-    if (z <= 0) z = default_zchunk(G, t);
+    if (z <= 0) z = default_zchunk(G, t, st);
     *zc = z;
     return t;
 }

@@ -130,14 +130,17 @@ int default_tile(const Geo &G, int st) {
     return 6;                                 // 16 x 8
 }
 
-int default_zchunk(const Geo &G, int tile) {
+int default_zchunk(const Geo &G, int tile, int st) {
     int tx, ty;
     tile_shape(tile, &tx, &ty);
     const long cols = (long)((G.nx + tx - 1) / tx) * ((G.ny + ty - 1) / ty);
-    // about one workgroup per CU (a workgroup holds 5-12 waves) while
-    // keeping >= 8 planes per chunk, so the two planes recomputed at each
-    // chunk boundary stay a small overhead
-    long chunks = (256 + cols - 1) / cols;
+    // about one workgroup per CU (a workgroup holds 5-12 waves) for FP64,
+    // two for the FP32/BF16 sweeps, whose smaller register footprint lets
+    // two workgroups share a CU and hide each other's per-plane latency;
+    // >= 8 planes per chunk, so the two planes recomputed at each chunk
+    // boundary stay a small overhead
+    const long target = st == ST_F64 ? 256 : 512;
+    long chunks = (target + cols - 1) / cols;
     long maxchunks = G.nz / 8;
     if (maxchunks < 1) maxchunks = 1;
     if (chunks > maxchunks) chunks = maxchunks;
