@@ -30,9 +30,9 @@ hipError_t smooth_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *
     SmoothArgs<T> A{static_cast<const T *>(uin), static_cast<T *>(uout), static_cast<const T *>(b), eps, bx,
                     by, bz, G, cz, tiles_x, tiles_y, nblk, done};
     if (zero_in)
-        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, true, kSmoothPD>), grid, block, 0, s, A);
+        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, true, kSmoothPDOf<T>>), grid, block, 0, s, A);
     else
-        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, false, kSmoothPD>), grid, block, 0, s, A);
+        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, false, kSmoothPDOf<T>>), grid, block, 0, s, A);
     return hipGetLastError();
 }
 
@@ -81,7 +81,7 @@ hipError_t rr_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, c
     RrArgs<T> A{static_cast<const T *>(u), static_cast<const T *>(b), eps, bx, by, bz, G,
                 static_cast<T *>(bc), cz, tiles_x, tiles_y, nblk, chk.ws, chk.slot, chk.ref_slot,
                 chk.rtol2, chk.done_out, chk.done_in};
-    hipLaunchKernelGGL((rr_col_k<T, MODE, TX, TY, kSmoothPD>), dim3(nblk), dim3(NTH), 0, s, A);
+    hipLaunchKernelGGL((rr_col_k<T, MODE, TX, TY, kSmoothPDOf<T>>), dim3(nblk), dim3(NTH), 0, s, A);
     return hipGetLastError();
 }
 

@@ -21,8 +21,12 @@
 
 namespace mg {
 
-// Prefetch depth of the column-pair kernels (planes in flight per array).
+// Prefetch depth of the column-pair kernels (planes in flight per array):
+// two planes for FP64; four for the 4- and 2-byte storage types, whose
+// planes carry half or a quarter of the bytes, so that about as many bytes
+// stay in flight per CU.
 constexpr int kSmoothPD = 2;
+template <class T> constexpr int kSmoothPDOf = sizeof(T) == 8 ? 2 : 4;
 
 template <class T> struct Num;
 template <> struct Num<double> {
