@@ -281,10 +281,10 @@ static SmoothArgs<T> smooth_args(const LvView &W, int tx, int ty, const int *don
     a.uin = static_cast<const T *>(W.u);
     a.uout = static_cast<T *>(W.t);
     a.b = static_cast<const T *>(W.b);
-    a.eps = static_cast<const T *>(W.C.eps);
-    a.fbx = static_cast<const T *>(W.C.bx);
-    a.fby = static_cast<const T *>(W.C.by);
-    a.fbz = static_cast<const T *>(W.C.bz);
+    a.eps = static_cast<const coef_t<T> *>(W.C.eps);
+    a.fbx = static_cast<const coef_t<T> *>(W.C.bx);
+    a.fby = static_cast<const coef_t<T> *>(W.C.by);
+    a.fbz = static_cast<const coef_t<T> *>(W.C.bz);
     a.G = W.G;
     a.tiles_x = (W.G.nx + tx - 1) / tx;
     a.tiles_y = (W.G.ny + ty - 1) / ty;
@@ -302,10 +302,10 @@ static RrArgs<T> rr_args(const LvView &W, const LvView &Wc, int tx, int ty, cons
     RrArgs<T> a{};
     a.u = static_cast<const T *>(W.u);
     a.b = static_cast<const T *>(W.b);
-    a.eps = static_cast<const T *>(W.C.eps);
-    a.fbx = static_cast<const T *>(W.C.bx);
-    a.fby = static_cast<const T *>(W.C.by);
-    a.fbz = static_cast<const T *>(W.C.bz);
+    a.eps = static_cast<const coef_t<T> *>(W.C.eps);
+    a.fbx = static_cast<const coef_t<T> *>(W.C.bx);
+    a.fby = static_cast<const coef_t<T> *>(W.C.by);
+    a.fbz = static_cast<const coef_t<T> *>(W.C.bz);
     a.G = W.G;
     a.bc = static_cast<T *>(Wc.bw);
     a.tiles_x = (W.G.nx + tx - 1) / tx;

@@ -478,10 +478,14 @@ int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) 
             c->tail++;
         }
         if (c->lp_store >= 0) {
-            const size_t es = store_size(c->lp_store);
+            // coefficients of the inner cycle: FP32 for both FP32 and BF16
+            // fields (BF16 coefficients perturb the inner operator enough to
+            // cost outer steps)
+            const int cst = ST_F32;
+            const size_t es = store_size(cst);
             if (!c->eps_lp) c->eps_lp = dalloc(c, n0 * es);
             if (!c->eps_lp) return set_err(MG_ENOMEM, "mg_set_coeffs: allocation failed");
-            CK(convert(s, c->eps, c->lp_store, c->eps_lp, n0));
+            CK(convert(s, c->eps, cst, c->eps_lp, n0));
             for (int l = 1; l < c->tail; ++l) {
                 Level &L = c->L[l];
                 const size_t nfx = (size_t)(L.nx + 1) * L.ny * L.nz, nfy = (size_t)L.nx * (L.ny + 1) * L.nz,
@@ -492,9 +496,9 @@ int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) 
                     L.lbz = dalloc(c, nfz * es);
                     if (!L.lbx || !L.lby || !L.lbz) return set_err(MG_ENOMEM, "mg_set_coeffs: allocation failed");
                 }
-                CK(convert(s, L.fbx, c->lp_store, L.lbx, nfx));
-                CK(convert(s, L.fby, c->lp_store, L.lby, nfy));
-                CK(convert(s, L.fbz, c->lp_store, L.lbz, nfz));
+                CK(convert(s, L.fbx, cst, L.lbx, nfx));
+                CK(convert(s, L.fby, cst, L.lby, nfy));
+                CK(convert(s, L.fbz, cst, L.lbz, nfz));
             }
         }
         c->has_eps = true;

@@ -11,17 +11,18 @@ constexpr int kTileTX[kNumTiles + 1] = {0, 64, 128, 64, 32, 32, 16};
 constexpr int kTileTY[kNumTiles + 1] = {0, 16, 8, 8, 8, 4, 8};
 
 template <class T>
-inline void coef_ptrs(const Coef &C, const T *&eps, const T *&bx, const T *&by, const T *&bz) {
-    eps = static_cast<const T *>(C.eps);
-    bx = static_cast<const T *>(C.bx);
-    by = static_cast<const T *>(C.by);
-    bz = static_cast<const T *>(C.bz);
+inline void coef_ptrs(const Coef &C, const coef_t<T> *&eps, const coef_t<T> *&bx, const coef_t<T> *&by,
+                      const coef_t<T> *&bz) {
+    eps = static_cast<const coef_t<T> *>(C.eps);
+    bx = static_cast<const coef_t<T> *>(C.bx);
+    by = static_cast<const coef_t<T> *>(C.by);
+    bz = static_cast<const coef_t<T> *>(C.bz);
 }
 
 template <class T, int MODE, int TX, int TY>
 hipError_t smooth_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *uin, void *uout,
                        const void *b, bool zero_in, int cz, const int *done) {
-    const T *eps, *bx, *by, *bz;
+    const coef_t<T> *eps, *bx, *by, *bz;
     coef_ptrs<T>(Cf, eps, bx, by, bz);
     const int tiles_x = (G.nx + TX - 1) / TX, tiles_y = (G.ny + TY - 1) / TY;
     const int chunks = (G.nz + cz - 1) / cz;
@@ -65,7 +66,7 @@ hipError_t smooth_T(hipStream_t s, const Geo &G, const Coef &Cf, const void *uin
 template <class T, int MODE, int TX, int TY>
 hipError_t rr_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, const void *b, void *bc,
                    const RrCheck &chk) {
-    const T *eps, *bx, *by, *bz;
+    const coef_t<T> *eps, *bx, *by, *bz;
     coef_ptrs<T>(Cf, eps, bx, by, bz);
     const int tiles_x = (G.nx + TX - 1) / TX, tiles_y = (G.ny + TY - 1) / TY;
     const long cols = (long)tiles_x * tiles_y;
@@ -131,7 +132,7 @@ hipError_t norm2_T(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, c
     const double rt2 = chk ? chk->rtol2 : 0.0;
     int *dout = chk ? chk->done_out : nullptr;
     const int *din = chk ? chk->done_in : nullptr;
-    const T *eps, *bx, *by, *bz;
+    const coef_t<T> *eps, *bx, *by, *bz;
     coef_ptrs<T>(Cf, eps, bx, by, bz);
     dim3 grid, block;
     int kz;

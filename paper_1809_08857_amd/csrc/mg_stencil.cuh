@@ -45,6 +45,13 @@ template <> struct Num<bf16> {
     __device__ static __forceinline__ bf16 cv(C v) { return __float2bfloat16(v); }
 };
 
+// Storage type of the coefficients (cell eps, stored faces) that go with
+// fields stored in T: BF16 fields keep FP32 coefficients, whose rounding
+// would otherwise perturb the inner operator enough to cost outer steps.
+template <class T> struct CoefStore { using type = T; };
+template <> struct CoefStore<bf16> { using type = float; };
+template <class T> using coef_t = typename CoefStore<T>::type;
+
 template <class T> struct alignas(2 * sizeof(T)) Pair {
     T v[2];
 };
@@ -262,10 +269,10 @@ __device__ __forceinline__ void six_faces(const Geo &G, int i, int j, int k, C e
 template <class T, int MODE>
 __device__ __forceinline__ typename Num<T>::C resid_global(const T *__restrict__ u,
                                                            const T *__restrict__ b,
-                                                           const T *__restrict__ eps,
-                                                           const T *__restrict__ bx,
-                                                           const T *__restrict__ by,
-                                                           const T *__restrict__ bz, const Geo &G,
+                                                           const coef_t<T> *__restrict__ eps,
+                                                           const coef_t<T> *__restrict__ bx,
+                                                           const coef_t<T> *__restrict__ by,
+                                                           const coef_t<T> *__restrict__ bz, const Geo &G,
                                                            int i, int j, int k) {
     using N = Num<T>;
     using C = typename N::C;
@@ -275,11 +282,11 @@ __device__ __forceinline__ typename Num<T>::C resid_global(const T *__restrict__
         return d == 0 ? p - 1 : d == 1 ? p + 1 : d == 2 ? p - sy : d == 3 ? p + sy : d == 4 ? p - sz : p + sz;
     };
     C eP = C(1);
-    if constexpr (MODE == COEF_CELL) eP = N::ld(eps[p]);
+    if constexpr (MODE == COEF_CELL) eP = Num<coef_t<T>>::ld(eps[p]);
     C off, dg;
     six_faces<C, MODE>(
         G, i, j, k, eP, [&](int d) { return N::ld(u[nb(d)]); },
-        [&](int d) { return N::ld(eps[nb(d)]); },
+        [&](int d) { return Num<coef_t<T>>::ld(eps[nb(d)]); },
         [&](int d) {
             switch (d) {
                 case 0: return face_x(bx, G, i, j, k);
@@ -316,8 +323,8 @@ template <class T> struct SmoothArgs {
     const T *uin;
     T *uout;
     const T *b;
-    const T *eps;
-    const T *fbx, *fby, *fbz;
+    const coef_t<T> *eps;
+    const coef_t<T> *fbx, *fby, *fbz;
     Geo G;
     int cz, tiles_x, tiles_y, nblk;
     const int *done;
@@ -377,7 +384,7 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
     const T *__restrict__ uin = A.uin;
     T *__restrict__ uout = A.uout;
     const T *__restrict__ b = A.b;
-    const T *__restrict__ eps = A.eps;
+    const coef_t<T> *__restrict__ eps = A.eps;
     const Geo &G = A.G;
     const int cz = A.cz, tiles_x = A.tiles_x, tiles_y = A.tiles_y;
 
@@ -422,28 +429,33 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
     const C gz_lo = C(G.g[4]), gz_hi = C(G.g[5]);
     const C ez_lo = ((G.bcmask >> 4) & 1) ? big : C(0), ez_hi = ((G.bcmask >> 5) & 1) ? big : C(0);
 
-    // byte offsets of the pair's cells within a plane (0 outside the box)
-    // and the byte offset of plane k: loads and stores take a uniform
-    // plane base plus a 32-bit lane offset
-    const uint32_t lb0 = (uint32_t)((c0_in ? rowoff + gx : 0) * sizeof(T));
-    const uint32_t lb1 = (uint32_t)((c1_in ? rowoff + gx + 1 : 0) * sizeof(T));
-    auto plane_at = [&](int k) -> size_t { return (size_t)min(max(k, 0), nz - 1) * plane * sizeof(T); };
+    // offsets (elements) of the pair's cells within a plane (0 outside the
+    // box) and of plane k: loads and stores take a uniform plane base plus
+    // a 32-bit lane offset, both scaled by the element size of the array
+    // (the coefficients may be wider than the fields)
+    const uint32_t le0 = (uint32_t)(c0_in ? rowoff + gx : 0);
+    const uint32_t le1 = (uint32_t)(c1_in ? rowoff + gx + 1 : 0);
+    auto plane_el = [&](int k) -> size_t { return (size_t)min(max(k, 0), nz - 1) * plane; };
+    const uint32_t lb0 = le0 * (uint32_t)sizeof(T), lb1 = le1 * (uint32_t)sizeof(T);
+    auto plane_at = [&](int k) -> size_t { return plane_el(k) * sizeof(T); };
 
     struct P2 { C v[2]; };
     P2 zero;
     zero.v[0] = zero.v[1] = C(0);
     // one pair of plane k (a plane outside the box reads the nearest one;
     // the caller masks what it uses)
-    auto ld_pair = [&](const T *__restrict__ a, int k) -> P2 {
-        const char *pk = reinterpret_cast<const char *>(a) + plane_at(k);
+    auto ld_pair = [&](const auto *__restrict__ a, int k) -> P2 {
+        using A_ = std::remove_cv_t<std::remove_reference_t<decltype(*a)>>;
+        constexpr uint32_t es = sizeof(A_);
+        const char *pk = reinterpret_cast<const char *>(a) + plane_el(k) * es;
         P2 r;
         if (even_nx) {
-            const Pair<T> w = *reinterpret_cast<const Pair<T> *>(pk + lb0);
-            r.v[0] = N::ld(w.v[0]);
-            r.v[1] = N::ld(w.v[1]);
+            const Pair<A_> w = *reinterpret_cast<const Pair<A_> *>(pk + le0 * es);
+            r.v[0] = Num<A_>::ld(w.v[0]);
+            r.v[1] = Num<A_>::ld(w.v[1]);
         } else {
-            r.v[0] = N::ld(*reinterpret_cast<const T *>(pk + lb0));
-            r.v[1] = N::ld(*reinterpret_cast<const T *>(pk + lb1));
+            r.v[0] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + le0 * es));
+            r.v[1] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + le1 * es));
         }
         return r;
     };
@@ -693,23 +705,31 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
     const C hz_lo = hv(4), hz_hi = hv(5), wz_lo = fw(4), wz_hi = fw(5);
     auto dg_z = [&](int k) -> C { return csel<C>(k > 0, C(1), wz_lo) + csel<C>(k < nz - 1, C(1), wz_hi); };
 
-    const uint32_t lb0 = (uint32_t)((c0_in ? rowoff + gx : 0) * sizeof(T));
-    const uint32_t lb1 = (uint32_t)((c1_in ? rowoff + gx + 1 : 0) * sizeof(T));
-    auto plane_at = [&](int k) -> size_t { return (size_t)min(max(k, 0), nz - 1) * plane * sizeof(T); };
+    // offsets (elements) of the pair's cells within a plane (0 outside the
+    // box) and of plane k: loads and stores take a uniform plane base plus
+    // a 32-bit lane offset, both scaled by the element size of the array
+    // (the coefficients may be wider than the fields)
+    const uint32_t le0 = (uint32_t)(c0_in ? rowoff + gx : 0);
+    const uint32_t le1 = (uint32_t)(c1_in ? rowoff + gx + 1 : 0);
+    auto plane_el = [&](int k) -> size_t { return (size_t)min(max(k, 0), nz - 1) * plane; };
+    const uint32_t lb0 = le0 * (uint32_t)sizeof(T), lb1 = le1 * (uint32_t)sizeof(T);
+    auto plane_at = [&](int k) -> size_t { return plane_el(k) * sizeof(T); };
 
     struct P2 { C v[2]; };
     P2 zero;
     zero.v[0] = zero.v[1] = C(0);
-    auto ld_pair = [&](const T *__restrict__ a, int k) -> P2 {
-        const char *pk = reinterpret_cast<const char *>(a) + plane_at(k);
+    auto ld_pair = [&](const auto *__restrict__ a, int k) -> P2 {
+        using A_ = std::remove_cv_t<std::remove_reference_t<decltype(*a)>>;
+        constexpr uint32_t es = sizeof(A_);
+        const char *pk = reinterpret_cast<const char *>(a) + plane_el(k) * es;
         P2 r;
         if (even_nx) {
-            const Pair<T> w = *reinterpret_cast<const Pair<T> *>(pk + lb0);
-            r.v[0] = N::ld(w.v[0]);
-            r.v[1] = N::ld(w.v[1]);
+            const Pair<A_> w = *reinterpret_cast<const Pair<A_> *>(pk + le0 * es);
+            r.v[0] = Num<A_>::ld(w.v[0]);
+            r.v[1] = Num<A_>::ld(w.v[1]);
         } else {
-            r.v[0] = N::ld(*reinterpret_cast<const T *>(pk + lb0));
-            r.v[1] = N::ld(*reinterpret_cast<const T *>(pk + lb1));
+            r.v[0] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + le0 * es));
+            r.v[1] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + le1 * es));
         }
         return r;
     };
@@ -856,10 +876,10 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
     const T *__restrict__ uin = A.uin;
     T *__restrict__ uout = A.uout;
     const T *__restrict__ b = A.b;
-    const T *__restrict__ eps = A.eps;
-    const T *__restrict__ fbx = A.fbx;
-    const T *__restrict__ fby = A.fby;
-    const T *__restrict__ fbz = A.fbz;
+    const coef_t<T> *__restrict__ eps = A.eps;
+    const coef_t<T> *__restrict__ fbx = A.fbx;
+    const coef_t<T> *__restrict__ fby = A.fby;
+    const coef_t<T> *__restrict__ fbz = A.fbz;
     const Geo &G = A.G;
     const int cz = A.cz, tiles_x = A.tiles_x, tiles_y = A.tiles_y;
 
@@ -887,18 +907,19 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
 
     struct P2 { C v[2]; };
     // load one pair of plane k (values outside the box are masked by the caller)
-    auto ld_pair = [&](const T *__restrict__ a, int k) -> P2 {
+    auto ld_pair = [&](const auto *__restrict__ a, int k) -> P2 {
+        using A_ = std::remove_cv_t<std::remove_reference_t<decltype(*a)>>;
         P2 r;
         const bool kin = k >= 0 && k < nz;
         if (even_nx) {
             const size_t g = (kin && c0_in) ? (size_t)k * plane + rowoff + gx : 0;
-            const Pair<T> w = *reinterpret_cast<const Pair<T> *>(a + g);
-            r.v[0] = N::ld(w.v[0]);
-            r.v[1] = N::ld(w.v[1]);
+            const Pair<A_> w = *reinterpret_cast<const Pair<A_> *>(a + g);
+            r.v[0] = Num<A_>::ld(w.v[0]);
+            r.v[1] = Num<A_>::ld(w.v[1]);
         } else {
             const size_t base = (size_t)(kin ? k : 0) * plane + rowoff;
-            r.v[0] = N::ld(a[(kin && c0_in) ? base + gx : 0]);
-            r.v[1] = N::ld(a[(kin && c1_in) ? base + gx + 1 : 0]);
+            r.v[0] = Num<A_>::ld(a[(kin && c0_in) ? base + gx : 0]);
+            r.v[1] = Num<A_>::ld(a[(kin && c1_in) ? base + gx + 1 : 0]);
         }
         return r;
     };
@@ -1128,8 +1149,8 @@ __global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void rbgs_col_k(SmoothArgs
 template <class T> struct RrArgs {
     const T *u;
     const T *b;
-    const T *eps;
-    const T *fbx, *fby, *fbz;
+    const coef_t<T> *eps;
+    const coef_t<T> *fbx, *fby, *fbz;
     Geo G;
     T *bc;
     int cz, tiles_x, tiles_y, nblk;
@@ -1159,10 +1180,10 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
     C(*s_acc)[PXW] = reinterpret_cast<C(*)[PXW]>(smem + (CELL ? 2 : 1) * RY * RX);
     const T *__restrict__ u = A.u;
     const T *__restrict__ b = A.b;
-    const T *__restrict__ eps = A.eps;
-    const T *__restrict__ fbx = A.fbx;
-    const T *__restrict__ fby = A.fby;
-    const T *__restrict__ fbz = A.fbz;
+    const coef_t<T> *__restrict__ eps = A.eps;
+    const coef_t<T> *__restrict__ fbx = A.fbx;
+    const coef_t<T> *__restrict__ fby = A.fby;
+    const coef_t<T> *__restrict__ fbz = A.fbz;
     T *__restrict__ bc = A.bc;
     const Geo &G = A.G;
     const int cz = A.cz, tiles_x = A.tiles_x, tiles_y = A.tiles_y;
@@ -1190,13 +1211,14 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
     const size_t rowoff = (size_t)(row_in ? gy : 0) * nx;
 
     struct P2 { C v[2]; };
-    auto ld_pair = [&](const T *__restrict__ p, int k) -> P2 {
+    auto ld_pair = [&](const auto *__restrict__ p, int k) -> P2 {
+        using A_ = std::remove_cv_t<std::remove_reference_t<decltype(*p)>>;
         const bool kin = k >= 0 && k < nz;
         const size_t g = (kin && c_in) ? (size_t)k * plane + rowoff + gx : 0;
-        const Pair<T> w = *reinterpret_cast<const Pair<T> *>(p + g);
+        const Pair<A_> w = *reinterpret_cast<const Pair<A_> *>(p + g);
         P2 r;
-        r.v[0] = N::ld(w.v[0]);
-        r.v[1] = N::ld(w.v[1]);
+        r.v[0] = Num<A_>::ld(w.v[0]);
+        r.v[1] = Num<A_>::ld(w.v[1]);
         return r;
     };
     auto vmask = [&](P2 v, int k, C fill) {
@@ -1473,10 +1495,10 @@ __global__ __launch_bounds__(BX *BY) void prolong_col_k(T *__restrict__ u, const
 // ||b - A u||^2 and (optionally) ||b + boundary terms||^2 (brick with kz planes).
 template <class T, int MODE>
 __global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, const T *__restrict__ b,
-                                                     const T *__restrict__ eps,
-                                                     const T *__restrict__ bx,
-                                                     const T *__restrict__ by,
-                                                     const T *__restrict__ bz, Geo G, RedWs ws,
+                                                     const coef_t<T> *__restrict__ eps,
+                                                     const coef_t<T> *__restrict__ bx,
+                                                     const coef_t<T> *__restrict__ by,
+                                                     const coef_t<T> *__restrict__ bz, Geo G, RedWs ws,
                                                      int slot, int bslot, int kz, int ref_slot,
                                                      double rtol2, int *__restrict__ done_out,
                                                      const int *__restrict__ done_in) {
@@ -1495,7 +1517,7 @@ __global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, co
             if (bslot >= 0) {
                 // b + h^-2 sum_Dirichlet 2 beta_b g  (boundary beta as in the operator)
                 double be = 1.0;
-                if constexpr (MODE == COEF_CELL) be = (double)N::ld(eps[p]);
+                if constexpr (MODE == COEF_CELL) be = (double)Num<coef_t<T>>::ld(eps[p]);
                 double add = 0.0;
 #pragma unroll
                 for (int d = 0; d < 6; ++d) {
