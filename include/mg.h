@@ -75,8 +75,8 @@ enum { MG_BC_DIRICHLET = 0, MG_BC_NEUMANN = 1 };
  *   MG_FP32_IR  FP64 iterative refinement: FP64 residual, correction update
  *               and bottom solve; the inner V-cycle smooths and transfers
  *               in FP32.
- *   MG_BF16_IR  as MG_FP32_IR with BF16 storage of the inner fields and
- *               coefficients (FP32 arithmetic, round-to-nearest-even).
+ *   MG_BF16_IR  as MG_FP32_IR with BF16 storage of the inner fields
+ *               (coefficients FP32; FP32 arithmetic, round-to-nearest-even).
  * Every precision converges to the same FP64 solution. */
 enum { MG_FP64 = 0, MG_FP32_IR = 1, MG_BF16_IR = 2 };
 
