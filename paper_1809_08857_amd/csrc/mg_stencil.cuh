@@ -1211,23 +1211,64 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
     const size_t rowoff = (size_t)(row_in ? gy : 0) * nx;
 
     struct P2 { C v[2]; };
+    // uniform plane base plus a 32-bit lane offset, scaled by the element
+    // size of the array (a plane outside the box reads the nearest one)
+    const uint32_t le = (uint32_t)(c_in ? rowoff + gx : 0);
     auto ld_pair = [&](const auto *__restrict__ p, int k) -> P2 {
         using A_ = std::remove_cv_t<std::remove_reference_t<decltype(*p)>>;
-        const bool kin = k >= 0 && k < nz;
-        const size_t g = (kin && c_in) ? (size_t)k * plane + rowoff + gx : 0;
-        const Pair<A_> w = *reinterpret_cast<const Pair<A_> *>(p + g);
+        constexpr uint32_t es = sizeof(A_);
+        const char *pk = reinterpret_cast<const char *>(p) + (size_t)min(max(k, 0), nz - 1) * plane * es;
+        const Pair<A_> w = *reinterpret_cast<const Pair<A_> *>(pk + le * es);
         P2 r;
         r.v[0] = Num<A_>::ld(w.v[0]);
         r.v[1] = Num<A_>::ld(w.v[1]);
         return r;
     };
+    // Box faces with beta = 1 and with cell coefficients take no branches,
+    // as in the sweeps: a cell outside the box carries the boundary term of
+    // the face it lies beyond (beta = 1: u = 2g or 0, the face weight being
+    // part of the cell's fixed diagonal; cell coefficients: u = g and a
+    // coefficient 0 or kBigCoef for harm_face).  Stored faces keep the
+    // general face sums.
+    const int sd = gx < 0 ? 0 : gx >= nx ? 1 : gy < 0 ? 2 : gy >= ny ? 3 : 4;  // pairs are all in or all out
+    auto dir = [&](int d) { return d < 6 && ((G.bcmask >> d) & 1) != 0; };
+    auto gval = [&](int d) -> C {
+        return d == 0 ? C(G.g[0]) : d == 1 ? C(G.g[1]) : d == 2 ? C(G.g[2]) : d == 3 ? C(G.g[3]) : C(0);
+    };
+    const C big = kBigCoef<C>;
+    const C uout = MODE == COEF_CONST ? (dir(sd) ? C(2) * gval(sd) : C(0)) : gval(sd);
+    const C uz_lo = MODE == COEF_CONST ? (dir(4) ? C(2) * C(G.g[4]) : C(0)) : C(G.g[4]);
+    const C uz_hi = MODE == COEF_CONST ? (dir(5) ? C(2) * C(G.g[5]) : C(0)) : C(G.g[5]);
+    const C eout = dir(sd) ? big : C(0), ez_lo = dir(4) ? big : C(0), ez_hi = dir(5) ? big : C(0);
+    // beta = 1: in-plane part of each cell's diagonal
+    auto dg_xy = [&](int c) -> C {
+        const int g = gx + c;
+        return (g > 0 ? C(1) : (dir(0) ? C(2) : C(0))) + (g < nx - 1 ? C(1) : (dir(1) ? C(2) : C(0))) +
+               (gy > 0 ? C(1) : (dir(2) ? C(2) : C(0))) + (gy < ny - 1 ? C(1) : (dir(3) ? C(2) : C(0)));
+    };
+    const C dxy0 = dg_xy(0), dxy1 = dg_xy(1);
+    const C wz_lo = dir(4) ? C(2) : C(0), wz_hi = dir(5) ? C(2) : C(0);
+    auto mask_out = [&](P2 v, int k, C out, C zlo, C zhi) -> P2 {
+        const bool kin = k >= 0 && k < nz;
+        const C alt = csel<C>(kin, out, csel<C>(k < 0, zlo, zhi));
+        P2 r;
+        r.v[0] = csel<C>(kin && c_in, v.v[0], alt);
+        r.v[1] = csel<C>(kin && c_in, v.v[1], alt);
+        return r;
+    };
     auto vmask = [&](P2 v, int k, C fill) {
         const bool ok = k >= 0 && k < nz && c_in;
         P2 r;
-        r.v[0] = ok ? v.v[0] : fill;
-        r.v[1] = ok ? v.v[1] : fill;
+        r.v[0] = csel<C>(ok, v.v[0], fill);
+        r.v[1] = csel<C>(ok, v.v[1], fill);
         return r;
     };
+    // u (and eps) of plane k with the values of the cells outside the box
+    auto masku = [&](P2 v, int k) -> P2 {
+        if constexpr (MODE == COEF_FACE) return vmask(v, k, C(0));
+        else return mask_out(v, k, uout, uz_lo, uz_hi);
+    };
+    auto maske = [&](P2 v, int k) -> P2 { return mask_out(v, k, eout, ez_lo, ez_hi); };
     P2 um, u0, up, e_m, e0, e_p, b0;
     static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
     P2 qu0, qu1, qu2, qu3, qe0, qe1, qe2, qe3, qb0, qb1, qb2, qb3;
@@ -1262,14 +1303,14 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
         if constexpr (PD > 1) { issue(z0 + 3, qu1, qe1); qb1 = ld_pair(b, z0 + 2); }
         if constexpr (PD > 2) { issue(z0 + 4, qu2, qe2); qb2 = ld_pair(b, z0 + 3); }
         if constexpr (PD > 3) { issue(z0 + 5, qu3, qe3); qb3 = ld_pair(b, z0 + 4); }
-        um = vmask(t0u, z0 - 1, C(0));
-        u0 = vmask(t1u, z0, C(0));
-        up = vmask(t2u, z0 + 1, C(0));
-        b0 = vmask(tb, z0, C(0));
+        um = masku(t0u, z0 - 1);
+        u0 = masku(t1u, z0);
+        up = masku(t2u, z0 + 1);
+        b0 = tb;  // used on the tile only
         if constexpr (CELL) {
-            e_m = vmask(t0e, z0 - 1, C(1));
-            e0 = vmask(t1e, z0, C(1));
-            e_p = vmask(t2e, z0 + 1, C(1));
+            e_m = maske(t0e, z0 - 1);
+            e0 = maske(t1e, z0);
+            e_p = maske(t2e, z0 + 1);
         }
     }
     double nrm = 0.0;
@@ -1293,10 +1334,28 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
             for (int c = 0; c < 2; ++c) {
                 const int lc = lx + c;
                 const int gxc = gx + c;
-                const C eP = CELL ? e0.v[c] : C(1);
+                const C uL = c ? u0.v[0] : s_u[ry][lc - 1], uR = c ? s_u[ry][lc + 1] : u0.v[1];
+                const C uD = s_u[ry - 1][lc], uU = s_u[ry + 1][lc];
                 C off, dg;
+                if constexpr (MODE == COEF_CONST) {
+                    off = ((uL + uR) + (uD + uU)) + (um.v[c] + up.v[c]);
+                    dg = (c ? dxy1 : dxy0) + (csel<C>(k > 0, C(1), wz_lo) + csel<C>(k < nz - 1, C(1), wz_hi));
+                } else if constexpr (MODE == COEF_CELL) {
+                    const C eP = e0.v[c];
+                    const C fL = harm_face(eP, c ? e0.v[0] : s_e[ry][lc - 1]);
+                    const C fR = harm_face(eP, c ? s_e[ry][lc + 1] : e0.v[1]);
+                    const C fD = harm_face(eP, s_e[ry - 1][lc]), fU = harm_face(eP, s_e[ry + 1][lc]);
+                    const C fB = harm_face(eP, e_m.v[c]), fA = harm_face(eP, e_p.v[c]);
+                    off = fL * uL;
+                    off = fma_c<C>(fR, uR, off);
+                    off = fma_c<C>(fD, uD, off);
+                    off = fma_c<C>(fU, uU, off);
+                    off = fma_c<C>(fB, um.v[c], off);
+                    off = fma_c<C>(fA, up.v[c], off);
+                    dg = ((fL + fR) + (fD + fU)) + (fB + fA);
+                } else {
                 six_faces<C, MODE, true>(
-                    G, gxc, gy, k, eP,
+                    G, gxc, gy, k, C(1),
                     [&](int d) -> C {
                         return d == 0   ? (c ? u0.v[0] : s_u[ry][lc - 1])
                                : d == 1 ? (c ? s_u[ry][lc + 1] : u0.v[1])
@@ -1323,6 +1382,7 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
                                         : face_z(fbz, G, gxc, gy, k + 1);
                     },
                     off, dg);
+                }
                 const C uP = u0.v[c];
                 rr[c] = b0.v[c] - a * uP - ih2 * (dg * uP - off);
             }
@@ -1344,9 +1404,9 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
     auto iter = [&](auto S, int k) {
         um = u0; u0 = up;
         if constexpr (CELL) { e_m = e0; e0 = e_p; }
-        up = vmask(QU(S), k + 1, C(0));
-        if constexpr (CELL) e_p = vmask(QE(S), k + 1, C(1));
-        b0 = vmask(QB(S), k, C(0));
+        up = masku(QU(S), k + 1);
+        if constexpr (CELL) e_p = maske(QE(S), k + 1);
+        b0 = QB(S);
         if (k + 1 + PD < z1 + 1) { issue(k + 1 + PD, QU(S), QE(S)); QB(S) = ld_pair(b, k + PD); }
         step(k);
     };
