@@ -76,7 +76,7 @@ __global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void b_smooth_k(const BSmo
                                                                       const WorkRef *__restrict__ work,
                                                                       int nwork) {
     const WorkRef r = work[xcd_remap(blockIdx.x, nwork)];
-    const BSmooth<T> it = items[r.item];
+    const BSmooth<T> &it = items[r.item];  // read in place: a local copy would live in scratch
     if (it.a.done && *it.a.done) return;
     __shared__ typename Num<T>::C smem[smooth_lds<COEF_CELL, TX, TY>()];
     switch (it.mode * 2 + it.zin) {
@@ -84,8 +84,11 @@ __global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void b_smooth_k(const BSmo
         case 1: rbgs_col_body<T, COEF_CONST, TX, TY, true, PD>(it.a, r.blk, smem); break;
         case 2: rbgs_col_body<T, COEF_CELL, TX, TY, false, PD>(it.a, r.blk, smem); break;
         case 3: rbgs_col_body<T, COEF_CELL, TX, TY, true, PD>(it.a, r.blk, smem); break;
-        case 4: rbgs_col_body<T, COEF_FACE, TX, TY, false, PD>(it.a, r.blk, smem); break;
-        default: rbgs_col_body<T, COEF_FACE, TX, TY, true, PD>(it.a, r.blk, smem); break;
+        // stored faces: the general pair body, whose register footprint is
+        // close to the other two; the streaming face body of the single
+        // engine would set this kernel's register count for every case
+        case 4: rbgs_pair_body<T, COEF_FACE, TX, TY, false, PD>(it.a, r.blk, smem); break;
+        default: rbgs_pair_body<T, COEF_FACE, TX, TY, true, PD>(it.a, r.blk, smem); break;
     }
 }
 
@@ -94,7 +97,7 @@ __global__ __launch_bounds__((rr_threads<TX, TY>())) void b_rr_k(const BRr<T> *_
                                                                  const WorkRef *__restrict__ work,
                                                                  int nwork) {
     const WorkRef r = work[xcd_remap(blockIdx.x, nwork)];
-    const BRr<T> it = items[r.item];
+    const BRr<T> &it = items[r.item];  // read in place: a local copy would live in scratch
     if (it.a.done_in && *it.a.done_in) return;
     __shared__ typename Num<T>::C smem[rr_lds<COEF_CELL, TX, TY>()];
     switch (it.mode) {

@@ -862,6 +862,299 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
     }
 }
 
+// ---------------------------------------------------------------------
+// The same sweep with stored face coefficients (coarse levels of a
+// variable-coefficient operator).  Each plane's faces stream in through the
+// prefetch ring with u and b: per pair, the three x faces of its row, the
+// y faces below and above it and the z faces below it.  A face on a box
+// face is scaled once on arrival by 2 (Dirichlet) or 0 (Neumann) and the
+// cell beyond it carries u = g, so the update is the plain sum over six
+// faces with no branches.
+template <class T, int TX, int TY, bool ZIN, int PD>
+__device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int blk,
+                                               typename Num<T>::C *smem) {
+    using N = Num<T>;
+    using C = typename N::C;
+    using F = coef_t<T>;
+    constexpr int PXW = (TX + 4) / 2;  // pairs per region row
+    constexpr int RX = TX + 4, RY = TY + 4, PL = RX * RY;
+    C(*s_u)[RX] = reinterpret_cast<C(*)[RX]>(smem);                  // old u, plane k
+    C(*s_r)[RY][RX] = reinterpret_cast<C(*)[RY][RX]>(smem + PL);      // new red u, by plane parity
+    const T *__restrict__ uin = A.uin;
+    T *__restrict__ uout = A.uout;
+    const T *__restrict__ b = A.b;
+    const F *__restrict__ fbx = A.fbx;
+    const F *__restrict__ fby = A.fby;
+    const F *__restrict__ fbz = A.fbz;
+    const Geo &G = A.G;
+    const int cz = A.cz, tiles_x = A.tiles_x, tiles_y = A.tiles_y;
+
+    const int tid = threadIdx.x;
+    const int tx = blk % tiles_x;
+    const int rest = blk / tiles_x;
+    const int ty = rest % tiles_y;
+    const int tc = rest / tiles_y;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tc * cz;
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int z1 = min(z0 + cz, nz);
+    const size_t plane = (size_t)nx * ny;
+    const C h2 = C(G.h2), ah2 = C(G.ah2);
+
+    const int ry = tid / PXW, pc = tid - ry * PXW;
+    const int lx = 2 * pc;                  // LDS column of the pair's first cell
+    const int x = lx - 2, y = ry - 2;       // tile coordinates of the pair
+    const int gx = x0 + x, gy = y0 + y;     // global coordinates of its first cell
+    const bool row_in = gy >= 0 && gy < ny;
+    const bool c0_in = row_in && gx >= 0 && gx < nx;
+    const bool c1_in = row_in && gx + 1 >= 0 && gx + 1 < nx;
+    const bool even_nx = (nx & 1) == 0;
+    const bool core = x >= 0 && x < TX && y >= 0 && y < TY;
+    const size_t rowoff = (size_t)(row_in ? gy : 0) * nx;
+
+    auto dir = [&](int d) { return ((G.bcmask >> d) & 1) != 0; };
+    auto bmul = [&](int d) -> C { return dir(d) ? C(2) : C(0); };
+    auto gval = [&](int d) -> C {
+        return d == 0 ? C(G.g[0]) : d == 1 ? C(G.g[1]) : d == 2 ? C(G.g[2]) : d == 3 ? C(G.g[3]) : C(0);
+    };
+    auto side = [&](int c) -> int {
+        const int g = gx + c;
+        return g < 0 ? 0 : g >= nx ? 1 : gy < 0 ? 2 : gy >= ny ? 3 : 4;
+    };
+    const C gout0 = gval(side(0)), gout1 = gval(side(1));
+    const C gz_lo = C(G.g[4]), gz_hi = C(G.g[5]);
+    // face multipliers of the pair: x faces at gx, gx+1, gx+2; y below and above
+    const C mx0 = gx == 0 ? bmul(0) : C(1);
+    const C mx1 = gx + 1 == nx ? bmul(1) : C(1);
+    const C mx2 = gx + 2 == nx ? bmul(1) : C(1);
+    const C myd = gy == 0 ? bmul(2) : C(1);
+    const C myu = gy + 1 == ny ? bmul(3) : C(1);
+    const C mz_lo = bmul(4), mz_hi = bmul(5);
+
+    // element offsets of the pair (0 for pairs outside the box, whose faces
+    // are never used): fields and z faces, x faces, y faces below / above
+    const bool pin = c0_in;  // the pair's first cell is in the box
+    const uint32_t le0 = (uint32_t)(c0_in ? rowoff + gx : 0);
+    const uint32_t le1 = (uint32_t)(c1_in ? rowoff + gx + 1 : 0);
+    const uint32_t lfx = (uint32_t)(pin ? (size_t)gy * (nx + 1) + gx : 0);
+    const uint32_t lfd = (uint32_t)(pin ? (size_t)gy * nx + gx : 0);
+    const uint32_t lfu = (uint32_t)(pin ? (size_t)(gy + 1) * nx + gx : 0);
+    const size_t fxpl = (size_t)ny * (nx + 1), fypl = (size_t)(ny + 1) * nx;
+    auto cl = [&](int k, int hi) { return min(max(k, 0), hi); };
+
+    struct P2 { C v[2]; };
+    struct FS { C x0, x1, x2; P2 yd, yu, zb; };  // faces of one plane (scaled)
+    P2 zero;
+    zero.v[0] = zero.v[1] = C(0);
+    auto ld_u = [&](const T *__restrict__ a, int k) -> P2 {
+        const T *pk = a + (size_t)cl(k, nz - 1) * plane;
+        P2 r;
+        if (even_nx) {
+            const Pair<T> w = *reinterpret_cast<const Pair<T> *>(pk + le0);
+            r.v[0] = N::ld(w.v[0]);
+            r.v[1] = N::ld(w.v[1]);
+        } else {
+            r.v[0] = N::ld(pk[le0]);
+            r.v[1] = N::ld(pk[le1]);
+        }
+        return r;
+    };
+    // raw faces of plane k (scaled when the plane is shifted in)
+    auto ld_f = [&](int k) -> FS {
+        FS f;
+        const F *px = fbx + (size_t)cl(k, nz - 1) * fxpl + lfx;
+        f.x0 = Num<F>::ld(px[0]);
+        f.x1 = Num<F>::ld(px[1]);
+        f.x2 = Num<F>::ld(px[c1_in || !pin ? 2 : 1]);  // odd nx: the pair may end at the box face
+        const F *py = fby + (size_t)cl(k, nz - 1) * fypl;
+        const F *pz = fbz + (size_t)cl(k, nz) * plane + lfd;
+        if (even_nx) {
+            const Pair<F> d = *reinterpret_cast<const Pair<F> *>(py + lfd);
+            const Pair<F> u = *reinterpret_cast<const Pair<F> *>(py + lfu);
+            const Pair<F> z = *reinterpret_cast<const Pair<F> *>(pz);
+            f.yd.v[0] = Num<F>::ld(d.v[0]);
+            f.yd.v[1] = Num<F>::ld(d.v[1]);
+            f.yu.v[0] = Num<F>::ld(u.v[0]);
+            f.yu.v[1] = Num<F>::ld(u.v[1]);
+            f.zb.v[0] = Num<F>::ld(z.v[0]);
+            f.zb.v[1] = Num<F>::ld(z.v[1]);
+        } else {
+            const uint32_t o1 = c1_in ? 1u : 0u;
+            f.yd.v[0] = Num<F>::ld(py[lfd]);
+            f.yd.v[1] = Num<F>::ld(py[lfd + o1]);
+            f.yu.v[0] = Num<F>::ld(py[lfu]);
+            f.yu.v[1] = Num<F>::ld(py[lfu + o1]);
+            f.zb.v[0] = Num<F>::ld(pz[0]);
+            f.zb.v[1] = Num<F>::ld(pz[o1]);
+        }
+        return f;
+    };
+    auto scale = [&](FS f, int k) -> FS {
+        f.x0 *= mx0;
+        f.x1 *= mx1;
+        f.x2 *= mx2;
+        f.yd.v[0] *= myd;
+        f.yd.v[1] *= myd;
+        f.yu.v[0] *= myu;
+        f.yu.v[1] *= myu;
+        const C mz = csel<C>(k == 0, mz_lo, csel<C>(k == nz, mz_hi, C(1)));
+        f.zb.v[0] *= mz;
+        f.zb.v[1] *= mz;
+        return f;
+    };
+    auto pick = [](const P2 &p, int c) -> C { return csel<C>(c, p.v[1], p.v[0]); };
+    auto masku = [&](P2 v, int k) -> P2 {
+        const bool kin = k >= 0 && k < nz;
+        const C zv = csel<C>(k < 0, gz_lo, gz_hi);
+        P2 r;
+        r.v[0] = csel<C>(kin && c0_in, v.v[0], csel<C>(kin, gout0, zv));
+        r.v[1] = csel<C>(kin && c1_in, v.v[1], csel<C>(kin, gout1, zv));
+        return r;
+    };
+
+    // current planes: u at k-1, k, k+1; b at k-1, k, k+1; faces at k-1, k, k+1
+    P2 um, u0, up, bm, b0, bp;
+    FS fm, f0, fp;
+    static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
+    P2 qu0, qu1, qu2, qu3, qb0, qb1, qb2, qb3;
+    FS qf0, qf1, qf2, qf3;
+    auto QU = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qu0; else if constexpr (v == 1) return qu1;
+        else if constexpr (v == 2) return qu2; else return qu3;
+    };
+    auto QB = [&](auto S) -> P2 & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qb0; else if constexpr (v == 1) return qb1;
+        else if constexpr (v == 2) return qb2; else return qb3;
+    };
+    auto QF = [&](auto S) -> FS & {
+        constexpr int v = decltype(S)::value;
+        if constexpr (v == 0) return qf0; else if constexpr (v == 1) return qf1;
+        else if constexpr (v == 2) return qf2; else return qf3;
+    };
+    auto issue = [&](int k, P2 &du, P2 &db, FS &df) {
+        if constexpr (!ZIN) du = ld_u(uin, k);
+        db = zero;  // b is used on the tile and its ring only
+        if (y >= -1 && y <= TY) db = ld_u(b, k);
+        df = ld_f(k);
+    };
+    {
+        P2 t0u, t0b, t1u, t1b, t2u, t2b;
+        FS t0f, t1f, t2f;
+        issue(z0 - 2, t0u, t0b, t0f);
+        issue(z0 - 1, t1u, t1b, t1f);
+        issue(z0, t2u, t2b, t2f);
+        issue(z0 + 1, qu0, qb0, qf0);
+        if constexpr (PD > 1) issue(z0 + 2, qu1, qb1, qf1);
+        if constexpr (PD > 2) issue(z0 + 3, qu2, qb2, qf2);
+        if constexpr (PD > 3) issue(z0 + 4, qu3, qb3, qf3);
+        if constexpr (ZIN) {
+            um = masku(zero, z0 - 2);
+            u0 = masku(zero, z0 - 1);
+            up = masku(zero, z0);
+        } else {
+            um = masku(t0u, z0 - 2);
+            u0 = masku(t1u, z0 - 1);
+            up = masku(t2u, z0);
+        }
+        bm = t0b;
+        b0 = t1b;
+        bp = t2b;
+        fm = scale(t0f, z0 - 2);
+        f0 = scale(t1f, z0 - 1);
+        fp = scale(t2f, z0);
+    }
+    C rn_cur = C(0), rn_prev = C(0), rn_prev2 = C(0);  // new red values of planes k, k-1, k-2
+
+    auto step = [&](int k) __attribute__((always_inline)) {
+        {
+            Pair<C> w;
+            w.v[0] = u0.v[0];
+            w.v[1] = u0.v[1];
+            *reinterpret_cast<Pair<C> *>(&s_u[ry][lx]) = w;
+        }
+        lds_barrier();
+        // ---- red cell of plane k (tile + 1-cell ring)
+        rn_prev2 = rn_prev;
+        rn_prev = rn_cur;
+        {
+            const int ro = (gy + k) & 1;  // red cell of the pair: x + ro
+            const int xr = x + ro;
+            const int lr = lx + ro;
+            const bool kin = k >= 0 && k < nz;
+            const bool ring = xr >= -1 && xr <= TX && y >= -1 && y <= TY;
+            C rv = csel<C>(kin, csel<C>(ro, gout1, gout0), csel<C>(k < 0, gz_lo, gz_hi));
+            if (kin && ring && (ro ? c1_in : c0_in)) {
+                const C fL = csel<C>(ro, f0.x1, f0.x0), fR = csel<C>(ro, f0.x2, f0.x1);
+                const C fD = pick(f0.yd, ro), fU = pick(f0.yu, ro);
+                const C fB = pick(f0.zb, ro), fA = pick(fp.zb, ro);
+                C off = fL * s_u[ry][lr - 1];
+                off = fma_c<C>(fR, s_u[ry][lr + 1], off);
+                off = fma_c<C>(fD, s_u[ry - 1][lr], off);
+                off = fma_c<C>(fU, s_u[ry + 1][lr], off);
+                off = fma_c<C>(fB, pick(um, ro), off);
+                off = fma_c<C>(fA, pick(up, ro), off);
+                const C dg = ((fL + fR) + (fD + fU)) + (fB + fA);
+                rv = qdiv<C>(fma_c<C>(h2, pick(b0, ro), off), ah2 + dg);
+            }
+            if (ring) s_r[k & 1][ry][lr] = rv;
+            rn_cur = rv;
+        }
+        // ---- black cell of plane k-1 (tile only); write the pair
+        {
+            const int kb = k - 1;
+            const int ro = (gy + kb) & 1;  // red cell of the pair on plane kb
+            const int bo = 1 - ro;         // black cell
+            if (core && kb >= z0 && kb < z1 && (bo ? c1_in : c0_in)) {
+                const int lb = lx + bo;
+                const C fL = csel<C>(bo, fm.x1, fm.x0), fR = csel<C>(bo, fm.x2, fm.x1);
+                const C fD = pick(fm.yd, bo), fU = pick(fm.yu, bo);
+                const C fB = pick(fm.zb, bo), fA = pick(f0.zb, bo);
+                C off = fL * s_r[kb & 1][ry][lb - 1];
+                off = fma_c<C>(fR, s_r[kb & 1][ry][lb + 1], off);
+                off = fma_c<C>(fD, s_r[kb & 1][ry - 1][lb], off);
+                off = fma_c<C>(fU, s_r[kb & 1][ry + 1][lb], off);
+                off = fma_c<C>(fB, rn_prev2, off);
+                off = fma_c<C>(fA, rn_cur, off);
+                const C dg = ((fL + fR) + (fD + fU)) + (fB + fA);
+                const C vb = qdiv<C>(fma_c<C>(h2, pick(bm, bo), off), ah2 + dg);
+                T *pk = uout + (size_t)kb * plane;
+                if (even_nx) {
+                    const T tb = N::cv(vb), tr = N::cv(rn_prev);
+                    store_pair_nt(pk + le0, bo ? tr : tb, bo ? tb : tr);
+                } else {
+                    pk[bo ? le1 : le0] = N::cv(vb);
+                    if (ro ? c1_in : c0_in) pk[ro ? le1 : le0] = N::cv(rn_prev);
+                }
+            } else if (core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
+                // odd nx: the pair's black cell lies outside the box
+                uout[(size_t)kb * plane + (ro ? le1 : le0)] = N::cv(rn_prev);
+            }
+        }
+        lds_barrier();
+    };
+
+    // shift in plane k+1 from ring slot S, refill the slot with k+1+PD, step k
+    auto iter = [&](auto S, int k) __attribute__((always_inline)) {
+        um = u0; u0 = up;
+        bm = b0; b0 = bp;
+        fm = f0; f0 = fp;
+        if constexpr (ZIN) up = masku(zero, k + 1);
+        else up = masku(QU(S), k + 1);
+        bp = QB(S);
+        fp = scale(QF(S), k + 1);
+        if (k + 1 + PD <= z1 + 1) issue(k + 1 + PD, QU(S), QB(S), QF(S));
+        step(k);
+    };
+    step(z0 - 1);
+    for (int kk = z0; kk <= z1; kk += PD) {
+        iter(std::integral_constant<int, 0>{}, kk);
+        if constexpr (PD > 1) { if (kk + 1 > z1) break; iter(std::integral_constant<int, 1>{}, kk + 1); }
+        if constexpr (PD > 2) { if (kk + 2 > z1) break; iter(std::integral_constant<int, 2>{}, kk + 2); }
+        if constexpr (PD > 3) { if (kk + 3 > z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
+    }
+}
+
 template <class T, int MODE, int TX, int TY, bool ZIN, int PD>
 __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int blk,
                                                typename Num<T>::C *smem) {
@@ -1124,7 +1417,7 @@ __device__ __forceinline__ void rbgs_col_body(const SmoothArgs<T> &A, const int 
                                               typename Num<T>::C *smem) {
     if constexpr (MODE == COEF_CELL) rbgs_cell_body<T, TX, TY, ZIN, PD>(A, blk, smem);
     else if constexpr (MODE == COEF_CONST) rbgs_const_body<T, TX, TY, ZIN, PD>(A, blk, smem);
-    else rbgs_pair_body<T, MODE, TX, TY, ZIN, PD>(A, blk, smem);
+    else rbgs_face_body<T, TX, TY, ZIN, PD>(A, blk, smem);
 }
 
 template <class T, int MODE, int TX, int TY, bool ZIN, int PD>
