@@ -311,14 +311,16 @@ __device__ __forceinline__ typename Num<T>::C resid_global(const T *__restrict__
 // black cell.  At step k the pair's red cell on plane k is updated (tile +
 // 1-cell ring) from old black values, and the black cell on plane k-1
 // (tile only) from new red values.  Vertical neighbours never leave the
-// thread's registers; in-plane neighbours are exchanged through LDS (one
-// plane of old u, two planes of new red values, two planes of the cell
-// coefficient).  u, b (and eps) stream in with one 16-byte load per array
-// and plane, PD planes ahead of use, and the compute phases issue no
-// global loads (except the stored faces of FACE mode), so a wait only ever
-// covers the oldest plane in flight.  Ring cells are recomputed by every
-// tile that needs them, from the same old values, so tiles never wait for
-// each other and the result equals a red sweep followed by a black sweep.
+// thread's registers; in-plane neighbours are exchanged through LDS (a
+// plane of old u and two planes of new red values; for cell coefficients
+// also eps and the face planes).  u, b and the coefficients stream in PD
+// planes ahead of use, so a wait only ever covers the oldest plane in
+// flight.  Ring cells are recomputed by every tile that needs them, from
+// the same old values, so tiles never wait for each other and the result
+// equals a red sweep followed by a black sweep.  One body per coefficient
+// kind: rbgs_const_body (beta = 1), rbgs_cell_body (cell eps, harmonic
+// faces), rbgs_face_body (stored faces); rbgs_pair_body is the general
+// stored-face form kept for the batched engine.
 template <class T> struct SmoothArgs {
     const T *uin;
     T *uout;
@@ -1155,21 +1157,23 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
     }
 }
 
+// The stored-face sweep in the general form (per-face sums with box-face
+// selects, faces read where they are used): the batched engine's, whose
+// one smoother kernel serves every coefficient kind and so must keep a
+// modest register footprint.
 template <class T, int MODE, int TX, int TY, bool ZIN, int PD>
 __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int blk,
                                                typename Num<T>::C *smem) {
+    static_assert(MODE == COEF_FACE, "stored face coefficients only");
     using N = Num<T>;
     using C = typename N::C;
     constexpr int PXW = (TX + 4) / 2;  // pairs per region row
     constexpr int RX = TX + 4, RY = TY + 4;
-    constexpr bool CELL = (MODE == COEF_CELL);
     C(*s_u)[RX] = reinterpret_cast<C(*)[RX]>(smem);
     C(*s_r)[RY][RX] = reinterpret_cast<C(*)[RY][RX]>(smem + RY * RX);
-    C(*s_e)[RY][RX] = reinterpret_cast<C(*)[RY][RX]>(smem + 3 * RY * RX);
     const T *__restrict__ uin = A.uin;
     T *__restrict__ uout = A.uout;
     const T *__restrict__ b = A.b;
-    const coef_t<T> *__restrict__ eps = A.eps;
     const coef_t<T> *__restrict__ fbx = A.fbx;
     const coef_t<T> *__restrict__ fby = A.fby;
     const coef_t<T> *__restrict__ fbz = A.fbz;
@@ -1220,12 +1224,12 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
     // select, not an index: a runtime index would force the pair into memory
     auto pick = [](const P2 &p, int c) -> C { return c ? p.v[1] : p.v[0]; };
 
-    // current planes: u at k-1, k, k+1; b at k-1, k, k+1; eps at k-2..k+1
-    P2 um, u0, up, bm, b0, bp, em2, em, e0, ep;
+    // current planes: u at k-1, k, k+1; b at k-1, k, k+1
+    P2 um, u0, up, bm, b0, bp;
     // prefetch ring (plane p in slot (p - z0 - 1) mod PD); one named
     // variable per slot so that the ring stays in registers
     static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
-    P2 qu0, qu1, qu2, qu3, qb0, qb1, qb2, qb3, qe0, qe1, qe2, qe3;
+    P2 qu0, qu1, qu2, qu3, qb0, qb1, qb2, qb3;
     auto QU = [&](auto S) -> P2 & {
         constexpr int v = decltype(S)::value;
         if constexpr (v == 0) return qu0; else if constexpr (v == 1) return qu1;
@@ -1236,28 +1240,20 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
         if constexpr (v == 0) return qb0; else if constexpr (v == 1) return qb1;
         else if constexpr (v == 2) return qb2; else return qb3;
     };
-    auto QE = [&](auto S) -> P2 & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qe0; else if constexpr (v == 1) return qe1;
-        else if constexpr (v == 2) return qe2; else return qe3;
-    };
     auto masku = [&](P2 v, int k) { P2 r; r.v[0] = valid(k, 0) ? v.v[0] : C(0); r.v[1] = valid(k, 1) ? v.v[1] : C(0); return r; };
-    auto maske = [&](P2 v, int k) { P2 r; r.v[0] = valid(k, 0) ? v.v[0] : C(1); r.v[1] = valid(k, 1) ? v.v[1] : C(1); return r; };
-    auto issue = [&](int k, P2 &du, P2 &db, P2 &de) {
+    auto issue = [&](int k, P2 &du, P2 &db) {
         if constexpr (!ZIN) du = ld_pair(uin, k);
         db = ld_pair(b, k);
-        if constexpr (CELL) de = ld_pair(eps, k);
     };
     {
-        P2 t0u, t0b, t0e, t1u, t1b, t1e, t2u, t2b, t2e, t3u, t3b, t3e;
-        issue(z0 - 3, t3u, t3b, t3e);
-        issue(z0 - 2, t0u, t0b, t0e);
-        issue(z0 - 1, t1u, t1b, t1e);
-        issue(z0, t2u, t2b, t2e);
-        issue(z0 + 1, qu0, qb0, qe0);
-        if constexpr (PD > 1) issue(z0 + 2, qu1, qb1, qe1);
-        if constexpr (PD > 2) issue(z0 + 3, qu2, qb2, qe2);
-        if constexpr (PD > 3) issue(z0 + 4, qu3, qb3, qe3);
+        P2 t0u, t0b, t1u, t1b, t2u, t2b;
+        issue(z0 - 2, t0u, t0b);
+        issue(z0 - 1, t1u, t1b);
+        issue(z0, t2u, t2b);
+        issue(z0 + 1, qu0, qb0);
+        if constexpr (PD > 1) issue(z0 + 2, qu1, qb1);
+        if constexpr (PD > 2) issue(z0 + 3, qu2, qb2);
+        if constexpr (PD > 3) issue(z0 + 4, qu3, qb3);
         P2 zero; zero.v[0] = zero.v[1] = C(0);
         um = ZIN ? zero : masku(t0u, z0 - 2);
         u0 = ZIN ? zero : masku(t1u, z0 - 1);
@@ -1265,27 +1261,16 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
         bm = masku(t0b, z0 - 2);
         b0 = masku(t1b, z0 - 1);
         bp = masku(t2b, z0);
-        if constexpr (CELL) {
-            em2 = maske(t3e, z0 - 3);
-            em = maske(t0e, z0 - 2);
-            e0 = maske(t1e, z0 - 1);
-            ep = maske(t2e, z0);
-        }
     }
     C rn_cur = C(0), rn_prev = C(0), rn_prev2 = C(0);  // new red values of planes k, k-1, k-2
 
     auto step = [&](int k) {
-        // ---- publish plane k (old u, eps) for the in-plane neighbours
+        // ---- publish plane k (old u) for the in-plane neighbours
         {
             Pair<C> w;
             w.v[0] = u0.v[0];
             w.v[1] = u0.v[1];
             *reinterpret_cast<Pair<C> *>(&s_u[ry][lx]) = w;
-            if constexpr (CELL) {
-                w.v[0] = e0.v[0];
-                w.v[1] = e0.v[1];
-                *reinterpret_cast<Pair<C> *>(&s_e[k & 1][ry][lx]) = w;
-            }
         }
         lds_barrier();
         // ---- red cell of plane k (tile + 1-cell ring)
@@ -1299,10 +1284,9 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
                               (ro ? c1_in : c0_in);
             if (doit) {
                 const int gxr = gx + ro;
-                const C eP = CELL ? pick(e0, ro) : C(1);
                 C off, dg;
                 six_faces<C, MODE, true>(
-                    G, gxr, gy, k, eP,
+                    G, gxr, gy, k, C(1),
                     [&](int d) -> C {
                         if constexpr (ZIN) return C(0);
                         else return d == 0   ? (ro ? u0.v[0] : s_u[ry][lr - 1])
@@ -1312,15 +1296,7 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
                                     : d == 4 ? pick(um, ro)
                                              : pick(up, ro);
                     },
-                    [&](int d) -> C {
-                        if constexpr (!CELL) return C(1);
-                        else return d == 0   ? (ro ? e0.v[0] : s_e[k & 1][ry][lr - 1])
-                                    : d == 1 ? (ro ? s_e[k & 1][ry][lr + 1] : e0.v[1])
-                                    : d == 2 ? s_e[k & 1][ry - 1][lr]
-                                    : d == 3 ? s_e[k & 1][ry + 1][lr]
-                                    : d == 4 ? pick(em, ro)
-                                             : pick(ep, ro);
-                    },
+                    [&](int) -> C { return C(1); },
                     [&](int d) -> C {
                         return d == 0   ? face_x(fbx, G, gxr, gy, k)
                                : d == 1 ? face_x(fbx, G, gxr + 1, gy, k)
@@ -1342,10 +1318,9 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
             if (core && kb >= z0 && kb < z1 && (bo ? c1_in : c0_in)) {
                 const int gxb = gx + bo;
                 const int lb = lx + bo;
-                const C eP = CELL ? pick(em, bo) : C(1);
                 C off, dg;
                 six_faces<C, MODE, true>(
-                    G, gxb, gy, kb, eP,
+                    G, gxb, gy, kb, C(1),
                     [&](int d) -> C {
                         return d == 0   ? (bo ? rn_prev : s_r[kb & 1][ry][lb - 1])
                                : d == 1 ? (bo ? s_r[kb & 1][ry][lb + 1] : rn_prev)
@@ -1354,15 +1329,7 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
                                : d == 4 ? rn_prev2
                                         : rn_cur;
                     },
-                    [&](int d) -> C {
-                        if constexpr (!CELL) return C(1);
-                        else return d == 0   ? (bo ? em.v[0] : s_e[kb & 1][ry][lb - 1])
-                                    : d == 1 ? (bo ? s_e[kb & 1][ry][lb + 1] : em.v[1])
-                                    : d == 2 ? s_e[kb & 1][ry - 1][lb]
-                                    : d == 3 ? s_e[kb & 1][ry + 1][lb]
-                                    : d == 4 ? pick(em2, bo)
-                                             : pick(e0, bo);
-                    },
+                    [&](int) -> C { return C(1); },
                     [&](int d) -> C {
                         return d == 0   ? face_x(fbx, G, gxb, gy, kb)
                                : d == 1 ? face_x(fbx, G, gxb + 1, gy, kb)
@@ -1396,11 +1363,9 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
     auto iter = [&](auto S, int k) {
         um = u0; u0 = up;
         bm = b0; b0 = bp;
-        if constexpr (CELL) { em2 = em; em = e0; e0 = ep; }
         if constexpr (!ZIN) up = masku(QU(S), k + 1);
         bp = masku(QB(S), k + 1);
-        if constexpr (CELL) ep = maske(QE(S), k + 1);
-        if (k + 1 + PD <= z1 + 1) issue(k + 1 + PD, QU(S), QB(S), QE(S));
+        if (k + 1 + PD <= z1 + 1) issue(k + 1 + PD, QU(S), QB(S));
         step(k);
     };
     step(z0 - 1);
