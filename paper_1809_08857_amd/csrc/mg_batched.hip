@@ -430,9 +430,9 @@ static int build_plan(BatchPlan *P, int count, mg_ctx *const *c, const double *c
         std::vector<BIr<TL>> it[4];
         std::vector<WorkRef> work;
         // Workgroups of the whole pass: about 32 per CU, shared out by cell
-        // count.  Each workgroup ends with an atomic on its problem's
-        // counter, and a problem's workgroups run side by side, so many
-        // short workgroups would serialise on those counters.
+        // count, so that each marches a long column: a workgroup of a few
+        // planes spends most of its time loading the planes around its
+        // chunk and in the closing reduction.
         int cus = 256;
         {
             int dev = 0, v = 0;
