@@ -122,6 +122,14 @@ __global__ __launch_bounds__(kBX *kBY) void b_prolong_k(const BProlong<T> *__res
 // body, one workgroup per (problem, tile and z chunk).
 constexpr int kIrTX = 64, kIrTY = 4;
 
+// Final sums of the refinement pass: workgroup i finishes problem i.
+template <class TL>
+__global__ __launch_bounds__(kFinalThreads) void b_ir_final_k(const BIr<TL> *__restrict__ items, int check_done) {
+    const BIr<TL> &it = items[blockIdx.x];
+    if (check_done && it.done && *it.done) return;
+    reduce2_final_body(it.ws, it.slot, it.bslot, it.nblk, it.ref_slot, it.rtol2, it.done);
+}
+
 template <class TL>
 __global__ __launch_bounds__(kIrTX *kIrTY) void b_ir_k(const BIr<TL> *__restrict__ items,
                                                        const WorkRef *__restrict__ work, int check_done) {
@@ -130,8 +138,7 @@ __global__ __launch_bounds__(kIrTX *kIrTY) void b_ir_k(const BIr<TL> *__restrict
     if (check_done && it.done && *it.done) return;
 #define MG_B_IR(MODE, HE)                                                                                     \
     ir_col_body<TL, MODE, HE, kIrTX, kIrTY>(it.x, it.e, it.xout, it.f, it.eps, it.G, it.rl, it.ws, it.slot,   \
-                                            it.bslot, it.kz, it.gx, it.gy, r.blk, it.nblk, it.ref_slot,       \
-                                            it.rtol2, it.done, it.zero_x != 0)
+                                            it.bslot, it.kz, it.gx, it.gy, r.blk, it.zero_x != 0)
     if (it.mode == COEF_CELL) {
         if (it.has_e) MG_B_IR(COEF_CELL, true);
         else MG_B_IR(COEF_CELL, false);
@@ -203,11 +210,14 @@ hipError_t launch_phase_st(hipStream_t s, const Launch &L, char *base, int st) {
 }
 
 template <class TL>
-hipError_t launch_ir(hipStream_t s, char *base, size_t items, size_t work, int nwork, bool check_done) {
+hipError_t launch_ir(hipStream_t s, char *base, size_t items, size_t work, int nwork, int count, bool check_done) {
     if (nwork <= 0) return hipSuccess;
     hipLaunchKernelGGL(b_ir_k<TL>, dim3(nwork), dim3(kIrTX * kIrTY), 0, s,
                        reinterpret_cast<const BIr<TL> *>(base + items), reinterpret_cast<const WorkRef *>(base + work),
                        check_done ? 1 : 0);
+    if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
+    hipLaunchKernelGGL(b_ir_final_k<TL>, dim3(count), dim3(kFinalThreads), 0, s,
+                       reinterpret_cast<const BIr<TL> *>(base + items), check_done ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -238,7 +248,6 @@ struct BatchPlan {
     int *h_flags = nullptr;      // pinned copies
     double *h_res = nullptr;
     double *partials = nullptr;  // per-problem reduction workspace
-    unsigned *counters = nullptr;
     double *results = nullptr;   // per problem: [0] ||r||^2, [1] ||b||^2
     std::vector<Launch> cycle;   // inner V-cycle phases
     size_t ir_items[4] = {0, 0, 0, 0}, ir_work = 0;  // [0],[1]: parities, [2],[3]: initial pass (zero x / guess)
@@ -255,7 +264,6 @@ static void plan_free(BatchPlan *p) {
     if (p->dbuf) (void)hipFree(p->dbuf);
     if (p->flags) (void)hipFree(p->flags);
     if (p->partials) (void)hipFree(p->partials);
-    if (p->counters) (void)hipFree(p->counters);
     if (p->results) (void)hipFree(p->results);
     if (p->h_flags) (void)hipHostFree(p->h_flags);
     if (p->h_res) (void)hipHostFree(p->h_res);
@@ -452,7 +460,7 @@ static int build_plan(BatchPlan *P, int count, mg_ctx *const *c, const double *c
             b.G = G0;
             b.mode = ci->has_eps ? COEF_CELL : COEF_CONST;
             b.rl = static_cast<TL *>(V[i][0].bw);
-            b.ws = RedWs{P->partials + (size_t)i * kMaxRedBlocks * 2, P->counters + 2 * i, P->results + 4 * i};
+            b.ws = RedWs{P->partials + (size_t)i * kMaxRedBlocks * 2, P->results + 4 * i};
             b.slot = 0;
             b.ref_slot = 1;
             b.rtol2 = ci->d.rtol * ci->d.rtol;
@@ -536,7 +544,7 @@ static int build_plan(BatchPlan *P, int count, mg_ctx *const *c, const double *c
         hipError_t err = hipSuccess;
         for (const Launch &L : P->cycle)
             if (err == hipSuccess) err = launch_phase_st(P->stream, L, P->dbuf, P->st);
-        if (err == hipSuccess) err = launch_ir<TL>(P->stream, P->dbuf, P->ir_items[par], P->ir_work, P->ir_nwork, true);
+        if (err == hipSuccess) err = launch_ir<TL>(P->stream, P->dbuf, P->ir_items[par], P->ir_work, P->ir_nwork, P->count, true);
         hipError_t e2 = hipStreamEndCapture(P->stream, &g);
         if (err != hipSuccess || e2 != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
@@ -585,14 +593,12 @@ static int solve_batched_ir(int count, mg_ctx *const *c, const double *const *f,
             hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming) != hipSuccess ||
             hipMalloc(&P->flags, sizeof(int) * count) != hipSuccess ||
             hipMalloc(&P->partials, sizeof(double) * (size_t)count * kMaxRedBlocks * 2) != hipSuccess ||
-            hipMalloc(&P->counters, sizeof(unsigned) * 2 * count) != hipSuccess ||
             hipMalloc(&P->results, sizeof(double) * 4 * count) != hipSuccess ||
             hipHostMalloc((void **)&P->h_flags, sizeof(int) * count, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&P->h_res, sizeof(double) * 4 * count, hipHostMallocDefault) != hipSuccess) {
             batch_release(c0);
             return set_err(MG_ENOMEM, "mg_solve_batched: allocation failed");
         }
-        BCK(hipMemsetAsync(P->counters, 0, sizeof(unsigned) * 2 * count, P->stream));
         int rc = build_plan<T, TL>(P, count, c, f, x);
         if (rc != MG_OK) {
             batch_release(c0);
@@ -605,7 +611,7 @@ static int solve_batched_ir(int count, mg_ctx *const *c, const double *const *f,
     BCK(hipStreamWaitEvent(s, P->ev_in, 0));
     // initial pass: x := 0 (unless guesses are given), r = b - A x, ||r||, ||b||, flags
     BCK(fill_zero(s, P->flags, sizeof(int) * count));
-    BCK(launch_ir<TL>(s, P->dbuf, P->ir_items[(flags & MG_GUESS) ? 3 : 2], P->ir_work, P->ir_nwork, false));
+    BCK(launch_ir<TL>(s, P->dbuf, P->ir_items[(flags & MG_GUESS) ? 3 : 2], P->ir_work, P->ir_nwork, P->count, false));
     BCK(hipMemcpyAsync(P->h_res, P->results, sizeof(double) * 4 * count, hipMemcpyDeviceToHost, s));
     BCK(hipStreamSynchronize(s));
     std::vector<double> bn(count), rel0(count);
@@ -623,7 +629,7 @@ static int solve_batched_ir(int count, mg_ctx *const *c, const double *const *f,
         }
     }
     if (refetch) {  // recompute the initial residuals (x now zero where rejected)
-        BCK(launch_ir<TL>(s, P->dbuf, P->ir_items[3], P->ir_work, P->ir_nwork, false));
+        BCK(launch_ir<TL>(s, P->dbuf, P->ir_items[3], P->ir_work, P->ir_nwork, P->count, false));
         BCK(hipMemcpyAsync(P->h_res, P->results, sizeof(double) * 4 * count, hipMemcpyDeviceToHost, s));
         BCK(hipStreamSynchronize(s));
     }

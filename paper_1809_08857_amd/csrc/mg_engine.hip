@@ -386,9 +386,8 @@ int mg_create(const mg_desc *d, void *hip_stream, mg_ctx **out) {
     ok &= c->d_done != nullptr;
     for (int q = 0; q < 2 && ok; ++q) ok &= hipEventCreateWithFlags(&c->ev_cyc[q], hipEventDisableTiming) == hipSuccess;
     c->ws.partials = (double *)dalloc(c, sizeof(double) * kRedSlots * kMaxRedBlocks * 2);
-    c->ws.counter = (unsigned *)dalloc(c, sizeof(unsigned) * kRedSlots);
     c->ws.result = (double *)dalloc(c, sizeof(double) * kRedSlots);
-    ok &= c->ws.partials && c->ws.counter && c->ws.result;
+    ok &= c->ws.partials && c->ws.result;
     if (ok && hipHostMalloc((void **)&c->h_pin, sizeof(double) * kRedSlots, hipHostMallocDefault) !=
                   hipSuccess)
         ok = false;
@@ -396,8 +395,7 @@ int mg_create(const mg_desc *d, void *hip_stream, mg_ctx **out) {
         mg_destroy(c);
         return set_err(MG_ENOMEM, "mg_create: device allocation failed");
     }
-    if (hipMemsetAsync(c->ws.counter, 0, sizeof(unsigned) * kRedSlots, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
         mg_destroy(c);
         return set_err(MG_EDEVICE, "mg_create: initialisation failed");
     }

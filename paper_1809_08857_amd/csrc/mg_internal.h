@@ -42,12 +42,11 @@ struct Coef {
     const void *bz;     // FACE: nx*ny*(nz+1)
 };
 
-// Deterministic reduction workspace: per-block partial sums, a
-// self-resetting arrival counter and the result slots.
+// Deterministic reduction workspace: per-block partial sums (kMaxRedBlocks
+// pairs per slot) and the result slots.
 struct RedWs {
-    double *partials;   // >= kMaxRedBlocks * 2
-    unsigned *counter;  // 1 counter per slot
-    double *result;     // result slots
+    double *partials;
+    double *result;
 };
 constexpr int kMaxRedBlocks = 2048;
 // Largest accepted cell coefficient (the smoothers encode Dirichlet box
@@ -131,6 +130,11 @@ hipError_t resid_out(hipStream_t s, const Geo &G, const Coef &C, const double *u
 // Mixed precision: r_lp = b - A x (FP64 arithmetic) cast to `stl`,
 // plus ||r||^2 into `slot`.  If e != nullptr the correction is applied
 // first: xout = x + e (e in store stl), and the residual is that of xout.
+// Final sum of the partials a reducing kernel stored in slot `slot` (nb
+// workgroups): result[slot] (and result[bslot] for the second sum) and the
+// convergence flag (skipped when done_in is set).
+hipError_t reduce2_final(hipStream_t s, const RedWs &ws, int slot, int bslot, int nb, int ref_slot, double rtol2,
+                         int *done, const int *done_in);
 hipError_t ir_update_resid(hipStream_t s, const Geo &G, const Coef &C, const double *x,
                            const void *e, double *xout, const double *b, int stl, void *r_lp,
                            const RrCheck &chk);

@@ -8,7 +8,8 @@ namespace mg {
 
 // xn = x + e (FP64 + low precision), r = b - A xn in FP64, r stored in the
 // low-precision type, ||r||^2 accumulated in FP64 (with bslot >= 0 also
-// ||b + boundary terms||^2).  zero_x: x is taken as 0 (nothing is read)
+// ||b + boundary terms||^2) into the partials of ws slot `slot`, summed by
+// reduce2_final after the launch.  zero_x: x is taken as 0 (nothing is read)
 // and xout receives zeros.
 //
 // Block: a TX x TY tile of columns (one thread each) marching up a chunk of
@@ -22,8 +23,7 @@ __device__ __forceinline__ void ir_col_body(const double *__restrict__ x, const 
                                             double *__restrict__ xout, const double *__restrict__ b,
                                             const double *__restrict__ eps, const Geo &G, TL *__restrict__ rl,
                                             const RedWs &ws, int slot, int bslot, int cz, int tiles_x,
-                                            int tiles_y, int blk, int nblk, int ref_slot, double rtol2,
-                                            int *__restrict__ done_out, bool zero_x) {
+                                            int tiles_y, int blk, bool zero_x) {
     constexpr bool CELL = (MODE == COEF_CELL);
     __shared__ double su[2][TY + 2][TX + 2];
     __shared__ double se[CELL ? 2 : 1][CELL ? TY + 2 : 1][CELL ? TX + 2 : 1];
@@ -46,33 +46,42 @@ __device__ __forceinline__ void ir_col_body(const double *__restrict__ x, const 
     const size_t coly = hy ? (size_t)hyj * nx + i : 0;
     const int sxl = lx == 0 ? 0 : TX + 1, syl = ly == 0 ? 0 : TY + 1;
 
-    auto X = [&](size_t m) -> double {
-        if constexpr (HAS_E) return x[m] + (double)Num<TL>::ld(e[m]);
-        else return x[m];
+    // Loads go to a clamped address (a plane outside the box reads the
+    // nearest one, a cell outside the box its column's first cell) and are
+    // masked where the value is consumed, one step later: a load under a
+    // branch would be waited for inside the branch.
+    auto at = [&](size_t c, int k) { return (size_t)min(max(k, 0), nz - 1) * plane + c; };
+    struct XR { double x; double e; };  // raw x and e of one cell
+    auto ldx = [&](size_t c, int k) -> XR {
+        XR r{0.0, 0.0};
+        if (!zero_x) {  // uniform
+            r.x = x[at(c, k)];
+            if constexpr (HAS_E) r.e = (double)Num<TL>::ld(e[at(c, k)]);
+        }
+        return r;
     };
-    auto ldx = [&](bool ok, size_t c, int k) -> double {
-        return (!zero_x && ok && k >= 0 && k < nz) ? X((size_t)k * plane + c) : 0.0;
+    auto xval = [&](bool ok, int k, const XR &r) -> double {
+        return (ok && k >= 0 && k < nz) ? r.x + r.e : 0.0;
     };
-    auto lde = [&](bool ok, size_t c, int k) -> double {
-        if constexpr (CELL) return (ok && k >= 0 && k < nz) ? eps[(size_t)k * plane + c] : 1.0;
+    auto lde = [&](size_t c, int k) -> double {
+        if constexpr (CELL) return eps[at(c, k)];
         else return 1.0;
     };
+    auto eval = [&](bool ok, int k, double v) -> double { return (ok && k >= 0 && k < nz) ? v : 1.0; };
     // own column: planes k-1, k, k+1 and the prefetch k+2; halo: k and k+1
-    double um = ldx(inc, col, z0 - 1), u0 = ldx(inc, col, z0), up = ldx(inc, col, z0 + 1), uq;
-    double em = lde(inc, col, z0 - 1), e0 = lde(inc, col, z0), ep = lde(inc, col, z0 + 1), eq;
-    double hx0 = ldx(hx, colx, z0), hy0 = ldx(hy, coly, z0), hx1, hy1;
-    double ehx0 = lde(hx, colx, z0), ehy0 = lde(hy, coly, z0), ehx1, ehy1;
-    double b0 = (inc && z0 < nz) ? b[(size_t)z0 * plane + col] : 0.0, b1;
+    double um = xval(inc, z0 - 1, ldx(col, z0 - 1)), u0 = xval(inc, z0, ldx(col, z0));
+    double up = xval(inc, z0 + 1, ldx(col, z0 + 1));
+    double em = eval(inc, z0 - 1, lde(col, z0 - 1)), e0 = eval(inc, z0, lde(col, z0));
+    double ep = eval(inc, z0 + 1, lde(col, z0 + 1));
+    double hx0 = xval(hx, z0, ldx(colx, z0)), hy0 = xval(hy, z0, ldx(coly, z0));
+    double ehx0 = eval(hx, z0, lde(colx, z0)), ehy0 = eval(hy, z0, lde(coly, z0));
+    double b0 = b[at(col, z0)];
     double sr = 0.0, sb = 0.0;
     for (int k = z0; k < z1; ++k) {
-        // loads for the next step
-        uq = ldx(inc, col, k + 2);
-        eq = lde(inc, col, k + 2);
-        hx1 = ldx(hx, colx, k + 1);
-        hy1 = ldx(hy, coly, k + 1);
-        ehx1 = lde(hx, colx, k + 1);
-        ehy1 = lde(hy, coly, k + 1);
-        b1 = (inc && k + 1 < z1) ? b[(size_t)(k + 1) * plane + col] : 0.0;
+        // loads for the next step (raw)
+        const XR uq = ldx(col, k + 2), hx1 = ldx(colx, k + 1), hy1 = ldx(coly, k + 1);
+        const double eq = lde(col, k + 2), ehx1 = lde(colx, k + 1), ehy1 = lde(coly, k + 1);
+        const double b1 = b[at(col, k + 1)];
         // publish plane k
         const int q = k & 1;
         su[q][ly + 1][lx + 1] = u0;
@@ -126,12 +135,13 @@ __device__ __forceinline__ void ir_col_body(const double *__restrict__ x, const 
                 sb += bb * bb;
             }
         }
-        um = u0, u0 = up, up = uq;
-        em = e0, e0 = ep, ep = eq;
-        hx0 = hx1, hy0 = hy1, ehx0 = ehx1, ehy0 = ehy1;
+        um = u0, u0 = up, up = xval(inc, k + 2, uq);
+        em = e0, e0 = ep, ep = eval(inc, k + 2, eq);
+        hx0 = xval(hx, k + 1, hx1), hy0 = xval(hy, k + 1, hy1);
+        ehx0 = eval(hx, k + 1, ehx1), ehy0 = eval(hy, k + 1, ehy1);
         b0 = b1;
     }
-    reduce2_finish<TX * TY>(sr, sb, ws, slot, bslot, blk, nblk, ref_slot, rtol2, done_out);
+    reduce2_finish<TX * TY>(sr, sb, ws, slot, blk);
 }
 
 }  // namespace mg

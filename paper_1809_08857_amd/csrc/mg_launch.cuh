@@ -83,6 +83,9 @@ hipError_t rr_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, c
                 static_cast<T *>(bc), cz, tiles_x, tiles_y, nblk, chk.ws, chk.slot, chk.ref_slot,
                 chk.rtol2, chk.done_out, chk.done_in};
     hipLaunchKernelGGL((rr_col_k<T, MODE, TX, TY, kSmoothPDOf<T>>), dim3(nblk), dim3(NTH), 0, s, A);
+    if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
+    if (chk.slot >= 0)
+        return reduce2_final(s, chk.ws, chk.slot, -1, nblk, chk.ref_slot, chk.rtol2, chk.done_out, chk.done_in);
     return hipGetLastError();
 }
 
@@ -141,19 +144,20 @@ hipError_t norm2_T(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, c
     switch (Cf.mode) {
         case COEF_CONST:
             hipLaunchKernelGGL((norm2_resid_k<T, COEF_CONST>), grid, block, 0, s, uu, bb, eps,
-                               bx, by, bz, G, ws, slot, bslot, kz, ref, rt2, dout, din);
+                               bx, by, bz, G, ws, slot, bslot, kz, din);
             break;
         case COEF_CELL:
             hipLaunchKernelGGL((norm2_resid_k<T, COEF_CELL>), grid, block, 0, s, uu, bb, eps,
-                               bx, by, bz, G, ws, slot, bslot, kz, ref, rt2, dout, din);
+                               bx, by, bz, G, ws, slot, bslot, kz, din);
             break;
         case COEF_FACE:
             hipLaunchKernelGGL((norm2_resid_k<T, COEF_FACE>), grid, block, 0, s, uu, bb, eps,
-                               bx, by, bz, G, ws, slot, bslot, kz, ref, rt2, dout, din);
+                               bx, by, bz, G, ws, slot, bslot, kz, din);
             break;
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
+    return reduce2_final(s, ws, slot, bslot, (int)(grid.x * grid.y * grid.z), ref, rt2, dout, din);
 }
 
 }  // namespace mg

@@ -60,6 +60,22 @@ hipError_t norm2_resid(hipStream_t s, int st, const Geo &G, const Coef &C, const
     return hipErrorInvalidValue;
 }
 
+// Final sum of a two-launch reduction (see reduce2_finish).
+__global__ __launch_bounds__(kFinalThreads) void reduce2_final_k(RedWs ws, int slot, int bslot, int nb,
+                                                                 int ref_slot, double rtol2, int *done,
+                                                                 const int *done_in) {
+    if (done_in && *done_in) return;  // the reducing kernel returned at once as well
+    reduce2_final_body(ws, slot, bslot, nb, ref_slot, rtol2, done);
+}
+
+hipError_t reduce2_final(hipStream_t s, const RedWs &ws, int slot, int bslot, int nb, int ref_slot, double rtol2,
+                         int *done, const int *done_in) {
+    if (nb < 1 || nb > kMaxRedBlocks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reduce2_final_k, dim3(1), dim3(kFinalThreads), 0, s, ws, slot, bslot, nb, ref_slot, rtol2,
+                       done, done_in);
+    return hipGetLastError();
+}
+
 // ||b||^2 with b = f + h^-2 sum_Dirichlet 2 beta g (the relative-residual
 // reference, and the residual of a zero iterate): one read of f per cell,
 // beta (cell coefficient, or 1) only on boundary cells.  Brick of kz
@@ -75,9 +91,9 @@ __global__ __launch_bounds__(256) void norm2_b_k(const double *__restrict__ f, c
     if (i < G.nx && j < G.ny) {
         const size_t plane = (size_t)G.nx * G.ny, col = (size_t)j * G.nx + i;
         const bool side = i == 0 || i == G.nx - 1 || j == 0 || j == G.ny - 1;
-        auto term = [&](int k) -> double {
+        // v = f at (i, j, k); the boundary part is added here
+        auto term = [&](int k, double v) -> double {
             const size_t p = (size_t)k * plane + col;
-            double v = f[p];
             if (side || k == 0 || k == G.nz - 1) {
                 const double be = CELL ? eps[p] : 1.0;
                 double add = 0.0;
@@ -93,12 +109,15 @@ __global__ __launch_bounds__(256) void norm2_b_k(const double *__restrict__ f, c
         };
         int k = k0;
         for (; k + 4 <= k1; k += 4) {
-            const double t0 = term(k), t1 = term(k + 1), t2 = term(k + 2), t3 = term(k + 3);
+            // the four loads are issued before any boundary test needs one
+            const double v0 = f[(size_t)k * plane + col], v1 = f[(size_t)(k + 1) * plane + col];
+            const double v2 = f[(size_t)(k + 2) * plane + col], v3 = f[(size_t)(k + 3) * plane + col];
+            const double t0 = term(k, v0), t1 = term(k + 1, v1), t2 = term(k + 2, v2), t3 = term(k + 3, v3);
             sb += (t0 + t1) + (t2 + t3);
         }
-        for (; k < k1; ++k) sb += term(k);
+        for (; k < k1; ++k) sb += term(k, f[(size_t)k * plane + col]);
     }
-    reduce2_finish<256>(0.0, sb, ws, slot, slot, brick_id(), brick_count());
+    reduce2_finish<256>(0.0, sb, ws, slot, brick_id());
 }
 
 hipError_t norm2_b(hipStream_t s, const Geo &G, const Coef &C, const double *f, const RedWs &ws, int slot) {
@@ -111,7 +130,8 @@ hipError_t norm2_b(hipStream_t s, const Geo &G, const Coef &C, const double *f, 
         hipLaunchKernelGGL((norm2_b_k<false>), grid, block, 0, s, f, nullptr, G, ws, slot, kz);
     else
         return hipErrorInvalidValue;
-    return hipGetLastError();
+    if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
+    return reduce2_final(s, ws, slot, slot, (int)(grid.x * grid.y * grid.z), -1, 0.0, nullptr, nullptr);
 }
 
 void tile_shape(int t, int *tx, int *ty) {
@@ -278,7 +298,7 @@ __global__ __launch_bounds__(256) void count_bad_k(const double *__restrict__ x,
         const double v = x[t];
         if (!(v > 0.0 && v <= kMaxCellCoef)) c += 1.0;
     }
-    reduce2_finish<256>(c, 0.0, ws, slot, -1, brick_id(), brick_count());
+    reduce2_finish<256>(c, 0.0, ws, slot, brick_id());
 }
 
 hipError_t count_bad(hipStream_t s, const double *x, size_t n, const RedWs &ws, int slot) {
@@ -286,7 +306,8 @@ hipError_t count_bad(hipStream_t s, const double *x, size_t n, const RedWs &ws, 
     if (g > (size_t)kMaxRedBlocks) g = kMaxRedBlocks;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(count_bad_k, dim3(g), dim3(256), 0, s, x, n, ws, slot);
-    return hipGetLastError();
+    if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
+    return reduce2_final(s, ws, slot, -1, (int)g, -1, 0.0, nullptr, nullptr);
 }
 
 // Zero fill by a kernel (a plain kernel node, safe inside captured graphs).
@@ -376,7 +397,7 @@ __global__ __launch_bounds__(TX *TY) void ir_col_k(const double *__restrict__ x,
                                                    const int *__restrict__ done_in) {
     if (done_in && *done_in) return;
     ir_col_body<TL, MODE, HAS_E, TX, TY>(x, e, xout, b, eps, G, rl, ws, slot, -1, cz, tiles_x, tiles_y,
-                                         xcd_remap(blockIdx.x, nblk), nblk, ref_slot, rtol2, done_out, false);
+                                         xcd_remap(blockIdx.x, nblk), false);
 }
 
 template <class TL>
@@ -408,7 +429,8 @@ static hipError_t ir_update_resid_T(hipStream_t s, const Geo &G, const Coef &C, 
         return hipErrorInvalidValue;
     }
 #undef MG_IR_LAUNCH
-    return hipGetLastError();
+    if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
+    return reduce2_final(s, k.ws, k.slot, -1, nblk, k.ref_slot, k.rtol2, k.done_out, k.done_in);
 }
 
 hipError_t ir_update_resid(hipStream_t s, const Geo &G, const Coef &C, const double *x,

@@ -135,17 +135,19 @@ __device__ __forceinline__ int brick_count() { return gridDim.x * gridDim.y * gr
 // Prolongation + correction: one thread per pair of fine cells (2I, 2I+1)
 // sharing a coarse x index.
 // ---------------------------------------------------------------------
-// Deterministic block reduction of two FP64 sums, finished by the last
-// block to arrive (fixed summation order, counter reset for the next use).
-// If done != nullptr, the last block also sets *done = 1 when the first
+// Deterministic reduction of two FP64 sums in two launches.  Each workgroup
+// of the reducing kernel stores its partial pair (reduce2_finish); a
+// one-workgroup kernel launched next on the same stream (reduce2_final_k)
+// sums the partials in a fixed order, writes ws.result[slot] (and
+// ws.result[bslot]) and, if done != nullptr, sets *done = 1 when the first
 // sum is <= rtol2 * result[ref_slot] (squared residual against squared
-// right-hand side), else 0.
+// right-hand side), else 0.  The kernel boundary orders the partial stores
+// before the final sum: a last-workgroup-finishes scheme would need a
+// device-scope fence in every workgroup, which writes back and invalidates
+// the L2 of its XCD.
 template <int NT>
-__device__ __forceinline__ void reduce2_finish(double s0, double s1, const RedWs &ws, int slot,
-                                               int bslot, int bid, int nb, int ref_slot = -1,
-                                               double rtol2 = 0.0, int *done = nullptr) {
+__device__ __forceinline__ void reduce2_finish(double s0, double s1, const RedWs &ws, int slot, int bid) {
     __shared__ double sh[2][NT / 64];
-    __shared__ bool last;
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int lane = tid & 63, w = tid >> 6;
 #pragma unroll
@@ -158,33 +160,38 @@ __device__ __forceinline__ void reduce2_finish(double s0, double s1, const RedWs
         sh[1][w] = s1;
     }
     __syncthreads();
-    double *part = ws.partials + (size_t)slot * kMaxRedBlocks * 2;
     if (tid == 0) {
         double a0 = 0.0, a1 = 0.0;
         for (int q = 0; q < NT / 64; ++q) {
             a0 += sh[0][q];
             a1 += sh[1][q];
         }
-        __hip_atomic_store(&part[2 * bid], a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&part[2 * bid + 1], a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned t = atomicAdd(&ws.counter[slot], 1u);
-        last = (t == (unsigned)nb - 1);
+        double *part = ws.partials + (size_t)slot * kMaxRedBlocks * 2;
+        part[2 * bid] = a0;
+        part[2 * bid + 1] = a1;
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+constexpr int kFinalThreads = 256;
+
+// The final sum of reduce2_finish's partials (one workgroup of kFinalThreads).
+__device__ __forceinline__ void reduce2_final_body(const RedWs &ws, int slot, int bslot, int nb, int ref_slot,
+                                                   double rtol2, int *done) {
+    constexpr int NT = kFinalThreads;
+    __shared__ double sh[2][NT / 64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const double *part = ws.partials + (size_t)slot * kMaxRedBlocks * 2;
     double a0 = 0.0, a1 = 0.0;
     for (int q = tid; q < nb; q += NT) {
-        a0 += __hip_atomic_load(&part[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a1 += __hip_atomic_load(&part[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a0 += part[2 * q];
+        a1 += part[2 * q + 1];
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         a0 += __shfl_down(a0, o, 64);
         a1 += __shfl_down(a1, o, 64);
     }
-    __syncthreads();
     if (lane == 0) {
         sh[0][w] = a0;
         sh[1][w] = a1;
@@ -203,7 +210,6 @@ __device__ __forceinline__ void reduce2_finish(double s0, double s1, const RedWs
             const double ref = (bslot >= 0 && ref_slot == bslot) ? t1 : ws.result[ref_slot];
             *done = (t0 <= rtol2 * ref) ? 1 : 0;
         }
-        ws.counter[slot] = 0u;
     }
 }
 
@@ -1676,7 +1682,7 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
         if constexpr (PD > 3) { if (kk + 3 >= z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
     }
     if (A.slot >= 0)
-        reduce2_finish<NTP>(nrm, 0.0, A.ws, A.slot, -1, blk, A.nblk, A.ref_slot, A.rtol2, A.done_out);
+        reduce2_finish<NTP>(nrm, 0.0, A.ws, A.slot, blk);
 }
 
 template <class T, int MODE, int TX, int TY, int PD>
@@ -1817,8 +1823,7 @@ __global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, co
                                                      const coef_t<T> *__restrict__ bx,
                                                      const coef_t<T> *__restrict__ by,
                                                      const coef_t<T> *__restrict__ bz, Geo G, RedWs ws,
-                                                     int slot, int bslot, int kz, int ref_slot,
-                                                     double rtol2, int *__restrict__ done_out,
+                                                     int slot, int bslot, int kz,
                                                      const int *__restrict__ done_in) {
     if (done_in && *done_in) return;
     using N = Num<T>;
@@ -1863,7 +1868,7 @@ __global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, co
             }
         }
     }
-    reduce2_finish<256>(sr, sb, ws, slot, bslot, brick_id(), brick_count(), ref_slot, rtol2, done_out);
+    reduce2_finish<256>(sr, sb, ws, slot, brick_id());
 }
 
 }  // namespace mg
