@@ -79,11 +79,24 @@ __global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void b_smooth_k(const BSmo
     const BSmooth<T> &it = items[r.item];  // read in place: a local copy would live in scratch
     if (it.a.done && *it.a.done) return;
     __shared__ typename Num<T>::C smem[smooth_lds<COEF_CELL, TX, TY>()];
+    const bool ev = (it.a.G.nx & 1) == 0;  // rows of even length: wide pair accesses
     switch (it.mode * 2 + it.zin) {
-        case 0: rbgs_col_body<T, COEF_CONST, TX, TY, false, PD>(it.a, r.blk, smem); break;
-        case 1: rbgs_col_body<T, COEF_CONST, TX, TY, true, PD>(it.a, r.blk, smem); break;
-        case 2: rbgs_col_body<T, COEF_CELL, TX, TY, false, PD>(it.a, r.blk, smem); break;
-        case 3: rbgs_col_body<T, COEF_CELL, TX, TY, true, PD>(it.a, r.blk, smem); break;
+        case 0:
+            if (ev) rbgs_col_body<T, COEF_CONST, TX, TY, false, PD, true>(it.a, r.blk, smem);
+            else rbgs_col_body<T, COEF_CONST, TX, TY, false, PD, false>(it.a, r.blk, smem);
+            break;
+        case 1:
+            if (ev) rbgs_col_body<T, COEF_CONST, TX, TY, true, PD, true>(it.a, r.blk, smem);
+            else rbgs_col_body<T, COEF_CONST, TX, TY, true, PD, false>(it.a, r.blk, smem);
+            break;
+        case 2:
+            if (ev) rbgs_col_body<T, COEF_CELL, TX, TY, false, PD, true>(it.a, r.blk, smem);
+            else rbgs_col_body<T, COEF_CELL, TX, TY, false, PD, false>(it.a, r.blk, smem);
+            break;
+        case 3:
+            if (ev) rbgs_col_body<T, COEF_CELL, TX, TY, true, PD, true>(it.a, r.blk, smem);
+            else rbgs_col_body<T, COEF_CELL, TX, TY, true, PD, false>(it.a, r.blk, smem);
+            break;
         // stored faces: the general pair body, whose register footprint is
         // close to the other two; the streaming face body of the single
         // engine would set this kernel's register count for every case

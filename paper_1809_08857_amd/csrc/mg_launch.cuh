@@ -30,10 +30,16 @@ hipError_t smooth_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *
     const dim3 grid(nblk), block((TX + 4) / 2 * (TY + 4));
     SmoothArgs<T> A{static_cast<const T *>(uin), static_cast<T *>(uout), static_cast<const T *>(b), eps, bx,
                     by, bz, G, cz, tiles_x, tiles_y, nblk, done};
-    if (zero_in)
-        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, true, kSmoothPDOf<T>>), grid, block, 0, s, A);
+    constexpr int PD = kSmoothPDOf<T>;
+    const bool even = (G.nx & 1) == 0;
+    if (zero_in && even)
+        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, true, PD, true>), grid, block, 0, s, A);
+    else if (zero_in)
+        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, true, PD, false>), grid, block, 0, s, A);
+    else if (even)
+        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, false, PD, true>), grid, block, 0, s, A);
     else
-        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, false, kSmoothPDOf<T>>), grid, block, 0, s, A);
+        hipLaunchKernelGGL((rbgs_col_k<T, MODE, TX, TY, false, PD, false>), grid, block, 0, s, A);
     return hipGetLastError();
 }
 

@@ -56,6 +56,22 @@ template <class T> struct alignas(2 * sizeof(T)) Pair {
     T v[2];
 };
 
+// Load two adjacent elements with one memory instruction.  The access goes
+// through an integer (vector) of the pair's width: a load of the struct
+// itself is split into its two elements early in compilation, and where a
+// branch beside it loads the same first element, the two no longer combine.
+template <class T> __device__ __forceinline__ Pair<T> ld_wide(const void *p) {
+    if constexpr (sizeof(T) == 8) {
+        typedef unsigned long long w_t __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(Pair<T>, *reinterpret_cast<const w_t *>(p));
+    } else if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(Pair<T>, *reinterpret_cast<const unsigned long long *>(p));
+    } else {
+        static_assert(sizeof(T) == 2, "element of 2, 4 or 8 bytes");
+        return __builtin_bit_cast(Pair<T>, *reinterpret_cast<const unsigned int *>(p));
+    }
+}
+
 // Store a pair with the non-temporal hint: the sweep's output is not read
 // again by the same launch, so it should not displace the halo planes that
 // neighbouring workgroups are still reading from L2.
@@ -375,7 +391,7 @@ template <class C> constexpr C kBigCoef = sizeof(C) == 8 ? C(0x1p400) : C(0x1p60
 // cell carries u = the boundary value of the box face it lies beyond and a
 // coefficient (0 beyond a Neumann face, kBigCoef beyond a Dirichlet face)
 // for which harm_face yields that face's term.
-template <class T, int TX, int TY, bool ZIN, int PD>
+template <class T, int TX, int TY, bool ZIN, int PD, bool EVEN>
 __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int blk,
                                                typename Num<T>::C *smem) {
     using N = Num<T>;
@@ -414,7 +430,7 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
     const bool row_in = gy >= 0 && gy < ny;
     const bool c0_in = row_in && gx >= 0 && gx < nx;
     const bool c1_in = row_in && gx + 1 >= 0 && gx + 1 < nx;
-    const bool even_nx = (nx & 1) == 0;
+    constexpr bool even_nx = EVEN;  // rows of even length: pairs never straddle a row
     const bool core = x >= 0 && x < TX && y >= 0 && y < TY;
     const size_t rowoff = (size_t)(row_in ? gy : 0) * nx;
     const int lx2 = min(lx + 2, RX - 2);    // next pair (clamped: its face is never read)
@@ -458,7 +474,7 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
         const char *pk = reinterpret_cast<const char *>(a) + plane_el(k) * es;
         P2 r;
         if (even_nx) {
-            const Pair<A_> w = *reinterpret_cast<const Pair<A_> *>(pk + le0 * es);
+            const Pair<A_> w = ld_wide<A_>(pk + le0 * es);
             r.v[0] = Num<A_>::ld(w.v[0]);
             r.v[1] = Num<A_>::ld(w.v[1]);
         } else {
@@ -659,7 +675,7 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
 // outside the box carries the boundary term of the box face it lies beyond
 // (2 g for Dirichlet, 0 for Neumann) and each cell's diagonal sum is fixed
 // by its position: no per-face branches or selects remain.
-template <class T, int TX, int TY, bool ZIN, int PD>
+template <class T, int TX, int TY, bool ZIN, int PD, bool EVEN>
 __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const int blk,
                                                 typename Num<T>::C *smem) {
     using N = Num<T>;
@@ -692,7 +708,7 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
     const bool row_in = gy >= 0 && gy < ny;
     const bool c0_in = row_in && gx >= 0 && gx < nx;
     const bool c1_in = row_in && gx + 1 >= 0 && gx + 1 < nx;
-    const bool even_nx = (nx & 1) == 0;
+    constexpr bool even_nx = EVEN;  // rows of even length: pairs never straddle a row
     const bool core = x >= 0 && x < TX && y >= 0 && y < TY;
     const size_t rowoff = (size_t)(row_in ? gy : 0) * nx;
 
@@ -712,6 +728,13 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
     const C hout0 = halo(0), hout1 = halo(1), dxy0 = dg_xy(0), dxy1 = dg_xy(1);
     const C hz_lo = hv(4), hz_hi = hv(5), wz_lo = fw(4), wz_hi = fw(5);
     auto dg_z = [&](int k) -> C { return csel<C>(k > 0, C(1), wz_lo) + csel<C>(k < nz - 1, C(1), wz_hi); };
+    // reciprocal diagonal of cell c of the pair on plane k: fixed for the
+    // planes between the z box faces, formed there once
+    const C rd0 = rcp_nr(ah2 + (dxy0 + C(2))), rd1 = rcp_nr(ah2 + (dxy1 + C(2)));
+    auto rdiag = [&](int c, int k) -> C {
+        if (k > 0 && k < nz - 1) return csel<C>(c, rd1, rd0);
+        return rcp_nr(ah2 + (csel<C>(c, dxy1, dxy0) + dg_z(k)));
+    };
 
     // offsets (elements) of the pair's cells within a plane (0 outside the
     // box) and of plane k: loads and stores take a uniform plane base plus
@@ -732,7 +755,7 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
         const char *pk = reinterpret_cast<const char *>(a) + plane_el(k) * es;
         P2 r;
         if (even_nx) {
-            const Pair<A_> w = *reinterpret_cast<const Pair<A_> *>(pk + le0 * es);
+            const Pair<A_> w = ld_wide<A_>(pk + le0 * es);
             r.v[0] = Num<A_>::ld(w.v[0]);
             r.v[1] = Num<A_>::ld(w.v[1]);
         } else {
@@ -816,8 +839,7 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
             if (kin && ring && (ro ? c1_in : c0_in)) {
                 const C off = ((s_u[ry][lr - 1] + s_u[ry][lr + 1]) + (s_u[ry - 1][lr] + s_u[ry + 1][lr])) +
                               (pick(um, ro) + pick(up, ro));
-                const C dg = csel<C>(ro, dxy1, dxy0) + dg_z(k);
-                rv = qdiv<C>(fma_c<C>(h2, pick(b0, ro), off), ah2 + dg);
+                rv = fma_c<C>(h2, pick(b0, ro), off) * rdiag(ro, k);
             }
             if (ring) s_r[k & 1][ry][lr] = rv;
             rn_cur = rv;
@@ -832,8 +854,7 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
                 const C off = ((s_r[kb & 1][ry][lb - 1] + s_r[kb & 1][ry][lb + 1]) +
                                (s_r[kb & 1][ry - 1][lb] + s_r[kb & 1][ry + 1][lb])) +
                               (rn_prev2 + rn_cur);
-                const C dg = csel<C>(bo, dxy1, dxy0) + dg_z(kb);
-                const C vb = qdiv<C>(fma_c<C>(h2, pick(bm, bo), off), ah2 + dg);
+                const C vb = fma_c<C>(h2, pick(bm, bo), off) * rdiag(bo, kb);
                 char *pk = reinterpret_cast<char *>(uout) + plane_at(kb);
                 if (even_nx) {
                     const T tb = N::cv(vb), tr = N::cv(rn_prev);
@@ -878,7 +899,7 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
 // face is scaled once on arrival by 2 (Dirichlet) or 0 (Neumann) and the
 // cell beyond it carries u = g, so the update is the plain sum over six
 // faces with no branches.
-template <class T, int TX, int TY, bool ZIN, int PD>
+template <class T, int TX, int TY, bool ZIN, int PD, bool EVEN>
 __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int blk,
                                                typename Num<T>::C *smem) {
     using N = Num<T>;
@@ -915,7 +936,7 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
     const bool row_in = gy >= 0 && gy < ny;
     const bool c0_in = row_in && gx >= 0 && gx < nx;
     const bool c1_in = row_in && gx + 1 >= 0 && gx + 1 < nx;
-    const bool even_nx = (nx & 1) == 0;
+    constexpr bool even_nx = EVEN;  // rows of even length: pairs never straddle a row
     const bool core = x >= 0 && x < TX && y >= 0 && y < TY;
     const size_t rowoff = (size_t)(row_in ? gy : 0) * nx;
 
@@ -957,7 +978,7 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
         const T *pk = a + (size_t)cl(k, nz - 1) * plane;
         P2 r;
         if (even_nx) {
-            const Pair<T> w = *reinterpret_cast<const Pair<T> *>(pk + le0);
+            const Pair<T> w = ld_wide<T>(pk + le0);
             r.v[0] = N::ld(w.v[0]);
             r.v[1] = N::ld(w.v[1]);
         } else {
@@ -976,9 +997,9 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
         const F *py = fby + (size_t)cl(k, nz - 1) * fypl;
         const F *pz = fbz + (size_t)cl(k, nz) * plane + lfd;
         if (even_nx) {
-            const Pair<F> d = *reinterpret_cast<const Pair<F> *>(py + lfd);
-            const Pair<F> u = *reinterpret_cast<const Pair<F> *>(py + lfu);
-            const Pair<F> z = *reinterpret_cast<const Pair<F> *>(pz);
+            const Pair<F> d = ld_wide<F>(py + lfd);
+            const Pair<F> u = ld_wide<F>(py + lfu);
+            const Pair<F> z = ld_wide<F>(pz);
             f.yd.v[0] = Num<F>::ld(d.v[0]);
             f.yd.v[1] = Num<F>::ld(d.v[1]);
             f.yu.v[0] = Num<F>::ld(u.v[0]);
@@ -1216,7 +1237,7 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
         const bool kin = k >= 0 && k < nz;
         if (even_nx) {
             const size_t g = (kin && c0_in) ? (size_t)k * plane + rowoff + gx : 0;
-            const Pair<A_> w = *reinterpret_cast<const Pair<A_> *>(a + g);
+            const Pair<A_> w = ld_wide<A_>(a + g);
             r.v[0] = Num<A_>::ld(w.v[0]);
             r.v[1] = Num<A_>::ld(w.v[1]);
         } else {
@@ -1383,19 +1404,23 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
     }
 }
 
-template <class T, int MODE, int TX, int TY, bool ZIN, int PD>
+template <class T, int MODE, int TX, int TY, bool ZIN, int PD, bool EVEN>
 __device__ __forceinline__ void rbgs_col_body(const SmoothArgs<T> &A, const int blk,
                                               typename Num<T>::C *smem) {
-    if constexpr (MODE == COEF_CELL) rbgs_cell_body<T, TX, TY, ZIN, PD>(A, blk, smem);
-    else if constexpr (MODE == COEF_CONST) rbgs_const_body<T, TX, TY, ZIN, PD>(A, blk, smem);
-    else rbgs_face_body<T, TX, TY, ZIN, PD>(A, blk, smem);
+    if constexpr (MODE == COEF_CELL) rbgs_cell_body<T, TX, TY, ZIN, PD, EVEN>(A, blk, smem);
+    else if constexpr (MODE == COEF_CONST) rbgs_const_body<T, TX, TY, ZIN, PD, EVEN>(A, blk, smem);
+    else rbgs_face_body<T, TX, TY, ZIN, PD, EVEN>(A, blk, smem);
 }
 
-template <class T, int MODE, int TX, int TY, bool ZIN, int PD>
+// EVEN: the level's rows have even length, so a pair is two adjacent
+// elements of one row and moves with one wide access; odd rows take the
+// per-element form.  The host picks the variant from nx.
+template <class T, int MODE, int TX, int TY, bool ZIN, int PD, bool EVEN>
 __global__ __launch_bounds__((TX + 4) / 2 * (TY + 4)) void rbgs_col_k(SmoothArgs<T> A) {
     if (A.done && *A.done) return;  // the solve has converged: nothing left to do
+    if (EVEN != ((A.G.nx & 1) == 0)) return;  // not launched this way by the host
     __shared__ typename Num<T>::C smem[smooth_lds<MODE, TX, TY>()];
-    rbgs_col_body<T, MODE, TX, TY, ZIN, PD>(A, xcd_remap(blockIdx.x, A.nblk), smem);
+    rbgs_col_body<T, MODE, TX, TY, ZIN, PD, EVEN>(A, xcd_remap(blockIdx.x, A.nblk), smem);
 }
 
 // ---------------------------------------------------------------------
@@ -1482,7 +1507,7 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
         using A_ = std::remove_cv_t<std::remove_reference_t<decltype(*p)>>;
         constexpr uint32_t es = sizeof(A_);
         const char *pk = reinterpret_cast<const char *>(p) + (size_t)min(max(k, 0), nz - 1) * plane * es;
-        const Pair<A_> w = *reinterpret_cast<const Pair<A_> *>(pk + le * es);
+        const Pair<A_> w = ld_wide<A_>(pk + le * es);
         P2 r;
         r.v[0] = Num<A_>::ld(w.v[0]);
         r.v[1] = Num<A_>::ld(w.v[1]);
