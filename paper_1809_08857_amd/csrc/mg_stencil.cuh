@@ -72,6 +72,17 @@ template <class T> __device__ __forceinline__ Pair<T> ld_wide(const void *p) {
     }
 }
 
+// A lane's byte offset within plane k, opaque to loop-invariant code
+// motion.  Each access is then formed as a uniform plane base (scalar
+// registers) plus a 32-bit lane offset, the saddr form of the global memory
+// instructions; otherwise the array base is folded into a 64-bit per-lane
+// address that is advanced with a 64-bit multiply-add at every plane.  The
+// statement emits no instruction.
+__device__ __forceinline__ uint32_t lane_at(uint32_t off, int k) {
+    asm("" : "+v"(off) : "s"(k));
+    return off;
+}
+
 // Store a pair with the non-temporal hint: the sweep's output is not read
 // again by the same launch, so it should not displace the halo planes that
 // neighbouring workgroups are still reading from L2.
@@ -640,7 +651,7 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
                     *reinterpret_cast<T *>(pk + (bo ? lb1 : lb0)) = N::cv(vb);
                     if (ro ? c1_in : c0_in) *reinterpret_cast<T *>(pk + (ro ? lb1 : lb0)) = N::cv(rn_prev);
                 }
-            } else if (core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
+            } else if (!even_nx && core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
                 // odd nx: the pair's black cell lies outside the box
                 char *pk = reinterpret_cast<char *>(uout) + plane_at(kb);
                 *reinterpret_cast<T *>(pk + (ro ? lb1 : lb0)) = N::cv(rn_prev);
@@ -755,12 +766,12 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
         const char *pk = reinterpret_cast<const char *>(a) + plane_el(k) * es;
         P2 r;
         if (even_nx) {
-            const Pair<A_> w = ld_wide<A_>(pk + le0 * es);
+            const Pair<A_> w = ld_wide<A_>(pk + lane_at(le0 * es, k));
             r.v[0] = Num<A_>::ld(w.v[0]);
             r.v[1] = Num<A_>::ld(w.v[1]);
         } else {
-            r.v[0] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + le0 * es));
-            r.v[1] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + le1 * es));
+            r.v[0] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + lane_at(le0 * es, k)));
+            r.v[1] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + lane_at(le1 * es, k)));
         }
         return r;
     };
@@ -774,51 +785,57 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
         return r;
     };
 
-    // current planes: u at k-1, k, k+1 (outside cells carry their boundary
-    // term); b at k-1, k, k+1 (never used outside the box)
-    P2 um, u0, up, bm, b0, bp;
+    // A ring of R = PD + 3 plane slots for u and for b: plane p occupies
+    // slot (p - z0 + 2) mod R from its load, PD steps before the step that
+    // first reads it, until the step after its own.  The steps are unrolled
+    // R at a time, so every slot index is a constant: each load lands in the
+    // registers its readers use and no value moves between registers (a
+    // move of a loaded register would wait for that load at once).  u is
+    // masked in place when its plane first becomes the upper neighbour
+    // (cells outside the box carry their boundary term).
     static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
-    P2 qu0, qu1, qu2, qu3, qb0, qb1, qb2, qb3;
-    auto QU = [&](auto S) -> P2 & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qu0; else if constexpr (v == 1) return qu1;
-        else if constexpr (v == 2) return qu2; else return qu3;
+    constexpr int R = PD + 3;
+    P2 su0, su1, su2, su3, su4, su5, su6, sb0, sb1, sb2, sb3, sb4, sb5, sb6;
+    auto SU = [&](auto I) -> P2 & {
+        constexpr int v = decltype(I)::value % R;
+        if constexpr (v == 0) return su0; else if constexpr (v == 1) return su1;
+        else if constexpr (v == 2) return su2; else if constexpr (v == 3) return su3;
+        else if constexpr (v == 4) return su4; else if constexpr (v == 5) return su5;
+        else return su6;
     };
-    auto QB = [&](auto S) -> P2 & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qb0; else if constexpr (v == 1) return qb1;
-        else if constexpr (v == 2) return qb2; else return qb3;
+    auto SB = [&](auto I) -> P2 & {
+        constexpr int v = decltype(I)::value % R;
+        if constexpr (v == 0) return sb0; else if constexpr (v == 1) return sb1;
+        else if constexpr (v == 2) return sb2; else if constexpr (v == 3) return sb3;
+        else if constexpr (v == 4) return sb4; else if constexpr (v == 5) return sb5;
+        else return sb6;
     };
     auto issue = [&](int k, P2 &du, P2 &db) {
         if constexpr (!ZIN) du = ld_pair(uin, k);
-        db = zero;  // b is used on the tile and its ring only
-        if (y >= -1 && y <= TY) db = ld_pair(b, k);
+        db = ld_pair(b, k);  // b is read on the tile and its ring only
     };
-    {
-        P2 t0u, t0b, t1u, t1b, t2u, t2b;
-        issue(z0 - 2, t0u, t0b);
-        issue(z0 - 1, t1u, t1b);
-        issue(z0, t2u, t2b);
-        issue(z0 + 1, qu0, qb0);
-        if constexpr (PD > 1) issue(z0 + 2, qu1, qb1);
-        if constexpr (PD > 2) issue(z0 + 3, qu2, qb2);
-        if constexpr (PD > 3) issue(z0 + 4, qu3, qb3);
-        if constexpr (ZIN) {
-            um = masku(zero, z0 - 2);
-            u0 = masku(zero, z0 - 1);
-            up = masku(zero, z0);
-        } else {
-            um = masku(t0u, z0 - 2);
-            u0 = masku(t1u, z0 - 1);
-            up = masku(t2u, z0);
-        }
-        bm = t0b;
-        b0 = t1b;
-        bp = t2b;
-    }
+    auto issue_at = [&](auto I) {
+        constexpr int q = decltype(I)::value;
+        if constexpr (q < R) issue(z0 - 2 + q, SU(I), SB(I));
+    };
+    issue_at(std::integral_constant<int, 0>{});
+    issue_at(std::integral_constant<int, 1>{});
+    issue_at(std::integral_constant<int, 2>{});
+    issue_at(std::integral_constant<int, 3>{});
+    issue_at(std::integral_constant<int, 4>{});
+    issue_at(std::integral_constant<int, 5>{});
+    issue_at(std::integral_constant<int, 6>{});
+    auto mask_at = [&](auto I, int p) {
+        if constexpr (ZIN) SU(I) = masku(zero, p);
+        else SU(I) = masku(SU(I), p);
+    };
+    mask_at(std::integral_constant<int, 0>{}, z0 - 2);
+    mask_at(std::integral_constant<int, 1>{}, z0 - 1);
+    mask_at(std::integral_constant<int, 2>{}, z0);
     C rn_cur = C(0), rn_prev = C(0), rn_prev2 = C(0);  // new red values of planes k, k-1, k-2
 
-    auto step = [&](int k) __attribute__((always_inline)) {
+    auto step = [&](const P2 &um, const P2 &u0, const P2 &up, const P2 &bm, const P2 &b0, int k)
+                    __attribute__((always_inline)) {
         {
             Pair<C> w;
             w.v[0] = u0.v[0];
@@ -858,12 +875,12 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
                 char *pk = reinterpret_cast<char *>(uout) + plane_at(kb);
                 if (even_nx) {
                     const T tb = N::cv(vb), tr = N::cv(rn_prev);
-                    store_pair_nt(reinterpret_cast<T *>(pk + lb0), bo ? tr : tb, bo ? tb : tr);
+                    store_pair_nt(reinterpret_cast<T *>(pk + lane_at(lb0, kb)), bo ? tr : tb, bo ? tb : tr);
                 } else {
                     *reinterpret_cast<T *>(pk + (bo ? lb1 : lb0)) = N::cv(vb);
                     if (ro ? c1_in : c0_in) *reinterpret_cast<T *>(pk + (ro ? lb1 : lb0)) = N::cv(rn_prev);
                 }
-            } else if (core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
+            } else if (!even_nx && core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
                 // odd nx: the pair's black cell lies outside the box
                 char *pk = reinterpret_cast<char *>(uout) + plane_at(kb);
                 *reinterpret_cast<T *>(pk + (ro ? lb1 : lb0)) = N::cv(rn_prev);
@@ -872,22 +889,29 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
         lds_barrier();
     };
 
-    // shift in plane k+1 from ring slot S, refill the slot with k+1+PD, step k
-    auto iter = [&](auto S, int k) __attribute__((always_inline)) {
-        um = u0; u0 = up;
-        bm = b0; b0 = bp;
-        if constexpr (ZIN) up = masku(zero, k + 1);
-        else up = masku(QU(S), k + 1);
-        bp = QB(S);
-        if (k + 1 + PD <= z1 + 1) issue(k + 1 + PD, QU(S), QB(S));
-        step(k);
+    // step k = kk + J of an unrolled group: refill slot J (plane k-2, read
+    // last by step k-1) with plane k+1+PD, mask plane k+1, step
+    auto iter = [&](auto J, int k) __attribute__((always_inline)) {
+        constexpr int q = decltype(J)::value;
+        using I1 = std::integral_constant<int, q + 1>;
+        using I2 = std::integral_constant<int, q + 2>;
+        using I3 = std::integral_constant<int, q + 3>;
+        issue(min(k + 1 + PD, z1 + 1), SU(J), SB(J));
+        mask_at(I3{}, k + 1);
+        step(SU(I1{}), SU(I2{}), SU(I3{}), SB(I1{}), SB(I2{}), k);
     };
-    step(z0 - 1);
-    for (int kk = z0; kk <= z1; kk += PD) {
+    step(su0, su1, su2, sb0, sb1, z0 - 1);
+    for (int kk = z0; kk <= z1; kk += R) {
         iter(std::integral_constant<int, 0>{}, kk);
-        if constexpr (PD > 1) { if (kk + 1 > z1) break; iter(std::integral_constant<int, 1>{}, kk + 1); }
-        if constexpr (PD > 2) { if (kk + 2 > z1) break; iter(std::integral_constant<int, 2>{}, kk + 2); }
-        if constexpr (PD > 3) { if (kk + 3 > z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
+        if (kk + 1 > z1) break;
+        iter(std::integral_constant<int, 1>{}, kk + 1);
+        if (kk + 2 > z1) break;
+        iter(std::integral_constant<int, 2>{}, kk + 2);
+        if (kk + 3 > z1) break;
+        iter(std::integral_constant<int, 3>{}, kk + 3);
+        if constexpr (R > 4) { if (kk + 4 > z1) break; iter(std::integral_constant<int, 4>{}, kk + 4); }
+        if constexpr (R > 5) { if (kk + 5 > z1) break; iter(std::integral_constant<int, 5>{}, kk + 5); }
+        if constexpr (R > 6) { if (kk + 6 > z1) break; iter(std::integral_constant<int, 6>{}, kk + 6); }
     }
 }
 
@@ -1155,7 +1179,7 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
                     pk[bo ? le1 : le0] = N::cv(vb);
                     if (ro ? c1_in : c0_in) pk[ro ? le1 : le0] = N::cv(rn_prev);
                 }
-            } else if (core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
+            } else if (!even_nx && core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
                 // odd nx: the pair's black cell lies outside the box
                 uout[(size_t)kb * plane + (ro ? le1 : le0)] = N::cv(rn_prev);
             }
@@ -1378,7 +1402,7 @@ __device__ __forceinline__ void rbgs_pair_body(const SmoothArgs<T> &A, const int
                     uout[gp + bo] = N::cv(vb);
                     if (ro ? c1_in : c0_in) uout[gp + ro] = N::cv(rn_prev);
                 }
-            } else if (core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
+            } else if (!even_nx && core && kb >= z0 && kb < z1 && (ro ? c1_in : c0_in)) {
                 // odd nx: the pair's black cell lies outside the box
                 uout[(size_t)kb * plane + rowoff + gx + ro] = N::cv(rn_prev);
             }
