@@ -485,12 +485,12 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
         const char *pk = reinterpret_cast<const char *>(a) + plane_el(k) * es;
         P2 r;
         if (even_nx) {
-            const Pair<A_> w = ld_wide<A_>(pk + le0 * es);
+            const Pair<A_> w = ld_wide<A_>(pk + lane_at(le0 * es, k));
             r.v[0] = Num<A_>::ld(w.v[0]);
             r.v[1] = Num<A_>::ld(w.v[1]);
         } else {
-            r.v[0] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + le0 * es));
-            r.v[1] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + le1 * es));
+            r.v[0] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + lane_at(le0 * es, k)));
+            r.v[1] = Num<A_>::ld(*reinterpret_cast<const A_ *>(pk + lane_at(le1 * es, k)));
         }
         return r;
     };
@@ -508,32 +508,56 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
     auto masku = [&](P2 v, int k) { return mask(v, k, gout0, gout1, gz_lo, gz_hi); };
     auto maske = [&](P2 v, int k) { return mask(v, k, eout0, eout1, ez_lo, ez_hi); };
 
-    // current planes: u at k-1, k, k+1; b at k-1, k, k+1 (values outside the
-    // box are never used); eps at k, k+1; vertical faces of the pair between
-    // planes k-2|k-1 (zA), k-1|k (zB), k|k+1 (zC)
-    P2 um, u0, up, bm, b0, bp, e0, ep, zA, zB, zC;
+    // A ring of R = PD + 3 plane slots for u, b and eps: plane p occupies
+    // slot (p - z0 + 2) mod R from its load, PD steps before the step that
+    // first reads it, until the step after its own.  The steps are unrolled
+    // R at a time, so every slot index is a constant and no loaded value
+    // moves between registers (such a move would wait for its load at
+    // once).  u and eps are masked in place when their plane first becomes
+    // the upper neighbour.  zA, zB, zC: the vertical faces of the pair
+    // between planes k-2|k-1, k-1|k and k|k+1.
     static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
-    P2 qu0, qu1, qu2, qu3, qb0, qb1, qb2, qb3, qe0, qe1, qe2, qe3;
-    auto QU = [&](auto S) -> P2 & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qu0; else if constexpr (v == 1) return qu1;
-        else if constexpr (v == 2) return qu2; else return qu3;
+    constexpr int R = PD + 3;
+    P2 su0, su1, su2, su3, su4, su5, su6, sb0, sb1, sb2, sb3, sb4, sb5, sb6;
+    P2 se0, se1, se2, se3, se4, se5, se6;
+    auto SU = [&](auto I) -> P2 & {
+        constexpr int v = decltype(I)::value % R;
+        if constexpr (v == 0) return su0; else if constexpr (v == 1) return su1;
+        else if constexpr (v == 2) return su2; else if constexpr (v == 3) return su3;
+        else if constexpr (v == 4) return su4; else if constexpr (v == 5) return su5;
+        else return su6;
     };
-    auto QB = [&](auto S) -> P2 & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qb0; else if constexpr (v == 1) return qb1;
-        else if constexpr (v == 2) return qb2; else return qb3;
+    auto SB = [&](auto I) -> P2 & {
+        constexpr int v = decltype(I)::value % R;
+        if constexpr (v == 0) return sb0; else if constexpr (v == 1) return sb1;
+        else if constexpr (v == 2) return sb2; else if constexpr (v == 3) return sb3;
+        else if constexpr (v == 4) return sb4; else if constexpr (v == 5) return sb5;
+        else return sb6;
     };
-    auto QE = [&](auto S) -> P2 & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qe0; else if constexpr (v == 1) return qe1;
-        else if constexpr (v == 2) return qe2; else return qe3;
+    auto SE = [&](auto I) -> P2 & {
+        constexpr int v = decltype(I)::value % R;
+        if constexpr (v == 0) return se0; else if constexpr (v == 1) return se1;
+        else if constexpr (v == 2) return se2; else if constexpr (v == 3) return se3;
+        else if constexpr (v == 4) return se4; else if constexpr (v == 5) return se5;
+        else return se6;
     };
+    P2 zA, zB, zC;
+    // every lane loads every plane (b outside the tile's ring and planes
+    // past the chunk are not used): loads under a condition would make the
+    // compiler wait for all outstanding loads where one of them is used
     auto issue = [&](int k, P2 &du, P2 &db, P2 &de) {
         if constexpr (!ZIN) du = ld_pair(uin, k);
-        db = zero;  // b is used on the tile and its ring only
-        if (y >= -1 && y <= TY) db = ld_pair(b, k);
+        db = ld_pair(b, k);
         de = ld_pair(eps, k);
+    };
+    auto issue_at = [&](auto I) {
+        constexpr int q = decltype(I)::value;
+        if constexpr (q < R) issue(z0 - 2 + q, SU(I), SB(I), SE(I));
+    };
+    auto mask_at = [&](auto I, int p) {
+        if constexpr (ZIN) SU(I) = masku(zero, p);
+        else SU(I) = masku(SU(I), p);
+        SE(I) = maske(SE(I), p);
     };
     auto vface = [&](const P2 &lo, const P2 &hi) {
         P2 r;
@@ -559,34 +583,26 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
         w.v[1] = e.v[1];
         *reinterpret_cast<Pair<C> *>(&s_e[ry][lx]) = w;
     };
-    {
-        P2 t0u, t0b, t0e, t1u, t1b, t1e, t2u, t2b, t2e;
-        issue(z0 - 2, t0u, t0b, t0e);
-        issue(z0 - 1, t1u, t1b, t1e);
-        issue(z0, t2u, t2b, t2e);
-        issue(z0 + 1, qu0, qb0, qe0);
-        if constexpr (PD > 1) issue(z0 + 2, qu1, qb1, qe1);
-        if constexpr (PD > 2) issue(z0 + 3, qu2, qb2, qe2);
-        if constexpr (PD > 3) issue(z0 + 4, qu3, qb3, qe3);
-        um = masku(ZIN ? zero : t0u, z0 - 2);
-        u0 = masku(ZIN ? zero : t1u, z0 - 1);
-        up = masku(ZIN ? zero : t2u, z0);
-        bm = t0b;
-        b0 = t1b;
-        bp = t2b;
-        const P2 em = maske(t0e, z0 - 2);
-        e0 = maske(t1e, z0 - 1);
-        ep = maske(t2e, z0);
-        // faces of plane z0-1 and the vertical faces below it
-        put_e(e0);
-        lds_barrier();
-        form_faces(z0 - 1, e0);
-        zB = vface(em, e0);
-        lds_barrier();
-    }
+    issue_at(std::integral_constant<int, 0>{});
+    issue_at(std::integral_constant<int, 1>{});
+    issue_at(std::integral_constant<int, 2>{});
+    issue_at(std::integral_constant<int, 3>{});
+    issue_at(std::integral_constant<int, 4>{});
+    issue_at(std::integral_constant<int, 5>{});
+    issue_at(std::integral_constant<int, 6>{});
+    mask_at(std::integral_constant<int, 0>{}, z0 - 2);
+    mask_at(std::integral_constant<int, 1>{}, z0 - 1);
+    mask_at(std::integral_constant<int, 2>{}, z0);
+    // faces of plane z0-1 and the vertical faces below it
+    put_e(se1);
+    lds_barrier();
+    form_faces(z0 - 1, se1);
+    zB = vface(se0, se1);
+    lds_barrier();
     C rn_cur = C(0), rn_prev = C(0), rn_prev2 = C(0);  // new red values of planes k, k-1, k-2
 
-    auto step = [&](int k) __attribute__((always_inline)) {
+    auto step = [&](const P2 &um, const P2 &u0, const P2 &up, const P2 &bm, const P2 &b0, const P2 &e0,
+                    const P2 &ep, int k) __attribute__((always_inline)) {
         zC = vface(e0, ep);
         {
             Pair<C> w;
@@ -646,7 +662,7 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
                 char *pk = reinterpret_cast<char *>(uout) + plane_at(kb);
                 if (even_nx) {
                     const T tb = N::cv(vb), tr = N::cv(rn_prev);
-                    store_pair_nt(reinterpret_cast<T *>(pk + lb0), bo ? tr : tb, bo ? tb : tr);
+                    store_pair_nt(reinterpret_cast<T *>(pk + lane_at(lb0, kb)), bo ? tr : tb, bo ? tb : tr);
                 } else {
                     *reinterpret_cast<T *>(pk + (bo ? lb1 : lb0)) = N::cv(vb);
                     if (ro ? c1_in : c0_in) *reinterpret_cast<T *>(pk + (ro ? lb1 : lb0)) = N::cv(rn_prev);
@@ -660,24 +676,32 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
         lds_barrier();
     };
 
-    // shift in plane k+1 from ring slot S, refill the slot with k+1+PD, step k
-    auto iter = [&](auto S, int k) __attribute__((always_inline)) {
-        um = u0; u0 = up;
-        bm = b0; b0 = bp;
-        e0 = ep;
-        zA = zB; zB = zC;
-        up = masku(ZIN ? zero : QU(S), k + 1);
-        bp = QB(S);
-        ep = maske(QE(S), k + 1);
-        if (k + 1 + PD <= z1 + 1) issue(k + 1 + PD, QU(S), QB(S), QE(S));
-        step(k);
+    // step k = kk + J of an unrolled group: refill slot J (plane k-2, read
+    // last by step k-1) with plane k+1+PD (the last plane of the chunk once
+    // past it), mask plane k+1, step
+    auto iter = [&](auto J, int k) __attribute__((always_inline)) {
+        constexpr int q = decltype(J)::value;
+        using I1 = std::integral_constant<int, q + 1>;
+        using I2 = std::integral_constant<int, q + 2>;
+        using I3 = std::integral_constant<int, q + 3>;
+        zA = zB;
+        zB = zC;
+        issue(min(k + 1 + PD, z1 + 1), SU(J), SB(J), SE(J));
+        mask_at(I3{}, k + 1);
+        step(SU(I1{}), SU(I2{}), SU(I3{}), SB(I1{}), SB(I2{}), SE(I2{}), SE(I3{}), k);
     };
-    step(z0 - 1);
-    for (int kk = z0; kk <= z1; kk += PD) {
+    step(su0, su1, su2, sb0, sb1, se1, se2, z0 - 1);
+    for (int kk = z0; kk <= z1; kk += R) {
         iter(std::integral_constant<int, 0>{}, kk);
-        if constexpr (PD > 1) { if (kk + 1 > z1) break; iter(std::integral_constant<int, 1>{}, kk + 1); }
-        if constexpr (PD > 2) { if (kk + 2 > z1) break; iter(std::integral_constant<int, 2>{}, kk + 2); }
-        if constexpr (PD > 3) { if (kk + 3 > z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
+        if (kk + 1 > z1) break;
+        iter(std::integral_constant<int, 1>{}, kk + 1);
+        if (kk + 2 > z1) break;
+        iter(std::integral_constant<int, 2>{}, kk + 2);
+        if (kk + 3 > z1) break;
+        iter(std::integral_constant<int, 3>{}, kk + 3);
+        if constexpr (R > 4) { if (kk + 4 > z1) break; iter(std::integral_constant<int, 4>{}, kk + 4); }
+        if constexpr (R > 5) { if (kk + 5 > z1) break; iter(std::integral_constant<int, 5>{}, kk + 5); }
+        if constexpr (R > 6) { if (kk + 6 > z1) break; iter(std::integral_constant<int, 6>{}, kk + 6); }
     }
 }
 
@@ -810,9 +834,12 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
         else if constexpr (v == 4) return sb4; else if constexpr (v == 5) return sb5;
         else return sb6;
     };
+    // every lane loads every plane (b outside the tile's ring and planes
+    // past the chunk are not used): loads under a condition would make the
+    // compiler wait for all outstanding loads where one of them is used
     auto issue = [&](int k, P2 &du, P2 &db) {
         if constexpr (!ZIN) du = ld_pair(uin, k);
-        db = ld_pair(b, k);  // b is read on the tile and its ring only
+        db = ld_pair(b, k);
     };
     auto issue_at = [&](auto I) {
         constexpr int q = decltype(I)::value;
@@ -890,7 +917,8 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
     };
 
     // step k = kk + J of an unrolled group: refill slot J (plane k-2, read
-    // last by step k-1) with plane k+1+PD, mask plane k+1, step
+    // last by step k-1) with plane k+1+PD (the last plane of the chunk once
+    // past it), mask plane k+1, step
     auto iter = [&](auto J, int k) __attribute__((always_inline)) {
         constexpr int q = decltype(J)::value;
         using I1 = std::integral_constant<int, q + 1>;
@@ -998,32 +1026,40 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
     struct FS { C x0, x1, x2; P2 yd, yu, zb; };  // faces of one plane (scaled)
     P2 zero;
     zero.v[0] = zero.v[1] = C(0);
+    // element e of plane k (plane length pl) of array a: a uniform plane
+    // base plus a 32-bit lane offset
+    auto at = [&](const auto *__restrict__ a, int k, size_t pl, uint32_t e) {
+        using A_ = std::remove_cv_t<std::remove_reference_t<decltype(*a)>>;
+        const char *pk = reinterpret_cast<const char *>(a) + (size_t)k * pl * sizeof(A_);
+        return reinterpret_cast<const A_ *>(pk + lane_at(e * (uint32_t)sizeof(A_), k));
+    };
     auto ld_u = [&](const T *__restrict__ a, int k) -> P2 {
-        const T *pk = a + (size_t)cl(k, nz - 1) * plane;
+        const int kc = cl(k, nz - 1);
         P2 r;
         if (even_nx) {
-            const Pair<T> w = ld_wide<T>(pk + le0);
+            const Pair<T> w = ld_wide<T>(at(a, kc, plane, le0));
             r.v[0] = N::ld(w.v[0]);
             r.v[1] = N::ld(w.v[1]);
         } else {
-            r.v[0] = N::ld(pk[le0]);
-            r.v[1] = N::ld(pk[le1]);
+            r.v[0] = N::ld(*at(a, kc, plane, le0));
+            r.v[1] = N::ld(*at(a, kc, plane, le1));
         }
         return r;
     };
     // raw faces of plane k (scaled when the plane is shifted in)
     auto ld_f = [&](int k) -> FS {
         FS f;
-        const F *px = fbx + (size_t)cl(k, nz - 1) * fxpl + lfx;
+        const int kc = cl(k, nz - 1);
+        const F *px = at(fbx, kc, fxpl, lfx);
         f.x0 = Num<F>::ld(px[0]);
         f.x1 = Num<F>::ld(px[1]);
         f.x2 = Num<F>::ld(px[c1_in || !pin ? 2 : 1]);  // odd nx: the pair may end at the box face
-        const F *py = fby + (size_t)cl(k, nz - 1) * fypl;
+        const F *py = fby + (size_t)kc * fypl;
         const F *pz = fbz + (size_t)cl(k, nz) * plane + lfd;
         if (even_nx) {
-            const Pair<F> d = ld_wide<F>(py + lfd);
-            const Pair<F> u = ld_wide<F>(py + lfu);
-            const Pair<F> z = ld_wide<F>(pz);
+            const Pair<F> d = ld_wide<F>(at(fby, kc, fypl, lfd));
+            const Pair<F> u = ld_wide<F>(at(fby, kc, fypl, lfu));
+            const Pair<F> z = ld_wide<F>(at(fbz, cl(k, nz), plane, lfd));
             f.yd.v[0] = Num<F>::ld(d.v[0]);
             f.yd.v[1] = Num<F>::ld(d.v[1]);
             f.yu.v[0] = Num<F>::ld(u.v[0]);
@@ -1064,62 +1100,69 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
         return r;
     };
 
-    // current planes: u at k-1, k, k+1; b at k-1, k, k+1; faces at k-1, k, k+1
-    P2 um, u0, up, bm, b0, bp;
-    FS fm, f0, fp;
+    // A ring of R = PD + 3 plane slots for u, b and the faces: plane p
+    // occupies slot (p - z0 + 2) mod R from its load, PD steps before the
+    // step that first reads it, until the step after its own.  The steps are
+    // unrolled R at a time, so every slot index is a constant and no loaded
+    // value moves between registers (such a move would wait for its load at
+    // once).  u is masked and the faces scaled in place when their plane
+    // first becomes the upper neighbour.
     static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
-    P2 qu0, qu1, qu2, qu3, qb0, qb1, qb2, qb3;
-    FS qf0, qf1, qf2, qf3;
-    auto QU = [&](auto S) -> P2 & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qu0; else if constexpr (v == 1) return qu1;
-        else if constexpr (v == 2) return qu2; else return qu3;
+    constexpr int R = PD + 3;
+    P2 su0, su1, su2, su3, su4, su5, su6, sb0, sb1, sb2, sb3, sb4, sb5, sb6;
+    FS sf0, sf1, sf2, sf3, sf4, sf5, sf6;
+    auto SU = [&](auto I) -> P2 & {
+        constexpr int v = decltype(I)::value % R;
+        if constexpr (v == 0) return su0; else if constexpr (v == 1) return su1;
+        else if constexpr (v == 2) return su2; else if constexpr (v == 3) return su3;
+        else if constexpr (v == 4) return su4; else if constexpr (v == 5) return su5;
+        else return su6;
     };
-    auto QB = [&](auto S) -> P2 & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qb0; else if constexpr (v == 1) return qb1;
-        else if constexpr (v == 2) return qb2; else return qb3;
+    auto SB = [&](auto I) -> P2 & {
+        constexpr int v = decltype(I)::value % R;
+        if constexpr (v == 0) return sb0; else if constexpr (v == 1) return sb1;
+        else if constexpr (v == 2) return sb2; else if constexpr (v == 3) return sb3;
+        else if constexpr (v == 4) return sb4; else if constexpr (v == 5) return sb5;
+        else return sb6;
     };
-    auto QF = [&](auto S) -> FS & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qf0; else if constexpr (v == 1) return qf1;
-        else if constexpr (v == 2) return qf2; else return qf3;
+    auto SF = [&](auto I) -> FS & {
+        constexpr int v = decltype(I)::value % R;
+        if constexpr (v == 0) return sf0; else if constexpr (v == 1) return sf1;
+        else if constexpr (v == 2) return sf2; else if constexpr (v == 3) return sf3;
+        else if constexpr (v == 4) return sf4; else if constexpr (v == 5) return sf5;
+        else return sf6;
     };
+    // every lane loads every plane (b outside the tile's ring and planes
+    // past the chunk are not used): loads under a condition would make the
+    // compiler wait for all outstanding loads where one of them is used
     auto issue = [&](int k, P2 &du, P2 &db, FS &df) {
         if constexpr (!ZIN) du = ld_u(uin, k);
-        db = zero;  // b is used on the tile and its ring only
-        if (y >= -1 && y <= TY) db = ld_u(b, k);
+        db = ld_u(b, k);
         df = ld_f(k);
     };
-    {
-        P2 t0u, t0b, t1u, t1b, t2u, t2b;
-        FS t0f, t1f, t2f;
-        issue(z0 - 2, t0u, t0b, t0f);
-        issue(z0 - 1, t1u, t1b, t1f);
-        issue(z0, t2u, t2b, t2f);
-        issue(z0 + 1, qu0, qb0, qf0);
-        if constexpr (PD > 1) issue(z0 + 2, qu1, qb1, qf1);
-        if constexpr (PD > 2) issue(z0 + 3, qu2, qb2, qf2);
-        if constexpr (PD > 3) issue(z0 + 4, qu3, qb3, qf3);
-        if constexpr (ZIN) {
-            um = masku(zero, z0 - 2);
-            u0 = masku(zero, z0 - 1);
-            up = masku(zero, z0);
-        } else {
-            um = masku(t0u, z0 - 2);
-            u0 = masku(t1u, z0 - 1);
-            up = masku(t2u, z0);
-        }
-        bm = t0b;
-        b0 = t1b;
-        bp = t2b;
-        fm = scale(t0f, z0 - 2);
-        f0 = scale(t1f, z0 - 1);
-        fp = scale(t2f, z0);
-    }
+    auto issue_at = [&](auto I) {
+        constexpr int q = decltype(I)::value;
+        if constexpr (q < R) issue(z0 - 2 + q, SU(I), SB(I), SF(I));
+    };
+    auto mask_at = [&](auto I, int p) {
+        if constexpr (ZIN) SU(I) = masku(zero, p);
+        else SU(I) = masku(SU(I), p);
+        SF(I) = scale(SF(I), p);
+    };
+    issue_at(std::integral_constant<int, 0>{});
+    issue_at(std::integral_constant<int, 1>{});
+    issue_at(std::integral_constant<int, 2>{});
+    issue_at(std::integral_constant<int, 3>{});
+    issue_at(std::integral_constant<int, 4>{});
+    issue_at(std::integral_constant<int, 5>{});
+    issue_at(std::integral_constant<int, 6>{});
+    mask_at(std::integral_constant<int, 0>{}, z0 - 2);
+    mask_at(std::integral_constant<int, 1>{}, z0 - 1);
+    mask_at(std::integral_constant<int, 2>{}, z0);
     C rn_cur = C(0), rn_prev = C(0), rn_prev2 = C(0);  // new red values of planes k, k-1, k-2
 
-    auto step = [&](int k) __attribute__((always_inline)) {
+    auto step = [&](const P2 &um, const P2 &u0, const P2 &up, const P2 &bm, const P2 &b0, const FS &fm,
+                    const FS &f0, const FS &fp, int k) __attribute__((always_inline)) {
         {
             Pair<C> w;
             w.v[0] = u0.v[0];
@@ -1174,7 +1217,7 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
                 T *pk = uout + (size_t)kb * plane;
                 if (even_nx) {
                     const T tb = N::cv(vb), tr = N::cv(rn_prev);
-                    store_pair_nt(pk + le0, bo ? tr : tb, bo ? tb : tr);
+                    store_pair_nt(const_cast<T *>(at(uout, kb, plane, le0)), bo ? tr : tb, bo ? tb : tr);
                 } else {
                     pk[bo ? le1 : le0] = N::cv(vb);
                     if (ro ? c1_in : c0_in) pk[ro ? le1 : le0] = N::cv(rn_prev);
@@ -1187,24 +1230,30 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
         lds_barrier();
     };
 
-    // shift in plane k+1 from ring slot S, refill the slot with k+1+PD, step k
-    auto iter = [&](auto S, int k) __attribute__((always_inline)) {
-        um = u0; u0 = up;
-        bm = b0; b0 = bp;
-        fm = f0; f0 = fp;
-        if constexpr (ZIN) up = masku(zero, k + 1);
-        else up = masku(QU(S), k + 1);
-        bp = QB(S);
-        fp = scale(QF(S), k + 1);
-        if (k + 1 + PD <= z1 + 1) issue(k + 1 + PD, QU(S), QB(S), QF(S));
-        step(k);
+    // step k = kk + J of an unrolled group: refill slot J (plane k-2, read
+    // last by step k-1) with plane k+1+PD (the last plane of the chunk once
+    // past it), mask and scale plane k+1, step
+    auto iter = [&](auto J, int k) __attribute__((always_inline)) {
+        constexpr int q = decltype(J)::value;
+        using I1 = std::integral_constant<int, q + 1>;
+        using I2 = std::integral_constant<int, q + 2>;
+        using I3 = std::integral_constant<int, q + 3>;
+        issue(min(k + 1 + PD, z1 + 1), SU(J), SB(J), SF(J));
+        mask_at(I3{}, k + 1);
+        step(SU(I1{}), SU(I2{}), SU(I3{}), SB(I1{}), SB(I2{}), SF(I1{}), SF(I2{}), SF(I3{}), k);
     };
-    step(z0 - 1);
-    for (int kk = z0; kk <= z1; kk += PD) {
+    step(su0, su1, su2, sb0, sb1, sf0, sf1, sf2, z0 - 1);
+    for (int kk = z0; kk <= z1; kk += R) {
         iter(std::integral_constant<int, 0>{}, kk);
-        if constexpr (PD > 1) { if (kk + 1 > z1) break; iter(std::integral_constant<int, 1>{}, kk + 1); }
-        if constexpr (PD > 2) { if (kk + 2 > z1) break; iter(std::integral_constant<int, 2>{}, kk + 2); }
-        if constexpr (PD > 3) { if (kk + 3 > z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
+        if (kk + 1 > z1) break;
+        iter(std::integral_constant<int, 1>{}, kk + 1);
+        if (kk + 2 > z1) break;
+        iter(std::integral_constant<int, 2>{}, kk + 2);
+        if (kk + 3 > z1) break;
+        iter(std::integral_constant<int, 3>{}, kk + 3);
+        if constexpr (R > 4) { if (kk + 4 > z1) break; iter(std::integral_constant<int, 4>{}, kk + 4); }
+        if constexpr (R > 5) { if (kk + 5 > z1) break; iter(std::integral_constant<int, 5>{}, kk + 5); }
+        if constexpr (R > 6) { if (kk + 6 > z1) break; iter(std::integral_constant<int, 6>{}, kk + 6); }
     }
 }
 
