@@ -1580,7 +1580,7 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
         using A_ = std::remove_cv_t<std::remove_reference_t<decltype(*p)>>;
         constexpr uint32_t es = sizeof(A_);
         const char *pk = reinterpret_cast<const char *>(p) + (size_t)min(max(k, 0), nz - 1) * plane * es;
-        const Pair<A_> w = ld_wide<A_>(pk + le * es);
+        const Pair<A_> w = ld_wide<A_>(pk + lane_at(le * es, k));
         P2 r;
         r.v[0] = Num<A_>::ld(w.v[0]);
         r.v[1] = Num<A_>::ld(w.v[1]);
@@ -1631,53 +1631,68 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
         else return mask_out(v, k, uout, uz_lo, uz_hi);
     };
     auto maske = [&](P2 v, int k) -> P2 { return mask_out(v, k, eout, ez_lo, ez_hi); };
-    P2 um, u0, up, e_m, e0, e_p, b0;
+    // A ring of R = PD + 3 plane slots for u, eps and b: plane p occupies
+    // slot (p - z0 + 1) mod R from its load, PD steps before the step that
+    // first reads it, until the step after its own.  The steps are unrolled
+    // R at a time, so every slot index is a constant and no loaded value
+    // moves between registers (such a move would wait for its load at
+    // once).  u and eps are masked in place when their plane first becomes
+    // the upper neighbour.
     static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
-    P2 qu0, qu1, qu2, qu3, qe0, qe1, qe2, qe3, qb0, qb1, qb2, qb3;
-    auto QU = [&](auto S) -> P2 & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qu0; else if constexpr (v == 1) return qu1;
-        else if constexpr (v == 2) return qu2; else return qu3;
+    constexpr int R = PD + 3;
+    P2 su0, su1, su2, su3, su4, su5, su6, se0, se1, se2, se3, se4, se5, se6;
+    P2 sb0, sb1, sb2, sb3, sb4, sb5, sb6;
+    auto SU = [&](auto I) -> P2 & {
+        constexpr int v = decltype(I)::value % R;
+        if constexpr (v == 0) return su0; else if constexpr (v == 1) return su1;
+        else if constexpr (v == 2) return su2; else if constexpr (v == 3) return su3;
+        else if constexpr (v == 4) return su4; else if constexpr (v == 5) return su5;
+        else return su6;
     };
-    auto QE = [&](auto S) -> P2 & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qe0; else if constexpr (v == 1) return qe1;
-        else if constexpr (v == 2) return qe2; else return qe3;
+    auto SE = [&](auto I) -> P2 & {
+        constexpr int v = decltype(I)::value % R;
+        if constexpr (v == 0) return se0; else if constexpr (v == 1) return se1;
+        else if constexpr (v == 2) return se2; else if constexpr (v == 3) return se3;
+        else if constexpr (v == 4) return se4; else if constexpr (v == 5) return se5;
+        else return se6;
     };
-    auto QB = [&](auto S) -> P2 & {
-        constexpr int v = decltype(S)::value;
-        if constexpr (v == 0) return qb0; else if constexpr (v == 1) return qb1;
-        else if constexpr (v == 2) return qb2; else return qb3;
+    auto SB = [&](auto I) -> P2 & {
+        constexpr int v = decltype(I)::value % R;
+        if constexpr (v == 0) return sb0; else if constexpr (v == 1) return sb1;
+        else if constexpr (v == 2) return sb2; else if constexpr (v == 3) return sb3;
+        else if constexpr (v == 4) return sb4; else if constexpr (v == 5) return sb5;
+        else return sb6;
     };
-    // u/eps of plane p wait in slot (p - z0 - 2) mod PD; b of plane p in slot (p - z0 - 1) mod PD
-    auto issue = [&](int k, P2 &du, P2 &de) {
+    // every lane loads every plane (planes past the chunk are not used):
+    // loads under a condition would make the compiler wait for all
+    // outstanding loads where one of them is used
+    auto issue = [&](int k, P2 &du, P2 &de, P2 &db) {
         du = ld_pair(u, k);
         if constexpr (CELL) de = ld_pair(eps, k);
+        db = ld_pair(b, k);
     };
-    {
-        P2 t0u, t0e, t1u, t1e, t2u, t2e, tb;
-        issue(z0 - 1, t0u, t0e);
-        issue(z0, t1u, t1e);
-        issue(z0 + 1, t2u, t2e);
-        tb = ld_pair(b, z0);
-        issue(z0 + 2, qu0, qe0);
-        qb0 = ld_pair(b, z0 + 1);
-        if constexpr (PD > 1) { issue(z0 + 3, qu1, qe1); qb1 = ld_pair(b, z0 + 2); }
-        if constexpr (PD > 2) { issue(z0 + 4, qu2, qe2); qb2 = ld_pair(b, z0 + 3); }
-        if constexpr (PD > 3) { issue(z0 + 5, qu3, qe3); qb3 = ld_pair(b, z0 + 4); }
-        um = masku(t0u, z0 - 1);
-        u0 = masku(t1u, z0);
-        up = masku(t2u, z0 + 1);
-        b0 = tb;  // used on the tile only
-        if constexpr (CELL) {
-            e_m = maske(t0e, z0 - 1);
-            e0 = maske(t1e, z0);
-            e_p = maske(t2e, z0 + 1);
-        }
-    }
+    auto issue_at = [&](auto I) {
+        constexpr int q = decltype(I)::value;
+        if constexpr (q < R) issue(z0 - 1 + q, SU(I), SE(I), SB(I));
+    };
+    auto mask_at = [&](auto I, int p) {
+        SU(I) = masku(SU(I), p);
+        if constexpr (CELL) SE(I) = maske(SE(I), p);
+    };
+    issue_at(std::integral_constant<int, 0>{});
+    issue_at(std::integral_constant<int, 1>{});
+    issue_at(std::integral_constant<int, 2>{});
+    issue_at(std::integral_constant<int, 3>{});
+    issue_at(std::integral_constant<int, 4>{});
+    issue_at(std::integral_constant<int, 5>{});
+    issue_at(std::integral_constant<int, 6>{});
+    mask_at(std::integral_constant<int, 0>{}, z0 - 1);
+    mask_at(std::integral_constant<int, 1>{}, z0);
+    mask_at(std::integral_constant<int, 2>{}, z0 + 1);
     double nrm = 0.0;
     C acc = C(0);
-    auto step = [&](int k) {
+    auto step = [&](const P2 &um, const P2 &u0, const P2 &up, const P2 &e_m, const P2 &e0, const P2 &e_p,
+                    const P2 &b0, int k) __attribute__((always_inline)) {
         if (live) {
             Pair<C> w;
             w.v[0] = u0.v[0];
@@ -1763,21 +1778,30 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
         }
         lds_barrier();
     };
-    auto iter = [&](auto S, int k) {
-        um = u0; u0 = up;
-        if constexpr (CELL) { e_m = e0; e0 = e_p; }
-        up = masku(QU(S), k + 1);
-        if constexpr (CELL) e_p = maske(QE(S), k + 1);
-        b0 = QB(S);
-        if (k + 1 + PD < z1 + 1) { issue(k + 1 + PD, QU(S), QE(S)); QB(S) = ld_pair(b, k + PD); }
-        step(k);
+    // step k = kk + J of an unrolled group: refill slot J (plane k-2, read
+    // last by step k-1) with plane k+1+PD (the chunk's upper neighbour plane
+    // once past it), mask plane k+1, step
+    auto iter = [&](auto J, int k) __attribute__((always_inline)) {
+        constexpr int q = decltype(J)::value;
+        using I1 = std::integral_constant<int, q + 1>;
+        using I2 = std::integral_constant<int, q + 2>;
+        using I3 = std::integral_constant<int, q + 3>;
+        issue(min(k + 1 + PD, z1), SU(J), SE(J), SB(J));
+        mask_at(I3{}, k + 1);
+        step(SU(I1{}), SU(I2{}), SU(I3{}), SE(I1{}), SE(I2{}), SE(I3{}), SB(I2{}), k);
     };
-    step(z0);
-    for (int kk = z0 + 1; kk < z1; kk += PD) {
+    step(su0, su1, su2, se0, se1, se2, sb1, z0);
+    for (int kk = z0 + 1; kk < z1; kk += R) {
         iter(std::integral_constant<int, 0>{}, kk);
-        if constexpr (PD > 1) { if (kk + 1 >= z1) break; iter(std::integral_constant<int, 1>{}, kk + 1); }
-        if constexpr (PD > 2) { if (kk + 2 >= z1) break; iter(std::integral_constant<int, 2>{}, kk + 2); }
-        if constexpr (PD > 3) { if (kk + 3 >= z1) break; iter(std::integral_constant<int, 3>{}, kk + 3); }
+        if (kk + 1 >= z1) break;
+        iter(std::integral_constant<int, 1>{}, kk + 1);
+        if (kk + 2 >= z1) break;
+        iter(std::integral_constant<int, 2>{}, kk + 2);
+        if (kk + 3 >= z1) break;
+        iter(std::integral_constant<int, 3>{}, kk + 3);
+        if constexpr (R > 4) { if (kk + 4 >= z1) break; iter(std::integral_constant<int, 4>{}, kk + 4); }
+        if constexpr (R > 5) { if (kk + 5 >= z1) break; iter(std::integral_constant<int, 5>{}, kk + 5); }
+        if constexpr (R > 6) { if (kk + 6 >= z1) break; iter(std::integral_constant<int, 6>{}, kk + 6); }
     }
     if (A.slot >= 0)
         reduce2_finish<NTP>(nrm, 0.0, A.ws, A.slot, blk);
