@@ -85,7 +85,7 @@ int set_err(int code, const char *fmt, ...);
 Geo level_geo(const Ctx *c, int l, bool with_g);
 Coef level_coef(const Ctx *c, int l, bool lowp);
 void build_tail(const Ctx *c, TailDesc &D, bool with_g);
-int tile_for(const Ctx *c, const Geo &G, int st, int l, int *zc);
+int tile_for(const Ctx *c, const Geo &G, int st, int mode, int l, int *zc);
 int vcycle(Ctx *c, std::vector<LvView> &V, int l, bool zero_start, const int *done = nullptr);
 void fp64_view(Ctx *c, std::vector<LvView> &V, const double *f, double *x);
 void lowp_view(Ctx *c, std::vector<LvView> &V);

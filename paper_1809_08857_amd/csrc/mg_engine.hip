@@ -129,13 +129,13 @@ void build_tail(const Ctx *c, TailDesc &D, bool with_g) {
 
 // ------------------------------------------------------------ V-cycle
 
-int tile_for(const Ctx *c, const Geo &G, int st, int l, int *zc) {
+int tile_for(const Ctx *c, const Geo &G, int st, int mode, int l, int *zc) {
     int t = 0, z = 0;
     if (l == 0) {
         t = (st == ST_F64) ? c->tile64 : c->tile_lp;
         z = (st == ST_F64) ? c->zc64 : c->zc_lp;
     }
-    if (t <= 0) t = default_tile(G, st);
+    if (t <= 0) t = default_tile(G, st, mode);
     if (z <= 0) z = default_zchunk(G, t, st);
     *zc = z;
     return t;
@@ -154,7 +154,7 @@ int vcycle(Ctx *c, std::vector<LvView> &V, int l, bool zero_start, const int *do
         return MG_OK;
     }
     int zc;
-    const int tile = tile_for(c, W.G, W.st, l, &zc);
+    const int tile = tile_for(c, W.G, W.st, W.C.mode, l, &zc);
     bool zin = zero_start;
     for (int q = 0; q < c->d.nu1; ++q) {
         CK(timed_smooth(c, l, W, zin, tile, zc, done));
@@ -600,7 +600,7 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
             W.u = cur;
             W.t = oth;
             int zc;
-            const int tile = tile_for(c, W.G, W.st, 0, &zc);
+            const int tile = tile_for(c, W.G, W.st, W.C.mode, 0, &zc);
             for (int q = 0; q < c->d.nu1; ++q) {
                 CK(timed_smooth(c, 0, W, false, tile, zc, done));
                 std::swap(W.u, W.t);
@@ -636,7 +636,7 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
             W.u = cur;
             W.t = oth;
             int zc;
-            const int tile = tile_for(c, W.G, W.st, 0, &zc);
+            const int tile = tile_for(c, W.G, W.st, W.C.mode, 0, &zc);
             for (int q = 0; q < c->d.nu2; ++q) {
                 CK(timed_smooth(c, 0, W, false, tile, zc, done));
                 std::swap(W.u, W.t);
@@ -651,7 +651,7 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
         // the FP64 pre-smoothing of the guess (the low-precision cycles
         // start from a residual)
         int zc;
-        const int tile = tile_for(c, G0, ST_F64, 0, &zc);
+        const int tile = tile_for(c, G0, ST_F64, C0.mode, 0, &zc);
         for (int q = 0; q < c->d.nu1; ++q) {
             CK(smooth(s, ST_F64, G0, C0, cur, oth, f, false, tile, zc));
             std::swap(cur, oth);
@@ -744,7 +744,7 @@ int mg_smooth(mg_ctx *c, const double *f_dev, double *x_dev, int sweeps) {
     const Geo G0 = level_geo(c, 0, true);
     const Coef C0 = level_coef(c, 0, false);
     int zc;
-    const int tile = tile_for(c, G0, ST_F64, 0, &zc);
+    const int tile = tile_for(c, G0, ST_F64, C0.mode, 0, &zc);
     double *u = x_dev, *t = c->xalt;
     for (int q = 0; q < sweeps; ++q) {
         CK(smooth(s, ST_F64, G0, C0, u, t, f_dev, false, tile, zc));

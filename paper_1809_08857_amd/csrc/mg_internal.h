@@ -98,7 +98,7 @@ inline void brick_shape(int nxi, int ny, int nz, int max_blocks, dim3 *grid, dim
 // Tile variants of the fused red-black smoother: (TX, TY) per index 1..6.
 constexpr int kNumTiles = 6;
 void tile_shape(int t, int *tx, int *ty);
-int default_tile(const Geo &G, int st);
+int default_tile(const Geo &G, int st, int mode);
 int default_zchunk(const Geo &G, int tile, int st);
 
 // One fused red-black Gauss-Seidel sweep, out of place: uout = sweep(uin).

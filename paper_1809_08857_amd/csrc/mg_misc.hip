@@ -142,9 +142,12 @@ void tile_shape(int t, int *tx, int *ty) {
     *ty = TY[t];
 }
 
-int default_tile(const Geo &G, int st) {
+int default_tile(const Geo &G, int st, int mode) {
     (void)st;
-    if (G.nx >= 64 && G.ny >= 16 && (long)G.nx * G.ny * G.nz >= (8L << 20)) return 1;  // 64 x 16
+    // stored faces keep nine face values per plane in flight: the 64 x 16
+    // tile (680 threads, at most 168 registers each) would spill them
+    if (mode != COEF_FACE && G.nx >= 64 && G.ny >= 16 && (long)G.nx * G.ny * G.nz >= (8L << 20))
+        return 1;                             // 64 x 16
     if (G.nx >= 64) return 3;                 // 64 x 8
     if (G.nx >= 32) return 4;                 // 32 x 8
     return 6;                                 // 16 x 8
