@@ -79,10 +79,12 @@ def test_smoother_parity(k, sweeps):
 
 @pytest.mark.parametrize("tile", range(1, mg.MG_NUM_TILES + 1))
 @pytest.mark.parametrize("zchunk", [3, 64])
-def test_smoother_every_tile_variant(tile, zchunk):
-    """Every (TX, TY) tile and a z-chunk that splits the grid unevenly."""
-    p = synth.random_problem(112, 24, 40, 21)
-    print(f"tile {tile} zchunk {zchunk}", flush=True)
+@pytest.mark.parametrize("cell_eps", [True, False])
+def test_smoother_every_tile_variant(tile, zchunk, cell_eps):
+    """Every (TX, TY) tile and a z-chunk that splits the grid unevenly, with
+    cell coefficients and with beta = 1."""
+    p = synth.random_problem(112, 24, 40, 21, variable_eps=cell_eps)
+    print(f"tile {tile} zchunk {zchunk} cell_eps {cell_eps}", flush=True)
     rng = np.random.default_rng(tile)
     u0 = rng.standard_normal(p.shape)
     ref = oracle.rbgs(p, u0, 1)
@@ -91,6 +93,30 @@ def test_smoother_every_tile_variant(tile, zchunk):
         mg.mg_set_tiling(s.ctx, tile, zchunk)
         x = dev(u0)
         mg.mg_smooth(s.ctx, dev(p.f), x, 1)
+        got = x.cpu().numpy()
+    finally:
+        s.close()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("zchunk", [1, 2, 4, 5, 6, 7, 9])
+@pytest.mark.parametrize("cell_eps", [True, False])
+@pytest.mark.parametrize("dims", [(64, 32, 24), (15, 13, 16)])
+def test_smoother_plane_ring_chunks(zchunk, cell_eps, dims):
+    """The sweeps stream z planes through a ring of PD + 3 register slots
+    (5 for FP64) and unroll the plane loop that many steps at a time: chunks
+    shorter than, equal to and longer than the ring, with ragged last
+    chunks, even and odd row lengths."""
+    p = synth.random_problem(*dims, 60 + zchunk, variable_eps=cell_eps)
+    print(f"plane ring: {p.name} zchunk {zchunk} cell_eps {cell_eps}", flush=True)
+    rng = np.random.default_rng(zchunk)
+    u0 = rng.standard_normal(p.shape)
+    ref = oracle.rbgs(p, u0, 2)
+    s = make_solver(p)
+    try:
+        mg.mg_set_tiling(s.ctx, 3, zchunk)
+        x = dev(u0)
+        mg.mg_smooth(s.ctx, dev(p.f), x, 2)
         got = x.cpu().numpy()
     finally:
         s.close()
