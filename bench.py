@@ -270,7 +270,7 @@ def unet_flops(n: int) -> float:
 def learned_line(args):
     """Learned initial guess at n^3: per step one test source s, the U-net
     prediction of the three photon-group fields, then the three FP64
-    solves from those guesses (fallback to zero judged by the engine),
+    solves from those guesses (fallback to zero decided by the engine),
     against the three solves from zero.  Sources are resident on the GPU."""
     import numpy as np
     import torch
@@ -341,7 +341,7 @@ def learned_line(args):
     plain_value = 3 * args.steps / dt_p
     fl = unet_flops(n)
     cfg = {"workload": f"3 photon-group solves (kappa h = 0.05, 0.3, 1.5) at {n}^3 per step, FP64 V-cycles to "
-                       f"rel. residual 1e-10, started from the U-net guess (fallback to zero judged after "
+                       f"rel. residual 1e-10, started from the U-net guess (fallback to zero decided after "
                        f"pre-smoothing); sources: filament seeds {TEST_SEED0}..{TEST_SEED0 + nsrc - 1}",
            "grid": [n, n, n], "solves_per_step": 3, "precision": prec,
            "plain_solves_per_s": round(plain_value, 3), "speedup_vs_plain": round(value / plain_value, 4),
@@ -360,7 +360,7 @@ def learned_line(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU; runs on several GPUs are not implemented (the sharded design is described, not built)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np

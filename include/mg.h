@@ -157,7 +157,7 @@ int mg_solve(mg_ctx *c, const double *f_dev, double *x_dev, unsigned flags, mg_s
  * cycle is captured once into a hipGraph and replayed, and converged
  * problems are skipped on the device.  f_dev[i], x_dev[i] as in mg_solve
  * for context c[i]; st (optional) receives count entries.  With MG_GUESS
- * each guess is judged on its raw residual (||b - A x|| <= ||b||). */
+ * each guess is screened on its raw residual (||b - A x|| <= ||b||). */
 int mg_solve_batched(int count, mg_ctx *const *c, const double *const *f_dev,
                      double *const *x_dev, unsigned flags, mg_stats *st);
 

@@ -528,19 +528,19 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
     int *done = c->d_done;
     int rc;
     // ||b|| and the residual of the starting iterate
-    // A guess is judged at its first convergence test, after the nu1
+    // A guess is screened at its first convergence test, after the nu1
     // pre-smoothing sweeps that open every cycle (they remove the
     // cell-scale noise that the operator would otherwise magnify), against
     // the residual of the zero guess, ||b||.  Without a multigrid hierarchy
     // or pre-smoothing the raw residual is compared.
-    const bool judge = (flags & MG_GUESS) && c->tail > 0 && c->d.nu1 > 0;
-    const bool raw_guess = (flags & MG_GUESS) && !judge;
+    const bool screen = (flags & MG_GUESS) && c->tail > 0 && c->d.nu1 > 0;
+    const bool raw_guess = (flags & MG_GUESS) && !screen;
     if (!(flags & MG_GUESS)) CK(fill_zero(s, x, n0 * 8));
     CK(fill_zero(s, done, sizeof(int)));
     if (raw_guess) {
         CK(norm2_resid(s, ST_F64, G0, C0, x, f, c->ws, SLOT_R0, SLOT_B));
     } else {
-        // zero start: ||b - A 0|| = ||b||; a judged guess is tested later
+        // zero start: ||b - A 0|| = ||b||; a screened guess is tested later
         CK(norm2_b(s, G0, C0, f, c->ws, SLOT_B));
     }
     if ((rc = read_results(c, 2))) return rc;
@@ -561,7 +561,7 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
     }
     S.rel_res0 = rn / bn;
     const double rtol = c->d.rtol;
-    if (!judge && S.rel_res0 <= rtol) {
+    if (!screen && S.rel_res0 <= rtol) {
         CK(hipStreamSynchronize(s));
         S.rel_res = S.rel_res0;
         if (st) *st = S;
@@ -647,7 +647,7 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
         return MG_OK;
     };
 
-    if (judge && lowp) {
+    if (screen && lowp) {
         // the FP64 pre-smoothing of the guess (the low-precision cycles
         // start from a residual)
         int zc;
@@ -658,7 +658,7 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
         }
     }
     if ((rc = check(0))) return rc;
-    if (judge) {
+    if (screen) {
         CK(hipEventSynchronize(c->ev_cyc[0]));
         const double rel_s = std::sqrt(c->h_pin[SLOT_CYC]) / bn;
         if (!(rel_s <= 1.0)) {  // worse than the zero guess (or not finite): start from zero
