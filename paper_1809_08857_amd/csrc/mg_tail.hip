@@ -82,16 +82,24 @@ __device__ double block_sum(double v, double *red) {
     return t;
 }
 
+// One red-black sweep.  The threads enumerate only the cells of the colour
+// being updated: item t = (h, j, k) names the h-th cell of that colour in row
+// (j, k), at i = 2h + ((colour + j + k) & 1), so no lane idles on a cell of
+// the other colour.  Cells of one colour are independent; the update of each
+// is the same expression as for any other order.
 __device__ void gs_sweep(const TailDesc &D, int l, double *lds, bool with_g) {
     const TailLevel &L = D.L[l];
     double *u = lds + L.off_u;
     const double *b = lds + L.off_b;
-    const int n = L.nx * L.ny * L.nz;
+    const int hx = (L.nx + 1) >> 1;  // cells of one colour per row, at most
+    const int m = hx * L.ny * L.nz;
     for (int colour = 0; colour < 2; ++colour) {
-        for (int idx = threadIdx.x; idx < n; idx += kNT) {
-            int i, j, k;
-            decode(idx, L.nx, L.ny, i, j, k);
-            if (((i + j + k) & 1) != colour) continue;
+        for (int t = threadIdx.x; t < m; t += kNT) {
+            int h, j, k;
+            decode(t, hx, L.ny, h, j, k);
+            const int i = 2 * h + ((colour + j + k) & 1);
+            if (i >= L.nx) continue;  // odd nx: this row has one cell fewer of this colour
+            const int idx = (k * L.ny + j) * L.nx + i;
             double off, dg;
             tail_terms(D, l, lds, u, i, j, k, with_g, off, dg);
             u[idx] = (L.h2 * b[idx] + off) / (L.ah2 + dg);
