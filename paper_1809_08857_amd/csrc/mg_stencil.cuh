@@ -22,11 +22,13 @@
 namespace mg {
 
 // Prefetch depth of the column-pair kernels (planes in flight per array):
-// two planes for FP64; four for the 4- and 2-byte storage types, whose
-// planes carry half or a quarter of the bytes, so that about as many bytes
-// stay in flight per CU.
+// two planes for FP64; five for the 4- and 2-byte storage types, whose
+// planes carry half or a quarter of the bytes.  An odd depth makes the
+// plane ring (PD + 3 slots) even, which fixes the red/black parity of each
+// unrolled step (FP64 measured no faster with three planes and the fixed
+// parity than with two).  The batched engine's kernels keep two.
 constexpr int kSmoothPD = 2;
-template <class T> constexpr int kSmoothPDOf = sizeof(T) == 8 ? 2 : 4;
+template <class T> constexpr int kSmoothPDOf = sizeof(T) == 8 ? 2 : 5;
 
 template <class T> struct Num;
 template <> struct Num<double> {
@@ -516,30 +518,38 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
     // once).  u and eps are masked in place when their plane first becomes
     // the upper neighbour.  zA, zB, zC: the vertical faces of the pair
     // between planes k-2|k-1, k-1|k and k|k+1.
-    static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
+    static_assert(PD >= 1 && PD <= 5, "prefetch depth 1..5");
     constexpr int R = PD + 3;
-    P2 su0, su1, su2, su3, su4, su5, su6, sb0, sb1, sb2, sb3, sb4, sb5, sb6;
-    P2 se0, se1, se2, se3, se4, se5, se6;
+    // parity of gy + k (which cell of the pair is red on plane k): with R
+    // even it is the same for step J of every unrolled group, a per-lane
+    // constant that needs no per-plane arithmetic
+    const int pz = (gy + z0) & 1;
+    auto par = [&](auto J, int k) -> int {
+        if constexpr (R % 2 == 0) return pz ^ (decltype(J)::value & 1);
+        else return (gy + k) & 1;
+    };
+    P2 su0, su1, su2, su3, su4, su5, su6, su7, sb0, sb1, sb2, sb3, sb4, sb5, sb6, sb7;
+    P2 se0, se1, se2, se3, se4, se5, se6, se7;
     auto SU = [&](auto I) -> P2 & {
         constexpr int v = decltype(I)::value % R;
         if constexpr (v == 0) return su0; else if constexpr (v == 1) return su1;
         else if constexpr (v == 2) return su2; else if constexpr (v == 3) return su3;
         else if constexpr (v == 4) return su4; else if constexpr (v == 5) return su5;
-        else return su6;
+        else if constexpr (v == 6) return su6; else return su7;
     };
     auto SB = [&](auto I) -> P2 & {
         constexpr int v = decltype(I)::value % R;
         if constexpr (v == 0) return sb0; else if constexpr (v == 1) return sb1;
         else if constexpr (v == 2) return sb2; else if constexpr (v == 3) return sb3;
         else if constexpr (v == 4) return sb4; else if constexpr (v == 5) return sb5;
-        else return sb6;
+        else if constexpr (v == 6) return sb6; else return sb7;
     };
     auto SE = [&](auto I) -> P2 & {
         constexpr int v = decltype(I)::value % R;
         if constexpr (v == 0) return se0; else if constexpr (v == 1) return se1;
         else if constexpr (v == 2) return se2; else if constexpr (v == 3) return se3;
         else if constexpr (v == 4) return se4; else if constexpr (v == 5) return se5;
-        else return se6;
+        else if constexpr (v == 6) return se6; else return se7;
     };
     P2 zA, zB, zC;
     // every lane loads every plane (b outside the tile's ring and planes
@@ -590,6 +600,7 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
     issue_at(std::integral_constant<int, 4>{});
     issue_at(std::integral_constant<int, 5>{});
     issue_at(std::integral_constant<int, 6>{});
+    issue_at(std::integral_constant<int, 7>{});
     mask_at(std::integral_constant<int, 0>{}, z0 - 2);
     mask_at(std::integral_constant<int, 1>{}, z0 - 1);
     mask_at(std::integral_constant<int, 2>{}, z0);
@@ -602,7 +613,7 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
     C rn_cur = C(0), rn_prev = C(0), rn_prev2 = C(0);  // new red values of planes k, k-1, k-2
 
     auto step = [&](const P2 &um, const P2 &u0, const P2 &up, const P2 &bm, const P2 &b0, const P2 &e0,
-                    const P2 &ep, int k) __attribute__((always_inline)) {
+                    const P2 &ep, int k, int pk) __attribute__((always_inline)) {
         zC = vface(e0, ep);
         {
             Pair<C> w;
@@ -617,7 +628,7 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
         rn_prev2 = rn_prev;
         rn_prev = rn_cur;
         {
-            const int ro = (gy + k) & 1;  // red cell of the pair: x + ro
+            const int ro = pk;  // red cell of the pair: x + ro
             const int xr = x + ro;
             const int lr = lx + ro;
             const bool kin = k >= 0 && k < nz;
@@ -643,7 +654,7 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
         // ---- black cell of plane k-1 (tile only); write the pair
         {
             const int kb = k - 1;
-            const int ro = (gy + kb) & 1;  // red cell of the pair on plane kb
+            const int ro = pk ^ 1;  // red cell of the pair on plane kb
             const int bo = 1 - ro;         // black cell
             if (core && kb >= z0 && kb < z1 && (bo ? c1_in : c0_in)) {
                 const int lb = lx + bo;
@@ -688,9 +699,9 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
         zB = zC;
         issue(min(k + 1 + PD, z1 + 1), SU(J), SB(J), SE(J));
         mask_at(I3{}, k + 1);
-        step(SU(I1{}), SU(I2{}), SU(I3{}), SB(I1{}), SB(I2{}), SE(I2{}), SE(I3{}), k);
+        step(SU(I1{}), SU(I2{}), SU(I3{}), SB(I1{}), SB(I2{}), SE(I2{}), SE(I3{}), k, par(J, k));
     };
-    step(su0, su1, su2, sb0, sb1, se1, se2, z0 - 1);
+    step(su0, su1, su2, sb0, sb1, se1, se2, z0 - 1, pz ^ 1);
     for (int kk = z0; kk <= z1; kk += R) {
         iter(std::integral_constant<int, 0>{}, kk);
         if (kk + 1 > z1) break;
@@ -702,6 +713,7 @@ __device__ __forceinline__ void rbgs_cell_body(const SmoothArgs<T> &A, const int
         if constexpr (R > 4) { if (kk + 4 > z1) break; iter(std::integral_constant<int, 4>{}, kk + 4); }
         if constexpr (R > 5) { if (kk + 5 > z1) break; iter(std::integral_constant<int, 5>{}, kk + 5); }
         if constexpr (R > 6) { if (kk + 6 > z1) break; iter(std::integral_constant<int, 6>{}, kk + 6); }
+        if constexpr (R > 7) { if (kk + 7 > z1) break; iter(std::integral_constant<int, 7>{}, kk + 7); }
     }
 }
 
@@ -800,12 +812,15 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
         return r;
     };
     auto pick = [](const P2 &p, int c) -> C { return csel<C>(c, p.v[1], p.v[0]); };
+    // (the plane test is uniform: a branch, leaving one select per cell)
     auto masku = [&](P2 v, int k) -> P2 {
-        const bool kin = k >= 0 && k < nz;
-        const C zv = csel<C>(k < 0, hz_lo, hz_hi);
         P2 r;
-        r.v[0] = csel<C>(kin && c0_in, v.v[0], csel<C>(kin, hout0, zv));
-        r.v[1] = csel<C>(kin && c1_in, v.v[1], csel<C>(kin, hout1, zv));
+        if (k >= 0 && k < nz) {
+            r.v[0] = csel<C>(c0_in, v.v[0], hout0);
+            r.v[1] = csel<C>(c1_in, v.v[1], hout1);
+        } else {
+            r.v[0] = r.v[1] = k < 0 ? hz_lo : hz_hi;
+        }
         return r;
     };
 
@@ -817,22 +832,30 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
     // move of a loaded register would wait for that load at once).  u is
     // masked in place when its plane first becomes the upper neighbour
     // (cells outside the box carry their boundary term).
-    static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
+    static_assert(PD >= 1 && PD <= 5, "prefetch depth 1..5");
     constexpr int R = PD + 3;
-    P2 su0, su1, su2, su3, su4, su5, su6, sb0, sb1, sb2, sb3, sb4, sb5, sb6;
+    // parity of gy + k (which cell of the pair is red on plane k): with R
+    // even it is the same for step J of every unrolled group, a per-lane
+    // constant that needs no per-plane arithmetic
+    const int pz = (gy + z0) & 1;
+    auto par = [&](auto J, int k) -> int {
+        if constexpr (R % 2 == 0) return pz ^ (decltype(J)::value & 1);
+        else return (gy + k) & 1;
+    };
+    P2 su0, su1, su2, su3, su4, su5, su6, su7, sb0, sb1, sb2, sb3, sb4, sb5, sb6, sb7;
     auto SU = [&](auto I) -> P2 & {
         constexpr int v = decltype(I)::value % R;
         if constexpr (v == 0) return su0; else if constexpr (v == 1) return su1;
         else if constexpr (v == 2) return su2; else if constexpr (v == 3) return su3;
         else if constexpr (v == 4) return su4; else if constexpr (v == 5) return su5;
-        else return su6;
+        else if constexpr (v == 6) return su6; else return su7;
     };
     auto SB = [&](auto I) -> P2 & {
         constexpr int v = decltype(I)::value % R;
         if constexpr (v == 0) return sb0; else if constexpr (v == 1) return sb1;
         else if constexpr (v == 2) return sb2; else if constexpr (v == 3) return sb3;
         else if constexpr (v == 4) return sb4; else if constexpr (v == 5) return sb5;
-        else return sb6;
+        else if constexpr (v == 6) return sb6; else return sb7;
     };
     // every lane loads every plane (b outside the tile's ring and planes
     // past the chunk are not used): loads under a condition would make the
@@ -852,6 +875,7 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
     issue_at(std::integral_constant<int, 4>{});
     issue_at(std::integral_constant<int, 5>{});
     issue_at(std::integral_constant<int, 6>{});
+    issue_at(std::integral_constant<int, 7>{});
     auto mask_at = [&](auto I, int p) {
         if constexpr (ZIN) SU(I) = masku(zero, p);
         else SU(I) = masku(SU(I), p);
@@ -861,7 +885,7 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
     mask_at(std::integral_constant<int, 2>{}, z0);
     C rn_cur = C(0), rn_prev = C(0), rn_prev2 = C(0);  // new red values of planes k, k-1, k-2
 
-    auto step = [&](const P2 &um, const P2 &u0, const P2 &up, const P2 &bm, const P2 &b0, int k)
+    auto step = [&](const P2 &um, const P2 &u0, const P2 &up, const P2 &bm, const P2 &b0, int k, int pk)
                     __attribute__((always_inline)) {
         {
             Pair<C> w;
@@ -874,12 +898,14 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
         rn_prev2 = rn_prev;
         rn_prev = rn_cur;
         {
-            const int ro = (gy + k) & 1;  // red cell of the pair: x + ro
+            const int ro = pk;  // red cell of the pair: x + ro
             const int xr = x + ro;
             const int lr = lx + ro;
             const bool kin = k >= 0 && k < nz;
             const bool ring = xr >= -1 && xr <= TX && y >= -1 && y <= TY;
-            C rv = csel<C>(kin, csel<C>(ro, hout1, hout0), csel<C>(k < 0, hz_lo, hz_hi));
+            C rv;
+            if (kin) rv = csel<C>(ro, hout1, hout0);
+            else rv = k < 0 ? hz_lo : hz_hi;
             if (kin && ring && (ro ? c1_in : c0_in)) {
                 const C off = ((s_u[ry][lr - 1] + s_u[ry][lr + 1]) + (s_u[ry - 1][lr] + s_u[ry + 1][lr])) +
                               (pick(um, ro) + pick(up, ro));
@@ -891,7 +917,7 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
         // ---- black cell of plane k-1 (tile only); write the pair
         {
             const int kb = k - 1;
-            const int ro = (gy + kb) & 1;  // red cell of the pair on plane kb
+            const int ro = pk ^ 1;  // red cell of the pair on plane kb
             const int bo = 1 - ro;         // black cell
             if (core && kb >= z0 && kb < z1 && (bo ? c1_in : c0_in)) {
                 const int lb = lx + bo;
@@ -926,9 +952,9 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
         using I3 = std::integral_constant<int, q + 3>;
         issue(min(k + 1 + PD, z1 + 1), SU(J), SB(J));
         mask_at(I3{}, k + 1);
-        step(SU(I1{}), SU(I2{}), SU(I3{}), SB(I1{}), SB(I2{}), k);
+        step(SU(I1{}), SU(I2{}), SU(I3{}), SB(I1{}), SB(I2{}), k, par(J, k));
     };
-    step(su0, su1, su2, sb0, sb1, z0 - 1);
+    step(su0, su1, su2, sb0, sb1, z0 - 1, pz ^ 1);
     for (int kk = z0; kk <= z1; kk += R) {
         iter(std::integral_constant<int, 0>{}, kk);
         if (kk + 1 > z1) break;
@@ -940,6 +966,7 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
         if constexpr (R > 4) { if (kk + 4 > z1) break; iter(std::integral_constant<int, 4>{}, kk + 4); }
         if constexpr (R > 5) { if (kk + 5 > z1) break; iter(std::integral_constant<int, 5>{}, kk + 5); }
         if constexpr (R > 6) { if (kk + 6 > z1) break; iter(std::integral_constant<int, 6>{}, kk + 6); }
+        if constexpr (R > 7) { if (kk + 7 > z1) break; iter(std::integral_constant<int, 7>{}, kk + 7); }
     }
 }
 
@@ -1107,30 +1134,38 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
     // value moves between registers (such a move would wait for its load at
     // once).  u is masked and the faces scaled in place when their plane
     // first becomes the upper neighbour.
-    static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
+    static_assert(PD >= 1 && PD <= 5, "prefetch depth 1..5");
     constexpr int R = PD + 3;
-    P2 su0, su1, su2, su3, su4, su5, su6, sb0, sb1, sb2, sb3, sb4, sb5, sb6;
-    FS sf0, sf1, sf2, sf3, sf4, sf5, sf6;
+    // parity of gy + k (which cell of the pair is red on plane k): with R
+    // even it is the same for step J of every unrolled group, a per-lane
+    // constant that needs no per-plane arithmetic
+    const int pz = (gy + z0) & 1;
+    auto par = [&](auto J, int k) -> int {
+        if constexpr (R % 2 == 0) return pz ^ (decltype(J)::value & 1);
+        else return (gy + k) & 1;
+    };
+    P2 su0, su1, su2, su3, su4, su5, su6, su7, sb0, sb1, sb2, sb3, sb4, sb5, sb6, sb7;
+    FS sf0, sf1, sf2, sf3, sf4, sf5, sf6, sf7;
     auto SU = [&](auto I) -> P2 & {
         constexpr int v = decltype(I)::value % R;
         if constexpr (v == 0) return su0; else if constexpr (v == 1) return su1;
         else if constexpr (v == 2) return su2; else if constexpr (v == 3) return su3;
         else if constexpr (v == 4) return su4; else if constexpr (v == 5) return su5;
-        else return su6;
+        else if constexpr (v == 6) return su6; else return su7;
     };
     auto SB = [&](auto I) -> P2 & {
         constexpr int v = decltype(I)::value % R;
         if constexpr (v == 0) return sb0; else if constexpr (v == 1) return sb1;
         else if constexpr (v == 2) return sb2; else if constexpr (v == 3) return sb3;
         else if constexpr (v == 4) return sb4; else if constexpr (v == 5) return sb5;
-        else return sb6;
+        else if constexpr (v == 6) return sb6; else return sb7;
     };
     auto SF = [&](auto I) -> FS & {
         constexpr int v = decltype(I)::value % R;
         if constexpr (v == 0) return sf0; else if constexpr (v == 1) return sf1;
         else if constexpr (v == 2) return sf2; else if constexpr (v == 3) return sf3;
         else if constexpr (v == 4) return sf4; else if constexpr (v == 5) return sf5;
-        else return sf6;
+        else if constexpr (v == 6) return sf6; else return sf7;
     };
     // every lane loads every plane (b outside the tile's ring and planes
     // past the chunk are not used): loads under a condition would make the
@@ -1156,13 +1191,14 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
     issue_at(std::integral_constant<int, 4>{});
     issue_at(std::integral_constant<int, 5>{});
     issue_at(std::integral_constant<int, 6>{});
+    issue_at(std::integral_constant<int, 7>{});
     mask_at(std::integral_constant<int, 0>{}, z0 - 2);
     mask_at(std::integral_constant<int, 1>{}, z0 - 1);
     mask_at(std::integral_constant<int, 2>{}, z0);
     C rn_cur = C(0), rn_prev = C(0), rn_prev2 = C(0);  // new red values of planes k, k-1, k-2
 
     auto step = [&](const P2 &um, const P2 &u0, const P2 &up, const P2 &bm, const P2 &b0, const FS &fm,
-                    const FS &f0, const FS &fp, int k) __attribute__((always_inline)) {
+                    const FS &f0, const FS &fp, int k, int pk) __attribute__((always_inline)) {
         {
             Pair<C> w;
             w.v[0] = u0.v[0];
@@ -1174,7 +1210,7 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
         rn_prev2 = rn_prev;
         rn_prev = rn_cur;
         {
-            const int ro = (gy + k) & 1;  // red cell of the pair: x + ro
+            const int ro = pk;  // red cell of the pair: x + ro
             const int xr = x + ro;
             const int lr = lx + ro;
             const bool kin = k >= 0 && k < nz;
@@ -1199,7 +1235,7 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
         // ---- black cell of plane k-1 (tile only); write the pair
         {
             const int kb = k - 1;
-            const int ro = (gy + kb) & 1;  // red cell of the pair on plane kb
+            const int ro = pk ^ 1;  // red cell of the pair on plane kb
             const int bo = 1 - ro;         // black cell
             if (core && kb >= z0 && kb < z1 && (bo ? c1_in : c0_in)) {
                 const int lb = lx + bo;
@@ -1240,9 +1276,9 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
         using I3 = std::integral_constant<int, q + 3>;
         issue(min(k + 1 + PD, z1 + 1), SU(J), SB(J), SF(J));
         mask_at(I3{}, k + 1);
-        step(SU(I1{}), SU(I2{}), SU(I3{}), SB(I1{}), SB(I2{}), SF(I1{}), SF(I2{}), SF(I3{}), k);
+        step(SU(I1{}), SU(I2{}), SU(I3{}), SB(I1{}), SB(I2{}), SF(I1{}), SF(I2{}), SF(I3{}), k, par(J, k));
     };
-    step(su0, su1, su2, sb0, sb1, sf0, sf1, sf2, z0 - 1);
+    step(su0, su1, su2, sb0, sb1, sf0, sf1, sf2, z0 - 1, pz ^ 1);
     for (int kk = z0; kk <= z1; kk += R) {
         iter(std::integral_constant<int, 0>{}, kk);
         if (kk + 1 > z1) break;
@@ -1254,6 +1290,7 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
         if constexpr (R > 4) { if (kk + 4 > z1) break; iter(std::integral_constant<int, 4>{}, kk + 4); }
         if constexpr (R > 5) { if (kk + 5 > z1) break; iter(std::integral_constant<int, 5>{}, kk + 5); }
         if constexpr (R > 6) { if (kk + 6 > z1) break; iter(std::integral_constant<int, 6>{}, kk + 6); }
+        if constexpr (R > 7) { if (kk + 7 > z1) break; iter(std::integral_constant<int, 7>{}, kk + 7); }
     }
 }
 
@@ -1638,30 +1675,30 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
     // moves between registers (such a move would wait for its load at
     // once).  u and eps are masked in place when their plane first becomes
     // the upper neighbour.
-    static_assert(PD >= 1 && PD <= 4, "prefetch depth 1..4");
+    static_assert(PD >= 1 && PD <= 5, "prefetch depth 1..5");
     constexpr int R = PD + 3;
-    P2 su0, su1, su2, su3, su4, su5, su6, se0, se1, se2, se3, se4, se5, se6;
-    P2 sb0, sb1, sb2, sb3, sb4, sb5, sb6;
+    P2 su0, su1, su2, su3, su4, su5, su6, su7, se0, se1, se2, se3, se4, se5, se6, se7;
+    P2 sb0, sb1, sb2, sb3, sb4, sb5, sb6, sb7;
     auto SU = [&](auto I) -> P2 & {
         constexpr int v = decltype(I)::value % R;
         if constexpr (v == 0) return su0; else if constexpr (v == 1) return su1;
         else if constexpr (v == 2) return su2; else if constexpr (v == 3) return su3;
         else if constexpr (v == 4) return su4; else if constexpr (v == 5) return su5;
-        else return su6;
+        else if constexpr (v == 6) return su6; else return su7;
     };
     auto SE = [&](auto I) -> P2 & {
         constexpr int v = decltype(I)::value % R;
         if constexpr (v == 0) return se0; else if constexpr (v == 1) return se1;
         else if constexpr (v == 2) return se2; else if constexpr (v == 3) return se3;
         else if constexpr (v == 4) return se4; else if constexpr (v == 5) return se5;
-        else return se6;
+        else if constexpr (v == 6) return se6; else return se7;
     };
     auto SB = [&](auto I) -> P2 & {
         constexpr int v = decltype(I)::value % R;
         if constexpr (v == 0) return sb0; else if constexpr (v == 1) return sb1;
         else if constexpr (v == 2) return sb2; else if constexpr (v == 3) return sb3;
         else if constexpr (v == 4) return sb4; else if constexpr (v == 5) return sb5;
-        else return sb6;
+        else if constexpr (v == 6) return sb6; else return sb7;
     };
     // every lane loads every plane (planes past the chunk are not used):
     // loads under a condition would make the compiler wait for all
@@ -1686,6 +1723,7 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
     issue_at(std::integral_constant<int, 4>{});
     issue_at(std::integral_constant<int, 5>{});
     issue_at(std::integral_constant<int, 6>{});
+    issue_at(std::integral_constant<int, 7>{});
     mask_at(std::integral_constant<int, 0>{}, z0 - 1);
     mask_at(std::integral_constant<int, 1>{}, z0);
     mask_at(std::integral_constant<int, 2>{}, z0 + 1);
@@ -1802,6 +1840,7 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
         if constexpr (R > 4) { if (kk + 4 >= z1) break; iter(std::integral_constant<int, 4>{}, kk + 4); }
         if constexpr (R > 5) { if (kk + 5 >= z1) break; iter(std::integral_constant<int, 5>{}, kk + 5); }
         if constexpr (R > 6) { if (kk + 6 >= z1) break; iter(std::integral_constant<int, 6>{}, kk + 6); }
+        if constexpr (R > 7) { if (kk + 7 >= z1) break; iter(std::integral_constant<int, 7>{}, kk + 7); }
     }
     if (A.slot >= 0)
         reduce2_finish<NTP>(nrm, 0.0, A.ws, A.slot, blk);
