@@ -30,14 +30,17 @@ __device__ __forceinline__ void tail_terms(const TailDesc &D, int l, const doubl
     for (int d = 0; d < 6; ++d) G.g[d] = with_g ? D.g[d] : 0.0;
     const int sy = L.nx, sz = L.nx * L.ny;
     const int p = k * sz + j * sy + i;
+    // neighbours across the box boundary read the cell itself (a valid
+    // address; six_faces does not use the value), so all six LDS reads are
+    // issued together instead of one at a time under per-face branches
     auto un = [&](int d) -> double {
         switch (d) {
-            case 0: return v[p - 1];
-            case 1: return v[p + 1];
-            case 2: return v[p - sy];
-            case 3: return v[p + sy];
-            case 4: return v[p - sz];
-            default: return v[p + sz];
+            case 0: return v[i > 0 ? p - 1 : p];
+            case 1: return v[i < L.nx - 1 ? p + 1 : p];
+            case 2: return v[j > 0 ? p - sy : p];
+            case 3: return v[j < L.ny - 1 ? p + sy : p];
+            case 4: return v[k > 0 ? p - sz : p];
+            default: return v[k < L.nz - 1 ? p + sz : p];
         }
     };
     auto en = [&](int) { return 1.0; };
@@ -56,9 +59,9 @@ __device__ __forceinline__ void tail_terms(const TailDesc &D, int l, const doubl
                 default: return face_z(fz, G, i, j, k + 1);
             }
         };
-        six_faces<double, COEF_FACE>(G, i, j, k, 1.0, un, en, fb, off, dg);
+        six_faces<double, COEF_FACE, true>(G, i, j, k, 1.0, un, en, fb, off, dg);
     } else {
-        six_faces<double, COEF_CONST>(G, i, j, k, 1.0, un, en, [&](int) { return 1.0; }, off, dg);
+        six_faces<double, COEF_CONST, true>(G, i, j, k, 1.0, un, en, [&](int) { return 1.0; }, off, dg);
     }
 }
 
