@@ -122,27 +122,34 @@ __device__ __forceinline__ double tail_resid(const TailDesc &D, int l, const dou
     return b[idx] - (L.ah2 * u[idx] + dg * u[idx] - off) / L.h2;
 }
 
+// Restriction: the mean of the 8 children's residuals.  Thread item t is
+// child t & 7 of coarse cell t >> 3, so all threads work (8 children per
+// coarse cell over up to 512 coarse cells); the 8 residuals of a coarse
+// cell lie in 8 adjacent lanes and are summed by lane shuffles in a fixed
+// tree order.
 __device__ void restrict_to(const TailDesc &D, int l, double *lds, bool with_g) {
     const TailLevel &F = D.L[l], &Cc = D.L[l + 1];
     const double *u = lds + F.off_u, *b = lds + F.off_b;
     double *bc = lds + Cc.off_b, *uc = lds + Cc.off_u;
     const int nc = Cc.nx * Cc.ny * Cc.nz;  // <= 512
-    const int I = threadIdx.x;
-    if (I < nc) {
-        int ci, cj, ck;
-        decode(I, Cc.nx, Cc.ny, ci, cj, ck);
+    const int items = (nc * 8 + 63) / 64 * 64;  // whole waves: every lane of a group of 8 takes part
+    for (int t = threadIdx.x; t < items; t += kNT) {
+        const int I = t >> 3, c = t & 7;
         double s = 0.0;
-#pragma unroll
-        for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-            for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 2; ++dx) {
-                    const int idx = ((2 * ck + dz) * F.ny + (2 * cj + dy)) * F.nx + (2 * ci + dx);
-                    s += tail_resid(D, l, lds, u, b, idx, with_g);
-                }
-        bc[I] = 0.125 * s;
-        uc[I] = 0.0;
+        if (I < nc) {
+            int ci, cj, ck;
+            decode(I, Cc.nx, Cc.ny, ci, cj, ck);
+            const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+            const int idx = ((2 * ck + dz) * F.ny + (2 * cj + dy)) * F.nx + (2 * ci + dx);
+            s = tail_resid(D, l, lds, u, b, idx, with_g);
+        }
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        s += __shfl_xor(s, 4, 64);
+        if (I < nc && c == 0) {
+            bc[I] = 0.125 * s;
+            uc[I] = 0.0;
+        }
     }
     __syncthreads();
 }
