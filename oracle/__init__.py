@@ -18,10 +18,14 @@ from .oracle import (  # noqa: F401
     solve_cg,
     solve_vcycle,
     rbgs,
+    rbgs_level,
+    level_dims,
     prolong_add,
     solve_reference,
     dense_matrix,
     dense_solve,
     num_levels,
     threads,
+    tga_coefficients,
+    tga_step,
 )

@@ -81,6 +81,25 @@ static void level_free(orc_level *L) {
 
 static double harm(double p, double q) { return 2.0 * p * q / (p + q); }
 
+/* Coefficients of the finest level: a cell coefficient eps (NULL = 1) whose
+ * faces are formed below, or face coefficients given directly (bx != NULL,
+ * layout as in the header comment; boundary entries are the coefficients
+ * of the Dirichlet terms), as the diffusion solves of the paper's implicit
+ * (TGA) step use them: a face-centred D. */
+typedef struct {
+    const double *eps;
+    const double *bx, *by, *bz;
+} orc_coef;
+
+static orc_coef cell_coef(const double *eps) {
+    orc_coef c = {eps, NULL, NULL, NULL};
+    return c;
+}
+static orc_coef face_coef(const double *bx, const double *by, const double *bz) {
+    orc_coef c = {NULL, bx, by, bz};
+    return c;
+}
+
 /* Finest-level face coefficients from the cell coefficient. */
 static void level0_faces(orc_level *L, const double *eps) {
     for (int k = 0; k < L->nz; ++k)
@@ -301,14 +320,24 @@ typedef struct {
     double *u[32], *b[32], *r[32];
 } orc_hier;
 
-static void hier_build(orc_hier *H, int nx, int ny, int nz, double h, double a, const double *eps,
+static void level0_coef(orc_level *L, orc_coef C) {
+    if (C.bx) {
+        memcpy(L->bx, C.bx, (size_t)(L->nx + 1) * L->ny * L->nz * sizeof(double));
+        memcpy(L->by, C.by, (size_t)L->nx * (L->ny + 1) * L->nz * sizeof(double));
+        memcpy(L->bz, C.bz, (size_t)L->nx * L->ny * (L->nz + 1) * sizeof(double));
+    } else {
+        level0_faces(L, C.eps);
+    }
+}
+
+static void hier_build(orc_hier *H, int nx, int ny, int nz, double h, double a, orc_coef coef,
                        const int *bct, int coarsest_max) {
     memset(H, 0, sizeof(*H));
     orc_level *L = &H->lev[0];
     L->nx = nx; L->ny = ny; L->nz = nz; L->h = h; L->a = a;
     memcpy(L->bc_type, bct, 6 * sizeof(int));
     level_alloc(L);
-    level0_faces(L, eps);
+    level0_coef(L, coef);
     H->nlev = 1;
     for (;;) {
         orc_level *F = &H->lev[H->nlev - 1];
@@ -360,61 +389,61 @@ static void vcycle(orc_hier *H, int l, int nu1, int nu2) {
 
 /* ---------------------------------------------------------------- API */
 
-static void bc_rhs(const orc_level *L, const double *eps, const double *g, const double *f,
-                   double *b) {
-    /* b = f + h^-2 sum_Dirichlet 2 beta_P g (beta_P: boundary cell's own) */
+static void bc_rhs(const orc_level *L, const double *g, const double *f, double *b) {
+    /* b = f + h^-2 sum_Dirichlet 2 beta_b g, beta_b the coefficient of the
+     * boundary face (for a cell coefficient: the boundary cell's own) */
     const double ih2 = 1.0 / (L->h * L->h);
     for (int k = 0; k < L->nz; ++k)
         for (int j = 0; j < L->ny; ++j)
             for (int i = 0; i < L->nx; ++i) {
                 size_t p = idx(L, i, j, k);
-                double be = eps ? eps[p] : 1.0, s = 0.0;
-                if (i == 0 && L->bc_type[0] == ORC_DIRICHLET) s += 2.0 * be * g[0];
-                if (i == L->nx - 1 && L->bc_type[1] == ORC_DIRICHLET) s += 2.0 * be * g[1];
-                if (j == 0 && L->bc_type[2] == ORC_DIRICHLET) s += 2.0 * be * g[2];
-                if (j == L->ny - 1 && L->bc_type[3] == ORC_DIRICHLET) s += 2.0 * be * g[3];
-                if (k == 0 && L->bc_type[4] == ORC_DIRICHLET) s += 2.0 * be * g[4];
-                if (k == L->nz - 1 && L->bc_type[5] == ORC_DIRICHLET) s += 2.0 * be * g[5];
+                double s = 0.0;
+                if (i == 0 && L->bc_type[0] == ORC_DIRICHLET) s += 2.0 * *bxp(L, 0, j, k) * g[0];
+                if (i == L->nx - 1 && L->bc_type[1] == ORC_DIRICHLET) s += 2.0 * *bxp(L, L->nx, j, k) * g[1];
+                if (j == 0 && L->bc_type[2] == ORC_DIRICHLET) s += 2.0 * *byp(L, i, 0, k) * g[2];
+                if (j == L->ny - 1 && L->bc_type[3] == ORC_DIRICHLET) s += 2.0 * *byp(L, i, L->ny, k) * g[3];
+                if (k == 0 && L->bc_type[4] == ORC_DIRICHLET) s += 2.0 * *bzp(L, i, j, 0) * g[4];
+                if (k == L->nz - 1 && L->bc_type[5] == ORC_DIRICHLET) s += 2.0 * *bzp(L, i, j, L->nz) * g[5];
                 b[p] = f[p] + ih2 * s;
             }
 }
 
 static void make_level0(orc_level *L, int nx, int ny, int nz, double h, double a,
-                        const double *eps, const int *bct) {
+                        orc_coef coef, const int *bct) {
     memset(L, 0, sizeof(*L));
     L->nx = nx; L->ny = ny; L->nz = nz; L->h = h; L->a = a;
     memcpy(L->bc_type, bct, 6 * sizeof(int));
     level_alloc(L);
-    level0_faces(L, eps);
+    level0_coef(L, coef);
 }
 
-/* out = A u (homogeneous boundary values). */
-void orc_apply(int nx, int ny, int nz, double h, double a, const double *eps, const int *bct,
-               const double *u, double *out) {
+/* Each public routine comes in two forms: with a cell coefficient eps
+ * (NULL = 1; faces by harmonic means) and, suffixed _faces, with the face
+ * coefficients bx, by, bz given directly. */
+
+static void apply_c(int nx, int ny, int nz, double h, double a, orc_coef C, const int *bct, const double *u,
+                    double *out) {
     orc_level L;
-    make_level0(&L, nx, ny, nz, h, a, eps, bct);
+    make_level0(&L, nx, ny, nz, h, a, C, bct);
     level_apply(&L, u, out);
     level_free(&L);
 }
 
-/* b = f + boundary terms of the Dirichlet values g[6]. */
-void orc_rhs(int nx, int ny, int nz, double h, double a, const double *eps, const int *bct,
-             const double *g, const double *f, double *b) {
+static void rhs_c(int nx, int ny, int nz, double h, double a, orc_coef C, const int *bct, const double *g,
+                  const double *f, double *b) {
     orc_level L;
-    make_level0(&L, nx, ny, nz, h, a, eps, bct);
-    bc_rhs(&L, eps, g, f, b);
+    make_level0(&L, nx, ny, nz, h, a, C, bct);
+    bc_rhs(&L, g, f, b);
     level_free(&L);
 }
 
-/* Writes r = b - A u and returns ||r||_2; *bnorm = ||b||_2. */
-double orc_residual(int nx, int ny, int nz, double h, double a, const double *eps,
-                    const int *bct, const double *g, const double *f, const double *u,
-                    double *r, double *bnorm) {
+static double residual_c(int nx, int ny, int nz, double h, double a, orc_coef C, const int *bct,
+                         const double *g, const double *f, const double *u, double *r, double *bnorm) {
     orc_level L;
-    make_level0(&L, nx, ny, nz, h, a, eps, bct);
+    make_level0(&L, nx, ny, nz, h, a, C, bct);
     size_t n = ncell(&L);
     double *b = (double *)malloc(n * sizeof(double));
-    bc_rhs(&L, eps, g, f, b);
+    bc_rhs(&L, g, f, b);
     level_residual(&L, b, u, r);
     *bnorm = sqrt(dot(b, b, n));
     double rn = sqrt(dot(r, r, n));
@@ -423,34 +452,27 @@ double orc_residual(int nx, int ny, int nz, double h, double a, const double *ep
     return rn;
 }
 
-/* CG from the given u to ||b - A u|| <= rtol ||b||.  Returns iterations. */
-int orc_cg(int nx, int ny, int nz, double h, double a, const double *eps, const int *bct,
-           const double *g, const double *f, double *u, double rtol, int maxit, double *relres) {
+static int cg_c(int nx, int ny, int nz, double h, double a, orc_coef C, const int *bct, const double *g,
+                const double *f, double *u, double rtol, int maxit, double *relres) {
     orc_level L;
-    make_level0(&L, nx, ny, nz, h, a, eps, bct);
+    make_level0(&L, nx, ny, nz, h, a, C, bct);
     size_t n = ncell(&L);
     double *b = (double *)malloc(n * sizeof(double));
-    bc_rhs(&L, eps, g, f, b);
+    bc_rhs(&L, g, f, b);
     int it = level_cg(&L, b, u, rtol, maxit, relres);
     free(b);
     level_free(&L);
     return it;
 }
 
-/* Multigrid V(nu1,nu2) cycles with lexicographic Gauss-Seidel from the given
- * u until ||b - A u|| <= rtol ||b|| or max_cycles.  Coarsening halves every
- * axis while all are even and the largest exceeds coarsest_max; the coarsest
- * level is solved by CG.  Returns cycles; *relres the final relative
- * residual. */
-int orc_vcycle_solve(int nx, int ny, int nz, double h, double a, const double *eps,
-                     const int *bct, const double *g, const double *f, double *u, double rtol,
-                     int max_cycles, int nu1, int nu2, int coarsest_max, double *relres,
-                     double *history) {
+static int vcycle_solve_c(int nx, int ny, int nz, double h, double a, orc_coef C, const int *bct,
+                          const double *g, const double *f, double *u, double rtol, int max_cycles, int nu1,
+                          int nu2, int coarsest_max, double *relres, double *history) {
     orc_hier H;
-    hier_build(&H, nx, ny, nz, h, a, eps, bct, coarsest_max);
+    hier_build(&H, nx, ny, nz, h, a, C, bct, coarsest_max);
     orc_level *L = &H.lev[0];
     size_t n = ncell(L);
-    bc_rhs(L, eps, g, f, H.b[0]);
+    bc_rhs(L, g, f, H.b[0]);
     memcpy(H.u[0], u, n * sizeof(double));
     double bn = sqrt(dot(H.b[0], H.b[0], n));
     if (bn == 0.0) bn = 1.0;
@@ -470,31 +492,18 @@ int orc_vcycle_solve(int nx, int ny, int nz, double h, double a, const double *e
     return c;
 }
 
-/* Number of levels the V-cycle oracle builds (for reporting). */
-int orc_num_levels(int nx, int ny, int nz, int coarsest_max) {
-    int n = 1;
-    for (;;) {
-        int mx = nx > ny ? nx : ny;
-        if (nz > mx) mx = nz;
-        if (mx <= coarsest_max || nx % 2 || ny % 2 || nz % 2) break;
-        nx /= 2; ny /= 2; nz /= 2;
-        ++n;
-    }
-    return n;
-}
-
 /* Red-black Gauss-Seidel sweeps of the finest-level equation (the paper's
  * smoother, Sec. 2 item (ii)): first every red cell ((i+j+k) even), then
  * every black cell, each set to the value that zeroes its own residual.
  * A red cell's neighbours are all black (and vice versa), so the order
  * inside a colour does not matter. */
-void orc_rbgs(int nx, int ny, int nz, double h, double a, const double *eps, const int *bct,
-              const double *g, const double *f, double *u, int sweeps) {
+static void rbgs_c(int nx, int ny, int nz, double h, double a, orc_coef C, const int *bct, const double *g,
+                   const double *f, double *u, int sweeps) {
     orc_level L;
-    make_level0(&L, nx, ny, nz, h, a, eps, bct);
+    make_level0(&L, nx, ny, nz, h, a, C, bct);
     size_t n = ncell(&L);
     double *b = (double *)malloc(n * sizeof(double));
-    bc_rhs(&L, eps, g, f, b);
+    bc_rhs(&L, g, f, b);
     const double ih2 = 1.0 / (h * h);
     for (int s = 0; s < sweeps; ++s)
         for (int colour = 0; colour < 2; ++colour)
@@ -511,6 +520,91 @@ void orc_rbgs(int nx, int ny, int nz, double h, double a, const double *eps, con
     level_free(&L);
 }
 
+/* out = A u (homogeneous boundary values). */
+void orc_apply(int nx, int ny, int nz, double h, double a, const double *eps, const int *bct,
+               const double *u, double *out) {
+    apply_c(nx, ny, nz, h, a, cell_coef(eps), bct, u, out);
+}
+void orc_apply_faces(int nx, int ny, int nz, double h, double a, const double *bx, const double *by,
+                     const double *bz, const int *bct, const double *u, double *out) {
+    apply_c(nx, ny, nz, h, a, face_coef(bx, by, bz), bct, u, out);
+}
+
+/* b = f + boundary terms of the Dirichlet values g[6]. */
+void orc_rhs(int nx, int ny, int nz, double h, double a, const double *eps, const int *bct,
+             const double *g, const double *f, double *b) {
+    rhs_c(nx, ny, nz, h, a, cell_coef(eps), bct, g, f, b);
+}
+void orc_rhs_faces(int nx, int ny, int nz, double h, double a, const double *bx, const double *by,
+                   const double *bz, const int *bct, const double *g, const double *f, double *b) {
+    rhs_c(nx, ny, nz, h, a, face_coef(bx, by, bz), bct, g, f, b);
+}
+
+/* Writes r = b - A u and returns ||r||_2; *bnorm = ||b||_2. */
+double orc_residual(int nx, int ny, int nz, double h, double a, const double *eps,
+                    const int *bct, const double *g, const double *f, const double *u,
+                    double *r, double *bnorm) {
+    return residual_c(nx, ny, nz, h, a, cell_coef(eps), bct, g, f, u, r, bnorm);
+}
+double orc_residual_faces(int nx, int ny, int nz, double h, double a, const double *bx, const double *by,
+                          const double *bz, const int *bct, const double *g, const double *f, const double *u,
+                          double *r, double *bnorm) {
+    return residual_c(nx, ny, nz, h, a, face_coef(bx, by, bz), bct, g, f, u, r, bnorm);
+}
+
+/* CG from the given u to ||b - A u|| <= rtol ||b||.  Returns iterations. */
+int orc_cg(int nx, int ny, int nz, double h, double a, const double *eps, const int *bct,
+           const double *g, const double *f, double *u, double rtol, int maxit, double *relres) {
+    return cg_c(nx, ny, nz, h, a, cell_coef(eps), bct, g, f, u, rtol, maxit, relres);
+}
+int orc_cg_faces(int nx, int ny, int nz, double h, double a, const double *bx, const double *by,
+                 const double *bz, const int *bct, const double *g, const double *f, double *u, double rtol,
+                 int maxit, double *relres) {
+    return cg_c(nx, ny, nz, h, a, face_coef(bx, by, bz), bct, g, f, u, rtol, maxit, relres);
+}
+
+/* Multigrid V(nu1,nu2) cycles with lexicographic Gauss-Seidel from the given
+ * u until ||b - A u|| <= rtol ||b|| or max_cycles.  Coarsening halves every
+ * axis while all are even and the largest exceeds coarsest_max; the coarsest
+ * level is solved by CG.  Returns cycles; *relres the final relative
+ * residual. */
+int orc_vcycle_solve(int nx, int ny, int nz, double h, double a, const double *eps,
+                     const int *bct, const double *g, const double *f, double *u, double rtol,
+                     int max_cycles, int nu1, int nu2, int coarsest_max, double *relres,
+                     double *history) {
+    return vcycle_solve_c(nx, ny, nz, h, a, cell_coef(eps), bct, g, f, u, rtol, max_cycles, nu1, nu2,
+                          coarsest_max, relres, history);
+}
+int orc_vcycle_solve_faces(int nx, int ny, int nz, double h, double a, const double *bx, const double *by,
+                           const double *bz, const int *bct, const double *g, const double *f, double *u,
+                           double rtol, int max_cycles, int nu1, int nu2, int coarsest_max, double *relres,
+                           double *history) {
+    return vcycle_solve_c(nx, ny, nz, h, a, face_coef(bx, by, bz), bct, g, f, u, rtol, max_cycles, nu1, nu2,
+                          coarsest_max, relres, history);
+}
+
+void orc_rbgs(int nx, int ny, int nz, double h, double a, const double *eps, const int *bct,
+              const double *g, const double *f, double *u, int sweeps) {
+    rbgs_c(nx, ny, nz, h, a, cell_coef(eps), bct, g, f, u, sweeps);
+}
+void orc_rbgs_faces(int nx, int ny, int nz, double h, double a, const double *bx, const double *by,
+                    const double *bz, const int *bct, const double *g, const double *f, double *u, int sweeps) {
+    rbgs_c(nx, ny, nz, h, a, face_coef(bx, by, bz), bct, g, f, u, sweeps);
+}
+
+/* Number of levels the V-cycle oracle builds (for reporting). */
+int orc_num_levels(int nx, int ny, int nz, int coarsest_max) {
+    int n = 1;
+    for (;;) {
+        int mx = nx > ny ? nx : ny;
+        if (nz > mx) mx = nz;
+        if (mx <= coarsest_max || nx % 2 || ny % 2 || nz % 2) break;
+        nx /= 2; ny /= 2; nz /= 2;
+        ++n;
+    }
+    return n;
+}
+
 /* u (2nxc x 2nyc x 2nzc) += P e, the trilinear prolongation of the coarse
  * field e (nxc x nyc x nzc) with the coarse level's face types bct, as one
  * V-cycle applies it to the coarse correction. */
@@ -523,6 +617,38 @@ void orc_prolong_add(int nxc, int nyc, int nzc, const int *bct, const double *e,
     memcpy(C.bc_type, bct, 6 * sizeof(int));
     memcpy(F.bc_type, bct, 6 * sizeof(int));
     prolong_add(&C, e, &F, u);
+}
+
+/* Red-black Gauss-Seidel sweeps of level `level` of the hierarchy that
+ * coarsens while every axis is even and the largest exceeds 1 (level 0 =
+ * the given grid): the homogeneous correction equation A_l u = b of that
+ * level (Dirichlet faces with value 0), with the level's rediscretised
+ * coefficients (level 0: harmonic-mean faces of eps; coarser levels: the
+ * mean of the four fine faces each coarse face covers).  b and u have the
+ * level's dimensions.  Returns the number of levels (u untouched if
+ * `level` does not exist). */
+int orc_rbgs_level(int nx, int ny, int nz, double h, double a, const double *eps, const int *bct, int level,
+                   const double *b, double *u, int sweeps) {
+    orc_hier H;
+    hier_build(&H, nx, ny, nz, h, a, cell_coef(eps), bct, 1);
+    const int nlev = H.nlev;
+    if (level >= 0 && level < nlev) {
+        const orc_level *L = &H.lev[level];
+        const double ih2 = 1.0 / (L->h * L->h);
+        for (int s = 0; s < sweeps; ++s)
+            for (int colour = 0; colour < 2; ++colour)
+                for (int k = 0; k < L->nz; ++k)
+                    for (int j = 0; j < L->ny; ++j)
+                        for (int i = 0; i < L->nx; ++i) {
+                            if (((i + j + k) & 1) != colour) continue;
+                            double o, d;
+                            cell_terms(L, u, i, j, k, &o, &d);
+                            size_t p = idx(L, i, j, k);
+                            u[p] = (b[p] + ih2 * o) / (L->a + ih2 * d);
+                        }
+    }
+    hier_free(&H);
+    return nlev;
 }
 
 /* Threads the oracle's parallel loops use (1 without OpenMP). */

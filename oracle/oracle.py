@@ -67,6 +67,25 @@ def _load():
             lib.orc_threads.restype = c_int
             lib.orc_prolong_add.argtypes = [c_int, c_int, c_int, ip, dp, dp]
             lib.orc_prolong_add.restype = None
+            for name, base in (("orc_apply_faces", [c_int, c_int, c_int, c_dbl, c_dbl, dp, dp, dp, ip, dp, dp]),
+                               ("orc_rhs_faces", [c_int, c_int, c_int, c_dbl, c_dbl, dp, dp, dp, ip, dp, dp, dp]),
+                               ("orc_residual_faces", [c_int, c_int, c_int, c_dbl, c_dbl, dp, dp, dp, ip, dp, dp, dp,
+                                                       dp, dp]),
+                               ("orc_cg_faces", [c_int, c_int, c_int, c_dbl, c_dbl, dp, dp, dp, ip, dp, dp, dp,
+                                                 c_dbl, c_int, dp]),
+                               ("orc_vcycle_solve_faces", [c_int, c_int, c_int, c_dbl, c_dbl, dp, dp, dp, ip, dp,
+                                                           dp, dp, c_dbl, c_int, c_int, c_int, c_int, dp, dp]),
+                               ("orc_rbgs_faces", [c_int, c_int, c_int, c_dbl, c_dbl, dp, dp, dp, ip, dp, dp, dp,
+                                                   c_int])):
+                getattr(lib, name).argtypes = base
+            lib.orc_apply_faces.restype = None
+            lib.orc_rhs_faces.restype = None
+            lib.orc_residual_faces.restype = c_dbl
+            lib.orc_cg_faces.restype = c_int
+            lib.orc_vcycle_solve_faces.restype = c_int
+            lib.orc_rbgs_faces.restype = None
+            lib.orc_rbgs_level.argtypes = [c_int, c_int, c_int, c_dbl, c_dbl, dp, ip, c_int, dp, dp, c_int]
+            lib.orc_rbgs_level.restype = c_int
             lib.orc_num_levels.argtypes = [c_int, c_int, c_int, c_int]
             lib.orc_num_levels.restype = c_int
             _lib = lib
@@ -91,13 +110,33 @@ def _ip(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
 
 
+def _faces(p):
+    """The face arrays of a face-coefficient problem (contiguous FP64), or None."""
+    if getattr(p, "faces", None) is None:
+        return None
+    if p.eps is not None:
+        raise ValueError("a problem has either a cell coefficient or face coefficients")
+    bx, by, bz = (np.ascontiguousarray(a, dtype=np.float64) for a in p.faces)
+    assert bx.shape == (p.nz, p.ny, p.nx + 1) and by.shape == (p.nz, p.ny + 1, p.nx)
+    assert bz.shape == (p.nz + 1, p.ny, p.nx)
+    return bx, by, bz
+
+
+def _call(lib, name, p, eps, *rest):
+    """Call orc_<name>(dims, h, a, coefficient, ...) in the cell or face form."""
+    fc = _faces(p)
+    if fc is None:
+        return getattr(lib, "orc_" + name)(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), *rest)
+    return getattr(lib, "orc_" + name + "_faces")(p.nx, p.ny, p.nz, p.h, p.a, *(_dp(a) for a in fc), *rest)
+
+
 def apply(p, u: np.ndarray) -> np.ndarray:
     """A u with homogeneous boundary values."""
     lib = _load()
     bct, _, eps = _prob_args(p)
     u = np.ascontiguousarray(u, dtype=np.float64)
     out = np.empty_like(u)
-    lib.orc_apply(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(u), _dp(out))
+    _call(lib, "apply", p, eps, _ip(bct), _dp(u), _dp(out))
     return out
 
 
@@ -107,7 +146,7 @@ def rhs(p) -> np.ndarray:
     bct, g, eps = _prob_args(p)
     f = np.ascontiguousarray(p.f, dtype=np.float64)
     b = np.empty_like(f)
-    lib.orc_rhs(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(g), _dp(f), _dp(b))
+    _call(lib, "rhs", p, eps, _ip(bct), _dp(g), _dp(f), _dp(b))
     return b
 
 
@@ -119,8 +158,7 @@ def residual(p, u: np.ndarray) -> Tuple[np.ndarray, float, float]:
     u = np.ascontiguousarray(u, dtype=np.float64)
     r = np.empty_like(f)
     bn = ctypes.c_double(0.0)
-    rn = lib.orc_residual(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(g), _dp(f), _dp(u), _dp(r),
-                          ctypes.byref(bn))
+    rn = _call(lib, "residual", p, eps, _ip(bct), _dp(g), _dp(f), _dp(u), _dp(r), ctypes.byref(bn))
     return r, float(rn), float(bn.value)
 
 
@@ -131,8 +169,7 @@ def solve_cg(p, rtol: float = 1e-13, maxit: int = 200000, u0: Optional[np.ndarra
     f = np.ascontiguousarray(p.f, dtype=np.float64)
     u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, order="C")
     rel = ctypes.c_double(0.0)
-    it = lib.orc_cg(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(g), _dp(f), _dp(u), rtol, maxit,
-                    ctypes.byref(rel))
+    it = _call(lib, "cg", p, eps, _ip(bct), _dp(g), _dp(f), _dp(u), rtol, maxit, ctypes.byref(rel))
     return u, int(it), float(rel.value)
 
 
@@ -145,8 +182,8 @@ def solve_vcycle(p, rtol: float = 1e-13, max_cycles: int = 100, nu1: int = 2, nu
     u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, order="C")
     rel = ctypes.c_double(0.0)
     hist = np.zeros(max_cycles, dtype=np.float64)
-    c = lib.orc_vcycle_solve(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(g), _dp(f), _dp(u), rtol,
-                             max_cycles, nu1, nu2, coarsest_max, ctypes.byref(rel), _dp(hist))
+    c = _call(lib, "vcycle_solve", p, eps, _ip(bct), _dp(g), _dp(f), _dp(u), rtol, max_cycles, nu1, nu2,
+              coarsest_max, ctypes.byref(rel), _dp(hist))
     if history:
         return u, int(c), float(rel.value), hist[:c].copy()
     return u, int(c), float(rel.value)
@@ -158,7 +195,34 @@ def rbgs(p, u: np.ndarray, sweeps: int = 1) -> np.ndarray:
     bct, g, eps = _prob_args(p)
     f = np.ascontiguousarray(p.f, dtype=np.float64)
     out = np.array(u, dtype=np.float64, order="C")
-    lib.orc_rbgs(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), _dp(g), _dp(f), _dp(out), sweeps)
+    _call(lib, "rbgs", p, eps, _ip(bct), _dp(g), _dp(f), _dp(out), sweeps)
+    return out
+
+
+def level_dims(p, level: int) -> Tuple[int, int, int]:
+    """(nx, ny, nz) of level `level` of the hierarchy that halves every axis
+    while all are even and the largest exceeds 1."""
+    nx, ny, nz = p.nx, p.ny, p.nz
+    for _ in range(level):
+        if nx % 2 or ny % 2 or nz % 2 or max(nx, ny, nz) <= 1:
+            raise ValueError(f"level {level} does not exist for {p.nx}x{p.ny}x{p.nz}")
+        nx, ny, nz = nx // 2, ny // 2, nz // 2
+    return nx, ny, nz
+
+
+def rbgs_level(p, level: int, b: np.ndarray, u: np.ndarray, sweeps: int = 1) -> np.ndarray:
+    """Red-black sweeps of the homogeneous equation A_l u = b of hierarchy
+    level `level` (level 0: the finest operator without boundary values)."""
+    lib = _load()
+    if _faces(p) is not None:
+        raise ValueError("rbgs_level takes cell-coefficient problems")
+    bct, _, eps = _prob_args(p)
+    nx, ny, nz = level_dims(p, level)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    out = np.array(u, dtype=np.float64, order="C")
+    assert b.shape == (nz, ny, nx) and out.shape == (nz, ny, nx)
+    nlev = lib.orc_rbgs_level(p.nx, p.ny, p.nz, p.h, p.a, _dp(eps), _ip(bct), level, _dp(b), _dp(out), sweeps)
+    assert level < nlev
     return out
 
 
@@ -203,13 +267,16 @@ def dense_matrix(p) -> Tuple[np.ndarray, np.ndarray]:
 
     Written independently of mg_oracle.c: it walks the six neighbours of
     every cell and adds the face term of the second-order cell-centred
-    discretisation (harmonic-mean interior faces, linear Dirichlet ghosts,
-    zero Neumann flux).  Only for tiny grids (n <= ~2000)."""
+    discretisation (interior faces: the harmonic mean of the two cell
+    coefficients, or the given face coefficient; Dirichlet faces: the linear
+    ghost with the boundary cell's coefficient, or the given boundary face
+    coefficient; zero Neumann flux).  Only for tiny grids (n <= ~2000)."""
     nx, ny, nz = p.nx, p.ny, p.nz
     n = nx * ny * nz
     A = np.zeros((n, n))
     b = np.array(p.f, dtype=np.float64).reshape(-1).copy()
     ih2 = 1.0 / (p.h * p.h)
+    faces = getattr(p, "faces", None)
     beta = np.ones((nz, ny, nx)) if p.eps is None else np.asarray(p.eps, dtype=np.float64)
     types = p.bc_types()
     vals = p.bc_values()
@@ -218,25 +285,76 @@ def dense_matrix(p) -> Tuple[np.ndarray, np.ndarray]:
     def lin(i, j, k):
         return (k * ny + j) * nx + i
 
+    def face(i, j, k, face_id):
+        """Given face coefficient on side face_id of cell (i, j, k)."""
+        bx, by, bz = faces
+        if face_id < 2:
+            return bx[k, j, i + (face_id == 1)]
+        if face_id < 4:
+            return by[k, j + (face_id == 3), i]
+        return bz[k + (face_id == 5), j, i]
+
     for k in range(nz):
         for j in range(ny):
             for i in range(nx):
                 P = lin(i, j, k)
                 A[P, P] += p.a
                 bP = beta[k, j, i]
-                for di, dj, dk, face in steps:
+                for di, dj, dk, fid in steps:
                     ii, jj, kk = i + di, j + dj, k + dk
                     if 0 <= ii < nx and 0 <= jj < ny and 0 <= kk < nz:
-                        bN = beta[kk, jj, ii]
-                        bf = 2.0 * bP * bN / (bP + bN)
+                        if faces is not None:
+                            bf = face(i, j, k, fid)
+                        else:
+                            bN = beta[kk, jj, ii]
+                            bf = 2.0 * bP * bN / (bP + bN)
                         A[P, P] += ih2 * bf
                         A[P, lin(ii, jj, kk)] -= ih2 * bf
-                    elif types[face] == "D":
-                        A[P, P] += 2.0 * ih2 * bP
-                        b[P] += 2.0 * ih2 * bP * vals[face]
+                    elif types[fid] == "D":
+                        bb = face(i, j, k, fid) if faces is not None else bP
+                        A[P, P] += 2.0 * ih2 * bb
+                        b[P] += 2.0 * ih2 * bb * vals[fid]
     return A, b
 
 
 def dense_solve(p) -> np.ndarray:
     A, b = dense_matrix(p)
     return np.linalg.solve(A, b).reshape(p.nz, p.ny, p.nx)
+
+
+# ---------------------------------------------------------------- TGA
+
+
+def tga_coefficients(dt: float, eps: float = 1e-6) -> Tuple[float, float, float]:
+    """(mu1, mu2, mu3) of the implicit diffusion advance of paper Sec. 2.1,
+    step (vi), Eq. (tga): (I - mu1 L)(I - mu2 L) n_new = (I + mu3 L) n.
+
+    The paper takes the coefficients from its software's documentation; this
+    is the Twizell-Gumel-Arigu choice (Twizell, Gumel & Arigu 1996): with
+    q = 2 - sqrt(2) - eps and r = sqrt(q^2 - 4q + 2) (real for eps > 0),
+    mu1 = (q - r)/2 dt, mu2 = (q + r)/2 dt, mu3 = (1 - q) dt.  The amplification
+    (1 + mu3 z)/((1 - mu1 z)(1 - mu2 z)) of an eigenvalue z dt of L then equals
+    exp(z dt) to second order and tends to 0 as z dt -> -infinity."""
+    q = 2.0 - np.sqrt(2.0) - eps
+    r = np.sqrt(q * q - 4.0 * q + 2.0)
+    return 0.5 * (q - r) * dt, 0.5 * (q + r) * dt, (1.0 - q) * dt
+
+
+def tga_step(faces, h: float, dt: float, n: np.ndarray, eps: float = 1e-6, rtol: float = 1e-13) -> np.ndarray:
+    """One TGA diffusion advance of n (Eq. (tga)) with the face diffusion
+    coefficients `faces` = (bx, by, bz) and zero flux on every box face (the
+    diffusion solves of Sec. 2, item (ii)).  L u = div(D grad u) is the
+    operator A of a = 0 with a minus sign.  First (I - mu1 L) y = (I + mu3 L) n,
+    then (I - mu2 L) n_new = y; each Helmholtz equation is solved by the
+    oracle in the form (1/mu) u - div(D grad u) = rhs / mu."""
+    from synth.problems import Problem
+    nz, ny, nx = n.shape
+    mu1, mu2, mu3 = tga_coefficients(dt, eps)
+    neu = (("N", 0.0),) * 6
+
+    def prob(a, f):
+        return Problem(nx, ny, nz, h, a, np.ascontiguousarray(f), None, neu, "tga", faces=faces)
+
+    Ln = -apply(prob(0.0, n), n)
+    y = solve_reference(prob(1.0 / mu1, (n + mu3 * Ln) / mu1), rtol)
+    return solve_reference(prob(1.0 / mu2, y / mu2), rtol)

@@ -12,5 +12,8 @@ from .problems import (  # noqa: F401
     streamer_set,
     batch_dims,
     random_problem,
+    random_faces,
+    diffusion_faces,
     HELMHOLTZ_KDX,
+    TGA_DIFFUSION_NUMBER,
 )

@@ -56,6 +56,10 @@ class Problem:
     eps: Optional[np.ndarray] = None
     bc: Tuple[Tuple[str, float], ...] = field(default_factory=lambda: (("N", 0.0),) * 6)
     name: str = ""
+    # face coefficients (bx [nz][ny][nx+1], by [nz][ny+1][nx], bz [nz+1][ny][nx])
+    # given directly instead of a cell coefficient; boundary entries are the
+    # coefficients of Dirichlet faces
+    faces: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None
 
     @property
     def shape(self) -> Tuple[int, int, int]:
@@ -198,3 +202,61 @@ def random_problem(nx: int, ny: int, nz: int, seed: int, *, variable_eps: bool =
     if a is None:
         a = float(rng.uniform(0.0, 50.0))
     return Problem(nx, ny, nz, h, float(a), f, eps, tuple(bc), f"random_s{seed}_{nx}x{ny}x{nz}")
+
+
+def random_faces(nx: int, ny: int, nz: int, seed: int, lo: float = 0.25, hi: float = 8.0):
+    """Face coefficients (bx, by, bz), log-uniform in [lo, hi], independent per face."""
+    rng = np.random.default_rng(seed)
+    shapes = ((nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx))
+    return tuple(np.exp(rng.uniform(np.log(lo), np.log(hi), size=sh)) for sh in shapes)
+
+
+# Diffusion coefficient of the implicit (TGA) diffusion solves: D(E) on the
+# faces.  The transport data that give D as a function of the field are not
+# in the paper, so a stand-in with the same structure is used: D rises from
+# D_GAS in the background to D_GAS * D_HEAD_RATIO in the high-field region
+# around the filament head and along the channel, with mean-one lognormal
+# noise per face.
+D_GAS = 1.0
+D_HEAD_RATIO = 10.0
+D_NOISE_SIGMA = 0.1
+TGA_DIFFUSION_NUMBER = 4.0  # max(D) dt / h^2 of the benchmark step
+
+
+def diffusion_faces(nx: int, ny: int, nz: int, seed: int):
+    """Seeded face diffusion coefficients (bx, by, bz) for the TGA solves on
+    an nx*ny*nz grid (h = 1/nz): D = D_GAS * (1 + (D_HEAD_RATIO - 1) * w) *
+    noise, where w in [0, 1] is the filament shape of filament_source (the
+    same tip-height draw for the same seed) evaluated at each face centre,
+    with the head weighted 1 and the channel 0.5.  Draw order: tip height,
+    then one standard normal per face (x faces, y faces, z faces, C order)."""
+    h = 1.0 / nz
+    rng = np.random.default_rng(seed)
+    z_tip = rng.uniform(*FIL_TIP_RANGE)
+    x0, y0 = 0.5 * nx * h, 0.5 * ny * h
+    r_fil = FIL_RADIUS_CELLS * h
+    w = FIL_ROLLOFF_CELLS * h
+
+    def shape(x, y, z):
+        g2 = np.exp(-((x - x0) ** 2 + (y - y0) ** 2) / r_fil**2)
+        dist = np.where(z < z_tip, z_tip - z, np.where(z > FIL_Z_TOP, z - FIL_Z_TOP, 0.0))
+        body = 0.5 * np.exp(-(dist**2) / w**2)
+        head = np.exp(-((z - z_tip) ** 2) / w**2)
+        return g2 * np.minimum(1.0, body + head)
+
+    xc, yc, zc = cell_centres(nx, ny, nz, h)
+    xf = np.arange(nx + 1) * h
+    yf = np.arange(ny + 1) * h
+    zf = np.arange(nz + 1) * h
+    grids = ((zc[:, None, None], yc[None, :, None], xf[None, None, :]),
+             (zc[:, None, None], yf[None, :, None], xc[None, None, :]),
+             (zf[:, None, None], yc[None, :, None], xc[None, None, :]))
+    out = []
+    for zz, yy, xx in grids:
+        wgt = shape(xx, yy, zz)
+        noise = rng.standard_normal(wgt.shape)
+        noise *= D_NOISE_SIGMA
+        noise -= 0.5 * D_NOISE_SIGMA**2
+        np.exp(noise, out=noise)
+        out.append(np.ascontiguousarray(D_GAS * (1.0 + (D_HEAD_RATIO - 1.0) * wgt) * noise))
+    return tuple(out)

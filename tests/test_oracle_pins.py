@@ -315,3 +315,61 @@ def test_prolong_dirichlet_ghost_halves_boundary_cells():
     # a Neumann face reflects without a sign: the same cell keeps c
     u = oracle.prolong_add(np.full((3, 3, 3), c), np.zeros((6, 6, 6)), ["N", "D", "D", "D", "D", "D"])
     assert u[3, 3, 0] == pytest.approx(c) and u[3, 3, 5] == pytest.approx(c / 2)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("level", [1, 2])
+def test_coarse_level_layered_exact(axis, level):
+    """The coarse operators are rediscretisations: a coarse face takes the
+    mean of the four fine faces it covers.  For permittivity layered along
+    one axis with the interface on a coarse face, the coarse equation then
+    has the same exact solution as the fine one: the continuum
+    piecewise-linear potential sampled at the coarse cell centres (each
+    coarse face between two layers holds the harmonic mean of the two, the
+    flux-continuous value; a face taken from the wrong fine plane would hold
+    a layer's own value and shift the kink).  The Dirichlet value 1 of the
+    far face enters the homogeneous coarse equation as the right-hand side
+    2 beta g / h_l^2 of the cells beside it (beta = 1 there)."""
+    n, m, kI = 32, 4, 8
+    h = 1.0 / n
+    eps1d = np.where(np.arange(n) < kI, 4.0, 1.0)
+    types = [("N", 0.0)] * 6
+    types[2 * axis] = ("D", 0.0)
+    types[2 * axis + 1] = ("D", 1.0)
+    shape = [m, m, m]  # (nz, ny, nx)
+    shape[2 - axis] = n
+    bshape = [1, 1, 1]
+    bshape[2 - axis] = n
+    eps = np.broadcast_to(eps1d.reshape(bshape), shape).copy()
+    nz, ny, nx = shape
+    p = Problem(nx, ny, nz, h, 0.0, np.zeros(shape), eps, tuple(types))
+    hl = h * 2**level
+    nl = n >> level
+    coord = _centres(nl, hl)
+    zI = kI * h
+    q = 1.0 / (zI / 4 + 1 - zI)
+    lin = np.where(coord < zI, q * coord / 4, q * zI / 4 + q * (coord - zI))
+    lx, ly, lz = oracle.level_dims(p, level)
+    lshape = [1, 1, 1]
+    lshape[2 - axis] = nl
+    exact = np.broadcast_to(lin.reshape(lshape), (lz, ly, lx))
+    b = np.zeros((lz, ly, lx))
+    sl = [slice(None)] * 3
+    sl[2 - axis] = nl - 1
+    b[tuple(sl)] = 2.0 / hl**2
+    u = np.zeros_like(b)
+    for _ in range(40):
+        u = oracle.rbgs_level(p, level, b, u, 100)
+    assert np.abs(u - exact).max() < 1e-11
+
+
+def test_rbgs_level_zero_is_the_homogeneous_finest_sweep():
+    """Level 0 of rbgs_level is the finest operator with zero boundary
+    values: the same as rbgs on the problem with every Dirichlet value set to
+    0 and f = b."""
+    p = synth.random_problem(12, 10, 8, 31)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(p.shape)
+    u0 = rng.standard_normal(p.shape)
+    q = Problem(p.nx, p.ny, p.nz, p.h, p.a, b, p.eps, tuple((t, 0.0) for t, _ in p.bc))
+    assert np.array_equal(oracle.rbgs_level(p, 0, b, u0, 2), oracle.rbgs(q, u0, 2))
