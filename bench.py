@@ -16,9 +16,16 @@ Other workloads (--workload):
              BF16-storage-in-FP64 refinement (value: the --precision one)
   batched64  64 instances with axes drawn from {32,48,64,96,128}, four solves
              each (256 solves), FP32-in-FP64 refinement: one fused batched
-             call (captured graphs) against a loop of single solves
+             call (captured graphs) against a loop of plain FP64 single solves
   learned128 the three photon-group solves at 128^3 from the learned initial
              guess (U-net inference included) against the zero guess
+  tga256     implicit (TGA) diffusion advances at 256^3 with face diffusion
+             coefficients: two Helmholtz solves per step (value: solves/s)
+
+The default run also reports "forms": the mixed-precision, batched and
+learned-guess forms each against the plain FP64 V-cycle on its own
+workload, in a few short steps after the headline's timed pass (--no-forms
+skips them).
 
 Prints one JSON line: solves/s (value), DoF/s, ms per step, the roofline of
 the dominant kernel (the finest-level red-black smoother of the photon-group
@@ -51,7 +58,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="streamer256",
-                    choices=["streamer256", "mixed512", "batched64", "learned128", "copycal"])
+                    choices=["streamer256", "mixed512", "batched64", "learned128", "tga256", "copycal"])
+    ap.add_argument("--no-forms", action="store_true", help="skip the forms comparison of the default run")
+    ap.add_argument("--oracle-leg", default=None, choices=["vcycle", "cg"],
+                    help="(internal) time one CPU oracle leg in this process and print it")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16"])
@@ -66,20 +76,58 @@ def rtol_for(p):
     return 1e-11 if p.a == 0.0 else 1e-10
 
 
-def cpu_baseline(n: int, seed: int):
-    """The oracle as it stands: lexicographic Gauss-Seidel V(2,2) cycles on
-    the host, timed on the potential solve of the same set (one solve: a
-    bounded sample of the four-solve step)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_leg(kind: str, n: int, seed: int):
+    """One CPU oracle timing, run in a process of its own (see cpu_baseline):
+    the potential by the lexicographic Gauss-Seidel V(2,2) cycle, or the
+    strongly screened photon group by plain CG, to relative residual 1e-10."""
     import oracle
     import synth
-    p = synth.streamer_set(n, seed=seed)[0]
-    oracle.build(force=False)
+    oracle.build(force=True)  # -O3 -march=native for this host (MG_ORACLE_NATIVE=1)
+    probs = synth.streamer_set(n, seed=seed)
     t = time.perf_counter()
-    _, cycles, rel = oracle.solve_vcycle(p, rtol=1e-10, max_cycles=50)
+    if kind == "vcycle":
+        _, it, rel = oracle.solve_vcycle(probs[0], rtol=1e-10, max_cycles=50)
+        what = f"potential (seed {seed}) at {n}^3, lexicographic GS V(2,2): {it} cycles"
+    else:
+        _, it, rel = oracle.solve_cg(probs[3], rtol=1e-10)
+        what = f"photon group kappa h = 1.5 (seed {seed}) at {n}^3, plain CG: {it} iterations"
     dt = time.perf_counter() - t
-    return {"value": round(1.0 / dt, 4), "unit": "solves/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"1 of the 4 solves (potential, seed {seed}) at {n}^3, lexicographic GS V(2,2) "
-                      f"to rel. residual 1e-10: {cycles} cycles, {dt:.1f} s"}
+    return {"value": round(1.0 / dt, 4), "unit": "solves/s", "cores": oracle.threads(), "seconds": round(dt, 2),
+            "rel_res": rel, "sample": what}
+
+
+def cpu_baseline(n: int, seed: int):
+    """The oracle as it stands, timed on the host's cores on a bounded sample
+    of the four-solve step (one solve per leg), built -O3 -march=native on
+    this host: the lexicographic V-cycle on one core (its Gauss-Seidel sweep
+    is sequential) and plain CG with OpenMP on every core the process may
+    use.  Each leg runs in a child process with its own OMP_NUM_THREADS."""
+    import subprocess
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    legs = {}
+    for kind, threads in (("vcycle", 1), ("cg", ncpu)):
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads), MG_ORACLE_NATIVE="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-leg", kind, "--n", str(n),
+                            "--seed", str(seed)], env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode != 0:
+            raise RuntimeError(f"oracle leg {kind} failed: {r.stderr[-2000:]}")
+        legs[kind] = json.loads(r.stdout.strip().splitlines()[-1])
+    v = legs["vcycle"]
+    return {"value": v["value"], "unit": "solves/s", "cores": v["cores"], "kind": "oracle",
+            "sample": f"1 of the 4 solves: {v['sample']}, to rel. residual 1e-10, {v['seconds']} s on "
+                      f"{v['cores']} core; built -O3 -march=native",
+            "cg_all_cores": legs["cg"], "host_cpu": cpu_model(), "host_cpus_usable": ncpu}
 
 
 # HBM traffic of the smoother measured by rocprofv3 counters (FETCH_SIZE,
@@ -190,7 +238,7 @@ def timed(step, steps, warmup, ctx=None):
     return dt, res, roof
 
 
-def run_set(n, seed, precision, steps, warmup, autotune, concurrent=True):
+def run_set(n, seed, precision, steps, warmup, autotune, concurrent=True, seq_pass=True):
     """Four solves of one field update at n^3.  The four equations are
     independent, so by default each has its own context on its own HIP
     stream and the four solves of a step run from four host threads at once:
@@ -228,7 +276,10 @@ def run_set(n, seed, precision, steps, warmup, autotune, concurrent=True):
     # the finest-level smoother of the first photon group (beta = 1: the
     # kernel with the largest share of the step) and of the potential
     # (cell permittivity), timed live in the sequential pass
-    dt_s, cycles_s, roofs = timed(step_seq, steps, warmup, [solvers[1].ctx, solvers[0].ctx])
+    if seq_pass or not concurrent:
+        dt_s, cycles_s, roofs = timed(step_seq, steps, warmup, [solvers[1].ctx, solvers[0].ctx])
+    else:
+        dt_s, roofs = dt, [None, None]
     if not concurrent:
         dt, cycles = dt_s, cycles_s
     for s in solvers:
@@ -357,16 +408,149 @@ def learned_line(args):
     return out
 
 
+def batched_run(prec: str, steps: int, warmup: int, loop_steps: int):
+    """64 uneven instances x 4 solves: one batched call (captured graphs) per
+    step in the given refinement precision, against a loop of plain FP64
+    single solves of the same 256 problems (the form it replaces) and a loop
+    of single solves in the same precision.  Returns (batched solves/s,
+    ms/step, cells, cfg)."""
+    import torch
+    import synth
+    from paper_1809_08857_amd import mg
+    dims = synth.batch_dims()
+    probs = []
+    for j, (nx, ny, nz) in enumerate(dims):
+        probs += synth.streamer_set(int(nx), int(ny), int(nz), seed=1000 + j)
+    cells = sum(p.cells for p in probs)
+    fs = [torch.from_numpy(p.f).cuda() for p in probs]
+    xs = [torch.zeros(p.shape, dtype=torch.float64, device="cuda") for p in probs]
+
+    def loop_rate(solvers):
+        def lstep():
+            for s, f, x in zip(solvers, fs, xs):
+                rc, st = s.solve(f, x)
+                if rc != mg.MG_OK:
+                    raise RuntimeError("solve did not converge")
+            return 0
+        dt, _, _ = timed(lstep, loop_steps, 1)
+        return len(probs) * loop_steps / dt
+
+    fp64 = make_solvers(probs, "fp64")
+    loop64 = loop_rate(fp64)
+    for s in fp64:
+        s.close()
+    solvers = make_solvers(probs, prec)
+    ctxs = [s.ctx for s in solvers]
+
+    def bstep():
+        rc, st = mg.mg_solve_batched(ctxs, fs, xs)
+        if rc != mg.MG_OK:
+            raise RuntimeError("batched solve did not converge")
+        return max(s.cycles for s in st)
+
+    dt_b, cyc, _ = timed(bstep, steps, warmup)
+    loop_same = loop_rate(solvers)
+    for s in solvers:
+        s.close()
+    value = len(probs) * steps / dt_b
+    cfg = {"workload": "64 instances (axes from {32,48,64,96,128}, seed 4) x (potential + 3 photon groups), "
+                       "one batched call with captured graphs", "instances": 64, "solves_per_step": len(probs),
+           "cells_total": int(cells), "precision": prec, "max_steps": int(max(cyc)),
+           "loop_of_plain_fp64_solves_solves_per_s": round(loop64, 3),
+           "speedup_vs_plain_fp64_loop": round(value / loop64, 3),
+           f"loop_of_{prec}_single_solves_solves_per_s": round(loop_same, 3)}
+    return value, dt_b / steps * 1e3, cells, cfg
+
+
+def tga_line(args):
+    """Implicit diffusion (TGA) advances at n^3: face diffusion coefficients
+    D from the seeded stand-in for D(E), the filament density as the
+    initial field, dt at diffusion number max(D) dt / h^2 = 4, zero flux on
+    every face.  One step = one mg_tga_step (the right-hand side
+    (I + mu3 L) n, then two Helmholtz solves to rel. residual 1e-10, each
+    started from the previous field); the output of a step feeds the next."""
+    import torch
+    import synth
+    from synth.problems import filament_source
+    from paper_1809_08857_amd import mg
+    n = args.n or 256
+    h = 1.0 / n
+    faces = synth.diffusion_faces(n, n, n, args.seed)
+    dt = synth.TGA_DIFFUSION_NUMBER * h * h / max(float(a.max()) for a in faces)
+    fdev = [torch.from_numpy(a).cuda() for a in faces]
+    s = mg.Solver(n, n, n, h, faces=fdev, a=1.0, rtol=1e-10)
+    bufs = [torch.from_numpy(filament_source(n, n, n, args.seed)).cuda(), torch.empty((n, n, n),
+                                                                                      dtype=torch.float64,
+                                                                                      device="cuda")]
+    it = {"k": 0, "cyc": []}
+
+    def step():
+        src, dst = bufs[it["k"] & 1], bufs[(it["k"] + 1) & 1]
+        rc, st = s.tga_step(dt, src, dst, mg.MG_GUESS)
+        if rc != mg.MG_OK:
+            raise RuntimeError(f"TGA step failed: {[q.as_dict() for q in st]}")
+        it["k"] += 1
+        it["cyc"].append([q.cycles for q in st])
+        return 0
+
+    dt_run, _, roof = timed(step, args.steps, args.warmup, s.ctx)
+    cyc = it["cyc"][args.warmup:]
+    s.close()
+    value = 2 * args.steps / dt_run
+    cfg = {"workload": f"TGA implicit diffusion advance at {n}^3: face D(E) stand-in (seed {args.seed}), "
+                       f"zero flux everywhere, diffusion number 4, two Helmholtz solves per step to rel. "
+                       f"residual 1e-10 started from the previous field", "grid": [n, n, n],
+           "solves_per_step": 2, "precision": "fp64", "dt": dt,
+           "cycles_per_solve": [round(sum(c[q] for c in cyc) / len(cyc), 2) for q in range(2)]}
+    return base_line(args, value, dt_run / args.steps * 1e3, cfg, "f64", roof, value * n**3)
+
+
+def forms(args):
+    """The three forms against the plain FP64 V-cycle, each on its own
+    workload, in a few short steps: mixed precision at 512^3 (four solves per
+    step on four streams; FP64, FP32-in-FP64, BF16-in-FP64), the batched form
+    on the 64-instance batch against a loop of plain FP64 single solves, and
+    the learned initial guess at 128^3 against the zero start."""
+    import torch
+    out = {}
+    t0 = time.perf_counter()
+    res = {}
+    for pr in ("fp64", "fp32", "bf16"):
+        v, ms, cyc, _, _, _ = run_set(512, 0, pr, 3, 1, False, True, seq_pass=False)
+        res[pr] = {"solves_per_s": round(v, 3), "ms_per_step": round(ms, 3), "cycles_per_solve": cyc}
+        torch.cuda.empty_cache()
+    out["mixed512"] = {"by_precision": res,
+                       "fp32_vs_fp64": round(res["fp32"]["solves_per_s"] / res["fp64"]["solves_per_s"], 3),
+                       "bf16_vs_fp64": round(res["bf16"]["solves_per_s"] / res["fp64"]["solves_per_s"], 3),
+                       "steps": 3}
+    v, ms, _, cfg = batched_run("fp32", 4, 1, 1)
+    out["batched64"] = {"solves_per_s": round(v, 3), "ms_per_step": round(ms, 3),
+                        "plain_fp64_loop_solves_per_s": cfg["loop_of_plain_fp64_solves_solves_per_s"],
+                        "speedup_vs_plain_fp64_loop": cfg["speedup_vs_plain_fp64_loop"], "steps": 4}
+    torch.cuda.empty_cache()
+    la = argparse.Namespace(**dict(vars(args), n=128, steps=8, warmup=2, precision="fp64"))
+    ln = learned_line(la)
+    c = ln["config"]
+    out["learned128"] = {"solves_per_s": ln["value"], "plain_solves_per_s": c["plain_solves_per_s"],
+                         "speedup_vs_plain": c["speedup_vs_plain"], "inference_ms": c["inference_ms"],
+                         "cycles_per_solve_plain": c["cycles_per_solve_plain"],
+                         "cycles_per_solve_learned": c["cycles_per_solve_learned"], "fallbacks": c["fallbacks"],
+                         "steps": 8}
+    out["seconds"] = round(time.perf_counter() - t0, 1)
+    return out
+
+
 def main():
     args = parse()
+    if args.oracle_leg:  # a child process of cpu_baseline: host only
+        print(json.dumps(oracle_leg(args.oracle_leg, args.n or 256, args.seed)), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; runs on several GPUs are not implemented (the sharded design is described, not built)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    import numpy as np
     import torch
-    import synth
-    from paper_1809_08857_amd import mg
+    from paper_1809_08857_amd import mg  # noqa: F401  (fails loudly without the built library)
 
     torch.cuda.set_device(0)
     if args.workload == "streamer256":
@@ -380,6 +564,9 @@ def main():
                "solves_in_flight": 1 if args.sequential else 4,
                "sequential_pass": {"solves_per_s": round(seq_v, 3), "ms_per_step": round(seq_ms, 3)}}
         out = base_line(args, value, ms, cfg, "f64" if prec == "fp64" else f"f64+{prec}", roof, value * n**3)
+        if not args.no_forms and args.n is None and prec == "fp64":
+            torch.cuda.empty_cache()
+            out["forms"] = forms(args)
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(n, args.seed)
     elif args.workload == "mixed512":
@@ -400,41 +587,11 @@ def main():
                         value * n**3)
     elif args.workload == "batched64":
         prec = args.precision or "fp32"
-        dims = synth.batch_dims()
-        probs = []
-        for j, (nx, ny, nz) in enumerate(dims):
-            probs += synth.streamer_set(int(nx), int(ny), int(nz), seed=1000 + j)
-        cells = sum(p.cells for p in probs)
-        solvers = make_solvers(probs, prec)
-        fs = [torch.from_numpy(p.f).cuda() for p in probs]
-        xs = [torch.zeros(p.shape, dtype=torch.float64, device="cuda") for p in probs]
-        ctxs = [s.ctx for s in solvers]
-
-        def bstep():
-            rc, st = mg.mg_solve_batched(ctxs, fs, xs)
-            if rc != mg.MG_OK:
-                raise RuntimeError("batched solve did not converge")
-            return max(s.cycles for s in st)
-
-        def lstep():
-            for s, f, x in zip(solvers, fs, xs):
-                rc, st = s.solve(f, x)
-                if rc != mg.MG_OK:
-                    raise RuntimeError("solve did not converge")
-            return 0
-
-        dt_l, _, _ = timed(lstep, max(1, args.steps // 2), 1)
-        dt_b, cyc, _ = timed(bstep, args.steps, args.warmup)
-        value = len(probs) * args.steps / dt_b
-        loop_value = len(probs) * max(1, args.steps // 2) / dt_l
-        cfg = {"workload": "64 instances (axes from {32,48,64,96,128}, seed 4) x (potential + 3 photon groups), "
-                           "one batched call with captured graphs", "instances": 64, "solves_per_step": len(probs),
-               "cells_total": int(cells), "precision": prec, "max_steps": int(max(cyc)),
-               "loop_of_single_solves_solves_per_s": round(loop_value, 3)}
-        out = base_line(args, value, dt_b / args.steps * 1e3, cfg, f"f64+{prec}", None, value / 4 * cells / 64 * 4)
-        out["dof_per_s"] = round(cells * args.steps / dt_b, 1)
-        for s in solvers:
-            s.close()
+        value, ms, cells, cfg = batched_run(prec, args.steps, args.warmup, max(1, args.steps // 2))
+        # every step solves each of the 256 problems once: DoF per step = all cells
+        out = base_line(args, value, ms, cfg, f"f64+{prec}", None, value / cfg["solves_per_step"] * cells)
+    elif args.workload == "tga256":
+        out = tga_line(args)
     elif args.workload == "copycal":
         out = copy_calibration(args)
     else:

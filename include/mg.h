@@ -42,7 +42,13 @@
  *   MG_EINVAL    invalid argument; x is left untouched
  *   MG_ENOMEM    device allocation failed
  *   MG_EDEVICE   a HIP runtime call failed
- *   MG_EDIVERGED non-finite or growing residual; x is unspecified
+ *   MG_EDIVERGED the residual diverged: it is not finite, or it exceeds
+ *                1e6 times the starting one, or it grew in each of 4
+ *                consecutive cycles to more than 10 times the smallest
+ *                residual of the solve; x is unspecified and the stats hold
+ *                the cycle and residual at which this was seen.  (A solve
+ *                that stalls at its rounding floor moves by small factors
+ *                and ends with MG_NOT_CONVERGED instead.)
  *
  * Threading: one context must not be used from two threads at once;
  * distinct contexts are independent.  All device work of a context is
@@ -126,7 +132,10 @@ typedef struct {
  * V(2,2), bottom_max 16, max_cycles 50, rtol 1e-10. */
 void mg_desc_default(mg_desc *d, int nx, int ny, int nz, double h);
 
-/* Create a context: validates d, builds the level hierarchy (every axis is
+/* Create a context for one cell-centred elliptic equation on an
+ * nx x ny x nz grid (paper Sec. 2, spatial-discretisation items (ii)-(iii):
+ * the Poisson and radiative-transfer equations on Cartesian cells, solved by
+ * geometric multigrid): validates d, builds the level hierarchy (every axis is
  * halved while all axes are even and the largest exceeds 1) and allocates
  * the device buffers.  The grid must reach a level whose largest dimension
  * is <= d->bottom_max with at most 4096 cells, otherwise MG_EINVAL.
@@ -134,37 +143,94 @@ void mg_desc_default(mg_desc *d, int nx, int ny, int nz, double h);
  * the context; it is NULL on error. */
 int mg_create(const mg_desc *d, void *hip_stream, mg_ctx **out);
 
-/* Set the operator: eps_dev = device array of nx*ny*nz cell coefficients
- * (beta; NULL means beta = 1), copied into library storage; a >= 0 the
- * screening coefficient kappa^2; bc the six face conditions.  Errors
- * (MG_EINVAL): eps outside (0, 1e100] (checked on the device), a < 0
- * or not finite, an unknown face type, or a singular operator (a == 0 and
- * no Dirichlet face). */
+/* Set the operator a u - div(beta grad u) of Sec. 2's model equations: the
+ * potential (Eq. (streamer_equations), second line, with the permittivity as
+ * beta, a = 0) or a photon group of the three-term radiative-transfer model
+ * (Eq. (rte) times 3 kappa_j: beta = 1, a = kappa^2); bc gives the electrode (Dirichlet) and
+ * zero-flux (Neumann) faces of the set-ups of Secs. 3-4.
+ * eps_dev = device array of nx*ny*nz cell coefficients (beta; NULL means
+ * beta = 1), copied into library storage; a >= 0 the screening coefficient
+ * kappa^2; bc the six face conditions.  Errors (MG_EINVAL): eps outside
+ * (0, 1e100] (checked on the device), a < 0 or not finite, an unknown face
+ * type, or a singular operator (a == 0 and no Dirichlet face).
+ * MG_FP32_IR and MG_BF16_IR contexts run their inner cycle on the
+ * coefficients times a power of two that centres them on 1; they reject
+ * (MG_EINVAL) coefficients whose largest and smallest value differ by more
+ * than 2^70 (about 1.2e21), and a above 2^100 times that scale: use MG_FP64
+ * for such operators. */
 int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc);
 
-/* Solve A x = b with b = f + boundary terms.  f_dev and x_dev are device
- * arrays of nx*ny*nz FP64 values; f_dev is read only; x_dev receives the
+/* Set an operator whose face coefficients are given directly: the
+ * face-centred diffusion coefficient D of the implicit diffusion solves
+ * (Sec. 2, item (ii): cell-centred discretisation of div(D grad n) with the
+ * coefficient on the faces).  bx_dev, by_dev, bz_dev are device arrays of
+ * (nx+1)*ny*nz, nx*(ny+1)*nz and nx*ny*(nz+1) FP64 values, laid out as
+ *     bx[(k*ny + j)*(nx+1) + i]   the face between cells i-1 and i, i = 0..nx
+ *     by[(k*(ny+1) + j)*nx + i]   j = 0..ny
+ *     bz[(k*ny + j)*nx + i]       k = 0..nz (nz+1 planes)
+ * and copied into library storage; the entries on the box faces are the
+ * coefficients of Dirichlet terms (unused on Neumann faces).  a, bc and the
+ * errors as mg_set_coeffs; every entry must lie in (0, 1e100] (checked on
+ * the device).  MG_FP64 contexts only (MG_EINVAL otherwise).  Coarser levels
+ * average the four fine faces each coarse face covers. */
+int mg_set_face_coeffs(mg_ctx *c, const double *bx_dev, const double *by_dev, const double *bz_dev, double a,
+                       const mg_bcs *bc);
+
+/* Solve A x = b with b = f + boundary terms by V-cycles (Sec. 2, item (ii):
+ * geometric multigrid with red-black Gauss-Seidel smoothing and a Krylov
+ * bottom solver) until ||b - A x||_2 <= rtol ||b||_2.  f_dev and x_dev are
+ * device arrays of nx*ny*nz FP64 values; f_dev is read only; x_dev receives the
  * solution (without MG_GUESS its input content is ignored).  st may be
  * NULL.  A non-finite f is MG_EINVAL; a non-finite guess is rejected like
  * any other guess worse than zero (MG_EINVAL where the raw residual is
  * compared). */
 int mg_solve(mg_ctx *c, const double *f_dev, double *x_dev, unsigned flags, mg_stats *st);
 
-/* Solve `count` independent problems (contexts may differ in size and
- * coefficients; all must share one stream and one precision).  The
+/* Solve `count` independent problems of the kind mg_solve solves (for
+ * instance the four elliptic solves of one field update of Sec. 2.1, or
+ * many grid patches); contexts may differ in size and coefficients; all must
+ * share one stream and one precision.  The
  * V-cycle levels of all problems advance together: each level phase of
  * the whole batch is one kernel launch over a work list of tiles, the
  * cycle is captured once into a hipGraph and replayed, and converged
  * problems are skipped on the device.  f_dev[i], x_dev[i] as in mg_solve
  * for context c[i]; st (optional) receives count entries.  With MG_GUESS
- * each guess is screened on its raw residual (||b - A x|| <= ||b||). */
+ * each guess is screened on its raw residual (||b - A x|| <= ||b||).
+ * Returns MG_EDIVERGED if any problem diverged (that problem is stopped, the
+ * others run on; st[i] tells which), else MG_NOT_CONVERGED if any problem
+ * did not converge, else MG_OK. */
 int mg_solve_batched(int count, mg_ctx *const *c, const double *const *f_dev,
                      double *const *x_dev, unsigned flags, mg_stats *st);
 
-/* Free a context and all its device memory (NULL is accepted). */
+/* One implicit diffusion advance of the paper's TGA scheme (Sec. 2.1,
+ * step (vi), Eq. (tga)):
+ *     (I - mu1 L)(I - mu2 L) out = (I + mu3 L) n,   L u = div(beta grad u),
+ * with beta the context's coefficients (face D from mg_set_face_coeffs, or a
+ * cell coefficient, or 1) and zero flux on every face (the context's bc must
+ * be all Neumann, else MG_EINVAL).  The coefficients are those of Twizell,
+ * Gumel and Arigu: q = 2 - sqrt(2) - 1e-6, r = sqrt(q^2 - 4q + 2),
+ * mu1 = (q - r)/2 dt, mu2 = (q + r)/2 dt, mu3 = (1 - q) dt (second order, and
+ * the amplification vanishes for stiff modes).  Two Helmholtz solves, each
+ * as mg_solve with the context's precision, rtol and max_cycles: first
+ * (1/mu1) y - div(beta grad y) = (I + mu3 L) n / mu1, then
+ * (1/mu2) out - div(beta grad out) = y / mu2.  The context's a is used as
+ * 1/mu1 and 1/mu2 during the call and restored afterwards.  n_dev, out_dev:
+ * distinct device arrays of nx*ny*nz FP64 values (n read only).  flags:
+ * MG_GUESS starts the first solve from n and the second from y (each
+ * screened as in mg_solve), else both start from zero.  st (optional)
+ * receives two entries, one per solve.  Returns the worse of the two
+ * solves' codes. */
+int mg_tga_step(mg_ctx *c, double dt, const double *n_dev, double *out_dev, unsigned flags, mg_stats *st);
+
+/* Free a context and all its device memory (NULL is accepted).  Returns
+ * MG_OK. */
 int mg_destroy(mg_ctx *c);
 
-/* Text of the last hard error raised on the calling thread ("" if none). */
+/* Text of the last hard error raised on the calling thread ("" if none).
+ * The message is kept per thread, not per context, so that it also reports
+ * errors of calls that have no context yet (mg_create) or several
+ * (mg_solve_batched); the pointer stays valid until the thread's next
+ * failing call. */
 const char *mg_last_error(void);
 
 /* ------------------------------------------------------------------ *
@@ -177,9 +243,46 @@ const char *mg_last_error(void);
 int mg_residual(mg_ctx *c, const double *f_dev, const double *x_dev, double *r_dev,
                 double *rnorm, double *bnorm);
 
+/* y_dev = alpha x_dev + beta A x_dev, with A the finest-level operator and
+ * zero boundary values (the matrix of the discretisation, Sec. 2 items
+ * (ii)-(iii)); x and y distinct FP64 device arrays of nx*ny*nz values. */
+int mg_apply(mg_ctx *c, double alpha, double beta, const double *x_dev, double *y_dev);
+
 /* Apply `sweeps` red-black Gauss-Seidel sweeps (red = (i+j+k) even first,
  * then black) of the finest-level equation to x_dev in place, FP64. */
 int mg_smooth(mg_ctx *c, const double *f_dev, double *x_dev, int sweeps);
+
+/* Storage types of mg_smooth_level. */
+enum { MG_STORE_F64 = 0, MG_STORE_F32 = 1, MG_STORE_BF16 = 2 };
+
+/* `sweeps` fused red-black Gauss-Seidel sweeps (Sec. 2, item (ii); red =
+ * (i+j+k) even first) of the equation of level l, in the storage type a
+ * solve uses there: level 0 in MG_STORE_F64 is the finest equation with its
+ * boundary values (as mg_smooth); every other (level, storage) pair is the
+ * homogeneous correction equation that the V-cycle smooths, with the level's
+ * coefficients (level 0: the cell coefficient; coarser levels: the averaged
+ * face coefficients).  MG_STORE_F32 / MG_STORE_BF16 need an MG_FP32_IR /
+ * MG_BF16_IR context and use its FP32 coefficient copies (levels below the
+ * bottom-solver level only, for cell coefficients).  b_dev and x_dev are FP64
+ * device arrays with the dimensions of level l (mg_level_dims): both are
+ * rounded to the storage type (to nearest even), swept on library buffers,
+ * and x is converted back to FP64.  tile (0 = heuristic, 1..MG_NUM_TILES) and
+ * zchunk (planes per workgroup, 0 = heuristic) select the launch.  For
+ * verification; it synchronises the context's stream. */
+int mg_smooth_level(mg_ctx *c, int l, int store, const double *b_dev, double *x_dev, int sweeps, int tile,
+                    int zchunk);
+
+/* Options of mg_set_option. */
+enum {
+    MG_OPT_CORRECTION_WEIGHT = 1 /* the coarse-grid correction is added to
+                                    the finest level as u += w * P e;
+                                    w in (0, 4], default 1 (the plain
+                                    V-cycle).  w > 2 over-corrects the
+                                    smooth error components, which then
+                                    grow: used to exercise the divergence
+                                    test. */
+};
+int mg_set_option(mg_ctx *c, int key, double value);
 
 /* u_dev (level l) += P e_dev (level l+1): the cell-centred trilinear
  * prolongation of a coarse correction, ghost values reflected across the

@@ -28,4 +28,6 @@ from .oracle import (  # noqa: F401
     threads,
     tga_coefficients,
     tga_step,
+    field,
+    relaxation_time,
 )

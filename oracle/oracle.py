@@ -22,7 +22,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mg_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# MG_ORACLE_NATIVE=1: a build tuned for the host it runs on (-O3 -march=native),
+# for timing the oracle on that host; the default build is portable.
+_NATIVE = os.environ.get("MG_ORACLE_NATIVE") == "1"
+_LIB_PATH = os.path.join(_HERE, "liboracle_native.so" if _NATIVE else "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
@@ -33,8 +36,9 @@ def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (OpenMP for the CG vector loops)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + f".tmp{os.getpid()}"
-        cmd = ["gcc", "-O2", "-march=x86-64-v3", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
-               "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
+        opt = ["-O3", "-march=native"] if _NATIVE else ["-O2", "-march=x86-64-v3"]
+        cmd = ["gcc", *opt, "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp,
+               _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -358,3 +362,40 @@ def tga_step(faces, h: float, dt: float, n: np.ndarray, eps: float = 1e-6, rtol:
     Ln = -apply(prob(0.0, n), n)
     y = solve_reference(prob(1.0 / mu1, (n + mu3 * Ln) / mu1), rtol)
     return solve_reference(prob(1.0 / mu2, y / mu2), rtol)
+
+
+# ---------------------------------------------------------------- field, relaxation time
+
+
+def field(p, phi: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """E = -grad(phi) at the cell centres by central differences over two
+    cells (paper Sec. 2: the field follows from the potential), with the
+    ghost values of the discretisation beyond the box: 2g - phi_P beyond a
+    Dirichlet face (value g), phi_P beyond a Neumann face.  Returns
+    (Ex, Ey, Ez), each [nz][ny][nx]."""
+    phi = np.asarray(phi, dtype=np.float64)
+    types, vals = p.bc_types(), p.bc_values()
+    out = []
+    for axis, (lo, hi) in zip((2, 1, 0), ((0, 1), (2, 3), (4, 5))):
+        first = np.take(phi, [0], axis=axis)
+        last = np.take(phi, [phi.shape[axis] - 1], axis=axis)
+        g_lo = 2.0 * vals[lo] - first if types[lo] == "D" else first
+        g_hi = 2.0 * vals[hi] - last if types[hi] == "D" else last
+        ext = np.concatenate([g_lo, phi, g_hi], axis=axis)
+        n = phi.shape[axis]
+        fwd = np.take(ext, np.arange(2, n + 2), axis=axis)
+        bwd = np.take(ext, np.arange(0, n), axis=axis)
+        out.append(-(fwd - bwd) / (2.0 * p.h))
+    return out[0], out[1], out[2]
+
+
+def relaxation_time(p, phi: np.ndarray, sigma: np.ndarray, eps0: float = 1.0):
+    """(max |E|, max |J|, dt_E) with J = sigma E (the drift current of a
+    conductivity sigma) and the dielectric relaxation time of the paper's
+    time-step table, dt_E = eps0 |E| / |J|, taken with the largest values
+    over the grid (one step size for the whole domain)."""
+    ex, ey, ez = field(p, phi)
+    emag = np.sqrt(ex * ex + ey * ey + ez * ez)
+    jmax = float(np.max(np.asarray(sigma) * emag))
+    emax = float(np.max(emag))
+    return emax, jmax, (eps0 * emax / jmax if jmax > 0 else np.inf)

@@ -69,7 +69,7 @@ extern "C" int mg_autotune(mg_ctx *c, int reps, int *tile, int *zchunk, double *
         if (us) *us = 0.0;
         return MG_OK;
     }
-    const Geo G = level_geo(c, 0, !lowp);
+    const Geo G = level_geo(c, 0, !lowp, lowp);
     const Coef C = level_coef(c, 0, lowp);
     const Key key{G.nx, G.ny, G.nz, st, C.mode};
     {

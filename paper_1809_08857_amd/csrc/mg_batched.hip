@@ -63,8 +63,12 @@ template <class TL> struct BIr {
     int slot, bslot, ref_slot;
     double rtol2;
     int *done;
-    int gx, gy, kz, nblk;  // column-kernel tiles in x and y, planes per z chunk, workgroups
+    int gx, gy, kz, nblk;  // column-kernel tiles in x and y, planes per z chunk, tiles
+    int nwg;               // workgroups (each covers the tiles q, q + nwg, ...)
     int has_e, zero_x;
+    double sc0;            // > 0: cast scale of this pass, else ws.result[2] (residual scaling)
+    double cs;             // power of two multiplying the inner operator's coefficients
+    double ncell;
 };
 
 constexpr int kBX = 32, kBY = 8;  // brick block of the batched element-wise kernels
@@ -140,7 +144,8 @@ template <class TL>
 __global__ __launch_bounds__(kFinalThreads) void b_ir_final_k(const BIr<TL> *__restrict__ items, int check_done) {
     const BIr<TL> &it = items[blockIdx.x];
     if (check_done && it.done && *it.done) return;
-    reduce2_final_body(it.ws, it.slot, it.bslot, it.nblk, it.ref_slot, it.rtol2, it.done);
+    ir_final_body(it.ws, it.slot, it.bslot, it.nwg, it.ref_slot, it.rtol2, it.done, it.ws.result + 2, it.sc0,
+                  it.ncell);
 }
 
 template <class TL>
@@ -149,9 +154,10 @@ __global__ __launch_bounds__(kIrTX *kIrTY) void b_ir_k(const BIr<TL> *__restrict
     const WorkRef r = work[blockIdx.x];
     const BIr<TL> it = items[r.item];
     if (check_done && it.done && *it.done) return;
-#define MG_B_IR(MODE, HE)                                                                                     \
-    ir_col_body<TL, MODE, HE, kIrTX, kIrTY>(it.x, it.e, it.xout, it.f, it.eps, it.G, it.rl, it.ws, it.slot,   \
-                                            it.bslot, it.kz, it.gx, it.gy, r.blk, it.zero_x != 0)
+#define MG_B_IR(MODE, HE)                                                                                      \
+    ir_tiles<TL, MODE, HE, kIrTX, kIrTY, false>(it.x, it.e, it.xout, it.f, it.eps, it.G, it.rl, it.ws, it.slot,  \
+                                                it.bslot, it.kz, it.gx, it.gy, r.blk, it.nblk, it.nwg, r.blk,   \
+                                                it.zero_x != 0, it.ws.result + 2, it.sc0, it.cs)
     if (it.mode == COEF_CELL) {
         if (it.has_e) MG_B_IR(COEF_CELL, true);
         else MG_B_IR(COEF_CELL, false);
@@ -260,10 +266,13 @@ struct BatchPlan {
     int *flags = nullptr;        // per-problem convergence flags (device)
     int *h_flags = nullptr;      // pinned copies
     double *h_res = nullptr;
+    int *h_one = nullptr;        // pinned constant 1 (stops a diverged problem)
     double *partials = nullptr;  // per-problem reduction workspace
     double *results = nullptr;   // per problem: [0] ||r||^2, [1] ||b||^2
     std::vector<Launch> cycle;   // inner V-cycle phases
-    size_t ir_items[4] = {0, 0, 0, 0}, ir_work = 0;  // [0],[1]: parities, [2],[3]: initial pass (zero x / guess)
+    // [0],[1]: parities; [2],[3]: initial pass (zero x / guess) with unit
+    // residual scale; [4],[5]: the same passes with the scale of the slot
+    size_t ir_items[6] = {0, 0, 0, 0, 0, 0}, ir_work = 0;
     int ir_nwork = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::vector<double *> xalt;
@@ -280,6 +289,7 @@ static void plan_free(BatchPlan *p) {
     if (p->results) (void)hipFree(p->results);
     if (p->h_flags) (void)hipHostFree(p->h_flags);
     if (p->h_res) (void)hipHostFree(p->h_res);
+    if (p->h_one) (void)hipHostFree(p->h_one);
     if (p->ev_in) (void)hipEventDestroy(p->ev_in);
     if (p->ev_out) (void)hipEventDestroy(p->ev_out);
     if (p->stream) (void)hipStreamDestroy(p->stream);
@@ -448,7 +458,7 @@ static int build_plan(BatchPlan *P, int count, mg_ctx *const *c, const double *c
     }
     // --- FP64 refinement passes: [0] x -> xalt, [1] xalt -> x, [2] initial
     {
-        std::vector<BIr<TL>> it[4];
+        std::vector<BIr<TL>> it[6];
         std::vector<WorkRef> work;
         // Workgroups of the whole pass: about 32 per CU, shared out by cell
         // count, so that each marches a long column: a workgroup of a few
@@ -478,7 +488,9 @@ static int build_plan(BatchPlan *P, int count, mg_ctx *const *c, const double *c
             b.ref_slot = 1;
             b.rtol2 = ci->d.rtol * ci->d.rtol;
             b.done = P->flags + i;
-            // tiles of the column kernel and z chunks, at most kMaxRedBlocks per problem
+            // tiles of the column kernel and z chunks; at most kMaxRedBlocks
+            // workgroups per problem, each covering several tiles of planes
+            // wider than that
             b.gx = (G0.nx + kIrTX - 1) / kIrTX;
             b.gy = (G0.ny + kIrTY - 1) / kIrTY;
             const int cols = b.gx * b.gy;
@@ -487,10 +499,10 @@ static int build_plan(BatchPlan *P, int count, mg_ctx *const *c, const double *c
             const int gz = std::max(1, std::min({G0.nz, room, (int)std::ceil(want / cols)}));
             b.kz = (G0.nz + gz - 1) / gz;
             b.nblk = b.gx * b.gy * ((G0.nz + b.kz - 1) / b.kz);
-            if (b.nblk > kMaxRedBlocks)
-                return set_err(MG_EINVAL, "mg_solve_batched: problem %d is too wide for the batched "
-                                          "refinement pass (more than %d tiles of %dx%d per plane)", i,
-                               kMaxRedBlocks, kIrTX, kIrTY);
+            b.nwg = std::min(b.nblk, kMaxRedBlocks);
+            b.sc0 = 0.0;
+            b.cs = ci->cscale;
+            b.ncell = (double)ci->L[0].n;
             b.has_e = 1;
             b.zero_x = 0;
             b.bslot = -1;
@@ -506,15 +518,21 @@ static int build_plan(BatchPlan *P, int count, mg_ctx *const *c, const double *c
             b2.e = nullptr;
             b2.has_e = 0;
             b2.bslot = 1;
+            b2.sc0 = 1.0;
             BIr<TL> b3 = b2;
             b2.zero_x = 1;
-            for (int q = 0; q < b.nblk; ++q) work.push_back(WorkRef{(int)it[0].size(), q});
+            BIr<TL> b4 = b2, b5 = b3;
+            b4.sc0 = 0.0;
+            b5.sc0 = 0.0;
+            for (int q = 0; q < b.nwg; ++q) work.push_back(WorkRef{(int)it[0].size(), q});
             it[0].push_back(b0);
             it[1].push_back(b1);
             it[2].push_back(b2);
             it[3].push_back(b3);
+            it[4].push_back(b4);
+            it[5].push_back(b5);
         }
-        for (int q = 0; q < 4; ++q) P->ir_items[q] = blob.add(it[q]);
+        for (int q = 0; q < 6; ++q) P->ir_items[q] = blob.add(it[q]);
         P->ir_work = blob.add(work);
         P->ir_nwork = (int)work.size();
     }
@@ -608,10 +626,12 @@ static int solve_batched_ir(int count, mg_ctx *const *c, const double *const *f,
             hipMalloc(&P->partials, sizeof(double) * (size_t)count * kMaxRedBlocks * 2) != hipSuccess ||
             hipMalloc(&P->results, sizeof(double) * 4 * count) != hipSuccess ||
             hipHostMalloc((void **)&P->h_flags, sizeof(int) * count, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&P->h_res, sizeof(double) * 4 * count, hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc((void **)&P->h_res, sizeof(double) * 4 * count, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&P->h_one, sizeof(int), hipHostMallocDefault) != hipSuccess) {
             batch_release(c0);
             return set_err(MG_ENOMEM, "mg_solve_batched: allocation failed");
         }
+        *P->h_one = 1;
         int rc = build_plan<T, TL>(P, count, c, f, x);
         if (rc != MG_OK) {
             batch_release(c0);
@@ -627,7 +647,7 @@ static int solve_batched_ir(int count, mg_ctx *const *c, const double *const *f,
     BCK(launch_ir<TL>(s, P->dbuf, P->ir_items[(flags & MG_GUESS) ? 3 : 2], P->ir_work, P->ir_nwork, P->count, false));
     BCK(hipMemcpyAsync(P->h_res, P->results, sizeof(double) * 4 * count, hipMemcpyDeviceToHost, s));
     BCK(hipStreamSynchronize(s));
-    std::vector<double> bn(count), rel0(count);
+    std::vector<double> bn(count), rel0(count), sc_used(count, 1.0);
     std::vector<int> fell(count, 0), conv_step(count, -1);
     bool refetch = false;
     for (int i = 0; i < count; ++i) {
@@ -641,10 +661,22 @@ static int solve_batched_ir(int count, mg_ctx *const *c, const double *const *f,
             refetch = true;
         }
     }
-    if (refetch) {  // recompute the initial residuals (x now zero where rejected)
-        BCK(launch_ir<TL>(s, P->dbuf, P->ir_items[3], P->ir_work, P->ir_nwork, P->count, false));
+    // Recompute the initial residuals where a guess was rejected (x is now
+    // zero there) or where the residual must be scaled for its cast to the
+    // inner storage type (the pass's final sum stored that scale; the
+    // repeated pass uses it).  At most a few rounds: the residual changes
+    // only where a guess was rejected.
+    for (int round = 0; round < 3; ++round) {
+        bool rescale = false;
+        for (int i = 0; i < count; ++i)
+            if (cast_scale(P->h_res[4 * i], (double)c[i]->L[0].n) != sc_used[i]) rescale = true;
+        if (!refetch && !rescale) break;
+        for (int i = 0; i < count; ++i) sc_used[i] = cast_scale(P->h_res[4 * i], (double)c[i]->L[0].n);
+        BCK(launch_ir<TL>(s, P->dbuf, P->ir_items[(flags & MG_GUESS) ? 5 : 4], P->ir_work, P->ir_nwork, P->count,
+                          false));
         BCK(hipMemcpyAsync(P->h_res, P->results, sizeof(double) * 4 * count, hipMemcpyDeviceToHost, s));
         BCK(hipStreamSynchronize(s));
+        refetch = false;
     }
     int active = 0;
     for (int i = 0; i < count; ++i) {
@@ -660,37 +692,60 @@ static int solve_batched_ir(int count, mg_ctx *const *c, const double *const *f,
     BCK(hipMemcpyAsync(P->flags, P->h_flags, sizeof(int) * count, hipMemcpyHostToDevice, s));
     int max_cycles = 0;
     for (int i = 0; i < count; ++i) max_cycles = std::max(max_cycles, c[i]->d.max_cycles);
+    // Each step: replay the graph, then read every problem's flag and
+    // residual.  A problem whose residual diverges is stopped: its device
+    // flag is set (from a pinned constant that the host never changes) so
+    // that its work returns at once, and the call reports MG_EDIVERGED.
+    std::vector<DivergenceWatch> watch(count);
+    std::vector<int> diverged(count, 0);
+    std::vector<double> rel_last(count, 0.0);
     int steps = 0;
     while (active > 0 && steps < max_cycles) {
         BCK(hipGraphLaunch(P->graph[steps & 1], s));
         BCK(hipMemcpyAsync(P->h_flags, P->flags, sizeof(int) * count, hipMemcpyDeviceToHost, s));
+        BCK(hipMemcpyAsync(P->h_res, P->results, sizeof(double) * 4 * count, hipMemcpyDeviceToHost, s));
         BCK(hipStreamSynchronize(s));
         ++steps;
         active = 0;
         for (int i = 0; i < count; ++i) {
-            if (conv_step[i] < 0 && P->h_flags[i]) conv_step[i] = steps;
-            if (conv_step[i] < 0) ++active;
+            if (conv_step[i] < 0 && !diverged[i]) {
+                if (P->h_flags[i]) {
+                    conv_step[i] = steps;
+                } else {
+                    const double rel = bn[i] > 0.0 ? std::sqrt(P->h_res[4 * i]) / bn[i] : 0.0;
+                    rel_last[i] = rel;
+                    if (watch[i].diverged(rel, rel0[i])) {
+                        diverged[i] = steps;
+                        BCK(hipMemcpyAsync(P->flags + i, P->h_one, sizeof(int), hipMemcpyHostToDevice, s));
+                    }
+                }
+            }
+            if (conv_step[i] < 0 && !diverged[i]) ++active;
         }
     }
     BCK(hipMemcpyAsync(P->h_res, P->results, sizeof(double) * 4 * count, hipMemcpyDeviceToHost, s));
     // iterates that stopped after an odd number of steps sit in the spare buffer
     for (int i = 0; i < count; ++i) {
-        const int used = conv_step[i] < 0 ? steps : conv_step[i];
+        const int used = diverged[i] ? diverged[i] : (conv_step[i] < 0 ? steps : conv_step[i]);
         if (used & 1) BCK(hipMemcpyAsync(x[i], P->xalt[i], c[i]->L[0].n * 8, hipMemcpyDeviceToDevice, s));
     }
     BCK(hipStreamSynchronize(s));
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    int worst = MG_OK;
+    int worst = MG_OK, first_div = -1;
     for (int i = 0; i < count; ++i) {
         mg_stats S{};
-        S.cycles = conv_step[i] < 0 ? steps : conv_step[i];
+        S.cycles = diverged[i] ? diverged[i] : (conv_step[i] < 0 ? steps : conv_step[i]);
         S.rel_res0 = fell[i] ? 1.0 : rel0[i];
-        S.rel_res = bn[i] > 0.0 ? std::sqrt(P->h_res[4 * i]) / bn[i] : 0.0;
+        S.rel_res = diverged[i] ? rel_last[i] : (bn[i] > 0.0 ? std::sqrt(P->h_res[4 * i]) / bn[i] : 0.0);
         S.fell_back = fell[i];
         S.ms = ms;
         if (conv_step[i] < 0) worst = MG_NOT_CONVERGED;
+        if (diverged[i] && first_div < 0) first_div = i;
         if (st) st[i] = S;
     }
+    if (first_div >= 0)
+        return set_err(MG_EDIVERGED, "mg_solve_batched: the residual of problem %d diverged (%g after %d steps)",
+                       first_div, rel_last[first_div], diverged[first_div]);
     return worst;
 }
 

@@ -2,6 +2,8 @@
 // (mg_engine.hip, mg_batched.hip, mg_autotune.hip).
 #pragma once
 
+#include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <string>
 #include <vector>
@@ -38,6 +40,24 @@ struct LvView {
 
 struct BatchPlan;  // mg_batched.hip
 
+// Divergence test of a sequence of relative residuals (one per cycle): a
+// non-finite value, growth by 1e6 over the start, or growth in each of
+// kGrowCycles consecutive cycles to more than 10x the smallest value seen.
+// A solve stalled at its rounding floor moves by small factors either way
+// and is reported as not converged instead.
+struct DivergenceWatch {
+    static constexpr int kGrowCycles = 4;
+    double rmin = HUGE_VAL, last = HUGE_VAL;
+    int grow = 0;
+    bool diverged(double rel, double rel0) {
+        if (!std::isfinite(rel)) return true;
+        grow = rel > last ? grow + 1 : 0;
+        last = rel;
+        rmin = std::min(rmin, rel);
+        return rel > 1e6 * std::max(1.0, rel0) || (grow >= kGrowCycles && rel > 10.0 * rmin);
+    }
+};
+
 }  // namespace mg
 
 struct mg_ctx {
@@ -46,16 +66,20 @@ struct mg_ctx {
     int lp_store = -1;  // ST_F32 / ST_BF16 for refinement, -1 for MG_FP64
     int nlev = 0, tail = 0, tail0 = 0;  // tail: first level of the bottom solver
     mg::Level L[mg::kMaxLevels];
-    bool has_eps = false;
+    bool has_eps = false;   // variable coefficients: stored faces on the coarse levels
+    bool face0 = false;     // the finest level's faces were given (mg_set_face_coeffs)
     double *eps = nullptr;
     void *eps_lp = nullptr;
     double a = 0.0;
+    double cscale = 1.0;  // power of two multiplying the inner (FP32/BF16) operator's coefficients
+    double corr_w = 1.0;  // weight of the coarse correction at the finest level (MG_OPT_CORRECTION_WEIGHT)
     int bcmask = 0;
     double g[6] = {0, 0, 0, 0, 0, 0};
     bool coeffs = false;
     unsigned version = 0;  // bumped by every mg_set_coeffs
     unsigned long uid = 0;  // unique per context in the process
     double *xalt = nullptr;
+    double *work = nullptr;  // right-hand sides of mg_tga_step (allocated at its first call)
     int *d_done = nullptr;             // device convergence flag of the running solve
     hipEvent_t ev_cyc[2] = {nullptr, nullptr};
     mg::RedWs ws{};
@@ -82,8 +106,16 @@ using Ctx = ::mg_ctx;
 
 extern thread_local std::string g_err;
 int set_err(int code, const char *fmt, ...);
-Geo level_geo(const Ctx *c, int l, bool with_g);
+// Geometry of level l; with_g: the Dirichlet values apply (finest level of
+// the FP64 problem); lowp: the inner low-precision operator (coefficients
+// multiplied by cscale).
+Geo level_geo(const Ctx *c, int l, bool with_g, bool lowp = false);
 Coef level_coef(const Ctx *c, int l, bool lowp);
+// Sets a and rebuilds the bottom-solver descriptors (host only).
+void set_screening(Ctx *c, double a);
+// Validation shared by the entry points (MG_OK or MG_EINVAL with a message).
+int check_grid(const char *who, const mg_desc *d);
+int parse_operator(const char *who, double a, const mg_bcs *bc, int *mask);
 void build_tail(const Ctx *c, TailDesc &D, bool with_g);
 int tile_for(const Ctx *c, const Geo &G, int st, int mode, int l, int *zc);
 int vcycle(Ctx *c, std::vector<LvView> &V, int l, bool zero_start, const int *done = nullptr);

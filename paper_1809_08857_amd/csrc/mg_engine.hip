@@ -56,7 +56,7 @@ static void dfree(Ctx *c, void *&p) {
     p = nullptr;
 }
 
-Geo level_geo(const Ctx *c, int l, bool with_g) {
+Geo level_geo(const Ctx *c, int l, bool with_g, bool lowp) {
     const Level &L = c->L[l];
     Geo G;
     G.nx = L.nx;
@@ -64,10 +64,11 @@ Geo level_geo(const Ctx *c, int l, bool with_g) {
     G.nz = L.nz;
     G.bcmask = c->bcmask;
     G.h2 = L.h * L.h;
-    G.ah2 = c->a * G.h2;
+    G.a = lowp ? c->a * c->cscale : c->a;
+    G.ah2 = G.a * G.h2;
     G.ih2 = 1.0 / G.h2;
-    G.a = c->a;
     for (int d = 0; d < 6; ++d) G.g[d] = (with_g && l == 0) ? c->g[d] : 0.0;
+    G.cw = l == 0 ? c->corr_w : 1.0;
     return G;
 }
 
@@ -77,7 +78,7 @@ Coef level_coef(const Ctx *c, int l, bool lowp) {
         C.mode = COEF_CONST;
         return C;
     }
-    if (l == 0) {
+    if (l == 0 && !c->face0) {
         C.mode = COEF_CELL;
         C.eps = lowp ? c->eps_lp : (const void *)c->eps;
         return C;
@@ -112,7 +113,7 @@ void build_tail(const Ctx *c, TailDesc &D, bool with_g) {
         T.ny = L.ny;
         T.nz = L.nz;
         T.h2 = L.h * L.h;
-        T.ah2 = c->a * T.h2;
+        T.ah2 = c->a * c->cscale * T.h2;  // cscale = 1 unless the faces are those of the inner operator
         T.bx = L.fbx;
         T.by = L.fby;
         T.bz = L.fbz;
@@ -125,6 +126,12 @@ void build_tail(const Ctx *c, TailDesc &D, bool with_g) {
         D.stage = 0;
         tail_layout(D);
     }
+}
+
+void set_screening(Ctx *c, double a) {
+    c->a = a;
+    build_tail(c, c->tails[0], false);
+    build_tail(c, c->tails[1], true);
 }
 
 // ------------------------------------------------------------ V-cycle
@@ -203,7 +210,7 @@ void lowp_view(Ctx *c, std::vector<LvView> &V) {
     for (int l = 0; l <= c->tail; ++l) {
         LvView &W = V[l];
         W.st = c->lp_store;
-        W.G = level_geo(c, l, false);
+        W.G = level_geo(c, l, false, true);
         W.C = level_coef(c, l, true);
         W.n = c->L[l].n;
         W.u = c->L[l].ul;
@@ -230,7 +237,7 @@ hipError_t timed_smooth(Ctx *c, int l, const LvView &W, bool zin, int tile, int 
     if (e != hipSuccess) return e;
     // algorithmic bytes: read u (unless zero), b and eps once, write u once
     const double es = (double)store_size(W.st);
-    const int arrays = (zin ? 0 : 1) + 1 + (W.C.mode == COEF_CELL ? 1 : 0) + 1;
+    const int arrays = (zin ? 0 : 1) + 1 + (W.C.mode == COEF_CELL ? 1 : 0) + (W.C.mode == COEF_FACE ? 3 : 0) + 1;
     c->ev_bytes[c->ev_used / 2] = (double)W.n * es * arrays;
     c->ev_step[c->ev_used / 2] = c->cur_step;
     c->ev_used += 2;
@@ -267,6 +274,16 @@ int read_results(Ctx *c, int n) {
     return MG_OK;
 }
 
+int check_grid(const char *who, const mg_desc *d) {
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1)
+        return set_err(MG_EINVAL, "%s: dimensions must be >= 1 (got %d x %d x %d)", who, d->nx, d->ny, d->nz);
+    if ((double)d->nx * d->ny * d->nz > 4.0e9) return set_err(MG_EINVAL, "%s: grid too large", who);
+    if ((double)d->nx * d->ny > (double)kMaxPlaneCells)
+        return set_err(MG_EINVAL, "%s: an x-y plane may hold at most 2^28 cells", who);
+    if (!(d->h > 0.0) || !std::isfinite(d->h)) return set_err(MG_EINVAL, "%s: h must be > 0", who);
+    return MG_OK;
+}
+
 }  // namespace mg
 
 using namespace mg;
@@ -294,14 +311,7 @@ const char *mg_last_error(void) { return g_err.c_str(); }
 int mg_create(const mg_desc *d, void *hip_stream, mg_ctx **out) {
     if (out) *out = nullptr;
     if (!d || !out) return set_err(MG_EINVAL, "mg_create: null argument");
-    if (d->nx < 1 || d->ny < 1 || d->nz < 1)
-        return set_err(MG_EINVAL, "mg_create: dimensions must be >= 1 (got %d x %d x %d)", d->nx,
-                       d->ny, d->nz);
-    if ((double)d->nx * d->ny * d->nz > 4.0e9)
-        return set_err(MG_EINVAL, "mg_create: grid too large");
-    if ((double)d->nx * d->ny > (double)kMaxPlaneCells)
-        return set_err(MG_EINVAL, "mg_create: an x-y plane may hold at most 2^28 cells");
-    if (!(d->h > 0.0) || !std::isfinite(d->h)) return set_err(MG_EINVAL, "mg_create: h must be > 0");
+    if (int rc = check_grid("mg_create", d)) return rc;
     if (d->precision < MG_FP64 || d->precision > MG_BF16_IR)
         return set_err(MG_EINVAL, "mg_create: unknown precision %d", d->precision);
     if (d->nu1 < 0 || d->nu2 < 0 || d->nu1 > 8 || d->nu2 > 8 || d->nu1 + d->nu2 < 1)
@@ -418,24 +428,94 @@ int mg_destroy(mg_ctx *c) {
     return MG_OK;
 }
 
-int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) {
-    if (!c || !bc) return set_err(MG_EINVAL, "mg_set_coeffs: null argument");
-    if (!(a >= 0.0) || !std::isfinite(a)) return set_err(MG_EINVAL, "mg_set_coeffs: a must be finite and >= 0");
-    int mask = 0;
+}  // extern "C"
+
+namespace mg {
+
+// Validates a and the face conditions of an operator; *mask gets the
+// Dirichlet faces.
+int parse_operator(const char *who, double a, const mg_bcs *bc, int *mask) {
+    if (!(a >= 0.0) || !std::isfinite(a)) return set_err(MG_EINVAL, "%s: a must be finite and >= 0", who);
+    int m = 0;
     for (int f = 0; f < 6; ++f) {
         if (bc->type[f] != MG_BC_DIRICHLET && bc->type[f] != MG_BC_NEUMANN)
-            return set_err(MG_EINVAL, "mg_set_coeffs: unknown boundary type %d on face %d", bc->type[f], f);
+            return set_err(MG_EINVAL, "%s: unknown boundary type %d on face %d", who, bc->type[f], f);
         if (bc->type[f] == MG_BC_DIRICHLET) {
             if (!std::isfinite(bc->value[f]))
-                return set_err(MG_EINVAL, "mg_set_coeffs: non-finite boundary value on face %d", f);
-            mask |= 1 << f;
+                return set_err(MG_EINVAL, "%s: non-finite boundary value on face %d", who, f);
+            m |= 1 << f;
         }
     }
-    if (a == 0.0 && mask == 0)
-        return set_err(MG_EINVAL, "mg_set_coeffs: singular operator (a = 0 and no Dirichlet face)");
+    if (a == 0.0 && m == 0) return set_err(MG_EINVAL, "%s: singular operator (a = 0 and no Dirichlet face)", who);
+    *mask = m;
+    return MG_OK;
+}
+
+static size_t nfaces_x(const Level &L) { return (size_t)(L.nx + 1) * L.ny * L.nz; }
+static size_t nfaces_y(const Level &L) { return (size_t)L.nx * (L.ny + 1) * L.nz; }
+static size_t nfaces_z(const Level &L) { return (size_t)L.nx * L.ny * (L.nz + 1); }
+
+// FP64 face arrays on every level (level 0 serves the coarsening, and the
+// bottom solver when it starts there).
+static int alloc_faces(Ctx *c, const char *who) {
+    for (int l = 0; l < c->nlev; ++l) {
+        Level &L = c->L[l];
+        if (!L.fbx) {
+            L.fbx = (double *)dalloc(c, nfaces_x(L) * 8);
+            L.fby = (double *)dalloc(c, nfaces_y(L) * 8);
+            L.fbz = (double *)dalloc(c, nfaces_z(L) * 8);
+            if (!L.fbx || !L.fby || !L.fbz) return set_err(MG_ENOMEM, "%s: allocation failed", who);
+        }
+    }
+    return MG_OK;
+}
+
+// Coarse face coefficients of levels 1.. from level 0's.
+static int coarsen_levels(Ctx *c) {
+    for (int l = 1; l < c->nlev; ++l) {
+        Level &L = c->L[l];
+        const Level &F = c->L[l - 1];
+        CK(coarsen_faces(c->stream, level_geo(c, l - 1, false), F.fbx, F.fby, F.fbz, level_geo(c, l, false), L.fbx,
+                         L.fby, L.fbz));
+    }
+    return MG_OK;
+}
+
+// Bottom level of a variable-coefficient operator: the first whose staged
+// coefficients fit in LDS.
+static void choose_bottom(Ctx *c) {
+    c->tail = c->tail0;
+    for (;;) {
+        TailDesc probe;
+        build_tail(c, probe, false);
+        if (probe.stage || c->tail == c->nlev - 1) break;
+        c->tail++;
+    }
+}
+
+// Common end of the set-up calls: scalar data, bottom descriptors, flags.
+static int finish_operator(Ctx *c, double a, int mask, const mg_bcs *bc) {
+    c->bcmask = mask;
+    for (int f = 0; f < 6; ++f) c->g[f] = (mask >> f & 1) ? bc->value[f] : 0.0;
+    set_screening(c, a);
+    CK(hipStreamSynchronize(c->stream));
+    c->coeffs = true;
+    c->version++;
+    return MG_OK;
+}
+
+}  // namespace mg
+
+extern "C" {
+
+int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) {
+    if (!c || !bc) return set_err(MG_EINVAL, "mg_set_coeffs: null argument");
+    int mask = 0, rc = parse_operator("mg_set_coeffs", a, bc, &mask);
+    if (rc) return rc;
     hipStream_t s = c->stream;
     const size_t n0 = c->L[0].n;
     c->coeffs = false;
+    c->face0 = false;
     if (eps_dev) {
         if (!c->eps) {
             c->eps = (double *)dalloc(c, n0 * 8);
@@ -443,39 +523,48 @@ int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) 
         }
         CK(hipMemcpyAsync(c->eps, eps_dev, n0 * 8, hipMemcpyDeviceToDevice, s));
         CK(count_bad(s, c->eps, n0, c->ws, 0));
-        int rc = read_results(c, 1);
-        if (rc) return rc;
+        if ((rc = read_results(c, 1))) return rc;
         if (c->h_pin[0] != 0.0)
             return set_err(MG_EINVAL, "mg_set_coeffs: %.0f coefficient entries are not in (0, 1e100]",
                            c->h_pin[0]);
-        // face coefficients of every level (level 0 only while coarsening,
-        // unless the bottom solver starts at level 0)
-        for (int l = 0; l < c->nlev; ++l) {
-            Level &L = c->L[l];
-            if (!L.fbx) {
-                L.fbx = (double *)dalloc(c, (size_t)(L.nx + 1) * L.ny * L.nz * 8);
-                L.fby = (double *)dalloc(c, (size_t)L.nx * (L.ny + 1) * L.nz * 8);
-                L.fbz = (double *)dalloc(c, (size_t)L.nx * L.ny * (L.nz + 1) * 8);
-                if (!L.fbx || !L.fby || !L.fbz) return set_err(MG_ENOMEM, "mg_set_coeffs: allocation failed");
-            }
-            Geo G = level_geo(c, l, false);
-            if (l == 0) CK(faces_from_cell(s, G, c->eps, L.fbx, L.fby, L.fbz));
-            else {
-                Geo Gf = level_geo(c, l - 1, false);
-                const Level &F = c->L[l - 1];
-                CK(coarsen_faces(s, Gf, F.fbx, F.fby, F.fbz, G, L.fbx, L.fby, L.fbz));
-            }
-        }
-        // bottom level: the first whose staged coefficients fit in LDS
+        if ((rc = alloc_faces(c, "mg_set_coeffs"))) return rc;
+        CK(faces_from_cell(s, level_geo(c, 0, false), c->eps, c->L[0].fbx, c->L[0].fby, c->L[0].fbz));
+        if ((rc = coarsen_levels(c))) return rc;
         c->has_eps = true;
-        c->tail = c->tail0;
-        for (;;) {
-            TailDesc probe;
-            build_tail(c, probe, false);
-            if (probe.stage || c->tail == c->nlev - 1) break;
-            c->tail++;
-        }
+        choose_bottom(c);
+        c->cscale = 1.0;
         if (c->lp_store >= 0) {
+            // The inner cycle runs on eps * cscale with cscale = 2^-m, m the
+            // mean binary exponent of the largest and smallest coefficient,
+            // so that its FP32 coefficients lie in [2^-35, 2^35]: harmonic
+            // means neither overflow nor underflow there, and the Dirichlet
+            // coefficient of the FP32 sweeps dominates them.  The scale is a
+            // power of two, so every rounding of the inner cycle is the same
+            // as without it.  The inner cycle's correction is multiplied by
+            // cscale on its way back (ir_update_resid).
+            CK(minmax(s, c->eps, n0, c->ws, 2));
+            if ((rc = read_results(c, 4))) return rc;
+            int emax, emin;
+            (void)std::frexp(c->h_pin[2], &emax);
+            (void)std::frexp(c->h_pin[3], &emin);
+            if (emax - emin > 70)
+                return set_err(MG_EINVAL,
+                               "mg_set_coeffs: coefficients from %g to %g span more than 2^70, the range of "
+                               "the FP32/BF16 inner cycle (use MG_FP64)", c->h_pin[3], c->h_pin[2]);
+            const int m = (emax + emin) / 2;
+            c->cscale = std::ldexp(1.0, -m);
+            if (a * c->cscale > 0x1p100)
+                return set_err(MG_EINVAL, "mg_set_coeffs: a = %g is too large against the coefficients for the "
+                                          "FP32/BF16 inner cycle (use MG_FP64)", a);
+            // the FP64 faces of a mixed-precision context serve only the
+            // inner cycle (its bottom solve and its FP32 copies): scale them
+            if (c->cscale != 1.0)
+                for (int l = 0; l < c->nlev; ++l) {
+                    Level &L = c->L[l];
+                    CK(scale_f64(s, L.fbx, nfaces_x(L), c->cscale));
+                    CK(scale_f64(s, L.fby, nfaces_y(L), c->cscale));
+                    CK(scale_f64(s, L.fbz, nfaces_z(L), c->cscale));
+                }
             // coefficients of the inner cycle: FP32 for both FP32 and BF16
             // fields (BF16 coefficients perturb the inner operator enough to
             // cost outer steps)
@@ -483,36 +572,62 @@ int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) 
             const size_t es = store_size(cst);
             if (!c->eps_lp) c->eps_lp = dalloc(c, n0 * es);
             if (!c->eps_lp) return set_err(MG_ENOMEM, "mg_set_coeffs: allocation failed");
-            CK(convert(s, c->eps, cst, c->eps_lp, n0));
+            CK(convert(s, c->eps, cst, c->eps_lp, n0, c->cscale));
             for (int l = 1; l < c->tail; ++l) {
                 Level &L = c->L[l];
-                const size_t nfx = (size_t)(L.nx + 1) * L.ny * L.nz, nfy = (size_t)L.nx * (L.ny + 1) * L.nz,
-                             nfz = (size_t)L.nx * L.ny * (L.nz + 1);
                 if (!L.lbx) {
-                    L.lbx = dalloc(c, nfx * es);
-                    L.lby = dalloc(c, nfy * es);
-                    L.lbz = dalloc(c, nfz * es);
+                    L.lbx = dalloc(c, nfaces_x(L) * es);
+                    L.lby = dalloc(c, nfaces_y(L) * es);
+                    L.lbz = dalloc(c, nfaces_z(L) * es);
                     if (!L.lbx || !L.lby || !L.lbz) return set_err(MG_ENOMEM, "mg_set_coeffs: allocation failed");
                 }
-                CK(convert(s, L.fbx, cst, L.lbx, nfx));
-                CK(convert(s, L.fby, cst, L.lby, nfy));
-                CK(convert(s, L.fbz, cst, L.lbz, nfz));
+                CK(convert(s, L.fbx, cst, L.lbx, nfaces_x(L)));
+                CK(convert(s, L.fby, cst, L.lby, nfaces_y(L)));
+                CK(convert(s, L.fbz, cst, L.lbz, nfaces_z(L)));
             }
         }
-        c->has_eps = true;
     } else {
         c->has_eps = false;
         c->tail = c->tail0;
+        c->cscale = 1.0;
+        if (c->lp_store >= 0 && a > 0x1p100)
+            return set_err(MG_EINVAL, "mg_set_coeffs: a = %g is too large for the FP32/BF16 inner cycle "
+                                      "(use MG_FP64)", a);
     }
-    c->a = a;
-    c->bcmask = mask;
-    for (int f = 0; f < 6; ++f) c->g[f] = (mask >> f & 1) ? bc->value[f] : 0.0;
-    build_tail(c, c->tails[0], false);
-    build_tail(c, c->tails[1], true);
-    CK(hipStreamSynchronize(s));
-    c->coeffs = true;
-    c->version++;
-    return MG_OK;
+    return finish_operator(c, a, mask, bc);
+}
+
+int mg_set_face_coeffs(mg_ctx *c, const double *bx_dev, const double *by_dev, const double *bz_dev, double a,
+                       const mg_bcs *bc) {
+    if (!c || !bc || !bx_dev || !by_dev || !bz_dev) return set_err(MG_EINVAL, "mg_set_face_coeffs: null argument");
+    if (c->lp_store >= 0)
+        return set_err(MG_EINVAL, "mg_set_face_coeffs: face coefficients need an MG_FP64 context");
+    int mask = 0, rc = parse_operator("mg_set_face_coeffs", a, bc, &mask);
+    if (rc) return rc;
+    hipStream_t s = c->stream;
+    c->coeffs = false;
+    c->face0 = false;
+    if ((rc = alloc_faces(c, "mg_set_face_coeffs"))) return rc;
+    Level &L0 = c->L[0];
+    CK(hipMemcpyAsync(L0.fbx, bx_dev, nfaces_x(L0) * 8, hipMemcpyDeviceToDevice, s));
+    CK(hipMemcpyAsync(L0.fby, by_dev, nfaces_y(L0) * 8, hipMemcpyDeviceToDevice, s));
+    CK(hipMemcpyAsync(L0.fbz, bz_dev, nfaces_z(L0) * 8, hipMemcpyDeviceToDevice, s));
+    double bad = 0.0;
+    const double *arrs[3] = {L0.fbx, L0.fby, L0.fbz};
+    const size_t ns[3] = {nfaces_x(L0), nfaces_y(L0), nfaces_z(L0)};
+    for (int q = 0; q < 3; ++q) {
+        CK(count_bad(s, arrs[q], ns[q], c->ws, 0));
+        if ((rc = read_results(c, 1))) return rc;
+        bad += c->h_pin[0];
+    }
+    if (bad != 0.0)
+        return set_err(MG_EINVAL, "mg_set_face_coeffs: %.0f face coefficients are not in (0, 1e100]", bad);
+    if ((rc = coarsen_levels(c))) return rc;
+    c->has_eps = true;
+    c->face0 = true;
+    c->cscale = 1.0;
+    choose_bottom(c);
+    return finish_operator(c, a, mask, bc);
 }
 
 // Result slots of the reduction workspace used by a solve.
@@ -582,6 +697,9 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
     // returns at once.
     std::vector<LvView> V;
     const bool lowp = c->lp_store >= 0;
+    // scale of the first residual cast to the inner storage type (from ||b||;
+    // later passes take theirs from the previous residual on the device)
+    const double sc0 = cast_scale_rms(bn / std::sqrt((double)n0));
     double *cur = x, *oth = c->xalt;  // FP64 iterate and its spare buffer
     if (lowp) lowp_view(c, V);
     else fp64_view(c, V, f, x);
@@ -591,7 +709,9 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
         if (lowp) {
             // FP64 residual of the starting iterate, cast into the inner
             // right-hand side (later steps get it from advance())
-            if (cyc == 0) CK(ir_update_resid(s, G0, C0, cur, nullptr, nullptr, f, c->lp_store, V[0].bw, chk));
+            if (cyc == 0)
+                CK(ir_update_resid(s, G0, C0, cur, nullptr, nullptr, f, c->lp_store, V[0].bw, chk, sc0,
+                                   c->cscale));
         } else if (c->tail == 0) {
             CK(norm2_resid(s, ST_F64, G0, C0, cur, f, c->ws, chk.slot, -1, &chk));
         } else {
@@ -623,7 +743,7 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
             if (r) return r;
             RrCheck k2 = chk;
             k2.slot = SLOT_CYC + ((cyc + 1) & 1);
-            CK(ir_update_resid(s, G0, C0, cur, V[0].u, oth, f, c->lp_store, V[0].bw, k2));
+            CK(ir_update_resid(s, G0, C0, cur, V[0].u, oth, f, c->lp_store, V[0].bw, k2, 0.0, c->cscale));
             std::swap(cur, oth);
         } else if (c->tail == 0) {
             CK(tail_solve(s, ST_F64, c->tails[1], f, cur, cur, done));
@@ -674,6 +794,7 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
         }
     }
     double *at_check[2] = {cur, nullptr};
+    DivergenceWatch watch;
     int cycles = 0;
     double rel = S.rel_res0;
     double *final_x = cur;
@@ -693,7 +814,7 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
             break;
         }
         if (cyc >= c->d.max_cycles) break;
-        if (!std::isfinite(rel) || rel > 1e6 * std::max(1.0, S.rel_res0)) {
+        if (watch.diverged(rel, S.rel_res0)) {
             CK(hipStreamSynchronize(s));
             S.cycles = cycles;
             S.rel_res = rel;
@@ -718,6 +839,61 @@ int mg_solve(mg_ctx *c, const double *f_dev, double *x_dev, unsigned flags, mg_s
     if (!c->coeffs) return set_err(MG_EINVAL, "mg_solve: mg_set_coeffs has not succeeded");
     if (flags & ~(unsigned)MG_GUESS) return set_err(MG_EINVAL, "mg_solve: unknown flags 0x%x", flags);
     return solve_impl(c, f_dev, x_dev, flags, st);
+}
+
+int mg_apply(mg_ctx *c, double alpha, double beta, const double *x_dev, double *y_dev) {
+    if (!c || !x_dev || !y_dev) return set_err(MG_EINVAL, "mg_apply: null argument");
+    if (!c->coeffs) return set_err(MG_EINVAL, "mg_apply: mg_set_coeffs has not succeeded");
+    if (x_dev == y_dev) return set_err(MG_EINVAL, "mg_apply: x and y must not be the same array");
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return set_err(MG_EINVAL, "mg_apply: alpha, beta not finite");
+    CK(apply_op(c->stream, level_geo(c, 0, false), level_coef(c, 0, false), alpha, beta, x_dev, y_dev));
+    CK(hipStreamSynchronize(c->stream));
+    return MG_OK;
+}
+
+int mg_tga_step(mg_ctx *c, double dt, const double *n_dev, double *out_dev, unsigned flags, mg_stats *st) {
+    if (!c || !n_dev || !out_dev) return set_err(MG_EINVAL, "mg_tga_step: null argument");
+    if (!c->coeffs) return set_err(MG_EINVAL, "mg_tga_step: mg_set_coeffs has not succeeded");
+    if (n_dev == out_dev) return set_err(MG_EINVAL, "mg_tga_step: n and out must not be the same array");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(MG_EINVAL, "mg_tga_step: dt must be finite and > 0");
+    if (c->bcmask != 0) return set_err(MG_EINVAL, "mg_tga_step: the diffusion operator needs zero flux on every face");
+    if (flags & ~(unsigned)MG_GUESS) return set_err(MG_EINVAL, "mg_tga_step: unknown flags 0x%x", flags);
+    const size_t n0 = c->L[0].n;
+    if (!c->work) {
+        c->work = (double *)dalloc(c, n0 * 8);
+        if (!c->work) return set_err(MG_ENOMEM, "mg_tga_step: allocation failed");
+    }
+    // Twizell-Gumel-Arigu coefficients: q = 2 - sqrt(2) - 1e-6, r = sqrt(q^2 - 4q + 2)
+    const double q = 2.0 - std::sqrt(2.0) - 1e-6, r = std::sqrt(q * q - 4.0 * q + 2.0);
+    const double mu1 = 0.5 * (q - r) * dt, mu2 = 0.5 * (q + r) * dt, mu3 = (1.0 - q) * dt;
+    const double a_keep = c->a;
+    hipStream_t s = c->stream;
+    const Coef C0 = level_coef(c, 0, false);
+    mg_stats S[2] = {};
+    int rc, worst = MG_OK;
+    // (I - mu1 L) y = (I + mu3 L) n, as (1/mu1) y - div(D grad y) = rhs / mu1.  With
+    // A the context's operator at a = 1/mu1, L n = a n - A n, so
+    // rhs / mu1 = ((1 + mu3 a) n - mu3 A n) / mu1.
+    set_screening(c, 1.0 / mu1);
+    CK(apply_op(s, level_geo(c, 0, false), C0, (1.0 + mu3 * c->a) / mu1, -mu3 / mu1, n_dev, c->work));
+    if (flags & MG_GUESS) CK(copy_f64(s, n_dev, out_dev, n0));  // n as the first guess of y
+    rc = solve_impl(c, c->work, out_dev, flags, &S[0]);
+    if (rc >= 0) {
+        worst = rc;
+        // (I - mu2 L) n_new = y, as (1/mu2) n_new - div(D grad n_new) = y / mu2 (y is the guess)
+        set_screening(c, 1.0 / mu2);
+        rc = MG_OK;
+        hipError_t e = apply_op(s, level_geo(c, 0, false), C0, 1.0 / mu2, 0.0, out_dev, c->work);
+        if (e != hipSuccess) rc = set_err(MG_EDEVICE, "mg_tga_step: %s", hipGetErrorString(e));
+        if (rc == MG_OK) rc = solve_impl(c, c->work, out_dev, flags, &S[1]);
+        if (rc > worst) worst = rc;
+    }
+    set_screening(c, a_keep);
+    if (st) {
+        st[0] = S[0];
+        st[1] = S[1];
+    }
+    return rc < 0 ? rc : worst;
 }
 
 int mg_residual(mg_ctx *c, const double *f_dev, const double *x_dev, double *r_dev, double *rnorm,
@@ -753,6 +929,75 @@ int mg_smooth(mg_ctx *c, const double *f_dev, double *x_dev, int sweeps) {
     if (u != x_dev) CK(copy_f64(s, u, x_dev, c->L[0].n));
     CK(hipStreamSynchronize(s));
     return MG_OK;
+}
+
+int mg_smooth_level(mg_ctx *c, int l, int store, const double *b_dev, double *x_dev, int sweeps, int tile,
+                    int zchunk) {
+    if (!c || !b_dev || !x_dev) return set_err(MG_EINVAL, "mg_smooth_level: null argument");
+    if (!c->coeffs) return set_err(MG_EINVAL, "mg_smooth_level: mg_set_coeffs has not succeeded");
+    if (l < 0 || l >= c->nlev) return set_err(MG_EINVAL, "mg_smooth_level: level %d out of range", l);
+    if (store < MG_STORE_F64 || store > MG_STORE_BF16)
+        return set_err(MG_EINVAL, "mg_smooth_level: unknown storage type %d", store);
+    if (sweeps < 0 || tile < 0 || tile > MG_NUM_TILES || zchunk < 0)
+        return set_err(MG_EINVAL, "mg_smooth_level: bad sweeps, tile or zchunk");
+    const bool lowp = store != MG_STORE_F64;
+    const int st = store == MG_STORE_F64 ? ST_F64 : (store == MG_STORE_F32 ? ST_F32 : ST_BF16);
+    if (lowp && st != c->lp_store)
+        return set_err(MG_EINVAL, "mg_smooth_level: storage type %d needs a context of that refinement precision",
+                       store);
+    if (lowp && c->has_eps && l >= 1 && l >= c->tail)
+        return set_err(MG_EINVAL, "mg_smooth_level: level %d has no FP32 face coefficients (bottom levels)", l);
+    hipStream_t s = c->stream;
+    Level &L = c->L[l];
+    const size_t n = L.n;
+    // the finest FP64 equation carries the boundary values; every other
+    // (level, storage) pair is the homogeneous equation the cycles solve
+    const bool with_g = l == 0 && !lowp;
+    const Geo G = level_geo(c, l, with_g, lowp);
+    const Coef C = level_coef(c, l, lowp);
+    // coefficients stored multiplied by cscale (every coarse FP64 face of a
+    // mixed-precision context, every FP32 copy): scale the right-hand side alike
+    const double fac = (lowp || l >= 1) ? c->cscale : 1.0;
+    int zc;
+    int t = tile_for(c, G, st, C.mode, l, &zc);
+    if (tile > 0) t = tile;
+    if (zchunk > 0) zc = zchunk;
+    else if (tile > 0) zc = default_zchunk(G, t, st);
+    void *u, *w;
+    const void *b;
+    if (!lowp && l == 0) {
+        u = x_dev;
+        w = c->xalt;
+        if (fac != 1.0) return set_err(MG_EINVAL, "mg_smooth_level: internal scale mismatch");
+        b = b_dev;
+    } else {
+        u = lowp ? L.ul : (void *)L.u;
+        w = lowp ? L.tl : (void *)L.t;
+        void *bw = lowp ? L.bl : (void *)L.b;
+        CK(convert(s, x_dev, st, u, n, 1.0));
+        CK(convert(s, b_dev, st, bw, n, fac));
+        b = bw;
+    }
+    for (int q = 0; q < sweeps; ++q) {
+        CK(smooth(s, st, G, C, u, w, b, false, t, zc));
+        std::swap(u, w);
+    }
+    if (u != x_dev) CK(convert_back(s, u, st, x_dev, n, 1.0));
+    CK(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
+int mg_set_option(mg_ctx *c, int key, double value) {
+    if (!c) return set_err(MG_EINVAL, "mg_set_option: null context");
+    switch (key) {
+        case MG_OPT_CORRECTION_WEIGHT:
+            if (!(value > 0.0 && value <= 4.0))
+                return set_err(MG_EINVAL, "mg_set_option: the correction weight must be in (0, 4]");
+            c->corr_w = value;
+            c->version++;  // a cached batch plan holds the old weight
+            return MG_OK;
+    }
+    return set_err(MG_EINVAL, "mg_set_option: unknown option %d", key);
 }
 
 int mg_prolong_add(mg_ctx *c, int l, const double *e_dev, double *u_dev) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 
@@ -31,6 +32,7 @@ struct Geo {
     double ih2;     // 1 / h^2
     double a;
     double g[6];    // Dirichlet values (0 for correction equations)
+    double cw;      // weight of the coarse correction prolongated into this level (1 by default)
 };
 
 // Coefficient arrays of one level, in the level's storage type.
@@ -56,6 +58,26 @@ constexpr double kMaxCellCoef = 1e100;
 // 32-bit byte offsets from a per-plane base.
 constexpr long kMaxPlaneCells = 1L << 28;
 constexpr int kRedSlots = 8;
+// Result slots of the refinement pass's residual scales (powers of two):
+// [kSlotScale] the scale applied to the residual before its cast to the
+// inner storage type, [kSlotScale + 1] the scale of the rhs that produced
+// the correction being added (see ir_update_resid).
+constexpr int kSlotScale = 4;
+
+// Power-of-two scale for the low-precision copy of a residual whose sum of
+// squares over n cells is ss: 1 while the root-mean-square value lies in
+// [2^-40, 2^40] (FP32 and BF16 hold such values and the inner cycle's
+// intermediate sums with ample range), else 2^-e with e the binary exponent
+// of the root mean square, which brings it into [1/2, 1).  A power of two
+// leaves every rounding of the inner cycle unchanged.
+__host__ __device__ inline double cast_scale_rms(double rms) {
+    if (!(rms > 0.0) || !(rms < 1e300)) return 1.0;
+    int e;
+    (void)frexp(rms, &e);
+    if (e >= -40 && e <= 40) return 1.0;
+    return ldexp(1.0, -e);
+}
+__host__ __device__ inline double cast_scale(double ss, double n) { return cast_scale_rms(sqrt(ss / n)); }
 
 // Fused convergence test of a residual pass: reduce ||r||^2 into
 // ws.result[slot] (slot < 0: no norm), and set *done_out when it is
@@ -123,6 +145,10 @@ hipError_t norm2_resid(hipStream_t s, int st, const Geo &G, const Coef &C, const
                        const void *b, const RedWs &ws, int slot, int bslot,
                        const RrCheck *chk = nullptr);
 
+// y = alpha x + beta A x with zero boundary values (FP64).
+hipError_t apply_op(hipStream_t s, const Geo &G, const Coef &C, double alpha, double beta, const double *x,
+                    double *y);
+
 // Residual in FP64 written out: r = b - A u (all FP64).
 hipError_t resid_out(hipStream_t s, const Geo &G, const Coef &C, const double *u, const double *b,
                      double *r);
@@ -135,16 +161,30 @@ hipError_t resid_out(hipStream_t s, const Geo &G, const Coef &C, const double *u
 // convergence flag (skipped when done_in is set).
 hipError_t reduce2_final(hipStream_t s, const RedWs &ws, int slot, int bslot, int nb, int ref_slot, double rtol2,
                          int *done, const int *done_in);
+//
+// Scales (see cast_scale): the residual is stored as r * sc, where sc = sc0
+// if sc0 > 0, else ws.result[kSlotScale]; the inner cycle solves
+// (cs A) e' = sc r with its coefficients multiplied by the power of two cs,
+// so e is added as e * cs / ws.result[kSlotScale + 1].  The final sum then
+// moves the scale used into slot kSlotScale + 1 and stores
+// cast_scale(||r||^2, n) in slot kSlotScale for the next pass.
 hipError_t ir_update_resid(hipStream_t s, const Geo &G, const Coef &C, const double *x,
                            const void *e, double *xout, const double *b, int stl, void *r_lp,
-                           const RrCheck &chk);
+                           const RrCheck &chk, double sc0, double cs);
+// p[0..n) *= factor (FP64).
+hipError_t scale_f64(hipStream_t s, double *p, size_t n, double factor);
+// max and min of x[0..n) into ws.result[slot] and ws.result[slot + 1].
+hipError_t minmax(hipStream_t s, const double *x, size_t n, const RedWs &ws, int slot);
 
 // Setup kernels.
 hipError_t faces_from_cell(hipStream_t s, const Geo &G, const double *eps, double *bx, double *by,
                            double *bz);
 hipError_t coarsen_faces(hipStream_t s, const Geo &Gf, const double *fbx, const double *fby,
                          const double *fbz, const Geo &Gc, double *cbx, double *cby, double *cbz);
-hipError_t convert(hipStream_t s, const double *src, int st, void *dst, size_t n);
+// dst = src * factor rounded to the storage type st (round to nearest even).
+hipError_t convert(hipStream_t s, const double *src, int st, void *dst, size_t n, double factor = 1.0);
+// src (storage type st) to FP64: dst = src * factor.
+hipError_t convert_back(hipStream_t s, const void *src, int st, double *dst, size_t n, double factor = 1.0);
 // count of entries that are not finite or not > 0, into ws slot (as double)
 hipError_t count_bad(hipStream_t s, const double *x, size_t n, const RedWs &ws, int slot);
 hipError_t fill_zero(hipStream_t s, void *p, size_t bytes, const int *done = nullptr);

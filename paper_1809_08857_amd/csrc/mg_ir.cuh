@@ -6,24 +6,28 @@
 
 namespace mg {
 
-// xn = x + e (FP64 + low precision), r = b - A xn in FP64, r stored in the
-// low-precision type, ||r||^2 accumulated in FP64 (with bslot >= 0 also
-// ||b + boundary terms||^2) into the partials of ws slot `slot`, summed by
-// reduce2_final after the launch.  zero_x: x is taken as 0 (nothing is read)
-// and xout receives zeros.
+// xn = x + e * se_inv (FP64 + low precision), r = b - A xn in FP64, r * sc
+// stored in the low-precision type, ||r||^2 (and with bslot >= 0 also
+// ||b + boundary terms||^2) added to sr (sb).  zero_x: x is taken as 0
+// (nothing is read) and xout receives zeros.  se and sc are the powers of two
+// of the residual scaling (cast_scale): se undoes the scale of the
+// right-hand side that produced e, sc keeps the stored residual within the
+// range of the storage type.
 //
-// Block: a TX x TY tile of columns (one thread each) marching up a chunk of
-// z planes.  xn (and eps) of planes k-1, k, k+1 stay in the thread's
-// registers, loaded one step ahead of use; the in-plane neighbours of
-// plane k come from an LDS plane with a one-cell halo (two buffers by plane
-// parity, so one barrier per plane).  Edge threads also carry the halo cell
-// beyond their edge; neighbours outside the box are never read.
+// One call covers one tile: a TX x TY tile of columns (one thread each)
+// marching up a chunk of z planes.  xn (and eps) of planes k-1, k, k+1 stay
+// in the thread's registers, loaded one step ahead of use; the in-plane
+// neighbours of plane k come from an LDS plane with a one-cell halo (two
+// buffers by plane parity, so one barrier per plane).  Edge threads also
+// carry the halo cell beyond their edge; neighbours outside the box are
+// never read.  A workgroup that covers several tiles separates them by a
+// barrier (ir_tiles).
 template <class TL, int MODE, bool HAS_E, int TX, int TY>
 __device__ __forceinline__ void ir_col_body(const double *__restrict__ x, const TL *__restrict__ e,
                                             double *__restrict__ xout, const double *__restrict__ b,
                                             const double *__restrict__ eps, const Geo &G, TL *__restrict__ rl,
-                                            const RedWs &ws, int slot, int bslot, int cz, int tiles_x,
-                                            int tiles_y, int blk, bool zero_x) {
+                                            int bslot, int cz, int tiles_x, int tiles_y, int blk, bool zero_x,
+                                            double se_inv, double sc, double &sr, double &sb) {
     constexpr bool CELL = (MODE == COEF_CELL);
     __shared__ double su[2][TY + 2][TX + 2];
     __shared__ double se[CELL ? 2 : 1][CELL ? TY + 2 : 1][CELL ? TX + 2 : 1];
@@ -56,7 +60,7 @@ __device__ __forceinline__ void ir_col_body(const double *__restrict__ x, const 
         XR r{0.0, 0.0};
         if (!zero_x) {  // uniform
             r.x = x[at(c, k)];
-            if constexpr (HAS_E) r.e = (double)Num<TL>::ld(e[at(c, k)]);
+            if constexpr (HAS_E) r.e = (double)Num<TL>::ld(e[at(c, k)]) * se_inv;
         }
         return r;
     };
@@ -76,7 +80,6 @@ __device__ __forceinline__ void ir_col_body(const double *__restrict__ x, const 
     double hx0 = xval(hx, z0, ldx(colx, z0)), hy0 = xval(hy, z0, ldx(coly, z0));
     double ehx0 = eval(hx, z0, lde(colx, z0)), ehy0 = eval(hy, z0, lde(coly, z0));
     double b0 = b[at(col, z0)];
-    double sr = 0.0, sb = 0.0;
     for (int k = z0; k < z1; ++k) {
         // loads for the next step (raw)
         const XR uq = ldx(col, k + 2), hx1 = ldx(colx, k + 1), hy1 = ldx(coly, k + 1);
@@ -123,7 +126,7 @@ __device__ __forceinline__ void ir_col_body(const double *__restrict__ x, const 
             const size_t p = (size_t)k * plane + col;
             if (HAS_E || zero_x) xout[p] = u0;
             const double r = b0 - G.a * u0 - G.ih2 * (dg * u0 - off);
-            rl[p] = Num<TL>::cv(typename Num<TL>::C(r));
+            rl[p] = Num<TL>::cv(typename Num<TL>::C(r * sc));
             sr += r * r;
             if (bslot >= 0) {  // b plus the boundary terms of the Dirichlet faces the cell touches
                 const bool at[6] = {i == 0, i == nx - 1, j == 0, j == ny - 1, k == 0, k == nz - 1};
@@ -141,7 +144,43 @@ __device__ __forceinline__ void ir_col_body(const double *__restrict__ x, const 
         ehx0 = eval(hx, k + 1, ehx1), ehy0 = eval(hy, k + 1, ehy1);
         b0 = b1;
     }
-    reduce2_finish<TX * TY>(sr, sb, ws, slot, blk);
+}
+
+// The tiles [first, nblk) with stride `stride` of one refinement pass, run
+// by one workgroup, whose partial sums it stores in ws slot `slot` at
+// position `wg`; REMAP: tile t is tile xcd_remap(t, nblk) of the grid.  The
+// scales: the residual is stored times sc, where sc0 > 0 is the cast scale
+// of this pass (its first pass), else it is read from scl[0].  The inner
+// cycle solves (cs A) e' = sc r with its coefficients multiplied by cs, so
+// the correction is e = e' * cs / scl[1] (scl[1]: the sc of the pass that
+// produced e's right-hand side).
+template <class TL, int MODE, bool HAS_E, int TX, int TY, bool REMAP>
+__device__ __forceinline__ void ir_tiles(const double *__restrict__ x, const TL *__restrict__ e,
+                                         double *__restrict__ xout, const double *__restrict__ b,
+                                         const double *__restrict__ eps, const Geo &G, TL *__restrict__ rl,
+                                         const RedWs &ws, int slot, int bslot, int cz, int tiles_x, int tiles_y,
+                                         int first, int nblk, int stride, int wg, bool zero_x,
+                                         const double *__restrict__ scl, double sc0, double cs) {
+    const double sc = sc0 > 0.0 ? sc0 : scl[0];
+    const double se_inv = HAS_E ? cs / scl[1] : 1.0;  // powers of two: exact
+    double sr = 0.0, sb = 0.0;
+    for (int t = first; t < nblk; t += stride) {
+        if (t != first) lds_barrier();  // the previous tile's last plane is still being read
+        ir_col_body<TL, MODE, HAS_E, TX, TY>(x, e, xout, b, eps, G, rl, bslot, cz, tiles_x, tiles_y,
+                                             REMAP ? xcd_remap(t, nblk) : t, zero_x, se_inv, sc, sr, sb);
+    }
+    reduce2_finish<TX * TY>(sr, sb, ws, slot, wg);
+}
+
+// Final sum of a refinement pass (one workgroup): the norms and the
+// convergence flag as reduce2_final_body, then the scales of the next pass.
+__device__ __forceinline__ void ir_final_body(const RedWs &ws, int slot, int bslot, int nb, int ref_slot,
+                                              double rtol2, int *done, double *scl, double sc0, double n) {
+    reduce2_final_body(ws, slot, bslot, nb, ref_slot, rtol2, done);
+    if (threadIdx.x == 0) {
+        scl[1] = sc0 > 0.0 ? sc0 : scl[0];
+        scl[0] = cast_scale(ws.result[slot], n);
+    }
 }
 
 }  // namespace mg

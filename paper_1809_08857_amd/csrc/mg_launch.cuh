@@ -84,14 +84,15 @@ hipError_t rr_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, c
     cz += cz & 1;  // chunks hold whole coarse planes
     const int nblk = tiles_x * tiles_y * ((G.nz + cz - 1) / cz);
     constexpr int NTH = rr_threads<TX, TY>();
-    if (chk.slot >= 0 && nblk > kMaxRedBlocks) return hipErrorInvalidValue;
+    // a checked pass reduces one partial norm per workgroup: at most kMaxRedBlocks
+    const int nwg = (chk.slot >= 0 && nblk > kMaxRedBlocks) ? kMaxRedBlocks : nblk;
     RrArgs<T> A{static_cast<const T *>(u), static_cast<const T *>(b), eps, bx, by, bz, G,
                 static_cast<T *>(bc), cz, tiles_x, tiles_y, nblk, chk.ws, chk.slot, chk.ref_slot,
                 chk.rtol2, chk.done_out, chk.done_in};
-    hipLaunchKernelGGL((rr_col_k<T, MODE, TX, TY, kSmoothPDOf<T>>), dim3(nblk), dim3(NTH), 0, s, A);
+    hipLaunchKernelGGL((rr_col_k<T, MODE, TX, TY, kSmoothPDOf<T>>), dim3(nwg), dim3(NTH), 0, s, A);
     if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
     if (chk.slot >= 0)
-        return reduce2_final(s, chk.ws, chk.slot, -1, nblk, chk.ref_slot, chk.rtol2, chk.done_out, chk.done_in);
+        return reduce2_final(s, chk.ws, chk.slot, -1, nwg, chk.ref_slot, chk.rtol2, chk.done_out, chk.done_in);
     return hipGetLastError();
 }
 
@@ -146,24 +147,27 @@ hipError_t norm2_T(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, c
     dim3 grid, block;
     int kz;
     brick_shape(G.nx, G.ny, G.nz, kMaxRedBlocks, &grid, &block, &kz);
+    const int nbrick = (int)(grid.x * grid.y * grid.z);
+    const int nwg = nbrick < kMaxRedBlocks ? nbrick : kMaxRedBlocks;
     const T *uu = static_cast<const T *>(u), *bb = static_cast<const T *>(b);
+    const int gx = (int)grid.x, gy = (int)grid.y;
     switch (Cf.mode) {
         case COEF_CONST:
-            hipLaunchKernelGGL((norm2_resid_k<T, COEF_CONST>), grid, block, 0, s, uu, bb, eps,
-                               bx, by, bz, G, ws, slot, bslot, kz, din);
+            hipLaunchKernelGGL((norm2_resid_k<T, COEF_CONST>), dim3(nwg), block, 0, s, uu, bb, eps,
+                               bx, by, bz, G, ws, slot, bslot, kz, gx, gy, nbrick, din);
             break;
         case COEF_CELL:
-            hipLaunchKernelGGL((norm2_resid_k<T, COEF_CELL>), grid, block, 0, s, uu, bb, eps,
-                               bx, by, bz, G, ws, slot, bslot, kz, din);
+            hipLaunchKernelGGL((norm2_resid_k<T, COEF_CELL>), dim3(nwg), block, 0, s, uu, bb, eps,
+                               bx, by, bz, G, ws, slot, bslot, kz, gx, gy, nbrick, din);
             break;
         case COEF_FACE:
-            hipLaunchKernelGGL((norm2_resid_k<T, COEF_FACE>), grid, block, 0, s, uu, bb, eps,
-                               bx, by, bz, G, ws, slot, bslot, kz, din);
+            hipLaunchKernelGGL((norm2_resid_k<T, COEF_FACE>), dim3(nwg), block, 0, s, uu, bb, eps,
+                               bx, by, bz, G, ws, slot, bslot, kz, gx, gy, nbrick, din);
             break;
         default: return hipErrorInvalidValue;
     }
     if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
-    return reduce2_final(s, ws, slot, bslot, (int)(grid.x * grid.y * grid.z), ref, rt2, dout, din);
+    return reduce2_final(s, ws, slot, bslot, nwg, ref, rt2, dout, din);
 }
 
 }  // namespace mg

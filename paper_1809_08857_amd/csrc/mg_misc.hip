@@ -80,28 +80,40 @@ hipError_t reduce2_final(hipStream_t s, const RedWs &ws, int slot, int bslot, in
 // reference, and the residual of a zero iterate): one read of f per cell,
 // beta (cell coefficient, or 1) only on boundary cells.  Brick of kz
 // planes per block, loads of four planes in flight.
-template <bool CELL>
-__global__ __launch_bounds__(256) void norm2_b_k(const double *__restrict__ f, const double *__restrict__ eps, Geo G,
-                                                 RedWs ws, int slot, int kz) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k0 = blockIdx.z * kz;
-    const int k1 = min(k0 + kz, G.nz);
+template <int MODE>
+__global__ __launch_bounds__(256) void norm2_b_k(const double *__restrict__ f, const double *__restrict__ eps,
+                                                 const double *__restrict__ bx, const double *__restrict__ by,
+                                                 const double *__restrict__ bz, Geo G, RedWs ws, int slot, int kz,
+                                                 int gx, int gy, int nbrick) {
     double sb = 0.0;
-    if (i < G.nx && j < G.ny) {
+    // bricks blockIdx.x, blockIdx.x + gridDim.x, ... (one each unless there
+    // are more than kMaxRedBlocks)
+    for (int t = blockIdx.x; t < nbrick; t += gridDim.x) {
+        const int i = (t % gx) * blockDim.x + threadIdx.x;
+        const int j = ((t / gx) % gy) * blockDim.y + threadIdx.y;
+        const int k0 = (t / gx / gy) * kz;
+        const int k1 = min(k0 + kz, G.nz);
+        if (i >= G.nx || j >= G.ny) continue;
         const size_t plane = (size_t)G.nx * G.ny, col = (size_t)j * G.nx + i;
         const bool side = i == 0 || i == G.nx - 1 || j == 0 || j == G.ny - 1;
         // v = f at (i, j, k); the boundary part is added here
         auto term = [&](int k, double v) -> double {
             const size_t p = (size_t)k * plane + col;
             if (side || k == 0 || k == G.nz - 1) {
-                const double be = CELL ? eps[p] : 1.0;
+                const double be = MODE == COEF_CELL ? eps[p] : 1.0;
                 double add = 0.0;
 #pragma unroll
                 for (int d = 0; d < 6; ++d) {
                     const bool at = d == 0 ? i == 0 : d == 1 ? i == G.nx - 1 : d == 2 ? j == 0
                                   : d == 3 ? j == G.ny - 1 : d == 4 ? k == 0 : k == G.nz - 1;
-                    if (at && ((G.bcmask >> d) & 1)) add += 2.0 * be * G.g[d];
+                    if (at && ((G.bcmask >> d) & 1)) {
+                        double bf = be;  // the boundary face's coefficient
+                        if constexpr (MODE == COEF_FACE)
+                            bf = d == 0 ? face_x(bx, G, i, j, k) : d == 1 ? face_x(bx, G, i + 1, j, k)
+                               : d == 2 ? face_y(by, G, i, j, k) : d == 3 ? face_y(by, G, i, j + 1, k)
+                               : d == 4 ? face_z(bz, G, i, j, k) : face_z(bz, G, i, j, k + 1);
+                        add += 2.0 * bf * G.g[d];
+                    }
                 }
                 v += G.ih2 * add;
             }
@@ -117,23 +129,35 @@ __global__ __launch_bounds__(256) void norm2_b_k(const double *__restrict__ f, c
         }
         for (; k < k1; ++k) sb += term(k, f[(size_t)k * plane + col]);
     }
-    reduce2_finish<256>(0.0, sb, ws, slot, brick_id());
+    reduce2_finish<256>(0.0, sb, ws, slot, blockIdx.x);
 }
-
 hipError_t norm2_b(hipStream_t s, const Geo &G, const Coef &C, const double *f, const RedWs &ws, int slot) {
     dim3 grid, block;
     int kz;
     brick_shape(G.nx, G.ny, G.nz, kMaxRedBlocks, &grid, &block, &kz);
-    if (C.mode == COEF_CELL)
-        hipLaunchKernelGGL((norm2_b_k<true>), grid, block, 0, s, f, (const double *)C.eps, G, ws, slot, kz);
-    else if (C.mode == COEF_CONST)
-        hipLaunchKernelGGL((norm2_b_k<false>), grid, block, 0, s, f, nullptr, G, ws, slot, kz);
-    else
-        return hipErrorInvalidValue;
+    const int nbrick = (int)(grid.x * grid.y * grid.z);
+    const int nwg = nbrick < kMaxRedBlocks ? nbrick : kMaxRedBlocks;
+    const double *eps = (const double *)C.eps, *bx = (const double *)C.bx, *by = (const double *)C.by,
+                 *bz = (const double *)C.bz;
+    const int gx = (int)grid.x, gy = (int)grid.y;
+    switch (C.mode) {
+        case COEF_CONST:
+            hipLaunchKernelGGL((norm2_b_k<COEF_CONST>), dim3(nwg), block, 0, s, f, eps, bx, by, bz, G, ws, slot, kz,
+                               gx, gy, nbrick);
+            break;
+        case COEF_CELL:
+            hipLaunchKernelGGL((norm2_b_k<COEF_CELL>), dim3(nwg), block, 0, s, f, eps, bx, by, bz, G, ws, slot, kz,
+                               gx, gy, nbrick);
+            break;
+        case COEF_FACE:
+            hipLaunchKernelGGL((norm2_b_k<COEF_FACE>), dim3(nwg), block, 0, s, f, eps, bx, by, bz, G, ws, slot, kz,
+                               gx, gy, nbrick);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
-    return reduce2_final(s, ws, slot, slot, (int)(grid.x * grid.y * grid.z), -1, 0.0, nullptr, nullptr);
+    return reduce2_final(s, ws, slot, slot, nwg, -1, 0.0, nullptr, nullptr);
 }
-
 void tile_shape(int t, int *tx, int *ty) {
     static const int TX[kNumTiles + 1] = {0, 64, 128, 64, 32, 32, 16};
     static const int TY[kNumTiles + 1] = {0, 16, 8, 8, 8, 4, 8};
@@ -268,31 +292,120 @@ hipError_t coarsen_faces(hipStream_t s, const Geo &Gf, const double *fbx, const 
 }
 
 template <class T>
-__global__ void convert_k(const double *__restrict__ src, T *__restrict__ dst, size_t n) {
+__global__ void convert_k(const double *__restrict__ src, T *__restrict__ dst, size_t n, double factor) {
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (size_t)gridDim.x * blockDim.x)
-        dst[t] = Num<T>::cv(typename Num<T>::C(src[t]));
+        dst[t] = Num<T>::cv(typename Num<T>::C(src[t] * factor));
 }
-
-hipError_t convert(hipStream_t s, const double *src, int st, void *dst, size_t n) {
+template <class T>
+__global__ void convert_back_k(const T *__restrict__ src, double *__restrict__ dst, size_t n, double factor) {
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x)
+        dst[t] = (double)Num<T>::ld(src[t]) * factor;
+}
+static size_t grid_for(size_t n) {
     size_t g = (n + 255) / 256;
     if (g > 16384) g = 16384;
     if (g < 1) g = 1;
+    return g;
+}
+hipError_t convert(hipStream_t s, const double *src, int st, void *dst, size_t n, double factor) {
+    const size_t g = grid_for(n);
     switch (st) {
         case ST_F64:
-            hipLaunchKernelGGL(convert_k<double>, dim3(g), dim3(256), 0, s, src, (double *)dst, n);
+            hipLaunchKernelGGL(convert_k<double>, dim3(g), dim3(256), 0, s, src, (double *)dst, n, factor);
             break;
         case ST_F32:
-            hipLaunchKernelGGL(convert_k<float>, dim3(g), dim3(256), 0, s, src, (float *)dst, n);
+            hipLaunchKernelGGL(convert_k<float>, dim3(g), dim3(256), 0, s, src, (float *)dst, n, factor);
             break;
         case ST_BF16:
-            hipLaunchKernelGGL(convert_k<bf16>, dim3(g), dim3(256), 0, s, src, (bf16 *)dst, n);
+            hipLaunchKernelGGL(convert_k<bf16>, dim3(g), dim3(256), 0, s, src, (bf16 *)dst, n, factor);
             break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-
+hipError_t convert_back(hipStream_t s, const void *src, int st, double *dst, size_t n, double factor) {
+    const size_t g = grid_for(n);
+    switch (st) {
+        case ST_F64:
+            hipLaunchKernelGGL(convert_back_k<double>, dim3(g), dim3(256), 0, s, (const double *)src, dst, n, factor);
+            break;
+        case ST_F32:
+            hipLaunchKernelGGL(convert_back_k<float>, dim3(g), dim3(256), 0, s, (const float *)src, dst, n, factor);
+            break;
+        case ST_BF16:
+            hipLaunchKernelGGL(convert_back_k<bf16>, dim3(g), dim3(256), 0, s, (const bf16 *)src, dst, n, factor);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+__global__ void scale_f64_k(double *__restrict__ p, size_t n, double factor) {
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x)
+        p[t] *= factor;
+}
+hipError_t scale_f64(hipStream_t s, double *p, size_t n, double factor) {
+    hipLaunchKernelGGL(scale_f64_k, dim3(grid_for(n)), dim3(256), 0, s, p, n, factor);
+    return hipGetLastError();
+}
+// Largest and smallest entry: per-workgroup partials, then one workgroup.
+__global__ __launch_bounds__(256) void minmax_k(const double *__restrict__ x, size_t n, RedWs ws, int slot) {
+    __shared__ double sh[2][4];
+    double mx = -HUGE_VAL, mn = HUGE_VAL;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x) {
+        mx = fmax(mx, x[t]);
+        mn = fmin(mn, x[t]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = fmax(mx, __shfl_down(mx, o, 64));
+        mn = fmin(mn, __shfl_down(mn, o, 64));
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[0][w] = mx;
+        sh[1][w] = mn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < 4; ++q) {
+            mx = fmax(mx, sh[0][q]);
+            mn = fmin(mn, sh[1][q]);
+        }
+        double *part = ws.partials + (size_t)slot * kMaxRedBlocks * 2;
+        part[2 * blockIdx.x] = mx;
+        part[2 * blockIdx.x + 1] = mn;
+    }
+}
+__global__ __launch_bounds__(64) void minmax_final_k(RedWs ws, int slot, int nb) {
+    const double *part = ws.partials + (size_t)slot * kMaxRedBlocks * 2;
+    double mx = -HUGE_VAL, mn = HUGE_VAL;
+    for (int q = threadIdx.x; q < nb; q += 64) {
+        mx = fmax(mx, part[2 * q]);
+        mn = fmin(mn, part[2 * q + 1]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = fmax(mx, __shfl_down(mx, o, 64));
+        mn = fmin(mn, __shfl_down(mn, o, 64));
+    }
+    if (threadIdx.x == 0) {
+        ws.result[slot] = mx;
+        ws.result[slot + 1] = mn;
+    }
+}
+hipError_t minmax(hipStream_t s, const double *x, size_t n, const RedWs &ws, int slot) {
+    size_t g = (n + 255) / 256;
+    if (g > (size_t)kMaxRedBlocks) g = kMaxRedBlocks;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(minmax_k, dim3(g), dim3(256), 0, s, x, n, ws, slot);
+    if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
+    hipLaunchKernelGGL(minmax_final_k, dim3(1), dim3(64), 0, s, ws, slot, (int)g);
+    return hipGetLastError();
+}
 __global__ __launch_bounds__(256) void count_bad_k(const double *__restrict__ x, size_t n, RedWs ws,
                                                    int slot) {
     double c = 0.0;
@@ -390,38 +503,107 @@ hipError_t resid_out(hipStream_t s, const Geo &G, const Coef &C, const double *u
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ operator apply
+// y = alpha x + beta A x, zero boundary values, one thread per cell of a
+// brick column (kz planes).
+template <int MODE>
+__global__ __launch_bounds__(256) void apply_k(const double *__restrict__ x, const double *__restrict__ eps,
+                                               const double *__restrict__ bx, const double *__restrict__ by,
+                                               const double *__restrict__ bz, Geo G, double alpha, double beta,
+                                               double *__restrict__ y, int kz) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k0 = blockIdx.z * kz, k1 = min(k0 + kz, G.nz);
+    if (i >= G.nx || j >= G.ny) return;
+    const size_t sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
+    for (int k = k0; k < k1; ++k) {
+        const size_t p = (size_t)k * sz + (size_t)j * sy + i;
+        auto nb = [&](int d) -> size_t {
+            return d == 0 ? p - 1 : d == 1 ? p + 1 : d == 2 ? p - sy : d == 3 ? p + sy : d == 4 ? p - sz : p + sz;
+        };
+        const double eP = MODE == COEF_CELL ? eps[p] : 1.0;
+        double off, dg;
+        six_faces<double, MODE>(
+            G, i, j, k, eP, [&](int d) { return x[nb(d)]; }, [&](int d) { return eps[nb(d)]; },
+            [&](int d) {
+                switch (d) {
+                    case 0: return face_x(bx, G, i, j, k);
+                    case 1: return face_x(bx, G, i + 1, j, k);
+                    case 2: return face_y(by, G, i, j, k);
+                    case 3: return face_y(by, G, i, j + 1, k);
+                    case 4: return face_z(bz, G, i, j, k);
+                    default: return face_z(bz, G, i, j, k + 1);
+                }
+            },
+            off, dg);
+        const double xP = x[p];
+        const double ax = G.a * xP + G.ih2 * (dg * xP - off);
+        y[p] = alpha * xP + beta * ax;
+    }
+}
+hipError_t apply_op(hipStream_t s, const Geo &G0, const Coef &C, double alpha, double beta, const double *x,
+                    double *y) {
+    Geo G = G0;
+    for (int d = 0; d < 6; ++d) G.g[d] = 0.0;
+    dim3 grid, block;
+    int kz;
+    brick_shape(G.nx, G.ny, G.nz, 4096, &grid, &block, &kz);
+    const double *eps = (const double *)C.eps, *bx = (const double *)C.bx, *by = (const double *)C.by,
+                 *bz = (const double *)C.bz;
+    switch (C.mode) {
+        case COEF_CONST:
+            hipLaunchKernelGGL(apply_k<COEF_CONST>, grid, block, 0, s, x, eps, bx, by, bz, G, alpha, beta, y, kz);
+            break;
+        case COEF_CELL:
+            hipLaunchKernelGGL(apply_k<COEF_CELL>, grid, block, 0, s, x, eps, bx, by, bz, G, alpha, beta, y, kz);
+            break;
+        case COEF_FACE:
+            hipLaunchKernelGGL(apply_k<COEF_FACE>, grid, block, 0, s, x, eps, bx, by, bz, G, alpha, beta, y, kz);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ refinement
 template <class TL, int MODE, bool HAS_E, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void ir_col_k(const double *__restrict__ x, const TL *__restrict__ e,
                                                    double *__restrict__ xout, const double *__restrict__ b,
                                                    const double *__restrict__ eps, Geo G, TL *__restrict__ rl,
                                                    RedWs ws, int slot, int cz, int tiles_x, int tiles_y,
-                                                   int nblk, int ref_slot, double rtol2, int *__restrict__ done_out,
+                                                   int nblk, double sc0, double cs,
                                                    const int *__restrict__ done_in) {
     if (done_in && *done_in) return;
-    ir_col_body<TL, MODE, HAS_E, TX, TY>(x, e, xout, b, eps, G, rl, ws, slot, -1, cz, tiles_x, tiles_y,
-                                         xcd_remap(blockIdx.x, nblk), false);
+    ir_tiles<TL, MODE, HAS_E, TX, TY, true>(x, e, xout, b, eps, G, rl, ws, slot, -1, cz, tiles_x, tiles_y,
+                                            blockIdx.x, nblk, gridDim.x, xcd_remap(blockIdx.x, gridDim.x), false,
+                                            ws.result + kSlotScale, sc0, cs);
 }
-
+__global__ __launch_bounds__(kFinalThreads) void ir_final_k(RedWs ws, int slot, int nb, int ref_slot, double rtol2,
+                                                            int *done, const int *done_in, double sc0, double n) {
+    if (done_in && *done_in) return;
+    ir_final_body(ws, slot, -1, nb, ref_slot, rtol2, done, ws.result + kSlotScale, sc0, n);
+}
 template <class TL>
 static hipError_t ir_update_resid_T(hipStream_t s, const Geo &G, const Coef &C, const double *x,
                                     const void *e, double *xout, const double *b, void *r_lp,
-                                    const RrCheck &k) {
+                                    const RrCheck &k, double sc0, double cs) {
     constexpr int TX = 64, TY = 4;
     const int tiles_x = (G.nx + TX - 1) / TX, tiles_y = (G.ny + TY - 1) / TY;
+    // about kMaxRedBlocks tiles (z chunks of the column tiles); planes wider
+    // than that many column tiles make each workgroup cover several tiles
     int chunks = kMaxRedBlocks / (tiles_x * tiles_y);
     if (chunks < 1) chunks = 1;
     if (chunks > G.nz) chunks = G.nz;
     const int cz = (G.nz + chunks - 1) / chunks;
     chunks = (G.nz + cz - 1) / cz;
     const int nblk = tiles_x * tiles_y * chunks;
-    if (nblk > kMaxRedBlocks) return hipErrorInvalidValue;
+    const int nwg = nblk < kMaxRedBlocks ? nblk : kMaxRedBlocks;
     const double *eps = (const double *)C.eps;
     const TL *el = (const TL *)e;
     TL *rl = (TL *)r_lp;
 #define MG_IR_LAUNCH(MODE, HE)                                                                                   \
-    hipLaunchKernelGGL((ir_col_k<TL, MODE, HE, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, x, el, xout, b, eps, G, \
-                       rl, k.ws, k.slot, cz, tiles_x, tiles_y, nblk, k.ref_slot, k.rtol2, k.done_out, k.done_in)
+    hipLaunchKernelGGL((ir_col_k<TL, MODE, HE, TX, TY>), dim3(nwg), dim3(TX * TY), 0, s, x, el, xout, b, eps, G,  \
+                       rl, k.ws, k.slot, cz, tiles_x, tiles_y, nblk, sc0, cs, k.done_in)
     if (C.mode == COEF_CELL) {
         if (e) MG_IR_LAUNCH(COEF_CELL, true);
         else MG_IR_LAUNCH(COEF_CELL, false);
@@ -433,15 +615,16 @@ static hipError_t ir_update_resid_T(hipStream_t s, const Geo &G, const Coef &C, 
     }
 #undef MG_IR_LAUNCH
     if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
-    return reduce2_final(s, k.ws, k.slot, -1, nblk, k.ref_slot, k.rtol2, k.done_out, k.done_in);
+    hipLaunchKernelGGL(ir_final_k, dim3(1), dim3(kFinalThreads), 0, s, k.ws, k.slot, nwg, k.ref_slot, k.rtol2,
+                       k.done_out, k.done_in, sc0, (double)G.nx * G.ny * G.nz);
+    return hipGetLastError();
 }
-
 hipError_t ir_update_resid(hipStream_t s, const Geo &G, const Coef &C, const double *x,
                            const void *e, double *xout, const double *b, int stl, void *r_lp,
-                           const RrCheck &chk) {
+                           const RrCheck &chk, double sc0, double cs) {
     switch (stl) {
-        case ST_F32: return ir_update_resid_T<float>(s, G, C, x, e, xout, b, r_lp, chk);
-        case ST_BF16: return ir_update_resid_T<bf16>(s, G, C, x, e, xout, b, r_lp, chk);
+        case ST_F32: return ir_update_resid_T<float>(s, G, C, x, e, xout, b, r_lp, chk, sc0, cs);
+        case ST_BF16: return ir_update_resid_T<bf16>(s, G, C, x, e, xout, b, r_lp, chk, sc0, cs);
     }
     return hipErrorInvalidValue;
 }

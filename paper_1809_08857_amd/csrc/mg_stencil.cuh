@@ -1566,7 +1566,7 @@ template <int MODE, int TX, int TY> constexpr int rr_lds() {
 template <int TX, int TY> constexpr int rr_threads() { return (((TX + 4) / 2 * (TY + 2)) + 63) / 64 * 64; }
 
 template <class T, int MODE, int TX, int TY, int PD>
-__device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, typename Num<T>::C *smem) {
+__device__ __forceinline__ double rr_col_body(const RrArgs<T> &A, const int blk, typename Num<T>::C *smem) {
     using N = Num<T>;
     using C = typename N::C;
     constexpr int PXW = (TX + 4) / 2;  // pairs per region row (1-cell halo, pair aligned)
@@ -1842,15 +1842,22 @@ __device__ __forceinline__ void rr_col_body(const RrArgs<T> &A, const int blk, t
         if constexpr (R > 6) { if (kk + 6 >= z1) break; iter(std::integral_constant<int, 6>{}, kk + 6); }
         if constexpr (R > 7) { if (kk + 7 >= z1) break; iter(std::integral_constant<int, 7>{}, kk + 7); }
     }
-    if (A.slot >= 0)
-        reduce2_finish<NTP>(nrm, 0.0, A.ws, A.slot, blk);
+    return nrm;  // this thread's share of ||r||^2 (A.slot >= 0)
 }
 
+// One workgroup per tile, or, where a checked pass has more tiles than
+// kMaxRedBlocks, the tiles blockIdx.x, blockIdx.x + gridDim.x, ... with a
+// barrier between them; the squared norm is reduced per workgroup.
 template <class T, int MODE, int TX, int TY, int PD>
 __global__ __launch_bounds__((rr_threads<TX, TY>())) void rr_col_k(RrArgs<T> A) {
     if (A.done_in && *A.done_in) return;
     __shared__ typename Num<T>::C smem[rr_lds<MODE, TX, TY>()];
-    rr_col_body<T, MODE, TX, TY, PD>(A, xcd_remap(blockIdx.x, A.nblk), smem);
+    double nrm = 0.0;
+    for (int t = blockIdx.x; t < A.nblk; t += gridDim.x) {
+        if (t != (int)blockIdx.x) __syncthreads();  // LDS of the previous tile is still being read
+        nrm += rr_col_body<T, MODE, TX, TY, PD>(A, xcd_remap(t, A.nblk), smem);
+    }
+    if (A.slot >= 0) reduce2_finish<rr_threads<TX, TY>()>(nrm, 0.0, A.ws, A.slot, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 template <class T, class TC>
@@ -1885,14 +1892,16 @@ __device__ __forceinline__ void prolong_body(T *__restrict__ u, const TC *__rest
     const size_t p = ((size_t)k * G.ny + j) * G.nx + 2 * I;
     const C v0 = C(0.75) * mid + C(0.25) * lo;
     const C v1 = C(0.75) * mid + C(0.25) * hi;
+    // u += cw * (P e); cw = 1 adds the correction with one rounding as well
+    const C cw = C(G.cw);
     if ((G.nx & 1) == 0) {
         Pair<T> o = *reinterpret_cast<const Pair<T> *>(u + p);
-        o.v[0] = Num<T>::cv(Num<T>::ld(o.v[0]) + v0);
-        o.v[1] = Num<T>::cv(Num<T>::ld(o.v[1]) + v1);
+        o.v[0] = Num<T>::cv(fma_c<C>(cw, v0, Num<T>::ld(o.v[0])));
+        o.v[1] = Num<T>::cv(fma_c<C>(cw, v1, Num<T>::ld(o.v[1])));
         *reinterpret_cast<Pair<T> *>(u + p) = o;
     } else {
-        u[p] = Num<T>::cv(Num<T>::ld(u[p]) + v0);
-        if (2 * I + 1 < G.nx) u[p + 1] = Num<T>::cv(Num<T>::ld(u[p + 1]) + v1);
+        u[p] = Num<T>::cv(fma_c<C>(cw, v0, Num<T>::ld(u[p])));
+        if (2 * I + 1 < G.nx) u[p + 1] = Num<T>::cv(fma_c<C>(cw, v1, Num<T>::ld(u[p + 1])));
     }
 }
 
@@ -1936,6 +1945,7 @@ __global__ __launch_bounds__(BX *BY) void prolong_col_k(T *__restrict__ u, const
     const size_t cplane = (size_t)ncx * ncy;
     const size_t r1 = (size_t)J * ncx, r2 = (size_t)J2 * ncx;
     const C wy2 = C(0.25) * sy;
+    const C cw = C(G.cw);
 
     struct R3 { C m, c, p; };
     // coarse plane Kc combined across its two rows (and its ghost sign)
@@ -1962,8 +1972,9 @@ __global__ __launch_bounds__(BX *BY) void prolong_col_k(T *__restrict__ u, const
         const C v1 = fma_c<C>(C(0.75), cc, C(0.25) * cp);
         Pair<T> *q = reinterpret_cast<Pair<T> *>(urow + (size_t)k * fplane);
         Pair<T> w = *q;
-        w.v[0] = N::cv(N::ld(w.v[0]) + v0);
-        w.v[1] = N::cv(N::ld(w.v[1]) + v1);
+        // u += cw * (P e); cw = 1 adds the correction with one rounding as well
+        w.v[0] = N::cv(fma_c<C>(cw, v0, N::ld(w.v[0])));
+        w.v[1] = N::cv(fma_c<C>(cw, v1, N::ld(w.v[1])));
         *q = w;
     };
     const int K0 = k0 >> 1;
@@ -1977,23 +1988,27 @@ __global__ __launch_bounds__(BX *BY) void prolong_col_k(T *__restrict__ u, const
     }
 }
 
-// ||b - A u||^2 and (optionally) ||b + boundary terms||^2 (brick with kz planes).
+// ||b - A u||^2 and (optionally) ||b + boundary terms||^2 over bricks of
+// blockDim.x x blockDim.y cells and kz planes, gx x gy x gz of them; a
+// workgroup sums the bricks blockIdx.x, blockIdx.x + gridDim.x, ... (one
+// brick each unless the grid has more bricks than kMaxRedBlocks).
 template <class T, int MODE>
 __global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, const T *__restrict__ b,
                                                      const coef_t<T> *__restrict__ eps,
                                                      const coef_t<T> *__restrict__ bx,
                                                      const coef_t<T> *__restrict__ by,
                                                      const coef_t<T> *__restrict__ bz, Geo G, RedWs ws,
-                                                     int slot, int bslot, int kz,
+                                                     int slot, int bslot, int kz, int gx, int gy, int nbrick,
                                                      const int *__restrict__ done_in) {
     if (done_in && *done_in) return;
     using N = Num<T>;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k0 = blockIdx.z * kz;
-    const int k1 = min(k0 + kz, G.nz);
     double sr = 0.0, sb = 0.0;
-    if (i < G.nx && j < G.ny) {
+    for (int t = blockIdx.x; t < nbrick; t += gridDim.x) {
+        const int i = (t % gx) * blockDim.x + threadIdx.x;
+        const int j = ((t / gx) % gy) * blockDim.y + threadIdx.y;
+        const int k0 = (t / gx / gy) * kz;
+        const int k1 = min(k0 + kz, G.nz);
+        if (i >= G.nx || j >= G.ny) continue;
         for (int k = k0; k < k1; ++k) {
             const size_t p = ((size_t)k * G.ny + j) * G.nx + i;
             const double rv = (double)resid_global<T, MODE>(u, b, eps, bx, by, bz, G, i, j, k);
@@ -2029,7 +2044,7 @@ __global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, co
             }
         }
     }
-    reduce2_finish<256>(sr, sb, ws, slot, brick_id());
+    reduce2_finish<256>(sr, sb, ws, slot, blockIdx.x);
 }
 
 }  // namespace mg

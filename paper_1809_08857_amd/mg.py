@@ -21,6 +21,8 @@ MG_BC_DIRICHLET, MG_BC_NEUMANN = 0, 1
 MG_FP64, MG_FP32_IR, MG_BF16_IR = 0, 1, 2
 MG_GUESS = 1
 MG_NUM_TILES = 6
+MG_STORE_F64, MG_STORE_F32, MG_STORE_BF16 = 0, 1, 2
+MG_OPT_CORRECTION_WEIGHT = 1
 
 PRECISIONS = {"fp64": MG_FP64, "fp32": MG_FP32_IR, "bf16": MG_BF16_IR}
 
@@ -75,6 +77,11 @@ def load() -> ctypes.CDLL:
         "mg_residual": (I, [P, P, P, P, pD, pD]),
         "mg_smooth": (I, [P, P, P, I]),
         "mg_prolong_add": (I, [P, I, P, P]),
+        "mg_smooth_level": (I, [P, I, I, P, P, I, I, I]),
+        "mg_set_face_coeffs": (I, [P, P, P, P, D, ctypes.POINTER(MgBcs)]),
+        "mg_apply": (I, [P, D, D, P, P]),
+        "mg_tga_step": (I, [P, D, P, P, ctypes.c_uint, ctypes.POINTER(MgStats)]),
+        "mg_set_option": (I, [P, I, D]),
         "mg_num_levels": (I, [P]),
         "mg_level_dims": (I, [P, I, pI, pI, pI]),
         "mg_set_tiling": (I, [P, I, I]),
@@ -151,6 +158,20 @@ def mg_set_coeffs(ctx, eps, a: float, bcs: MgBcs) -> int:
     return _check(load().mg_set_coeffs(ctx, _ptr(eps), float(a), ctypes.byref(bcs)))
 
 
+def mg_set_face_coeffs(ctx, bx, by, bz, a: float, bcs: MgBcs) -> int:
+    return _check(load().mg_set_face_coeffs(ctx, _ptr(bx), _ptr(by), _ptr(bz), float(a), ctypes.byref(bcs)))
+
+
+def mg_apply(ctx, alpha: float, beta: float, x, y) -> int:
+    return _check(load().mg_apply(ctx, float(alpha), float(beta), _ptr(x), _ptr(y)))
+
+
+def mg_tga_step(ctx, dt: float, n, out, flags: int = 0) -> Tuple[int, List[MgStats]]:
+    st = (MgStats * 2)()
+    rc = _check(load().mg_tga_step(ctx, float(dt), _ptr(n), _ptr(out), flags, st))
+    return rc, list(st)
+
+
 def mg_solve(ctx, f, x, flags: int = 0) -> Tuple[int, MgStats]:
     st = MgStats()
     rc = _check(load().mg_solve(ctx, _ptr(f), _ptr(x), flags, ctypes.byref(st)))
@@ -180,6 +201,14 @@ def mg_residual(ctx, f, x, r=None) -> Tuple[float, float]:
 
 def mg_smooth(ctx, f, x, sweeps: int) -> int:
     return _check(load().mg_smooth(ctx, _ptr(f), _ptr(x), sweeps))
+
+
+def mg_smooth_level(ctx, l: int, store: int, b, x, sweeps: int, tile: int = 0, zchunk: int = 0) -> int:
+    return _check(load().mg_smooth_level(ctx, l, store, _ptr(b), _ptr(x), sweeps, tile, zchunk))
+
+
+def mg_set_option(ctx, key: int, value: float) -> int:
+    return _check(load().mg_set_option(ctx, key, float(value)))
 
 
 def mg_prolong_add(ctx, l: int, e, u) -> int:
@@ -227,12 +256,15 @@ def mg_timing_read(ctx) -> Tuple[int, float, str, float]:
 class Solver:
     """Owns one context: create + set_coeffs on construction, destroy on close."""
 
-    def __init__(self, nx, ny, nz, h, *, eps=None, a=0.0, bc_types=("N",) * 6, bc_values=(0.0,) * 6,
-                 stream=None, **desc_kw):
+    def __init__(self, nx, ny, nz, h, *, eps=None, faces=None, a=0.0, bc_types=("N",) * 6,
+                 bc_values=(0.0,) * 6, stream=None, **desc_kw):
         self.desc = mg_desc_default(nx, ny, nz, h, **desc_kw)
         self.ctx = mg_create(self.desc, stream)
         try:
-            mg_set_coeffs(self.ctx, eps, a, make_bcs(bc_types, bc_values))
+            if faces is not None:
+                mg_set_face_coeffs(self.ctx, *faces, a, make_bcs(bc_types, bc_values))
+            else:
+                mg_set_coeffs(self.ctx, eps, a, make_bcs(bc_types, bc_values))
         except Exception:
             mg_destroy(self.ctx)
             self.ctx = None
@@ -243,6 +275,9 @@ class Solver:
 
     def residual(self, f, x, r=None):
         return mg_residual(self.ctx, f, x, r)
+
+    def tga_step(self, dt, n, out, flags: int = 0):
+        return mg_tga_step(self.ctx, dt, n, out, flags)
 
     def close(self):
         if self.ctx is not None:

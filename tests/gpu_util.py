@@ -12,8 +12,9 @@ def dev(a):
 
 def make_solver(p, **desc_kw):
     eps = dev(p.eps) if p.eps is not None else None
-    return mg.Solver(p.nx, p.ny, p.nz, p.h, eps=eps, a=p.a, bc_types=p.bc_types(), bc_values=p.bc_values(),
-                     **desc_kw)
+    faces = tuple(dev(a) for a in p.faces) if getattr(p, "faces", None) is not None else None
+    return mg.Solver(p.nx, p.ny, p.nz, p.h, eps=eps, faces=faces, a=p.a, bc_types=p.bc_types(),
+                     bc_values=p.bc_values(), **desc_kw)
 
 
 def gpu_solve(p, x0=None, flags=0, **desc_kw):

@@ -38,3 +38,17 @@ def test_traffic_not_reported_for_other_grid_or_kernel():
     alg = float(kv["algorithmic_bytes_per_launch"])
     assert bench.measured_traffic(kv["kernel"], alg * 8) is None
     assert bench.measured_traffic("some other kernel", alg) is None
+
+
+def test_oracle_leg_runs_on_the_host():
+    """The CPU-baseline legs run in child processes that never touch the
+    GPU; at a tiny size both legs solve and report their core count."""
+    import json
+    import subprocess
+    for kind, threads in (("vcycle", "1"), ("cg", "2")):
+        env = dict(os.environ, OMP_NUM_THREADS=threads, MG_ORACLE_NATIVE="1")
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-leg", kind, "--n", "16"],
+                           env=env, capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr
+        leg = json.loads(r.stdout.strip().splitlines()[-1])
+        assert leg["cores"] == int(threads) and leg["rel_res"] <= 1e-10 and leg["value"] > 0

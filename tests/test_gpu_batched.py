@@ -93,3 +93,41 @@ def test_batched_guess_fallback_and_fp64_loop():
     finally:
         for s in solvers:
             s.close()
+
+
+def test_batched_config4_shape():
+    """The benchmark's batch shape: the first 16 instances of the seeded
+    draw of axes from {32, 48, 64, 96, 128} (it holds 96- and 128-cell axes),
+    four solves each (64 problems), FP32-in-FP64 refinement.  Every problem
+    matches its own single solve (to 1e-12 when both took the same number of
+    steps) and the oracle's solution, continued from the batched answer to
+    relative residual 1e-13, to 1e-9."""
+    dims = synth.batch_dims()[:16]
+    probs = []
+    for j, (nx, ny, nz) in enumerate(dims):
+        probs += synth.streamer_set(int(nx), int(ny), int(nz), seed=1000 + j)
+    print("batch of", len(probs), "problems", flush=True)
+    solvers = [make_solver(p, precision="fp32", rtol=_rtol(p)) for p in probs]
+    try:
+        fs = [dev(p.f) for p in probs]
+        xs = [torch.zeros(p.shape, dtype=torch.float64, device="cuda") for p in probs]
+        rc, stats = mg.mg_solve_batched([s.ctx for s in solvers], fs, xs)
+        torch.cuda.synchronize()
+        assert rc == mg.MG_OK
+        worst = 0.0
+        for p, s, f, x, st in zip(probs, solvers, fs, xs, stats):
+            x_b = x.cpu().numpy()
+            xsng = torch.zeros(p.shape, dtype=torch.float64, device="cuda")
+            rc1, st1 = s.solve(f, xsng)
+            assert rc1 == mg.MG_OK and st.rel_res <= _rtol(p)
+            if st.cycles == st1.cycles:
+                assert rel_l2(x_b, xsng.cpu().numpy()) <= 1e-12, p.name
+            ref, ocyc, orel = oracle.solve_vcycle(p, rtol=1e-13, max_cycles=40, u0=x_b)
+            assert orel <= 1e-13
+            err = rel_l2(x_b, ref)
+            worst = max(worst, err)
+            assert err <= 1e-9, (p.name, err)
+        print(f"worst error vs oracle {worst:.2e}", flush=True)
+    finally:
+        for s in solvers:
+            s.close()
