@@ -319,6 +319,33 @@ int mg_timing(mg_ctx *c, int enable);
  * *kernel (may be NULL) receives a static description of the kernel. */
 int mg_timing_read(const mg_ctx *c, long *launches, double *ms, double *bytes, const char **kernel);
 
+/* ------------------------------------------------------------------ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * ------------------------------------------------------------------ */
+
+/* Bytes of the library's file-scope device array that holds the partial
+ * sums of mg_residual_noalloc's reductions (one copy per GPU, kept until the
+ * process ends): 2048 workgroup pairs plus 8 result slots. */
+#define MG_NOALLOC_SCRATCH_BYTES 32832
+
+/* mg_residual without a context and without allocating: r_dev = b - A x and
+ * the norms ||b - A x||_2, ||b||_2 (b = f + boundary terms), for the grid of
+ * d (only nx, ny, nz and h are read), the cell coefficient eps_dev (NULL = 1;
+ * its entries must lie in (0, 1e100], checked on the device), a and bc as in
+ * mg_set_coeffs.  f_dev, x_dev, r_dev as in mg_residual (r_dev may be NULL);
+ * rnorm, bnorm host pointers (either may be NULL).  hip_stream: the stream
+ * (NULL = default) whose device is the current device.  Calls no hipMalloc
+ * or hipFree and keeps no pointer.  Grid limits and errors as in mg_create
+ * and mg_set_coeffs; the scratch of MG_NOALLOC_SCRATCH_BYTES serves every
+ * grid size (each reduction uses at most 2048 workgroups).  All calls on one
+ * GPU share its scratch array: calls that overlap in time on the same GPU
+ * (two host threads, or two streams) race and must be serialised by the
+ * caller.  It synchronises the stream before it returns. */
+int mg_residual_noalloc(const mg_desc *d, const double *eps_dev, double a, const mg_bcs *bc,
+                        const double *f_dev, const double *x_dev, double *r_dev, double *rnorm,
+                        double *bnorm, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

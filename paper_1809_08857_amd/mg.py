@@ -81,6 +81,7 @@ def load() -> ctypes.CDLL:
         "mg_set_face_coeffs": (I, [P, P, P, P, D, ctypes.POINTER(MgBcs)]),
         "mg_apply": (I, [P, D, D, P, P]),
         "mg_tga_step": (I, [P, D, P, P, ctypes.c_uint, ctypes.POINTER(MgStats)]),
+        "mg_residual_noalloc": (I, [ctypes.POINTER(MgDesc), P, D, ctypes.POINTER(MgBcs), P, P, P, pD, pD, P]),
         "mg_set_option": (I, [P, I, D]),
         "mg_num_levels": (I, [P]),
         "mg_level_dims": (I, [P, I, pI, pI, pI]),
@@ -196,6 +197,13 @@ def mg_destroy(ctx) -> int:
 def mg_residual(ctx, f, x, r=None) -> Tuple[float, float]:
     rn, bn = ctypes.c_double(), ctypes.c_double()
     _check(load().mg_residual(ctx, _ptr(f), _ptr(x), _ptr(r), ctypes.byref(rn), ctypes.byref(bn)))
+    return rn.value, bn.value
+
+
+def mg_residual_noalloc(desc: MgDesc, eps, a: float, bcs: MgBcs, f, x, r=None, stream=None) -> Tuple[float, float]:
+    rn, bn = ctypes.c_double(), ctypes.c_double()
+    _check(load().mg_residual_noalloc(ctypes.byref(desc), _ptr(eps), float(a), ctypes.byref(bcs), _ptr(f), _ptr(x),
+                                      _ptr(r), ctypes.byref(rn), ctypes.byref(bn), _stream_handle(stream)))
     return rn.value, bn.value
 
 
