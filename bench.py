@@ -21,6 +21,12 @@ Other workloads (--workload):
              guess (U-net inference included) against the zero guess
   tga256     implicit (TGA) diffusion advances at 256^3 with face diffusion
              coefficients: two Helmholtz solves per step (value: solves/s)
+  multirate  an advancing streamer (tip 2 cells further per coarse step):
+             the four solves re-run each coarse step from the previous
+             step's solutions against a zero start (and, at --n 128, the
+             photon groups from the learned guess), with the relaxation
+             time and the multirate schedule of each step (--steps = coarse
+             steps)
 
 The default run also reports "forms": the mixed-precision, batched and
 learned-guess forms each against the plain FP64 V-cycle on its own
@@ -58,7 +64,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="streamer256",
-                    choices=["streamer256", "mixed512", "batched64", "learned128", "tga256", "copycal"])
+                    choices=["streamer256", "mixed512", "batched64", "learned128", "tga256", "multirate",
+                             "copycal"])
     ap.add_argument("--no-forms", action="store_true", help="skip the forms comparison of the default run")
     ap.add_argument("--oracle-leg", default=None, choices=["vcycle", "cg"],
                     help="(internal) time one CPU oracle leg in this process and print it")
@@ -505,6 +512,97 @@ def tga_line(args):
     return base_line(args, value, dt_run / args.steps * 1e3, cfg, "f64", roof, value * n**3)
 
 
+def multirate_line(args):
+    """Warm starts and the multirate schedule on an advancing streamer at
+    n^3 (Sec. 2.2): in coarse step k the filament's tip has moved 2k cells
+    towards z = 0.  Every coarse step re-solves the four equations of the
+    field update (potential + 3 photon groups) to the headline tolerances,
+    once from zero and once from the previous coarse step's solutions
+    (MG_GUESS, screened as usual); with the trained network at 128^3 the
+    photon groups are also solved from the learned guess (inference
+    included).  After each potential solve the field kernel gives max|E|,
+    max|J| (sigma = the filament density) and dt_E, and the schedule the
+    number m of fine advective steps (CFL 0.5 for v = mu |E|, mu = 1) that
+    fit in alpha dt_E (alpha = 1) before the next field update."""
+    import numpy as np
+    import torch
+    import synth
+    from synth.problems import filament_source
+    from paper_1809_08857_amd import mg
+    n = args.n or 256
+    K = max(2, args.steps)
+    h = 1.0 / n
+    probs = synth.streamer_set(n, seed=args.seed)
+    solvers = make_solvers(probs, "fp64")
+    srcs = [torch.from_numpy(filament_source(n, n, n, args.seed, tip_shift=2 * k * h)).cuda() for k in range(K + 1)]
+    prev = [torch.zeros((n, n, n), dtype=torch.float64, device="cuda") for _ in probs]
+    xs = [torch.zeros((n, n, n), dtype=torch.float64, device="cuda") for _ in probs]
+    for q, sv in enumerate(solvers):  # step 0 from zero: the state the warm chain starts from
+        rc, _ = sv.solve(srcs[0], prev[q])
+        assert rc == mg.MG_OK
+    net = None
+    wpath = os.path.join(os.path.dirname(mg.__file__), "weights", f"unet{n}.mglw")
+    if os.path.exists(wpath):
+        from paper_1809_08857_amd import learned as L
+        net = L.mgl_create(n, n, n)
+        L.mgl_load(net, wpath)
+        k2 = tuple(p.a for p in probs[1:])
+
+    def run(mode):
+        cyc, sched = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(1, K + 1):
+            row = []
+            if mode == "learned":
+                L.mgl_predict(net, srcs[k], k2, xs[1:])
+            for q, sv in enumerate(solvers):
+                if mode == "warm" or (mode == "learned" and q == 0):
+                    xs[q].copy_(prev[q])
+                    rc, st = sv.solve(srcs[k], xs[q], mg.MG_GUESS)
+                elif mode == "learned":
+                    rc, st = sv.solve(srcs[k], xs[q], mg.MG_GUESS)
+                else:
+                    rc, st = sv.solve(srcs[k], xs[q])
+                if rc != mg.MG_OK:
+                    raise RuntimeError(f"{mode} solve failed at step {k}: {st.as_dict()}")
+                row.append(st.cycles)
+            if mode != "cold":
+                emax, jmax, dte = mg.mg_field(solvers[0].ctx, xs[0], srcs[k])
+                dtf = 0.5 * h / emax
+                sched.append({"dt_E": dte, "dt_fine": dtf, "m": mg.mg_relaxation_substeps(dtf, dte, 1.0)})
+                for q in range(len(xs)):
+                    prev[q].copy_(xs[q])
+            cyc.append(row)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, cyc, sched
+
+    t_cold, c_cold, _ = run("cold")
+    t_warm, c_warm, sched = run("warm")
+    learned = None
+    if net is not None:
+        for q, sv in enumerate(solvers):  # restart the chain for the learned pass
+            prev[q].zero_()
+            sv.solve(srcs[0], prev[q])
+        t_l, c_l, _ = run("learned")
+        learned = {"solves_per_s": round(4 * K / t_l, 3),
+                   "cycles_per_solve": [round(float(c), 2) for c in np.mean(c_l, axis=0)],
+                   "note": "potential warm-started, photon groups from the learned guess (inference included)"}
+        L.mgl_destroy(net)
+    for sv in solvers:
+        sv.close()
+    nsol = 4 * K
+    cfg = {"workload": f"advancing streamer at {n}^3: {K} coarse steps, tip 2 cells further each step; "
+                       f"potential + 3 photon groups re-solved each step from the previous step's solutions",
+           "grid": [n, n, n], "solves_per_step": 4, "coarse_steps": K,
+           "zero_start_solves_per_s": round(nsol / t_cold, 3),
+           "speedup_vs_zero_start": round(t_cold / t_warm, 3),
+           "cycles_per_solve_zero_start": [round(float(c), 2) for c in np.mean(c_cold, axis=0)],
+           "cycles_per_solve_warm": [round(float(c), 2) for c in np.mean(c_warm, axis=0)],
+           "schedule": sched, "learned_guess": learned}
+    return base_line(args, nsol / t_warm, t_warm / K * 1e3, cfg, "f64", None, nsol / t_warm * n**3)
+
+
 def forms(args):
     """The three forms against the plain FP64 V-cycle, each on its own
     workload, in a few short steps: mixed precision at 512^3 (four solves per
@@ -592,6 +690,8 @@ def main():
         out = base_line(args, value, ms, cfg, f"f64+{prec}", None, value / cfg["solves_per_step"] * cells)
     elif args.workload == "tga256":
         out = tga_line(args)
+    elif args.workload == "multirate":
+        out = multirate_line(args)
     elif args.workload == "copycal":
         out = copy_calibration(args)
     else:

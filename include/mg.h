@@ -248,6 +248,32 @@ int mg_residual(mg_ctx *c, const double *f_dev, const double *x_dev, double *r_d
  * (ii)-(iii)); x and y distinct FP64 device arrays of nx*ny*nz values. */
 int mg_apply(mg_ctx *c, double alpha, double beta, const double *x_dev, double *y_dev);
 
+/* The electric field and the dielectric relaxation time of the multirate
+ * scheme (Sec. 2.2; the time-step table's dt_E = eps0 |E| / |J|): with the
+ * potential phi_dev of this context's grid and boundary conditions (the
+ * solution of an mg_solve of the potential),
+ *     E = -grad(phi)  at the cell centres, by central differences over two
+ *                     cells, with the discretisation's ghost values beyond
+ *                     the box (2g - phi beyond a Dirichlet face of value g,
+ *                     phi beyond a Neumann face),
+ *     J = sigma E     the drift current of the cell conductivity sigma_dev
+ *                     (sigma = e mu_e n_e for electrons; NULL: no current),
+ *     *emax = max |E|, *jmax = max |J| over the grid,
+ *     *dt_e = eps0 * max|E| / max|J| (infinity where there is no current),
+ * the largest values over the grid giving one step size for the domain.
+ * ex_dev, ey_dev, ez_dev (nx*ny*nz FP64 each, any may be NULL) receive the
+ * components of E; emax, jmax, dt_e are host pointers (any may be NULL).
+ * eps0 > 0 in the units of the potential equation (1 where eps0 is folded
+ * into the source, as in mg_set_coeffs). */
+int mg_field(mg_ctx *c, const double *phi_dev, const double *sigma_dev, double eps0, double *ex_dev,
+             double *ey_dev, double *ez_dev, double *emax, double *jmax, double *dt_e);
+
+/* The multirate schedule of Sec. 2.2: the elliptic equations are re-solved
+ * once per coarse step dt_c = m dt_fine with m the largest integer such that
+ * dt_c <= alpha dt_e (at least 1): the advective-reactive part takes m fine
+ * steps between two field updates.  *m receives m (capped at 1e9). */
+int mg_relaxation_substeps(double dt_fine, double dt_e, double alpha, int *m);
+
 /* Apply `sweeps` red-black Gauss-Seidel sweeps (red = (i+j+k) even first,
  * then black) of the finest-level equation to x_dev in place, FP64. */
 int mg_smooth(mg_ctx *c, const double *f_dev, double *x_dev, int sweeps);

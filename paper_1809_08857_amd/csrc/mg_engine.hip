@@ -896,6 +896,30 @@ int mg_tga_step(mg_ctx *c, double dt, const double *n_dev, double *out_dev, unsi
     return rc < 0 ? rc : worst;
 }
 
+int mg_field(mg_ctx *c, const double *phi_dev, const double *sigma_dev, double eps0, double *ex_dev,
+             double *ey_dev, double *ez_dev, double *emax, double *jmax, double *dt_e) {
+    if (!c || !phi_dev) return set_err(MG_EINVAL, "mg_field: null argument");
+    if (!c->coeffs) return set_err(MG_EINVAL, "mg_field: mg_set_coeffs has not succeeded");
+    if (!(eps0 > 0.0) || !std::isfinite(eps0)) return set_err(MG_EINVAL, "mg_field: eps0 must be finite and > 0");
+    CK(field(c->stream, level_geo(c, 0, true), c->L[0].h, phi_dev, sigma_dev, ex_dev, ey_dev, ez_dev, c->ws, 2));
+    int rc = read_results(c, 4);
+    if (rc) return rc;
+    const double me = c->h_pin[2], mj = c->h_pin[3];
+    if (emax) *emax = me;
+    if (jmax) *jmax = mj;
+    if (dt_e) *dt_e = mj > 0.0 ? eps0 * me / mj : HUGE_VAL;
+    return MG_OK;
+}
+
+int mg_relaxation_substeps(double dt_fine, double dt_e, double alpha, int *m) {
+    if (!m) return set_err(MG_EINVAL, "mg_relaxation_substeps: null argument");
+    if (!(dt_fine > 0.0) || !(dt_e > 0.0) || !(alpha > 0.0) || !std::isfinite(dt_fine) || !std::isfinite(alpha))
+        return set_err(MG_EINVAL, "mg_relaxation_substeps: dt_fine, dt_e and alpha must be > 0");
+    const double q = alpha * dt_e / dt_fine;  // dt_e may be infinite (no current): one coarse step of the cap
+    *m = q >= 1e9 ? 1000000000 : (q < 1.0 ? 1 : (int)std::floor(q));
+    return MG_OK;
+}
+
 int mg_residual(mg_ctx *c, const double *f_dev, const double *x_dev, double *r_dev, double *rnorm,
                 double *bnorm) {
     if (!c || !f_dev || !x_dev) return set_err(MG_EINVAL, "mg_residual: null argument");

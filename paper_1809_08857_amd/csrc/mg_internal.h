@@ -149,6 +149,13 @@ hipError_t norm2_resid(hipStream_t s, int st, const Geo &G, const Coef &C, const
 hipError_t apply_op(hipStream_t s, const Geo &G, const Coef &C, double alpha, double beta, const double *x,
                     double *y);
 
+// E = -grad(phi) at the cell centres (central differences over two cells,
+// ghost values 2g - phi beyond Dirichlet faces and phi beyond Neumann
+// faces); any of ex, ey, ez may be null (not written).  ws.result[slot] =
+// max |E| and ws.result[slot + 1] = max sigma |E| (0 without sigma).
+hipError_t field(hipStream_t s, const Geo &G, double h, const double *phi, const double *sigma, double *ex,
+                 double *ey, double *ez, const RedWs &ws, int slot);
+
 // Residual in FP64 written out: r = b - A u (all FP64).
 hipError_t resid_out(hipStream_t s, const Geo &G, const Coef &C, const double *u, const double *b,
                      double *r);

@@ -565,6 +565,94 @@ hipError_t apply_op(hipStream_t s, const Geo &G0, const Coef &C, double alpha, d
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ field
+// E = -grad(phi) by central differences, |E| and sigma |E| maximised per
+// workgroup (partials of ws slot `slot`, then field_final_k).  Bricks as
+// norm2_b_k.
+__global__ __launch_bounds__(256) void field_k(const double *__restrict__ phi, const double *__restrict__ sigma,
+                                               Geo G, double inv2h, double *__restrict__ ex,
+                                               double *__restrict__ ey, double *__restrict__ ez, RedWs ws,
+                                               int slot, int kz, int gx, int gy, int nbrick) {
+    double me = 0.0, mj = 0.0;
+    const size_t sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
+    for (int t = blockIdx.x; t < nbrick; t += gridDim.x) {
+        const int i = (t % gx) * blockDim.x + threadIdx.x;
+        const int j = ((t / gx) % gy) * blockDim.y + threadIdx.y;
+        const int k0 = (t / gx / gy) * kz, k1 = min(k0 + kz, G.nz);
+        if (i >= G.nx || j >= G.ny) continue;
+        for (int k = k0; k < k1; ++k) {
+            const size_t p = (size_t)k * sz + (size_t)j * sy + i;
+            const double u = phi[p];
+            // neighbour or ghost value in direction d
+            auto nb = [&](int d, bool in, size_t q) -> double {
+                if (in) return phi[q];
+                return ((G.bcmask >> d) & 1) ? 2.0 * G.g[d] - u : u;
+            };
+            const double xm = nb(0, i > 0, p - 1), xp = nb(1, i < G.nx - 1, p + 1);
+            const double ym = nb(2, j > 0, p - sy), yp = nb(3, j < G.ny - 1, p + sy);
+            const double zm = nb(4, k > 0, p - sz), zp = nb(5, k < G.nz - 1, p + sz);
+            const double fx = (xm - xp) * inv2h, fy = (ym - yp) * inv2h, fz = (zm - zp) * inv2h;
+            if (ex) ex[p] = fx;
+            if (ey) ey[p] = fy;
+            if (ez) ez[p] = fz;
+            const double e = sqrt(fx * fx + fy * fy + fz * fz);
+            me = fmax(me, e);
+            if (sigma) mj = fmax(mj, sigma[p] * e);
+        }
+    }
+    __shared__ double sh[2][4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        me = fmax(me, __shfl_down(me, o, 64));
+        mj = fmax(mj, __shfl_down(mj, o, 64));
+    }
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y, lane = tid & 63, w = tid >> 6;
+    if (lane == 0) {
+        sh[0][w] = me;
+        sh[1][w] = mj;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int q = 1; q < 4; ++q) {
+            me = fmax(me, sh[0][q]);
+            mj = fmax(mj, sh[1][q]);
+        }
+        double *part = ws.partials + (size_t)slot * kMaxRedBlocks * 2;
+        part[2 * blockIdx.x] = me;
+        part[2 * blockIdx.x + 1] = mj;
+    }
+}
+__global__ __launch_bounds__(64) void field_final_k(RedWs ws, int slot, int nb) {
+    const double *part = ws.partials + (size_t)slot * kMaxRedBlocks * 2;
+    double me = 0.0, mj = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 64) {
+        me = fmax(me, part[2 * q]);
+        mj = fmax(mj, part[2 * q + 1]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        me = fmax(me, __shfl_down(me, o, 64));
+        mj = fmax(mj, __shfl_down(mj, o, 64));
+    }
+    if (threadIdx.x == 0) {
+        ws.result[slot] = me;
+        ws.result[slot + 1] = mj;
+    }
+}
+hipError_t field(hipStream_t s, const Geo &G, double h, const double *phi, const double *sigma, double *ex,
+                 double *ey, double *ez, const RedWs &ws, int slot) {
+    dim3 grid, block;
+    int kz;
+    brick_shape(G.nx, G.ny, G.nz, kMaxRedBlocks, &grid, &block, &kz);
+    const int nbrick = (int)(grid.x * grid.y * grid.z);
+    const int nwg = nbrick < kMaxRedBlocks ? nbrick : kMaxRedBlocks;
+    hipLaunchKernelGGL(field_k, dim3(nwg), block, 0, s, phi, sigma, G, 0.5 / h, ex, ey, ez, ws, slot, kz,
+                       (int)grid.x, (int)grid.y, nbrick);
+    if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
+    hipLaunchKernelGGL(field_final_k, dim3(1), dim3(64), 0, s, ws, slot, nwg);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ refinement
 template <class TL, int MODE, bool HAS_E, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void ir_col_k(const double *__restrict__ x, const TL *__restrict__ e,

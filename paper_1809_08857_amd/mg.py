@@ -80,6 +80,8 @@ def load() -> ctypes.CDLL:
         "mg_smooth_level": (I, [P, I, I, P, P, I, I, I]),
         "mg_set_face_coeffs": (I, [P, P, P, P, D, ctypes.POINTER(MgBcs)]),
         "mg_apply": (I, [P, D, D, P, P]),
+        "mg_field": (I, [P, P, P, D, P, P, P, pD, pD, pD]),
+        "mg_relaxation_substeps": (I, [D, D, D, pI]),
         "mg_tga_step": (I, [P, D, P, P, ctypes.c_uint, ctypes.POINTER(MgStats)]),
         "mg_residual_noalloc": (I, [ctypes.POINTER(MgDesc), P, D, ctypes.POINTER(MgBcs), P, P, P, pD, pD, P]),
         "mg_set_option": (I, [P, I, D]),
@@ -161,6 +163,20 @@ def mg_set_coeffs(ctx, eps, a: float, bcs: MgBcs) -> int:
 
 def mg_set_face_coeffs(ctx, bx, by, bz, a: float, bcs: MgBcs) -> int:
     return _check(load().mg_set_face_coeffs(ctx, _ptr(bx), _ptr(by), _ptr(bz), float(a), ctypes.byref(bcs)))
+
+
+def mg_field(ctx, phi, sigma=None, eps0: float = 1.0, ex=None, ey=None, ez=None) -> Tuple[float, float, float]:
+    """(max |E|, max |J|, dt_E); E components written to ex, ey, ez if given."""
+    me, mj, dte = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load().mg_field(ctx, _ptr(phi), _ptr(sigma), float(eps0), _ptr(ex), _ptr(ey), _ptr(ez), ctypes.byref(me),
+                           ctypes.byref(mj), ctypes.byref(dte)))
+    return me.value, mj.value, dte.value
+
+
+def mg_relaxation_substeps(dt_fine: float, dt_e: float, alpha: float) -> int:
+    m = ctypes.c_int()
+    _check(load().mg_relaxation_substeps(float(dt_fine), float(dt_e), float(alpha), ctypes.byref(m)))
+    return m.value
 
 
 def mg_apply(ctx, alpha: float, beta: float, x, y) -> int:

@@ -113,7 +113,7 @@ def manufactured_poisson(nx: int = 32, ny: Optional[int] = None, nz: Optional[in
     return Problem(nx, ny, nz, h, 0.0, np.ascontiguousarray(f), None, POISSON_BC, f"manufactured_{nx}x{ny}x{nz}")
 
 
-def filament_source(nx: int, ny: int, nz: int, seed: int) -> np.ndarray:
+def filament_source(nx: int, ny: int, nz: int, seed: int, tip_shift: float = 0.0) -> np.ndarray:
     """Seeded streamer-like space charge rho on an nx*ny*nz grid, h = 1/nz.
 
     A Gaussian column of radius 6 cells on the x-y centre of the box runs
@@ -121,10 +121,12 @@ def filament_source(nx: int, ny: int, nz: int, seed: int) -> np.ndarray:
     over 2 cells, the tip carries a head of amplitude 1e3 and width 2 cells,
     and the whole field is multiplied by mean-one lognormal noise (sigma 0.1).
     Draw order: tip height, then one standard normal per cell in C order.
+    tip_shift lowers the drawn tip by that length (the same draws otherwise):
+    the filament of a later time of a streamer advancing towards z = 0.
     """
     h = 1.0 / nz
     rng = np.random.default_rng(seed)
-    z_tip = rng.uniform(*FIL_TIP_RANGE)
+    z_tip = rng.uniform(*FIL_TIP_RANGE) - tip_shift
     x, y, z = cell_centres(nx, ny, nz, h)
     x0, y0 = 0.5 * nx * h, 0.5 * ny * h
     r_fil = FIL_RADIUS_CELLS * h

@@ -107,3 +107,19 @@ def test_learned_guess_null_arguments():
     assert lib.mgl_set_params(None, None, 0) == mg.MG_EINVAL
     assert lib.mgl_predict(None, None, None, None) == mg.MG_EINVAL
     assert lib.mgl_destroy(None) == mg.MG_OK
+
+
+def test_relaxation_substeps(lib):
+    """m = floor(alpha dt_E / dt_fine), at least 1 (the host side of the
+    multirate schedule; no device work)."""
+    m = ctypes.c_int()
+    assert lib.mg_relaxation_substeps(ctypes.c_double(1e-3), ctypes.c_double(2.5e-2), ctypes.c_double(1.0),
+                                      ctypes.byref(m)) == 0 and m.value == 25
+    assert lib.mg_relaxation_substeps(ctypes.c_double(1e-3), ctypes.c_double(2.5e-2), ctypes.c_double(0.1),
+                                      ctypes.byref(m)) == 0 and m.value == 2
+    assert lib.mg_relaxation_substeps(ctypes.c_double(1.0), ctypes.c_double(0.1), ctypes.c_double(1.0),
+                                      ctypes.byref(m)) == 0 and m.value == 1
+    assert lib.mg_relaxation_substeps(ctypes.c_double(1.0), ctypes.c_double(float("inf")), ctypes.c_double(1.0),
+                                      ctypes.byref(m)) == 0 and m.value == 1000000000
+    assert lib.mg_relaxation_substeps(ctypes.c_double(0.0), ctypes.c_double(1.0), ctypes.c_double(1.0),
+                                      ctypes.byref(m)) == -1
