@@ -9,6 +9,8 @@ Contents
                 Gauss-Seidel V-cycle (built into liboracle.so by build.py)
   oracle.py     ctypes front end + a pure-Python dense assembly for tiny grids
   nn_oracle.py  FP64 NumPy forward/backward of the 3D conv network layers
+  amr_oracle.py the composite (base grid + refined patches) problem, assembled
+                cell by cell and solved by a sparse direct solver
 """
 from .oracle import (  # noqa: F401
     build,
