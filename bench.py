@@ -137,10 +137,13 @@ def cpu_baseline(n: int, seed: int):
             "cg_all_cores": legs["cg"], "host_cpu": cpu_model(), "host_cpus_usable": ncpu}
 
 
-# HBM traffic of the smoother measured by rocprofv3 counters (FETCH_SIZE,
-# WRITE_SIZE, scaled by a copy-kernel calibration); valid only while the
-# smoother's sources hash to the value recorded with the counters.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rbgs_col_k_streamer256_traffic.txt")
+# HBM traffic of the smoothers measured by rocprofv3 counters (FETCH_SIZE,
+# WRITE_SIZE, scaled by a copy-kernel calibration), one summary file per
+# kernel; valid only while the smoother's sources hash to the value recorded
+# with the counters.
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
+                 ("rbgs_col_k_streamer256_traffic.txt", "rbgs_col_k_cell_streamer256_traffic.txt")]
+TRAFFIC_FILE = TRAFFIC_FILES[0]
 SMOOTHER_SOURCES = ["paper_1809_08857_amd/csrc/mg_stencil.cuh", "paper_1809_08857_amd/csrc/mg_launch.cuh",
                     "paper_1809_08857_amd/csrc/mg_kern_f64.hip", "paper_1809_08857_amd/csrc/mg_internal.h"]
 
@@ -161,24 +164,26 @@ def smoother_source_hash() -> str:
 
 
 def measured_traffic(kernel: str, algorithmic_bytes: float):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None (no summary, another kernel or grid size, or sources changed
+    """HBM bytes per launch of `kernel` from the committed counter summaries,
+    or None (no summary for that kernel and grid size, or sources changed
     since)."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    kv = {}
-    for line in open(TRAFFIC_FILE):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("source_sha256_16") != smoother_source_hash() or kv.get("kernel") != kernel:
-        return None
-    try:
-        if float(kv["algorithmic_bytes_per_launch"]) != float(algorithmic_bytes):
-            return None
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    for path in TRAFFIC_FILES:
+        if not os.path.exists(path):
+            continue
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("kernel") != kernel or kv.get("source_sha256_16") != smoother_source_hash():
+            continue
+        try:
+            if float(kv["algorithmic_bytes_per_launch"]) != float(algorithmic_bytes):
+                continue
+            return float(kv["hbm_bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def roofline(ctx):
