@@ -21,6 +21,11 @@ Other workloads (--workload):
              guess (U-net inference included) against the zero guess
   tga256     implicit (TGA) diffusion advances at 256^3 with face diffusion
              coefficients: two Helmholtz solves per step (value: solves/s)
+  amr256     the potential on a composite grid: a 256^3 base grid refined
+             (ratio 2) by a column of 32^3-cell boxes around the filament,
+             solved to rel. residual 1e-10 by BiCGStab preconditioned with
+             base and patch V-cycles (value: composite solves/s), beside the
+             uniform 512^3 FP64 solve of the same potential
   multirate  an advancing streamer (tip 2 cells further per coarse step):
              the four solves re-run each coarse step from the previous
              step's solutions against a zero start (and, at --n 128, the
@@ -65,7 +70,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="streamer256",
                     choices=["streamer256", "mixed512", "batched64", "learned128", "tga256", "multirate",
-                             "copycal"])
+                             "amr256", "copycal"])
     ap.add_argument("--no-forms", action="store_true", help="skip the forms comparison of the default run")
     ap.add_argument("--oracle-leg", default=None, choices=["vcycle", "cg"],
                     help="(internal) time one CPU oracle leg in this process and print it")
@@ -188,7 +193,10 @@ def measured_traffic(kernel: str, algorithmic_bytes: float):
 
 def roofline(ctx):
     from paper_1809_08857_amd import mg
-    launches, kern_ms, kname, bytes_per_launch = mg.mg_timing_read(ctx)
+    return roofline_from(*mg.mg_timing_read(ctx))
+
+
+def roofline_from(launches, kern_ms, kname, bytes_per_launch):
     if launches <= 0:
         return None
     avg_s = kern_ms / launches / 1e3
@@ -608,6 +616,83 @@ def multirate_line(args):
     return base_line(args, nsol / t_warm, t_warm / K * 1e3, cfg, "f64", None, nsol / t_warm * n**3)
 
 
+def amr_line(args):
+    """The potential on a two-level composite grid (Secs. 2-4): the base
+    grid at n^3 (n = 256, the paper's base grid) with the slab permittivity, grounded z = 0 and
+    phi = 1 at z = 1, refined by a column of boxes of 16^3 coarse cells
+    (32^3 fine cells) along the filament; fine sources and permittivities
+    from the same recipes at 2n.  One step = one composite solve from zero
+    to rel. residual 1e-10.  Beside it: the same potential on the uniform
+    (2n)^3 grid, plain FP64 V-cycles to 1e-10 (the resolution the boxes
+    give, everywhere)."""
+    import torch
+    import synth
+    from synth.problems import streamer_composite
+    from paper_1809_08857_amd import mg
+    n = args.n or 256
+    base, boxes, ff, ef = streamer_composite(n, seed=args.seed)
+    d = mg.mg_desc_default(n, n, n, base.h, rtol=1e-10, max_cycles=200)
+    ctx = mg.mga_create(d, boxes)
+    dv = lambda a: torch.from_numpy(a).cuda()
+    mg.mga_set_coeffs(ctx, dv(base.eps), [dv(e) for e in ef], base.a, mg.make_bcs(base.bc_types(), base.bc_values()))
+    fb, fl = dv(base.f), [dv(f) for f in ff]
+    xb = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    xf = [torch.zeros(f.shape, dtype=torch.float64, device="cuda") for f in ff]
+    stats = []
+
+    def step():
+        rc, st = mg.mga_solve(ctx, fb, fl, xb, xf)
+        if rc != mg.MG_OK:
+            raise RuntimeError(f"composite solve failed: {st.as_dict()}")
+        stats.append(st.as_dict())
+        return 0
+
+    for _ in range(args.warmup):
+        step()
+    mg.mga_timing(ctx, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt_run = time.perf_counter() - t0
+    roof = roofline_from(*mg.mga_timing_read(ctx))
+    if roof is not None:
+        roof["timed_in"] = "the base grid's V-cycles of the preconditioner (finest base level)"
+    mg.mga_timing(ctx, 0)
+    mg.mga_destroy(ctx)
+    del xb, xf, fb, fl
+    torch.cuda.empty_cache()
+    cov = sum((hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) // 8 for lo, hi in boxes)
+    unknowns = n**3 - cov + sum(f.size for f in ff)
+    # the uniform fine grid of the same potential
+    uni = synth.streamer_set(2 * n, seed=args.seed)[0]
+    su = make_solvers([uni], "fp64")[0]
+    fu = dv(uni.f)
+    xu = torch.zeros(uni.shape, dtype=torch.float64, device="cuda")
+    ucyc = []
+
+    def ustep():
+        rc, st = su.solve(fu, xu)
+        if rc != mg.MG_OK:
+            raise RuntimeError(f"uniform solve failed: {st.as_dict()}")
+        ucyc.append(st.cycles)
+        return 0
+
+    dt_u, _, _ = timed(ustep, args.steps, args.warmup)
+    su.close()
+    value = args.steps / dt_run
+    its = [s["cycles"] for s in stats[args.warmup:]]
+    cfg = {"workload": f"potential on a composite grid: {n}^3 base (eps slab, seed {args.seed}) + {len(boxes)} "
+                       f"boxes of 32^3 fine cells along the filament, BiCGStab with base + patch V-cycles to "
+                       f"rel. residual 1e-10 from zero", "grid": [n, n, n], "boxes": [list(map(list, b)) for b in boxes],
+           "composite_unknowns": unknowns, "solves_per_step": 1, "precision": "fp64",
+           "bicgstab_iterations": round(sum(its) / len(its), 2), "rel_res": stats[-1]["rel_res"],
+           "uniform_fine": {"grid": [2 * n] * 3, "solves_per_s": round(args.steps / dt_u, 3),
+                            "cycles_per_solve": round(sum(ucyc[args.warmup:]) / args.steps, 2)}}
+    return base_line(args, value, dt_run / args.steps * 1e3, cfg, "f64", roof, value * unknowns)
+
+
 def forms(args):
     """The three forms against the plain FP64 V-cycle, each on its own
     workload, in a few short steps: mixed precision at 512^3 (four solves per
@@ -697,6 +782,8 @@ def main():
         out = tga_line(args)
     elif args.workload == "multirate":
         out = multirate_line(args)
+    elif args.workload == "amr256":
+        out = amr_line(args)
     elif args.workload == "copycal":
         out = copy_calibration(args)
     else:

@@ -111,32 +111,28 @@ class _Index:
         return self.off[p] + ((k - lo[2]) * nyp + (j - lo[1])) * nxp + (i - lo[0])
 
 
-def assemble(comp: Composite):
-    """Sparse A (CSR, per-volume rows) and b of the composite problem."""
-    import scipy.sparse as sp
-    q = comp.base
-    check_boxes(q.nx, q.ny, q.nz, comp.boxes)
-    ix = _Index(comp)
-    hc, hf = q.h, 0.5 * q.h
-    ic2, if2 = 1.0 / hc**2, 1.0 / hf**2
-    beta_c = np.ones(q.shape) if q.eps is None else np.asarray(q.eps, dtype=np.float64)
-    beta_f = [np.ones(comp.shape(p)) if comp.eps_fine is None else np.asarray(comp.eps_fine[p], dtype=np.float64)
-              for p in range(len(comp.boxes))]
-    types, vals = q.bc_types(), q.bc_values()
-    rows, cols, data = [], [], []
-    b = np.zeros(ix.n)
-
-    def add(r, c, v):
-        rows.append(r)
-        cols.append(c)
-        data.append(v)
+class _Rows:
+    """The equations of the composite problem, one row at a time: the
+    unknowns and weights of a row and its right-hand side."""
 
     steps = [(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
 
-    def ghost_terms(p, fi, fj, fk, d, coef):
-        """coef * (G) expressed through unknowns, for the ghost beyond face d of
+    def __init__(self, comp: Composite):
+        q = comp.base
+        check_boxes(q.nx, q.ny, q.nz, comp.boxes)
+        self.comp, self.q = comp, q
+        self.ix = _Index(comp)
+        self.hc, self.hf = q.h, 0.5 * q.h
+        self.beta_c = np.ones(q.shape) if q.eps is None else np.asarray(q.eps, dtype=np.float64)
+        self.beta_f = [np.ones(comp.shape(p)) if comp.eps_fine is None
+                       else np.asarray(comp.eps_fine[p], dtype=np.float64) for p in range(len(comp.boxes))]
+        self.types, self.vals = q.bc_types(), q.bc_values()
+
+    def ghost_terms(self, p, fi, fj, fk, d, coef):
+        """coef * G expressed through unknowns, for the ghost beyond face d of
         fine cell (fi, fj, fk) of box p: a list of (unknown, weight)."""
-        di, dj, dk = steps[d]
+        ix = self.ix
+        di, dj, dk = self.steps[d]
         gi, gj, gk = fi + di, fj + dj, fk + dk               # ghost (fine indices)
         C = (gi // 2, gj // 2, gk // 2)                      # coarse cell holding it
         axis = d // 2
@@ -157,74 +153,110 @@ def assemble(comp: Composite):
                 terms.append((uid, ct * s * w / 8.0))
         return terms
 
-    # base cells
+    def base_row(self, I, J, K):
+        """(terms, rhs) of uncovered base cell (I, J, K)."""
+        q, ix, comp = self.q, self.ix, self.comp
+        ic2, hf = 1.0 / self.hc**2, self.hf
+        r = ix.base_id[K, J, I]
+        bC = self.beta_c[K, J, I]
+        terms = [(r, q.a)]
+        rhs = q.f[K, J, I]
+        for d, (di, dj, dk) in enumerate(self.steps):
+            N = (I + di, J + dj, K + dk)
+            if not (0 <= N[0] < q.nx and 0 <= N[1] < q.ny and 0 <= N[2] < q.nz):
+                if self.types[d] == "D":
+                    terms.append((r, 2.0 * bC * ic2))
+                    rhs += 2.0 * bC * ic2 * self.vals[d]
+                continue
+            pn = ix.mask[N[2], N[1], N[0]]
+            if pn < 0:
+                bf = _harm(bC, self.beta_c[N[2], N[1], N[0]])
+                terms += [(r, bf * ic2), (ix.base_id[N[2], N[1], N[0]], -bf * ic2)]
+                continue
+            # coarse-fine face: the four fine fluxes (refluxing)
+            axis = d // 2
+            fn = [2 * N[0], 2 * N[1], 2 * N[2]]
+            if di + dj + dk < 0:  # the fine layer of N beside C is its last one
+                fn[axis] += 1
+            tang = [t for t in range(3) if t != axis]
+            for o1 in range(2):
+                for o2 in range(2):
+                    f = list(fn)
+                    f[tang[0]] += o1
+                    f[tang[1]] += o2
+                    lo = comp.boxes[pn][0]
+                    bF = self.beta_f[pn][f[2] - lo[2], f[1] - lo[1], f[0] - lo[0]]
+                    w = _harm(bF, bC) / (8.0 * hf * hf)  # beta_i / h_f * h_f^2 / h_c^3
+                    # + w (G - F), with G the ghost of F beyond the face towards C
+                    terms += self.ghost_terms(pn, f[0], f[1], f[2], d ^ 1, w)
+                    terms.append((ix.fine(pn, *f), -w))
+        return terms, rhs
+
+    def fine_row(self, p, i, j, k):
+        """(terms, rhs) of fine cell (i, j, k) (global fine indices) of box p."""
+        ix, comp = self.ix, self.comp
+        if2 = 1.0 / self.hf**2
+        lo, hi = comp.boxes[p]
+        r = ix.fine(p, i, j, k)
+        bF = self.beta_f[p][k - lo[2], j - lo[1], i - lo[0]]
+        terms = [(r, self.q.a)]
+        rhs = comp.f_fine[p][k - lo[2], j - lo[1], i - lo[0]]
+        for d, (di, dj, dk) in enumerate(self.steps):
+            n = (i + di, j + dj, k + dk)
+            if all(lo[e] <= n[e] < hi[e] for e in range(3)):
+                bf = _harm(bF, self.beta_f[p][n[2] - lo[2], n[1] - lo[1], n[0] - lo[0]])
+                terms += [(r, bf * if2), (ix.fine(p, *n), -bf * if2)]
+                continue
+            C = (n[0] // 2, n[1] // 2, n[2] // 2)
+            bi = _harm(bF, self.beta_c[C[2], C[1], C[0]])
+            # beta_i (F - G) / h_f^2
+            terms.append((r, bi * if2))
+            terms += self.ghost_terms(p, i, j, k, d, -bi * if2)
+        return terms, rhs
+
+
+def assemble(comp: Composite):
+    """Sparse A (CSR, per-volume rows) and b of the composite problem."""
+    import scipy.sparse as sp
+    R = _Rows(comp)
+    q, ix = comp.base, R.ix
+    rows, cols, data = [], [], []
+    b = np.zeros(ix.n)
+
+    def put(r, terms, rhs):
+        for c, v in terms:
+            rows.append(r)
+            cols.append(c)
+            data.append(v)
+        b[r] += rhs
+
     for K in range(q.nz):
         for J in range(q.ny):
             for I in range(q.nx):
                 r = ix.base_id[K, J, I]
-                if r < 0:
-                    continue
-                bC = beta_c[K, J, I]
-                add(r, r, q.a)
-                b[r] += q.f[K, J, I]
-                for d, (di, dj, dk) in enumerate(steps):
-                    N = (I + di, J + dj, K + dk)
-                    if not (0 <= N[0] < q.nx and 0 <= N[1] < q.ny and 0 <= N[2] < q.nz):
-                        if types[d] == "D":
-                            add(r, r, 2.0 * bC * ic2)
-                            b[r] += 2.0 * bC * ic2 * vals[d]
-                        continue
-                    pn = ix.mask[N[2], N[1], N[0]]
-                    if pn < 0:
-                        bf = _harm(bC, beta_c[N[2], N[1], N[0]])
-                        add(r, r, bf * ic2)
-                        add(r, ix.base_id[N[2], N[1], N[0]], -bf * ic2)
-                        continue
-                    # coarse-fine face: the four fine fluxes (refluxing)
-                    axis = d // 2
-                    fn = [2 * N[0], 2 * N[1], 2 * N[2]]
-                    if di + dj + dk < 0:  # the fine layer of N beside C is its last one
-                        fn[axis] += 1
-                    tang = [t for t in range(3) if t != axis]
-                    for o1 in range(2):
-                        for o2 in range(2):
-                            f = list(fn)
-                            f[tang[0]] += o1
-                            f[tang[1]] += o2
-                            lo = comp.boxes[pn][0]
-                            bF = beta_f[pn][f[2] - lo[2], f[1] - lo[1], f[0] - lo[0]]
-                            bi = _harm(bF, bC)
-                            w = bi / (8.0 * hf * hf)  # beta_i / h_f * h_f^2 / h_c^3
-                            # + w (G - F), with G the ghost of F beyond the face towards C
-                            for u, cw in ghost_terms(pn, f[0], f[1], f[2], d ^ 1, w):
-                                add(r, u, cw)
-                            add(r, ix.fine(pn, *f), -w)
-    # fine cells
+                if r >= 0:
+                    put(r, *R.base_row(I, J, K))
     for p, (lo, hi) in enumerate(comp.boxes):
-        nzp, nyp, nxp = comp.shape(p)
         for k in range(lo[2], hi[2]):
             for j in range(lo[1], hi[1]):
                 for i in range(lo[0], hi[0]):
-                    r = ix.fine(p, i, j, k)
-                    bF = beta_f[p][k - lo[2], j - lo[1], i - lo[0]]
-                    add(r, r, q.a)
-                    b[r] += comp.f_fine[p][k - lo[2], j - lo[1], i - lo[0]]
-                    for d, (di, dj, dk) in enumerate(steps):
-                        n = (i + di, j + dj, k + dk)
-                        if all(lo[e] <= n[e] < hi[e] for e in range(3)):
-                            bf = _harm(bF, beta_f[p][n[2] - lo[2], n[1] - lo[1], n[0] - lo[0]])
-                            add(r, r, bf * if2)
-                            add(r, ix.fine(p, *n), -bf * if2)
-                            continue
-                        C = (n[0] // 2, n[1] // 2, n[2] // 2)
-                        bi = _harm(bF, beta_c[C[2], C[1], C[0]])
-                        # beta_i (F - G) / h_f^2
-                        add(r, r, bi * if2)
-                        for u, cw in ghost_terms(p, i, j, k, d, -bi * if2):
-                            add(r, u, cw)
+                    put(ix.fine(p, i, j, k), *R.fine_row(p, i, j, k))
     A = sp.csr_matrix((data, (rows, cols)), shape=(ix.n, ix.n))
     A.sum_duplicates()
     return A, b, ix
+
+
+def residual_at(comp: Composite, base: np.ndarray, fine: Sequence[np.ndarray], cells) -> np.ndarray:
+    """b - A u at sampled cells, one row at a time (for grids too large to
+    assemble): cells are ("c", I, J, K) for uncovered base cells or
+    ("f", p, i, j, k) for fine cells (global fine indices)."""
+    R = _Rows(comp)
+    u = pack(comp, base, fine, R.ix)
+    out = np.empty(len(cells))
+    for n, c in enumerate(cells):
+        terms, rhs = R.base_row(*c[1:]) if c[0] == "c" else R.fine_row(*c[1:])
+        out[n] = rhs - sum(w * u[col] for col, w in terms)
+    return out
 
 
 def unpack(comp: Composite, u: np.ndarray, ix: "_Index"):

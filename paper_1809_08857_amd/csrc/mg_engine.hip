@@ -224,9 +224,11 @@ static const char *mode_name(int m) {
     return m == COEF_CELL ? "cell-eps" : (m == COEF_FACE ? "face" : "const");
 }
 
-// Finest-level smoother launch, bracketed by events while timing is on.
+// Finest-level smoother launch, bracketed by events while timing is on
+// (sweeps of a given iterate only: the zero-input variant of a cycle's
+// first sweep is another kernel).
 hipError_t timed_smooth(Ctx *c, int l, const LvView &W, bool zin, int tile, int zc, const int *done) {
-    const bool rec = c->timing && l == 0 && c->ev_used + 2 <= (int)c->ev.size();
+    const bool rec = c->timing && l == 0 && !zin && c->ev_used + 2 <= (int)c->ev.size();
     if (rec) {
         hipError_t e = hipEventRecord(c->ev[c->ev_used], c->stream);
         if (e != hipSuccess) return e;
@@ -237,7 +239,7 @@ hipError_t timed_smooth(Ctx *c, int l, const LvView &W, bool zin, int tile, int 
     if (e != hipSuccess) return e;
     // algorithmic bytes: read u (unless zero), b and eps once, write u once
     const double es = (double)store_size(W.st);
-    const int arrays = (zin ? 0 : 1) + 1 + (W.C.mode == COEF_CELL ? 1 : 0) + (W.C.mode == COEF_FACE ? 3 : 0) + 1;
+    const int arrays = 1 + 1 + (W.C.mode == COEF_CELL ? 1 : 0) + (W.C.mode == COEF_FACE ? 3 : 0) + 1;
     c->ev_bytes[c->ev_used / 2] = (double)W.n * es * arrays;
     c->ev_step[c->ev_used / 2] = c->cur_step;
     c->ev_used += 2;
@@ -245,9 +247,9 @@ hipError_t timed_smooth(Ctx *c, int l, const LvView &W, bool zin, int tile, int 
         int tx, ty;
         tile_shape(tile, &tx, &ty);
         char buf[160];
-        snprintf(buf, sizeof buf, "rbgs_col_k<%s,%s,%d,%d,zero_in=%d> (finest-level fused red-black sweep)",
+        snprintf(buf, sizeof buf, "rbgs_col_k<%s,%s,%d,%d,zero_in=0> (finest-level fused red-black sweep)",
                  W.st == ST_F64 ? "double" : (W.st == ST_F32 ? "float" : "bf16"), mode_name(W.C.mode), tx,
-                 ty, (int)zin);
+                 ty);
         c->t_kernel = buf;
     }
     return hipSuccess;

@@ -541,6 +541,59 @@ __global__ __launch_bounds__(256) void apply_k(const double *__restrict__ x, con
         y[p] = alpha * xP + beta * ax;
     }
 }
+// The same for a constant or cell coefficient, marching along z with the
+// values of the planes below and above (u, the coefficient and the z face)
+// kept in registers: per cell one new u and coefficient load on the axis
+// plus the four lateral neighbours, and one new z face.
+template <int MODE>
+__global__ __launch_bounds__(256) void apply_z_k(const double *__restrict__ x, const double *__restrict__ eps,
+                                                 Geo G, double alpha, double beta, double *__restrict__ y, int kz) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k0 = blockIdx.z * kz, k1 = min(k0 + kz, G.nz);
+    if (i >= G.nx || j >= G.ny) return;
+    const size_t sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
+    const bool cell = MODE == COEF_CELL;
+    const bool in_x0 = i > 0, in_x1 = i < G.nx - 1, in_y0 = j > 0, in_y1 = j < G.ny - 1;
+    const bool dz0 = (G.bcmask >> 4) & 1, dz1 = (G.bcmask >> 5) & 1;
+    size_t p = (size_t)k0 * sz + (size_t)j * sy + i;
+    double xc = x[p], ec = cell ? eps[p] : 1.0;
+    double xm = 0.0, fm = dz0 ? 2.0 * ec : 0.0;  // the face below: a Dirichlet domain face or none
+    if (k0 > 0) {
+        xm = x[p - sz];
+        fm = cell ? harm_face(ec, eps[p - sz]) : 1.0;
+    }
+    for (int k = k0; k < k1; ++k, p += sz) {
+        const bool up = k < G.nz - 1;
+        double xp = 0.0, ep = 1.0;
+        if (up) {
+            xp = x[p + sz];
+            if (cell) ep = eps[p + sz];
+        }
+        const double fp = up ? (cell ? harm_face(ec, ep) : 1.0) : (dz1 ? 2.0 * ec : 0.0);
+        double off = fm * xm + fp * xp, dg = fm + fp;
+        auto side = [&](bool in, int d, size_t q) {
+            if (in) {
+                const double f = cell ? harm_face(ec, eps[q]) : 1.0;
+                off += f * x[q];
+                dg += f;
+            } else if ((G.bcmask >> d) & 1) {
+                dg += 2.0 * ec;
+            }
+        };
+        side(in_x0, 0, p - 1);
+        side(in_x1, 1, p + 1);
+        side(in_y0, 2, p - sy);
+        side(in_y1, 3, p + sy);
+        const double ax = G.a * xc + G.ih2 * (dg * xc - off);
+        y[p] = alpha * xc + beta * ax;
+        xm = xc;
+        xc = xp;
+        fm = fp;
+        ec = ep;
+    }
+}
+
 hipError_t apply_op(hipStream_t s, const Geo &G0, const Coef &C, double alpha, double beta, const double *x,
                     double *y) {
     Geo G = G0;
@@ -552,10 +605,10 @@ hipError_t apply_op(hipStream_t s, const Geo &G0, const Coef &C, double alpha, d
                  *bz = (const double *)C.bz;
     switch (C.mode) {
         case COEF_CONST:
-            hipLaunchKernelGGL(apply_k<COEF_CONST>, grid, block, 0, s, x, eps, bx, by, bz, G, alpha, beta, y, kz);
+            hipLaunchKernelGGL(apply_z_k<COEF_CONST>, grid, block, 0, s, x, eps, G, alpha, beta, y, kz);
             break;
         case COEF_CELL:
-            hipLaunchKernelGGL(apply_k<COEF_CELL>, grid, block, 0, s, x, eps, bx, by, bz, G, alpha, beta, y, kz);
+            hipLaunchKernelGGL(apply_z_k<COEF_CELL>, grid, block, 0, s, x, eps, G, alpha, beta, y, kz);
             break;
         case COEF_FACE:
             hipLaunchKernelGGL(apply_k<COEF_FACE>, grid, block, 0, s, x, eps, bx, by, bz, G, alpha, beta, y, kz);

@@ -45,6 +45,10 @@ class MgStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class MgaBox(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int * 3), ("hi", ctypes.c_int * 3)]
+
+
 class MgError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"[{code}] {msg}")
@@ -92,6 +96,13 @@ def load() -> ctypes.CDLL:
         "mg_autotune": (I, [P, I, pI, pI, pD]),
         "mg_timing": (I, [P, I]),
         "mg_timing_read": (I, [P, ctypes.POINTER(ctypes.c_long), pD, pD, ctypes.POINTER(ctypes.c_char_p)]),
+        "mga_create": (I, [ctypes.POINTER(MgDesc), I, ctypes.POINTER(MgaBox), P, ctypes.POINTER(P)]),
+        "mga_set_coeffs": (I, [P, P, ctypes.POINTER(P), D, ctypes.POINTER(MgBcs)]),
+        "mga_solve": (I, [P, P, ctypes.POINTER(P), P, ctypes.POINTER(P), ctypes.c_uint, ctypes.POINTER(MgStats)]),
+        "mga_apply": (I, [P, P, ctypes.POINTER(P), P, ctypes.POINTER(P)]),
+        "mga_destroy": (I, [P]),
+        "mga_timing": (I, [P, I]),
+        "mga_timing_read": (I, [P, ctypes.POINTER(ctypes.c_long), pD, pD, ctypes.POINTER(ctypes.c_char_p)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -275,6 +286,54 @@ def mg_timing_read(ctx) -> Tuple[int, float, str, float]:
     _check(load().mg_timing_read(ctx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(k)))
     per = by.value / n.value if n.value else 0.0
     return n.value, ms.value, (k.value or b"").decode(), per
+
+
+def _ptr_array(ts: Optional[Sequence]):
+    if ts is None:
+        return None
+    return (ctypes.c_void_p * max(len(ts), 1))(*[_ptr(t) for t in ts])
+
+
+def mga_create(desc: MgDesc, boxes: Sequence, stream=None) -> ctypes.c_void_p:
+    """boxes: ((lo_x, lo_y, lo_z), (hi_x, hi_y, hi_z)) fine-cell ranges."""
+    arr = (MgaBox * max(len(boxes), 1))()
+    for q, (lo, hi) in enumerate(boxes):
+        arr[q].lo[:] = [int(v) for v in lo]
+        arr[q].hi[:] = [int(v) for v in hi]
+    ctx = ctypes.c_void_p()
+    _check(load().mga_create(ctypes.byref(desc), len(boxes), arr, _stream_handle(stream), ctypes.byref(ctx)))
+    return ctx
+
+
+def mga_set_coeffs(ctx, eps_base, eps_fine, a: float, bcs: MgBcs) -> int:
+    return _check(load().mga_set_coeffs(ctx, _ptr(eps_base), _ptr_array(eps_fine), float(a), ctypes.byref(bcs)))
+
+
+def mga_solve(ctx, f_base, f_fine: Sequence, x_base, x_fine: Sequence, flags: int = 0) -> Tuple[int, MgStats]:
+    st = MgStats()
+    rc = _check(load().mga_solve(ctx, _ptr(f_base), _ptr_array(f_fine), _ptr(x_base), _ptr_array(x_fine), flags,
+                                 ctypes.byref(st)))
+    return rc, st
+
+
+def mga_apply(ctx, x_base, x_fine: Sequence, y_base, y_fine: Sequence) -> int:
+    return _check(load().mga_apply(ctx, _ptr(x_base), _ptr_array(x_fine), _ptr(y_base), _ptr_array(y_fine)))
+
+
+def mga_timing(ctx, enable: int) -> int:
+    return _check(load().mga_timing(ctx, int(enable)))
+
+
+def mga_timing_read(ctx) -> Tuple[int, float, str, float]:
+    """(launches, ms, kernel, algorithmic bytes per launch) of the base grid's timed smoother."""
+    n, ms, by, k = ctypes.c_long(), ctypes.c_double(), ctypes.c_double(), ctypes.c_char_p()
+    _check(load().mga_timing_read(ctx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(k)))
+    per = by.value / n.value if n.value else 0.0
+    return n.value, ms.value, (k.value or b"").decode(), per
+
+
+def mga_destroy(ctx) -> int:
+    return _check(load().mga_destroy(ctx))
 
 
 class Solver:

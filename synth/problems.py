@@ -262,3 +262,38 @@ def diffusion_faces(nx: int, ny: int, nz: int, seed: int):
         np.exp(noise, out=noise)
         out.append(np.ascontiguousarray(D_GAS * (1.0 + (D_HEAD_RATIO - 1.0) * wgt) * noise))
     return tuple(out)
+
+
+AMR_BOX_COARSE = 16   # coarse cells per box side along x and y (32 fine cells)
+AMR_BOX_GAP = 1       # uncovered coarse cells between consecutive boxes along z
+AMR_BOX_MARGIN = 4    # coarse cells the column extends beyond the filament's ends
+
+
+def streamer_composite(n: int, seed: int = 0, box: int = AMR_BOX_COARSE):
+    """A two-level composite problem around a seeded filament: the potential
+    problem of streamer_set(n) on the base grid, refined (ratio 2) by a
+    column of boxes of box x box x box coarse cells centred on the filament's
+    axis, from AMR_BOX_MARGIN cells below its tip to as far above its top,
+    AMR_BOX_GAP uncovered coarse cells between consecutive boxes, each box at
+    least one coarse cell inside the domain.  The fine sources and
+    permittivities are the same recipes (filament_source, slab_permittivity)
+    on the 2n^3 grid, cut to the boxes; the fine source draws use seed + 1.
+
+    Returns (base Problem, boxes as ((lo), (hi)) fine ranges x y z, f_fine,
+    eps_fine)."""
+    base = streamer_set(n, seed=seed)[0]
+    z_tip = np.random.default_rng(seed).uniform(*FIL_TIP_RANGE)
+    k_lo = max(1, int(np.floor(z_tip * n)) - AMR_BOX_MARGIN)
+    k_hi = min(n - 1, int(np.ceil(FIL_Z_TOP * n)) + AMR_BOX_MARGIN)
+    c0 = n // 2 - box // 2
+    boxes = []
+    k = k_lo
+    while k + box <= k_hi or (not boxes and k + box <= n - 1):
+        boxes.append(((2 * c0, 2 * c0, 2 * k), (2 * (c0 + box), 2 * (c0 + box), 2 * (k + box))))
+        k += box + AMR_BOX_GAP
+    rho_f = filament_source(2 * n, 2 * n, 2 * n, seed + 1)
+    eps_f = slab_permittivity(2 * n, 2 * n, 2 * n)
+    cut = lambda a, lo, hi: np.ascontiguousarray(a[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]])
+    f_fine = [cut(rho_f, lo, hi) for lo, hi in boxes]
+    eps_fine = [cut(eps_f, lo, hi) for lo, hi in boxes]
+    return base, boxes, f_fine, eps_fine

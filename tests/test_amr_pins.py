@@ -89,3 +89,28 @@ def test_without_patches_is_the_single_grid_problem():
 def test_bad_boxes_rejected(boxes):
     with pytest.raises(ValueError):
         amr.check_boxes(16, 16, 16, boxes)
+
+
+def test_sampled_rows_match_the_assembled_residual():
+    n = 16
+    rng = np.random.default_rng(5)
+    bc = (("D", 0.3), ("N", 0.0), ("D", -1.0), ("N", 0.0), ("N", 0.0), ("D", 2.0))
+    p = Problem(n, n, n, 1.0 / n, 1.5, rng.standard_normal((n, n, n)), np.exp(rng.uniform(-1, 1, (n, n, n))), bc)
+    fz = _zero_fine(BOXES)
+    comp = amr.Composite(p, BOXES, [rng.standard_normal(a.shape) for a in fz],
+                         [np.exp(rng.uniform(-1, 1, a.shape)) for a in fz])
+    ub = rng.standard_normal((n, n, n))
+    uf = [rng.standard_normal(a.shape) for a in fz]
+    A, b, ix = amr.assemble(comp)
+    r = b - A @ amr.pack(comp, ub, uf, ix)
+    cells, want = [], []
+    for K, J, I in [(0, 0, 0), (5, 7, 1), (3, 2, 3), (15, 15, 15), (4, 9, 6)]:  # (4, 9, 6) borders box 0
+        if ix.base_id[K, J, I] >= 0:
+            cells.append(("c", I, J, K))
+            want.append(r[ix.base_id[K, J, I]])
+    for q, (lo, hi) in enumerate(BOXES):
+        for c in (lo, tuple(h - 1 for h in hi), tuple((l + h) // 2 for l, h in zip(lo, hi))):
+            cells.append(("f", q, *c))
+            want.append(r[ix.fine(q, *c)])
+    got = amr.residual_at(comp, ub, uf, cells)
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-12 * np.abs(r).max())

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared(header):
     src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[a-zA-Z_][\w\s\*]*?\b((?:mg|mgl)_\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?[a-zA-Z_][\w\s\*]*?\b((?:mg|mgl|mga)_\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
@@ -27,10 +27,10 @@ def lib():
     return mg.load()
 
 
-@pytest.mark.parametrize("header,libfile", [("mg.h", "libmg.so"), ("mgl.h", "libmgl.so")])
+@pytest.mark.parametrize("header,libfile", [("mg.h", "libmg.so"), ("mgl.h", "libmgl.so"), ("mga.h", "libmg.so")])
 def test_every_declared_symbol_is_exported(header, libfile):
     names = _declared(header)
-    assert len(names) >= 10
+    assert len(names) >= 5
     so = ctypes.CDLL(os.path.join(ROOT, "paper_1809_08857_amd", libfile))
     missing = [n for n in names if not hasattr(so, n)]
     assert not missing, missing
@@ -123,3 +123,30 @@ def test_relaxation_substeps(lib):
                                       ctypes.byref(m)) == 0 and m.value == 1000000000
     assert lib.mg_relaxation_substeps(ctypes.c_double(0.0), ctypes.c_double(1.0), ctypes.c_double(1.0),
                                       ctypes.byref(m)) == -1
+
+
+@pytest.mark.parametrize("boxes,why", [
+    ([((0, 4, 4), (8, 12, 12))], "inside the domain"),
+    ([((4, 4, 4), (12, 12, 13))], "even"),
+    ([((4, 4, 4), (4, 12, 12))], "even"),
+    ([((4, 4, 4), (10, 10, 10)), ((10, 4, 4), (16, 10, 10))], "apart"),
+    ([((4, 4, 4), (10, 10, 10)), ((6, 6, 6), (8, 8, 8))], "apart"),
+])
+def test_mga_create_rejects_bad_boxes(lib, boxes, why):
+    d = mg.mg_desc_default(16, 16, 16, 1 / 16)
+    with pytest.raises(mg.MgError) as e:
+        mg.mga_create(d, boxes, stream=_NoStream())
+    assert e.value.code == mg.MG_EINVAL and why in mg.mg_last_error()
+    assert mg.mg_last_error().startswith("mga_create")
+
+
+def test_mga_create_rejects_low_precision(lib):
+    d = mg.mg_desc_default(16, 16, 16, 1 / 16)
+    d.precision = mg.MG_FP32_IR
+    with pytest.raises(mg.MgError):
+        mg.mga_create(d, [((4, 4, 4), (12, 12, 12))], stream=_NoStream())
+    assert "MG_FP64" in mg.mg_last_error()
+
+
+class _NoStream:
+    cuda_stream = None
