@@ -26,6 +26,10 @@ Other workloads (--workload):
              solved to rel. residual 1e-10 by BiCGStab preconditioned with
              base and patch V-cycles (value: composite solves/s), beside the
              uniform 512^3 FP64 solve of the same potential
+  eb256      the needle-plane potential of the paper's large example at 256^3
+             with the needle as an embedded boundary (cut cells), solved to
+             rel. residual 1e-10 by BiCGStab with engine V-cycles (value:
+             solves/s), beside the same potential without the electrode
   multirate  an advancing streamer (tip 2 cells further per coarse step):
              the four solves re-run each coarse step from the previous
              step's solutions against a zero start (and, at --n 128, the
@@ -70,7 +74,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="streamer256",
                     choices=["streamer256", "mixed512", "batched64", "learned128", "tga256", "multirate",
-                             "amr256", "copycal"])
+                             "amr256", "eb256", "copycal"])
     ap.add_argument("--no-forms", action="store_true", help="skip the forms comparison of the default run")
     ap.add_argument("--oracle-leg", default=None, choices=["vcycle", "cg"],
                     help="(internal) time one CPU oracle leg in this process and print it")
@@ -693,6 +697,78 @@ def amr_line(args):
     return base_line(args, value, dt_run / args.steps * 1e3, cfg, "f64", roof, value * unknowns)
 
 
+def eb_line(args):
+    """The needle-plane potential (Sec. 4's geometry) at n^3, n = 256: the
+    needle (radius 500 um of a 2 cm box, tip 1 cm below the top face) as an
+    embedded boundary at potential 1 with the top face, the bottom face
+    grounded, zero flux on the sides, the seeded filament as the space
+    charge.  One step = one cut-cell solve from zero to rel. residual 1e-10.
+    Beside it: the same source and faces without the electrode, plain FP64
+    V-cycles to 1e-10."""
+    import torch
+    from synth.geometry import needle_plane
+    from paper_1809_08857_amd import mg
+    n = args.n or 256
+    p, G, gv = needle_plane(n, seed=args.seed)
+    import numpy as np
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    d = mg.mg_desc_default(n, n, n, p.h, rtol=1e-10, max_cycles=300)
+    ctx = mg.mge_create(d)
+    mg.mge_set_geometry(ctx, dv(G.kappa), dv(G.ax), dv(G.ay), dv(G.az), G.bidx, G.boff, None, p.a,
+                        mg.make_bcs(p.bc_types(), p.bc_values()), None, gv)
+    f = dv(p.f)
+    x = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    stats = []
+
+    def step():
+        rc, st = mg.mge_solve(ctx, f, x)
+        if rc != mg.MG_OK:
+            raise RuntimeError(f"cut-cell solve failed: {st.as_dict()}")
+        stats.append(st.as_dict())
+        return 0
+
+    for _ in range(args.warmup):
+        step()
+    mg.mge_timing(ctx, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt_run = time.perf_counter() - t0
+    roof = roofline_from(*mg.mge_timing_read(ctx))
+    if roof is not None:
+        roof["timed_in"] = "the preconditioner's V-cycles (finest level)"
+    mg.mge_timing(ctx, 0)
+    mg.mge_destroy(ctx)
+    del x
+    torch.cuda.empty_cache()
+    # the same problem without the electrode
+    su = make_solvers([p], "fp64")[0]
+    xu = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    ucyc = []
+
+    def ustep():
+        rc, st = su.solve(f, xu)
+        if rc != mg.MG_OK:
+            raise RuntimeError(f"plain solve failed: {st.as_dict()}")
+        ucyc.append(st.cycles)
+        return 0
+
+    dt_u, _, _ = timed(ustep, args.steps, args.warmup)
+    su.close()
+    value = args.steps / dt_run
+    its = [q["cycles"] for q in stats[args.warmup:]]
+    cfg = {"workload": f"needle-plane potential at {n}^3: needle radius 0.025, tip at z = 0.5 (Sec. 4 geometry) as an "
+                       f"embedded boundary, filament space charge (seed {args.seed}), BiCGStab with engine V-cycles "
+                       f"to rel. residual 1e-10 from zero", "grid": [n, n, n], "boundary_cells": int(G.bidx.size),
+           "covered_cells": int((G.kappa == 0).sum()), "solves_per_step": 1, "precision": "fp64",
+           "bicgstab_iterations": round(sum(its) / len(its), 2), "rel_res": stats[-1]["rel_res"],
+           "without_electrode": {"solves_per_s": round(args.steps / dt_u, 3),
+                                 "cycles_per_solve": round(sum(ucyc[args.warmup:]) / args.steps, 2)}}
+    return base_line(args, value, dt_run / args.steps * 1e3, cfg, "f64", roof, value * n**3)
+
+
 def forms(args):
     """The three forms against the plain FP64 V-cycle, each on its own
     workload, in a few short steps: mixed precision at 512^3 (four solves per
@@ -784,6 +860,8 @@ def main():
         out = multirate_line(args)
     elif args.workload == "amr256":
         out = amr_line(args)
+    elif args.workload == "eb256":
+        out = eb_line(args)
     elif args.workload == "copycal":
         out = copy_calibration(args)
     else:

@@ -174,6 +174,35 @@ def assemble(prob: EBProblem):
     return Am, b
 
 
+def rhs_only(prob: EBProblem) -> np.ndarray:
+    """The right-hand side b without assembling the operator (the same
+    terms as assemble's b, for grids too large to assemble)."""
+    q, G = prob.base, prob.geom
+    nx, ny, nz, h = q.nx, q.ny, q.nz, q.h
+    ih2 = 1.0 / (h * h)
+    beta = np.ones((nz, ny, nx)) if q.eps is None else np.asarray(q.eps, dtype=np.float64)
+    cov = G.kappa <= 0
+    b = np.where(cov, 0.0, G.kappa * q.f)
+    types, values = q.bc_types(), q.bc_values()
+    for d in range(6):
+        if types[d] != "D":
+            continue
+        axis, hi = d // 2, d % 2
+        sl = [slice(None)] * 3
+        sl[2 - axis] = -1 if hi else 0
+        ap = (G.ax, G.ay, G.az)[axis][tuple(sl)]
+        gv = values[d] if not (prob.face_values and d in prob.face_values) else np.asarray(prob.face_values[d])
+        c = 2.0 * beta[tuple(sl)] * ap * ih2
+        b[tuple(sl)] += np.where(cov[tuple(sl)], 0.0, c * gv)
+    bf = b.reshape(-1)
+    A, _, _, _ = embedded_faces(prob)
+    coef = beta.reshape(-1)[G.bidx] * A * ih2
+    bf[G.bidx] += coef * 1.5 * _gcell(prob, G.bidx)
+    covi = np.flatnonzero(cov.reshape(-1))
+    bf[covi] = ih2 * _gcell(prob, covi)
+    return b
+
+
 def solve(prob: EBProblem) -> np.ndarray:
     import scipy.sparse.linalg as spla
     Am, b = assemble(prob)
@@ -199,3 +228,50 @@ def residual(prob: EBProblem, u: np.ndarray):
     Am, b = assemble(prob)
     r = b - Am @ np.asarray(u, dtype=np.float64).reshape(-1)
     return float(np.linalg.norm(r)), float(np.linalg.norm(b))
+
+
+def residual_at(prob: EBProblem, u: np.ndarray, cells) -> np.ndarray:
+    """b - A u at the given flat cell indices, one row at a time (for grids
+    too large to assemble)."""
+    q, G = prob.base, prob.geom
+    nx, ny, nz, h = q.nx, q.ny, q.nz, q.h
+    ih2 = 1.0 / (h * h)
+    uf = np.asarray(u, dtype=np.float64).reshape(-1)
+    beta = None if q.eps is None else np.asarray(q.eps, dtype=np.float64).reshape(-1)
+    bet = (lambda p: 1.0) if beta is None else (lambda p: beta[p])
+    kap = G.kappa.reshape(-1)
+    f = np.asarray(q.f, dtype=np.float64).reshape(-1)
+    types, values = q.bc_types(), q.bc_values()
+    A, nu, idx, w = embedded_faces(prob)
+    pos = {int(p): m for m, p in enumerate(G.bidx)}
+    out = np.empty(len(cells))
+    for t, P in enumerate(cells):
+        P = int(P)
+        k, r = divmod(P, nx * ny)
+        j, i = divmod(r, nx)
+        if kap[P] <= 0:
+            gP = float(prob.g) if np.isscalar(prob.g) else float(np.asarray(prob.g).reshape(-1)[P])
+            out[t] = ih2 * gP - ih2 * uf[P]
+            continue
+        bP = bet(P)
+        acc = kap[P] * q.a * uf[P]
+        rhs_ = kap[P] * f[P]
+        faces = ((G.ax[k, j, i], i > 0, P - 1, 0), (G.ax[k, j, i + 1], i < nx - 1, P + 1, 1),
+                 (G.ay[k, j, i], j > 0, P - nx, 2), (G.ay[k, j + 1, i], j < ny - 1, P + nx, 3),
+                 (G.az[k, j, i], k > 0, P - nx * ny, 4), (G.az[k + 1, j, i], k < nz - 1, P + nx * ny, 5))
+        for al, inside, N, d in faces:
+            if inside:
+                c = al * _harm(bP, bet(N)) * ih2
+                acc += c * (uf[P] - uf[N])
+            elif types[d] == "D":
+                c = 2.0 * bP * al * ih2
+                acc += c * uf[P]
+                rhs_ += c * values[d]
+        if P in pos:
+            m = pos[P]
+            coef = bP * A[m] * ih2
+            acc += coef * (2.0 * (w[m, 0] * uf[idx[m, 0]]).sum() - 0.5 * (w[m, 1] * uf[idx[m, 1]]).sum())
+            gP = float(prob.g) if np.isscalar(prob.g) else float(np.asarray(prob.g).reshape(-1)[P])
+            rhs_ += coef * 1.5 * gP
+        out[t] = rhs_ - acc
+    return out

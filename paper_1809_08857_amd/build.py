@@ -28,7 +28,7 @@ FLAGS = [
 
 LIBS = {
     "libmg.so": ["mg_kern_f64.hip", "mg_kern_f32.hip", "mg_kern_bf16.hip", "mg_misc.hip",
-                 "mg_tail.hip", "mg_engine.hip", "mg_batched.hip", "mg_autotune.hip", "mg_noalloc.hip", "mg_amr.hip"],
+                 "mg_tail.hip", "mg_engine.hip", "mg_batched.hip", "mg_autotune.hip", "mg_noalloc.hip", "mg_krylov.hip", "mg_amr.hip", "mg_eb.hip"],
     "libmgl.so": ["nn_kernels.hip", "nn_net.hip"],
 }
 

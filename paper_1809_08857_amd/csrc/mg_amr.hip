@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "mg_engine.h"
+#include "mg_krylov.h"
 #include "mg_stencil.cuh"
 #include "mga.h"
 
@@ -45,18 +46,6 @@ struct AmrGeo {
 
 constexpr int kAmrMaxBoxes = 256;
 constexpr int kAmrBoxStreams = 4;  // streams for the boxes' V-cycles
-
-// Result slots of the iteration's reductions and its device scalars.
-enum {
-    S_RHO = 0,   // (r^, r)
-    S_RR = 1,    // (r, r)
-    S_RHV = 2,   // (r^, v)
-    S_TS = 3,    // (t, s)
-    S_TT = 4,    // (t, t)
-    S_RHO0 = 5,  // rho of the previous iteration
-    S_ALPHA = 6,
-    S_OMEGA = 7
-};
 
 namespace {
 
@@ -204,92 +193,6 @@ __global__ void amr_rhs_k(double *__restrict__ b, const int *__restrict__ mask, 
     }
 }
 
-// Inner products weighted by cell volume relative to a fine cell: 8 per
-// base cell (covered entries are 0), 1 per fine cell.  Partial pair
-// (x1.y1, x2.y2) per workgroup into reduction slot `slot`.
-__global__ __launch_bounds__(256) void amr_dot_k(const double *__restrict__ x1, const double *__restrict__ y1,
-                                                 const double *__restrict__ x2, const double *__restrict__ y2,
-                                                 long nc, long ntot, RedWs ws, int slot) {
-    double s1 = 0.0, s2 = 0.0, f1 = 0.0, f2 = 0.0;
-    const long stride = (long)gridDim.x * blockDim.x;
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i < nc; i += stride) {
-        s1 += x1[i] * y1[i];
-        if (x2) s2 += x2[i] * y2[i];
-    }
-    for (; i < ntot; i += stride) {
-        f1 += x1[i] * y1[i];
-        if (x2) f2 += x2[i] * y2[i];
-    }
-    reduce2_finish<256>(8.0 * s1 + f1, 8.0 * s2 + f2, ws, slot, blockIdx.x);
-}
-
-__device__ __forceinline__ double beta_of(const double *R) {
-    const double rho0 = R[S_RHO0], om = R[S_OMEGA];
-    return (rho0 != 0.0 && om != 0.0) ? (R[S_RHO] / rho0) * (R[S_ALPHA] / om) : 0.0;
-}
-
-// p = r + beta (p - omega v)
-__global__ __launch_bounds__(256) void amr_p_k(double *__restrict__ p, const double *__restrict__ r,
-                                               const double *__restrict__ v, const double *__restrict__ R, long n) {
-    const double beta = beta_of(R), bw = beta * R[S_OMEGA];
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        p[i] = r[i] + beta * p[i] - bw * v[i];
-}
-
-// s = r - alpha v
-__global__ __launch_bounds__(256) void amr_s_k(double *__restrict__ s, const double *__restrict__ r,
-                                               const double *__restrict__ v, const double *__restrict__ R, long n) {
-    const double al = R[S_ALPHA];
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        s[i] = r[i] - al * v[i];
-}
-
-// x += alpha y + omega z; r = s - omega t; partials of (r^, r) and (r, r)
-__global__ __launch_bounds__(256) void amr_xr_k(double *__restrict__ x, const double *__restrict__ y,
-                                                const double *__restrict__ z, double *__restrict__ r,
-                                                const double *__restrict__ s, const double *__restrict__ t,
-                                                const double *__restrict__ rh, const double *__restrict__ R,
-                                                long nc, long ntot, RedWs ws) {
-    const double al = R[S_ALPHA], om = R[S_OMEGA];
-    double a1 = 0.0, a2 = 0.0, f1 = 0.0, f2 = 0.0;
-    const long stride = (long)gridDim.x * blockDim.x;
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i < ntot; i += stride) {
-        x[i] += al * y[i] + om * z[i];
-        const double ri = s[i] - om * t[i];
-        r[i] = ri;
-        if (i < nc) {
-            a1 += rh[i] * ri;
-            a2 += ri * ri;
-        } else {
-            f1 += rh[i] * ri;
-            f2 += ri * ri;
-        }
-    }
-    reduce2_finish<256>(8.0 * a1 + f1, 8.0 * a2 + f2, ws, S_RHO, blockIdx.x);
-}
-
-// Scalars between the reductions (one thread).  phase 0: alpha = rho /
-// (r^, v); phase 1: omega = (t, s) / (t, t) and rho kept for the next
-// iteration; phase 2: start values (rho0 = alpha = omega = 1).
-__global__ void amr_scalar_k(double *R, int phase) {
-    if (phase == 0) {
-        R[S_ALPHA] = R[S_RHV] != 0.0 ? R[S_RHO] / R[S_RHV] : 0.0;
-    } else if (phase == 1) {
-        R[S_OMEGA] = R[S_TT] > 0.0 ? R[S_TS] / R[S_TT] : 0.0;
-        R[S_RHO0] = R[S_RHO];
-    } else {
-        R[S_RHO0] = R[S_ALPHA] = R[S_OMEGA] = 1.0;
-    }
-}
-
-// out = c1 v1 + c2 v2
-__global__ void amr_axpby_k(double *out, double c1, const double *v1, double c2, const double *v2, long n) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        out[i] = c1 * v1[i] + c2 * v2[i];
-}
-
 // Covered base cells of v: the mean of the eight fine values below them
 // (one thread per covered cell; list of covered cells with their box).
 __global__ void amr_restrict_k(double *__restrict__ v, const long *__restrict__ cov, const int *__restrict__ mask,
@@ -354,7 +257,6 @@ __global__ void amr_mark_k(int *mask, const long *cov, const int *owner, long nc
 }
 
 unsigned grid1(long n) { return (unsigned)std::min<long>(std::max<long>((n + 255) / 256, 1), 16384); }
-unsigned gridr(long n) { return (unsigned)std::min<long>(std::max<long>((n + 255) / 256, 1), kMaxRedBlocks); }
 
 }  // namespace
 }  // namespace mg
@@ -369,9 +271,8 @@ struct mga_ctx {
     long *cf = nullptr, *cov = nullptr;  // base cells beside a box; covered base cells
     long ncf = 0, ncov = 0;
     double *eps = nullptr;  // composite coefficient vector (or null)
-    double *vec = nullptr;  // V_NUM composite vectors
-    mg::RedWs ws{};
-    double *h_pin = nullptr;
+    double *vec = nullptr;  // two composite vectors: x and b (b serves mga_apply's output)
+    mg::KrylovSpace K;      // the iteration's vectors (covered entries stay 0) and reductions
     mg_ctx *base = nullptr;    // base-grid operator with zero boundary values
     std::vector<mg_ctx *> pc;  // one per box, zero values on its boundary
     // the boxes' V-cycles run on a few streams of their own, beside the base cycle
@@ -393,31 +294,9 @@ namespace {
                            __FILE__, __LINE__);                                                    \
     } while (0)
 
-enum { V_X = 0, V_B, V_R, V_RH, V_P, V_V, V_S, V_T, V_Y, V_Z, V_NUM };
+enum { V_X = 0, V_B, V_NUM };
 
 double *vecp(mga_ctx *m, int k) { return m->vec + (size_t)k * m->G.ntot; }
-
-// weighted (x1, y1) [and (x2, y2)] into result slots slot [and slot + 1]
-int dot(mga_ctx *m, const double *x1, const double *y1, const double *x2, const double *y2, int slot) {
-    const unsigned nb = gridr(m->G.ntot);
-    hipLaunchKernelGGL(amr_dot_k, dim3(nb), dim3(256), 0, m->stream, x1, y1, x2, y2, m->G.nc, m->G.ntot, m->ws,
-                       slot);
-    ACK(hipGetLastError());
-    ACK(reduce2_final(m->stream, m->ws, slot, x2 ? slot + 1 : -1, (int)nb, -1, 0.0, nullptr, nullptr));
-    return MG_OK;
-}
-
-int read_slots(mga_ctx *m) {
-    ACK(hipMemcpyAsync(m->h_pin, m->ws.result, kRedSlots * sizeof(double), hipMemcpyDeviceToHost, m->stream));
-    ACK(hipStreamSynchronize(m->stream));
-    return MG_OK;
-}
-
-int scalar(mga_ctx *m, int phase) {
-    hipLaunchKernelGGL(amr_scalar_k, dim3(1), dim3(1), 0, m->stream, m->ws.result, phase);
-    ACK(hipGetLastError());
-    return MG_OK;
-}
 
 // y = A x (x zero on covered cells; y zero there afterwards)
 int apply(mga_ctx *m, const double *x, double *y) {
@@ -582,9 +461,9 @@ int mga_destroy(mga_ctx *m) {
     for (hipEvent_t e : m->join) (void)hipEventDestroy(e);
     if (m->fork) (void)hipEventDestroy(m->fork);
     for (void *p : {(void *)m->dboxes, (void *)m->mask, (void *)m->cf, (void *)m->cov, (void *)m->eps,
-                    (void *)m->vec, (void *)m->ws.partials, (void *)m->ws.result})
+                    (void *)m->vec})
         if (p) (void)hipFree(p);
-    if (m->h_pin) (void)hipHostFree(m->h_pin);
+    krylov_free(m->K);
     delete m;
     return MG_OK;
 }
@@ -665,10 +544,7 @@ int mga_create(const mg_desc *d, int nbox, const mga_box *boxes, void *hip_strea
               hipMalloc(&m->cov, sizeof(long) * std::max<long>(1, m->ncov)) == hipSuccess &&
               hipMalloc(&d_owner, sizeof(int) * std::max<long>(1, m->ncov)) == hipSuccess &&
               hipMalloc(&m->cf, sizeof(long) * std::max<long>(1, m->ncf)) == hipSuccess &&
-              hipMalloc(&m->vec, sizeof(double) * V_NUM * G.ntot) == hipSuccess &&
-              hipMalloc(&m->ws.partials, sizeof(double) * kRedSlots * kMaxRedBlocks * 2) == hipSuccess &&
-              hipMalloc(&m->ws.result, sizeof(double) * kRedSlots) == hipSuccess &&
-              hipHostMalloc((void **)&m->h_pin, sizeof(double) * kRedSlots, hipHostMallocDefault) == hipSuccess;
+              hipMalloc(&m->vec, sizeof(double) * V_NUM * G.ntot) == hipSuccess;
     if (!ok) {
         if (d_owner) (void)hipFree(d_owner);
         mga_destroy(m);
@@ -693,6 +569,11 @@ int mga_create(const mg_desc *d, int nbox, const mga_box *boxes, void *hip_strea
         mga_destroy(m);
         return set_err(MG_EDEVICE, "mga_create: set-up copies or kernels failed");
     }
+    // inner products weigh a base cell 8 fine cells (covered entries are 0)
+    if ((rc = krylov_alloc(m->K, s, G.ntot, G.nc, 8.0))) {
+        mga_destroy(m);
+        return rc;
+    }
     *out = m;
     return MG_OK;
 }
@@ -711,11 +592,12 @@ int mga_set_coeffs(mga_ctx *m, const double *eps_base, const double *const *eps_
         if (!m->eps && hipMalloc(&m->eps, sizeof(double) * m->G.ntot) != hipSuccess)
             return set_err(MG_ENOMEM, "mga_set_coeffs: allocation failed");
         if (int rc = pack(m, m->eps, eps_base, eps_fine)) return rc;
-        ACK(count_bad(s, m->eps, m->G.ntot, m->ws, 0));
-        ACK(hipMemcpyAsync(m->h_pin, m->ws.result, sizeof(double), hipMemcpyDeviceToHost, s));
+        ACK(count_bad(s, m->eps, m->G.ntot, m->K.ws, 0));
+        ACK(hipMemcpyAsync(m->K.h_pin, m->K.ws.result, sizeof(double), hipMemcpyDeviceToHost, s));
         ACK(hipStreamSynchronize(s));
-        if (m->h_pin[0] != 0.0)
-            return set_err(MG_EINVAL, "mga_set_coeffs: %.0f coefficient entries are not in (0, 1e100]", m->h_pin[0]);
+        if (m->K.h_pin[0] != 0.0)
+            return set_err(MG_EINVAL, "mga_set_coeffs: %.0f coefficient entries are not in (0, 1e100]",
+                           m->K.h_pin[0]);
     } else if (m->eps) {
         (void)hipFree(m->eps);
         m->eps = nullptr;
@@ -754,7 +636,7 @@ int mga_apply(mga_ctx *m, const double *x_base, const double *const *x_fine, dou
     if (!m || !x_base || !y_base || (m->G.nbox > 0 && (!x_fine || !y_fine)))
         return set_err(MG_EINVAL, "mga_apply: null argument");
     if (!m->coeffs) return set_err(MG_EINVAL, "mga_apply: mga_set_coeffs has not succeeded");
-    double *x = vecp(m, V_X), *y = vecp(m, V_Y);
+    double *x = vecp(m, V_X), *y = vecp(m, V_B);
     int rc;
     if ((rc = pack(m, x, x_base, x_fine)) || (rc = zero_covered(m, x)) || (rc = apply(m, x, y)) ||
         (rc = unpack(m, y, y_base, y_fine, false)))
@@ -774,10 +656,7 @@ int mga_solve(mga_ctx *m, const double *f_base, const double *const *f_fine, dou
     if (flags & ~(unsigned)MG_GUESS) return set_err(MG_EINVAL, "mga_solve: unknown flags 0x%x", flags);
     hipStream_t s = m->stream;
     const long n = m->G.ntot;
-    const unsigned g1 = grid1(n), gr = gridr(n);
-    double *x = vecp(m, V_X), *b = vecp(m, V_B), *r = vecp(m, V_R), *rh = vecp(m, V_RH), *p = vecp(m, V_P),
-           *v = vecp(m, V_V), *sv = vecp(m, V_S), *t = vecp(m, V_T), *y = vecp(m, V_Y), *z = vecp(m, V_Z);
-    const double *R = m->ws.result;
+    double *x = vecp(m, V_X), *b = vecp(m, V_B);
     int rc;
     if ((rc = pack(m, b, f_base, f_fine))) return rc;
     hipLaunchKernelGGL(amr_rhs_k, dim3(grid1(m->G.nc)), dim3(256), 0, s, b, m->mask, m->eps, m->G);
@@ -787,79 +666,17 @@ int mga_solve(mga_ctx *m, const double *f_base, const double *const *f_fine, dou
     } else {
         ACK(fill_zero(s, x, n * 8));
     }
-    // r = b - A x, r^ = r, the start values of the scalars
-    if ((rc = apply(m, x, r))) return rc;
-    hipLaunchKernelGGL(amr_axpby_k, dim3(g1), dim3(256), 0, s, r, 1.0, b, -1.0, r, n);
-    ACK(hipGetLastError());
-    ACK(hipMemcpyAsync(rh, r, n * 8, hipMemcpyDeviceToDevice, s));
-    ACK(fill_zero(s, p, n * 8));
-    ACK(fill_zero(s, v, n * 8));
-    if ((rc = dot(m, rh, r, r, r, S_RHO)) || (rc = dot(m, b, b, nullptr, nullptr, S_RHV)) || (rc = scalar(m, 2)) ||
-        (rc = read_slots(m)))
-        return rc;
-    const double bn = std::sqrt(m->h_pin[S_RHV]);
     mg_stats S{};
-    if (!std::isfinite(bn) || !std::isfinite(m->h_pin[S_RR]))
-        return set_err(MG_EINVAL, "mga_solve: source or guess not finite");
-    if (bn == 0.0) {
-        ACK(fill_zero(s, x, n * 8));
-        if ((rc = unpack(m, x, x_base, x_fine, true))) return rc;
-        ACK(hipStreamSynchronize(s));
-        if (st) *st = S;
-        return MG_OK;
-    }
-    S.rel_res0 = std::sqrt(m->h_pin[S_RR]) / bn;
-    double rel = S.rel_res0;
-    const double rtol = m->d.rtol;
-    int it = 0, result = MG_NOT_CONVERGED;
-    const char *why = nullptr;
-    // BiCGStab with right preconditioning (van der Vorst), scalars on the device
-    while (rel > rtol && it < m->d.max_cycles) {
-        hipLaunchKernelGGL(amr_p_k, dim3(g1), dim3(256), 0, s, p, r, v, R, n);
-        ACK(hipGetLastError());
-        if ((rc = precond(m, p, y)) || (rc = apply(m, y, v)) || (rc = dot(m, rh, v, nullptr, nullptr, S_RHV)) ||
-            (rc = scalar(m, 0)))
-            return rc;
-        hipLaunchKernelGGL(amr_s_k, dim3(g1), dim3(256), 0, s, sv, r, v, R, n);
-        ACK(hipGetLastError());
-        if ((rc = precond(m, sv, z)) || (rc = apply(m, z, t)) || (rc = dot(m, t, sv, t, t, S_TS)) ||
-            (rc = scalar(m, 1)))
-            return rc;
-        hipLaunchKernelGGL(amr_xr_k, dim3(gr), dim3(256), 0, s, x, y, z, r, sv, t, rh, R, m->G.nc, n, m->ws);
-        ACK(hipGetLastError());
-        ACK(reduce2_final(s, m->ws, S_RHO, S_RR, (int)gr, -1, 0.0, nullptr, nullptr));
-        if ((rc = read_slots(m))) return rc;
-        ++it;
-        const double *H = m->h_pin;
-        rel = std::sqrt(H[S_RR]) / bn;
-        if (!std::isfinite(rel)) {
-            why = "non-finite residual";
-            break;
-        }
-        if (rel <= rtol) break;
-        if (H[S_RHV] == 0.0 || H[S_OMEGA] == 0.0 || H[S_RHO] == 0.0) {
-            why = H[S_RHV] == 0.0 ? "(r^, v) = 0" : H[S_OMEGA] == 0.0 ? "omega = 0" : "rho = 0";
-            break;
-        }
-    }
-    if (!why && rel <= rtol) {
-        // the recursively updated residual drifts: confirm with the true one
-        if ((rc = apply(m, x, r))) return rc;
-        hipLaunchKernelGGL(amr_axpby_k, dim3(g1), dim3(256), 0, s, r, 1.0, b, -1.0, r, n);
-        ACK(hipGetLastError());
-        if ((rc = dot(m, r, r, nullptr, nullptr, S_RR)) || (rc = read_slots(m))) return rc;
-        rel = std::sqrt(m->h_pin[S_RR]) / bn;
-        result = rel <= rtol * 1.01 ? MG_OK : MG_NOT_CONVERGED;
-    }
+    const int res = bicgstab(
+        m->K, [&](const double *u, double *y) { return apply(m, u, y); },
+        [&](double *v, double *z) { return precond(m, v, z); }, b, x, m->d.rtol, m->d.max_cycles, S, "mga_solve");
+    if (res < 0 && res != MG_EDIVERGED) return res;
     if ((rc = unpack(m, x, x_base, x_fine, true))) return rc;
     ACK(hipStreamSynchronize(s));
     if ((rc = timing_flush(m->base))) return rc;
-    S.cycles = it;
-    S.rel_res = rel;
     S.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (st) *st = S;
-    if (why) return set_err(MG_EDIVERGED, "mga_solve: BiCGStab broke down (%s) after %d iterations", why, it);
-    return result;
+    return res;
 }
 
 }  // extern "C"

@@ -544,7 +544,9 @@ __global__ __launch_bounds__(256) void apply_k(const double *__restrict__ x, con
 // The same for a constant or cell coefficient, marching along z with the
 // values of the planes below and above (u, the coefficient and the z face)
 // kept in registers: per cell one new u and coefficient load on the axis
-// plus the four lateral neighbours, and one new z face.
+// plus the four lateral neighbours, and one new z face.  Every load is
+// unconditional (a neighbour outside the box reads the cell itself and is
+// masked), so a plane's loads are all in flight together.
 template <int MODE>
 __global__ __launch_bounds__(256) void apply_z_k(const double *__restrict__ x, const double *__restrict__ eps,
                                                  Geo G, double alpha, double beta, double *__restrict__ y, int kz) {
@@ -552,45 +554,51 @@ __global__ __launch_bounds__(256) void apply_z_k(const double *__restrict__ x, c
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int k0 = blockIdx.z * kz, k1 = min(k0 + kz, G.nz);
     if (i >= G.nx || j >= G.ny) return;
-    const size_t sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
+    const long sy = G.nx, sz = (long)G.nx * G.ny;
     const bool cell = MODE == COEF_CELL;
-    const bool in_x0 = i > 0, in_x1 = i < G.nx - 1, in_y0 = j > 0, in_y1 = j < G.ny - 1;
-    const bool dz0 = (G.bcmask >> 4) & 1, dz1 = (G.bcmask >> 5) & 1;
-    size_t p = (size_t)k0 * sz + (size_t)j * sy + i;
+    // per-thread neighbour offsets (0 outside the box) and the weights of the
+    // lateral boundary faces (2 on a Dirichlet face, else 0)
+    const bool in[4] = {i > 0, i < G.nx - 1, j > 0, j < G.ny - 1};
+    const long off4[4] = {in[0] ? -1 : 0, in[1] ? 1 : 0, in[2] ? -sy : 0, in[3] ? sy : 0};
+    double bw = 0.0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+        if (!in[d] && ((G.bcmask >> d) & 1)) bw += 2.0;
+    const double bz0 = ((G.bcmask >> 4) & 1) ? 2.0 : 0.0, bz1 = ((G.bcmask >> 5) & 1) ? 2.0 : 0.0;
+    long p = (long)k0 * sz + (long)j * sy + i;
     double xc = x[p], ec = cell ? eps[p] : 1.0;
-    double xm = 0.0, fm = dz0 ? 2.0 * ec : 0.0;  // the face below: a Dirichlet domain face or none
+    double xm = 0.0, fm = bz0 * ec;  // the face below: a Dirichlet domain face or none
     if (k0 > 0) {
         xm = x[p - sz];
         fm = cell ? harm_face(ec, eps[p - sz]) : 1.0;
     }
     for (int k = k0; k < k1; ++k, p += sz) {
         const bool up = k < G.nz - 1;
-        double xp = 0.0, ep = 1.0;
-        if (up) {
-            xp = x[p + sz];
-            if (cell) ep = eps[p + sz];
+        const long pu = up ? p + sz : p;
+        double xn[4], en[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) xn[d] = x[p + off4[d]];
+        const double xp_raw = x[pu];
+        const double ep_raw = cell ? eps[pu] : 1.0;
+        if (cell) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) en[d] = eps[p + off4[d]];
         }
-        const double fp = up ? (cell ? harm_face(ec, ep) : 1.0) : (dz1 ? 2.0 * ec : 0.0);
-        double off = fm * xm + fp * xp, dg = fm + fp;
-        auto side = [&](bool in, int d, size_t q) {
-            if (in) {
-                const double f = cell ? harm_face(ec, eps[q]) : 1.0;
-                off += f * x[q];
-                dg += f;
-            } else if ((G.bcmask >> d) & 1) {
-                dg += 2.0 * ec;
-            }
-        };
-        side(in_x0, 0, p - 1);
-        side(in_x1, 1, p + 1);
-        side(in_y0, 2, p - sy);
-        side(in_y1, 3, p + sy);
+        const double xp = up ? xp_raw : 0.0;
+        const double fp = up ? (cell ? harm_face(ec, ep_raw) : 1.0) : bz1 * ec;
+        double off = fm * xm + fp * xp, dg = fm + fp + bw * ec;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const double f = in[d] ? (cell ? harm_face(ec, en[d]) : 1.0) : 0.0;
+            off += f * xn[d];
+            dg += f;
+        }
         const double ax = G.a * xc + G.ih2 * (dg * xc - off);
         y[p] = alpha * xc + beta * ax;
         xm = xc;
         xc = xp;
         fm = fp;
-        ec = ep;
+        ec = up ? ep_raw : ec;
     }
 }
 

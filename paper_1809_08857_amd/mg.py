@@ -101,6 +101,15 @@ def load() -> ctypes.CDLL:
         "mga_solve": (I, [P, P, ctypes.POINTER(P), P, ctypes.POINTER(P), ctypes.c_uint, ctypes.POINTER(MgStats)]),
         "mga_apply": (I, [P, P, ctypes.POINTER(P), P, ctypes.POINTER(P)]),
         "mga_destroy": (I, [P]),
+        "mge_create": (I, [ctypes.POINTER(MgDesc), P, ctypes.POINTER(P)]),
+        "mge_set_geometry": (I, [P, P, P, P, P, ctypes.c_long, ctypes.POINTER(ctypes.c_long), pD, P, D,
+                                 ctypes.POINTER(MgBcs), P, D]),
+        "mge_solve": (I, [P, P, P, ctypes.c_uint, ctypes.POINTER(MgStats)]),
+        "mge_apply": (I, [P, P, P]),
+        "mge_rhs": (I, [P, P, P]),
+        "mge_timing": (I, [P, I]),
+        "mge_timing_read": (I, [P, ctypes.POINTER(ctypes.c_long), pD, pD, ctypes.POINTER(ctypes.c_char_p)]),
+        "mge_destroy": (I, [P]),
         "mga_timing": (I, [P, I]),
         "mga_timing_read": (I, [P, ctypes.POINTER(ctypes.c_long), pD, pD, ctypes.POINTER(ctypes.c_char_p)]),
     }
@@ -334,6 +343,52 @@ def mga_timing_read(ctx) -> Tuple[int, float, str, float]:
 
 def mga_destroy(ctx) -> int:
     return _check(load().mga_destroy(ctx))
+
+
+def mge_create(desc: MgDesc, stream=None) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(load().mge_create(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(ctx)))
+    return ctx
+
+
+def mge_set_geometry(ctx, kappa, ax, ay, az, bidx, boff, eps, a: float, bcs: MgBcs, g=None, g_eb: float = 0.0) -> int:
+    """bidx (int64) and boff ([nb][3] float64) are host numpy arrays; the others device tensors."""
+    import numpy as np
+    bi = np.ascontiguousarray(bidx, dtype=np.int64)
+    bo = np.ascontiguousarray(boff, dtype=np.float64).reshape(-1)
+    return _check(load().mge_set_geometry(
+        ctx, _ptr(kappa), _ptr(ax), _ptr(ay), _ptr(az), bi.size,
+        bi.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), bo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        _ptr(eps), float(a), ctypes.byref(bcs), _ptr(g), float(g_eb)))
+
+
+def mge_solve(ctx, f, x, flags: int = 0) -> Tuple[int, MgStats]:
+    st = MgStats()
+    rc = _check(load().mge_solve(ctx, _ptr(f), _ptr(x), flags, ctypes.byref(st)))
+    return rc, st
+
+
+def mge_apply(ctx, x, y) -> int:
+    return _check(load().mge_apply(ctx, _ptr(x), _ptr(y)))
+
+
+def mge_rhs(ctx, f, b) -> int:
+    return _check(load().mge_rhs(ctx, _ptr(f), _ptr(b)))
+
+
+def mge_timing(ctx, enable: int) -> int:
+    return _check(load().mge_timing(ctx, int(enable)))
+
+
+def mge_timing_read(ctx) -> Tuple[int, float, str, float]:
+    n, ms, by, k = ctypes.c_long(), ctypes.c_double(), ctypes.c_double(), ctypes.c_char_p()
+    _check(load().mge_timing_read(ctx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(k)))
+    per = by.value / n.value if n.value else 0.0
+    return n.value, ms.value, (k.value or b"").decode(), per
+
+
+def mge_destroy(ctx) -> int:
+    return _check(load().mge_destroy(ctx))
 
 
 class Solver:

@@ -168,3 +168,18 @@ def cut_geometry(shape: Shape, nx: int, ny: int, nz: int, h: float, nsub: int = 
     sx, sy, sz = shape.closest(cxp, cyp, czp)
     boff = np.stack([(sx - cxp) / h, (sy - cyp) / h, (sz - czp) / h], axis=1)
     return Geometry(kappa, ax, ay, az, bidx, np.ascontiguousarray(boff), shape.name)
+
+
+def needle_plane(n: int, seed: int = 0, radius: float = NEEDLE_RADIUS, tip_z: float = NEEDLE_TIP_Z, nsub: int = 4):
+    """The needle-plane potential of the paper's large example on n^3 cells
+    of the unit box (a (2 cm)^3 cube): the needle (radius 500 um, tip 1 cm
+    below the top face) and the top face at potential 1, the bottom face
+    grounded, zero flux on the sides; the space charge is the seeded
+    filament recipe (synth.problems.filament_source; its part inside the
+    electrode is not used).  Returns (Problem, Geometry, g)."""
+    from synth.problems import Problem, filament_source
+    h = 1.0 / n
+    G = cut_geometry(needle(radius, tip_z), n, n, n, h, nsub)
+    f = filament_source(n, n, n, seed)
+    bc = (("N", 0.0),) * 4 + (("D", 0.0), ("D", 1.0))
+    return Problem(n, n, n, h, 0.0, f, None, bc, f"needle_plane_s{seed}_{n}"), G, 1.0

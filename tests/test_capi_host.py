@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared(header):
     src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[a-zA-Z_][\w\s\*]*?\b((?:mg|mgl|mga)_\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?[a-zA-Z_][\w\s\*]*?\b((?:mg|mgl|mga|mge)_\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
@@ -27,7 +27,8 @@ def lib():
     return mg.load()
 
 
-@pytest.mark.parametrize("header,libfile", [("mg.h", "libmg.so"), ("mgl.h", "libmgl.so"), ("mga.h", "libmg.so")])
+@pytest.mark.parametrize("header,libfile", [("mg.h", "libmg.so"), ("mgl.h", "libmgl.so"), ("mga.h", "libmg.so"),
+                                                ("mge.h", "libmg.so")])
 def test_every_declared_symbol_is_exported(header, libfile):
     names = _declared(header)
     assert len(names) >= 5

@@ -127,3 +127,19 @@ def test_covered_cells_hold_the_electrode_potential():
     # exceed it)
     gas = u[G.kappa == 1]
     assert gas.min() > 0.0 and gas.max() < 1.0
+
+
+def test_rows_one_at_a_time_match_the_assembled_residual():
+    n = 14
+    rng = np.random.default_rng(3)
+    G = geo.cut_geometry(geo.needle(0.2, 0.45), n, n, n, 1.0 / n)
+    bc = (("N", 0.0), ("D", 0.4), ("N", 0.0), ("N", 0.0), ("D", -0.2), ("D", 1.0))
+    p = Problem(n, n, n, 1.0 / n, 2.5, rng.standard_normal((n, n, n)), np.exp(rng.uniform(-1, 1, (n, n, n))), bc)
+    prob = eb.EBProblem(p, G, 0.8)
+    u = rng.standard_normal((n, n, n))
+    Am, b = eb.assemble(prob)
+    r = b - Am @ u.reshape(-1)
+    cells = np.concatenate([G.bidx[::7], np.flatnonzero(G.kappa.reshape(-1) == 0)[::5], rng.integers(0, n**3, 40)])
+    got = eb.residual_at(prob, u, cells)
+    assert np.allclose(got, r[cells], rtol=1e-12, atol=1e-12 * np.abs(r).max())
+    assert np.allclose(eb.rhs_only(prob).reshape(-1), b, rtol=1e-13, atol=1e-13 * np.abs(b).max())
