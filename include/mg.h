@@ -176,6 +176,19 @@ int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc);
 int mg_set_face_coeffs(mg_ctx *c, const double *bx_dev, const double *by_dev, const double *bz_dev, double a,
                        const mg_bcs *bc);
 
+/* Stored face coefficients plus a per-cell extra diagonal d: the operator
+ * (a + d_P) u - div(beta grad u), as mg_set_face_coeffs with d (device,
+ * nx*ny*nz FP64 in [0, 1e100], copied) and faces allowed to vanish (in
+ * [0, 1e100]); coarse levels take the mean of the 8 children's d.  This is
+ * the symmetric part of a cut-cell operator (Sec. 2, the embedded boundary
+ * formalism): faces scaled by their gas apertures, the embedded face's
+ * diagonal and identity rows for covered cells, used to precondition the
+ * cut-cell solves of mge.h.  MG_FP64 contexts only; every cell needs
+ * a + d + h^-2 (its interior and Dirichlet faces) > 0, else MG_EINVAL.
+ * mg_solve_batched rejects such contexts. */
+int mg_set_face_coeffs_diag(mg_ctx *c, const double *bx_dev, const double *by_dev, const double *bz_dev,
+                            const double *d_dev, double a, const mg_bcs *bc);
+
 /* Solve A x = b with b = f + boundary terms by V-cycles (Sec. 2, item (ii):
  * geometric multigrid with red-black Gauss-Seidel smoothing and a Krylov
  * bottom solver) until ||b - A x||_2 <= rtol ||b||_2.  f_dev and x_dev are

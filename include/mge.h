@@ -23,9 +23,10 @@
  *   - covered cells (kappa = 0) hold u = g.
  * The operator is not symmetric.  mge_solve runs BiCGStab (the Krylov
  * method the paper pairs with its multigrid) on it, preconditioned by one
- * V-cycle of the engine on the regular-grid operator of the same
- * permittivity and box faces without the electrode (covered cells start at
- * g and receive no correction).
+ * V-cycle of the engine on the operator's symmetric part (aperture-weighted
+ * faces, the embedded face's diagonal 1.5 beta A / h^2, identity rows on
+ * covered cells; mg_set_face_coeffs_diag).  Covered cells start at g and
+ * receive no correction.
  *
  * Arrays are FP64 device arrays in C order [z][y][x] unless stated; face
  * arrays use mg_set_face_coeffs's layout (ax [nz][ny][nx+1], ay

@@ -762,6 +762,8 @@ extern "C" int mg_solve_batched(int count, mg_ctx *const *c, const double *const
     for (int i = 0; i < count; ++i) {
         if (!c[i] || !f_dev[i] || !x_dev[i]) return set_err(MG_EINVAL, "mg_solve_batched: null entry %d", i);
         if (!c[i]->coeffs) return set_err(MG_EINVAL, "mg_solve_batched: problem %d has no coefficients", i);
+        if (c[i]->has_diag)
+            return set_err(MG_EINVAL, "mg_solve_batched: problem %d has a per-cell diagonal (single solves only)", i);
         if (c[i]->d.precision != c[0]->d.precision)
             return set_err(MG_EINVAL, "mg_solve_batched: problems must share one precision");
         if (c[i]->stream != c[0]->stream)

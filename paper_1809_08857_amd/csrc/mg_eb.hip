@@ -7,9 +7,12 @@
 // normal ray).  The stencils are built on the device at set-up from the
 // apertures and the surface points.  BiCGStab (mg_krylov) solves the
 // non-symmetric system with one engine V-cycle per preconditioner call on
-// the regular-grid operator of the same permittivity without the electrode;
-// covered cells are fixed at the electrode potential from the start and the
-// preconditioner's output is zero there, so their rows stay satisfied.
+// the symmetric part of the cut-cell operator: the aperture-weighted faces,
+// the diagonal of the embedded face's stencil (its 1.5 beta A / h^2 at the
+// surface) and identity rows for covered cells, set up through
+// mg_set_face_coeffs_diag.  Covered cells are fixed at the electrode
+// potential from the start and the preconditioner's output is zero there,
+// so their rows stay satisfied.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -119,7 +122,8 @@ __global__ void eb_rhs_fix_k(double *__restrict__ b, const long *__restrict__ bi
 __global__ void eb_setup_k(const long *__restrict__ bidx, const double *__restrict__ boff,
                            const double *__restrict__ eps, const double *__restrict__ ax,
                            const double *__restrict__ ay, const double *__restrict__ az, EbGeo G, long nb,
-                           long *__restrict__ sidx, double *__restrict__ sw, double *__restrict__ c15) {
+                           long *__restrict__ sidx, double *__restrict__ sw, double *__restrict__ c15,
+                           double *__restrict__ pc_diag) {
     const long sz = (long)G.nx * G.ny;
     for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < nb; q += (long)gridDim.x * blockDim.x) {
         const long p = bidx[q];
@@ -159,7 +163,47 @@ __global__ void eb_setup_k(const long *__restrict__ bidx, const double *__restri
             }
         }
         c15[q] = 1.5 * coef;
+        pc_diag[p] += 1.5 * coef;  // the stencil's weight at the surface point
     }
+}
+
+// The preconditioner's face coefficients: aperture times the harmonic
+// beta inside, aperture times the cell's beta on the box faces.
+__global__ void eb_pc_faces_k(const double *__restrict__ ax, const double *__restrict__ ay,
+                              const double *__restrict__ az, const double *__restrict__ eps, EbGeo G,
+                              double *__restrict__ bx, double *__restrict__ by, double *__restrict__ bz) {
+    const long nfx = (long)(G.nx + 1) * G.ny * G.nz, nfy = (long)G.nx * (G.ny + 1) * G.nz;
+    const long nfz = (long)G.nx * G.ny * (G.nz + 1), sz = (long)G.nx * G.ny;
+    auto beta = [&](long p) { return eps ? eps[p] : 1.0; };
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < nfx + nfy + nfz;
+         q += (long)gridDim.x * blockDim.x) {
+        if (q < nfx) {
+            const int i = (int)(q % (G.nx + 1));
+            const long row = q / (G.nx + 1);  // k * ny + j
+            const long p = row * G.nx + i;    // the cell above the face (i), if any
+            const double b = i == 0 ? beta(p) : i == G.nx ? beta(p - 1) : harm_face(beta(p - 1), beta(p));
+            bx[q] = ax[q] * b;
+        } else if (q < nfx + nfy) {
+            const long t = q - nfx;
+            const int i = (int)(t % G.nx), j = (int)((t / G.nx) % (G.ny + 1));
+            const long k = t / ((long)G.nx * (G.ny + 1));
+            const long p = (k * G.ny + j) * G.nx + i;
+            const double b = j == 0 ? beta(p) : j == G.ny ? beta(p - G.nx) : harm_face(beta(p - G.nx), beta(p));
+            by[t] = ay[t] * b;
+        } else {
+            const long t = q - nfx - nfy;
+            const long k = t / sz;
+            const double b = k == 0 ? beta(t) : k == G.nz ? beta(t - sz) : harm_face(beta(t - sz), beta(t));
+            bz[t] = az[t] * b;
+        }
+    }
+}
+
+// The preconditioner's diagonal: kappa a, or 1 / h^2 on covered cells; the
+// embedded faces add theirs in eb_setup_k.
+__global__ void eb_pc_diag_k(const double *__restrict__ kappa, EbGeo G, double *__restrict__ d, long n) {
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x)
+        d[p] = kappa[p] <= 0.0 ? G.ih2 : kappa[p] * G.a;
 }
 
 __global__ void eb_set_list_k(double *__restrict__ v, const long *__restrict__ list, long m,
@@ -401,31 +445,40 @@ int mge_set_geometry(mge_ctx *e, const double *kappa, const double *ax, const do
     }
     e->nb = nb;
     if (nb > 0) ECK(hipMemcpy(e->bidx, bidx, 8 * nb, hipMemcpyHostToDevice));
-    double *d_boff = nullptr;
-    if (nb > 0 && hipMalloc(&d_boff, 24 * nb) != hipSuccess) {
+    double *d_boff = nullptr, *pcb = nullptr;  // surface points; the preconditioner's faces and diagonal
+    if ((nb > 0 && hipMalloc(&d_boff, 24 * nb) != hipSuccess) ||
+        hipMalloc(&pcb, 8 * (nfx + nfy + nfz + n)) != hipSuccess) {
+        if (d_boff) (void)hipFree(d_boff);
         free_geometry(e);
         return set_err(MG_ENOMEM, "mge_set_geometry: device allocation failed");
     }
+    double *pbx = pcb, *pby = pcb + nfx, *pbz = pcb + nfx + nfy, *pdiag = pcb + nfx + nfy + nfz;
     if (nb > 0) ECK(hipMemcpy(d_boff, boff, 24 * nb, hipMemcpyHostToDevice));
     e->G.a = a;
     e->G.bcmask = mask;
     for (int f = 0; f < 6; ++f) e->G.g[f] = (mask >> f & 1) ? bc->value[f] : 0.0;
     e->g_eb = g_eb;
+    hipLaunchKernelGGL(eb_pc_faces_k, dim3(grid1(nfx + nfy + nfz)), dim3(256), 0, s, e->ax, e->ay, e->az, e->eps,
+                       e->G, pbx, pby, pbz);
+    hipLaunchKernelGGL(eb_pc_diag_k, dim3(grid1(n)), dim3(256), 0, s, e->kappa, e->G, pdiag, n);
     if (nb > 0)
         hipLaunchKernelGGL(eb_setup_k, dim3(grid1(nb)), dim3(256), 0, s, e->bidx, d_boff, e->eps, e->ax, e->ay,
-                           e->az, e->G, nb, e->sidx, e->sw, e->c15);
+                           e->az, e->G, nb, e->sidx, e->sw, e->c15, pdiag);
     const hipError_t le = hipGetLastError();
     const hipError_t se = hipStreamSynchronize(s);
     if (d_boff) (void)hipFree(d_boff);
+    if (le != hipSuccess || se != hipSuccess) (void)hipFree(pcb);
     ECK(le);
     ECK(se);
-    // the preconditioner's operator: the same permittivity and box faces
-    // (zero values) on the grid without the electrode
+    // the preconditioner's operator: the symmetric part of the cut-cell
+    // operator, zero box-face values (its a enters through the diagonal)
     mg_bcs hb = *bc;
     for (int f = 0; f < 6; ++f) hb.value[f] = 0.0;
-    if (int rc = mg_set_coeffs(e->pc, e->eps, a, &hb)) {
+    const int prc = mg_set_face_coeffs_diag(e->pc, pbx, pby, pbz, pdiag, 0.0, &hb);
+    (void)hipFree(pcb);
+    if (prc != MG_OK) {
         free_geometry(e);
-        return rc;
+        return prc;
     }
     e->ready = true;
     return MG_OK;

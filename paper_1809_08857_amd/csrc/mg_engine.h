@@ -23,6 +23,7 @@ struct Level {
     void *lbx = nullptr, *lby = nullptr, *lbz = nullptr;    // low-precision copies
     double *u = nullptr, *t = nullptr, *b = nullptr;        // FP64 work (levels >= 1)
     void *ul = nullptr, *tl = nullptr, *bl = nullptr;       // low-precision work
+    double *dd = nullptr;                                   // extra diagonal (mg_set_face_coeffs_diag)
 };
 
 // One level as seen by a V-cycle: storage type, operator and arrays.
@@ -68,6 +69,7 @@ struct mg_ctx {
     mg::Level L[mg::kMaxLevels];
     bool has_eps = false;   // variable coefficients: stored faces on the coarse levels
     bool face0 = false;     // the finest level's faces were given (mg_set_face_coeffs)
+    bool has_diag = false;  // faces plus a per-cell diagonal (mg_set_face_coeffs_diag)
     double *eps = nullptr;
     void *eps_lp = nullptr;
     double a = 0.0;

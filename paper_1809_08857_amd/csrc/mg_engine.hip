@@ -83,8 +83,9 @@ Coef level_coef(const Ctx *c, int l, bool lowp) {
         C.eps = lowp ? c->eps_lp : (const void *)c->eps;
         return C;
     }
-    C.mode = COEF_FACE;
+    C.mode = c->has_diag ? COEF_FACED : COEF_FACE;
     const Level &L = c->L[l];
+    C.dd = c->has_diag ? L.dd : nullptr;
     if (lowp) {
         C.bx = L.lbx;
         C.by = L.lby;
@@ -100,7 +101,7 @@ Coef level_coef(const Ctx *c, int l, bool lowp) {
 void build_tail(const Ctx *c, TailDesc &D, bool with_g) {
     std::memset(&D, 0, sizeof D);
     D.nlev = c->nlev - c->tail;
-    D.mode = c->has_eps ? COEF_FACE : COEF_CONST;
+    D.mode = c->has_diag ? COEF_FACED : (c->has_eps ? COEF_FACE : COEF_CONST);
     D.bcmask = c->bcmask;
     for (int d = 0; d < 6; ++d) D.g[d] = (with_g && c->tail == 0) ? c->g[d] : 0.0;
     D.nu1 = std::max(1, c->d.nu1);
@@ -117,6 +118,7 @@ void build_tail(const Ctx *c, TailDesc &D, bool with_g) {
         T.bx = L.fbx;
         T.by = L.fby;
         T.bz = L.fbz;
+        T.dd = c->has_diag ? L.dd : nullptr;
     }
     const TailLevel &Lc = D.L[D.nlev - 1];
     D.cg_maxit = 2 * Lc.nx * Lc.ny * Lc.nz + 50;
@@ -221,7 +223,7 @@ void lowp_view(Ctx *c, std::vector<LvView> &V) {
 }
 
 static const char *mode_name(int m) {
-    return m == COEF_CELL ? "cell-eps" : (m == COEF_FACE ? "face" : "const");
+    return m == COEF_CELL ? "cell-eps" : (m == COEF_FACE ? "face" : (m == COEF_FACED ? "face+diag" : "const"));
 }
 
 // Finest-level smoother launch, bracketed by events while timing is on
@@ -239,7 +241,8 @@ hipError_t timed_smooth(Ctx *c, int l, const LvView &W, bool zin, int tile, int 
     if (e != hipSuccess) return e;
     // algorithmic bytes: read u (unless zero), b and eps once, write u once
     const double es = (double)store_size(W.st);
-    const int arrays = 1 + 1 + (W.C.mode == COEF_CELL ? 1 : 0) + (W.C.mode == COEF_FACE ? 3 : 0) + 1;
+    const int arrays = 1 + 1 + (W.C.mode == COEF_CELL ? 1 : 0) + (is_face_mode(W.C.mode) ? 3 : 0) +
+                       (W.C.mode == COEF_FACED ? 1 : 0) + 1;
     c->ev_bytes[c->ev_used / 2] = (double)W.n * es * arrays;
     c->ev_step[c->ev_used / 2] = c->cur_step;
     c->ev_used += 2;
@@ -518,6 +521,7 @@ int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) 
     const size_t n0 = c->L[0].n;
     c->coeffs = false;
     c->face0 = false;
+    c->has_diag = false;
     if (eps_dev) {
         if (!c->eps) {
             c->eps = (double *)dalloc(c, n0 * 8);
@@ -599,17 +603,17 @@ int mg_set_coeffs(mg_ctx *c, const double *eps_dev, double a, const mg_bcs *bc) 
     return finish_operator(c, a, mask, bc);
 }
 
-int mg_set_face_coeffs(mg_ctx *c, const double *bx_dev, const double *by_dev, const double *bz_dev, double a,
-                       const mg_bcs *bc) {
-    if (!c || !bc || !bx_dev || !by_dev || !bz_dev) return set_err(MG_EINVAL, "mg_set_face_coeffs: null argument");
-    if (c->lp_store >= 0)
-        return set_err(MG_EINVAL, "mg_set_face_coeffs: face coefficients need an MG_FP64 context");
-    int mask = 0, rc = parse_operator("mg_set_face_coeffs", a, bc, &mask);
+static int set_face_impl(const char *who, mg_ctx *c, const double *bx_dev, const double *by_dev,
+                         const double *bz_dev, const double *d_dev, double a, const mg_bcs *bc) {
+    if (!c || !bc || !bx_dev || !by_dev || !bz_dev) return set_err(MG_EINVAL, "%s: null argument", who);
+    if (c->lp_store >= 0) return set_err(MG_EINVAL, "%s: face coefficients need an MG_FP64 context", who);
+    int mask = 0, rc = parse_operator(who, a, bc, &mask);
     if (rc) return rc;
     hipStream_t s = c->stream;
     c->coeffs = false;
     c->face0 = false;
-    if ((rc = alloc_faces(c, "mg_set_face_coeffs"))) return rc;
+    c->has_diag = false;
+    if ((rc = alloc_faces(c, who))) return rc;
     Level &L0 = c->L[0];
     CK(hipMemcpyAsync(L0.fbx, bx_dev, nfaces_x(L0) * 8, hipMemcpyDeviceToDevice, s));
     CK(hipMemcpyAsync(L0.fby, by_dev, nfaces_y(L0) * 8, hipMemcpyDeviceToDevice, s));
@@ -618,18 +622,52 @@ int mg_set_face_coeffs(mg_ctx *c, const double *bx_dev, const double *by_dev, co
     const double *arrs[3] = {L0.fbx, L0.fby, L0.fbz};
     const size_t ns[3] = {nfaces_x(L0), nfaces_y(L0), nfaces_z(L0)};
     for (int q = 0; q < 3; ++q) {
-        CK(count_bad(s, arrs[q], ns[q], c->ws, 0));
+        // with a diagonal, faces may vanish (a cut-cell aperture of 0)
+        if (d_dev) CK(count_outside(s, arrs[q], ns[q], 0.0, kMaxCellCoef, c->ws, 0));
+        else CK(count_bad(s, arrs[q], ns[q], c->ws, 0));
         if ((rc = read_results(c, 1))) return rc;
         bad += c->h_pin[0];
     }
     if (bad != 0.0)
-        return set_err(MG_EINVAL, "mg_set_face_coeffs: %.0f face coefficients are not in (0, 1e100]", bad);
+        return set_err(MG_EINVAL, "%s: %.0f face coefficients are not in %s1e100]", who, bad, d_dev ? "[0, " : "(0, ");
     if ((rc = coarsen_levels(c))) return rc;
+    if (d_dev) {
+        for (int l = 0; l < c->nlev; ++l)
+            if (!c->L[l].dd && !(c->L[l].dd = (double *)dalloc(c, c->L[l].n * 8)))
+                return set_err(MG_ENOMEM, "%s: allocation failed", who);
+        CK(hipMemcpyAsync(L0.dd, d_dev, L0.n * 8, hipMemcpyDeviceToDevice, s));
+        CK(count_outside(s, L0.dd, L0.n, 0.0, kMaxCellCoef, c->ws, 0));
+        if ((rc = read_results(c, 1))) return rc;
+        if (c->h_pin[0] != 0.0)
+            return set_err(MG_EINVAL, "%s: %.0f diagonal entries are not in [0, 1e100]", who, c->h_pin[0]);
+        for (int l = 1; l < c->nlev; ++l)
+            CK(coarsen_cells(s, level_geo(c, l - 1, false), c->L[l - 1].dd, level_geo(c, l, false), c->L[l].dd));
+        // every cell of the finest level needs a positive diagonal
+        Geo G0 = level_geo(c, 0, false);
+        G0.bcmask = mask;
+        G0.a = a;
+        CK(count_singular(s, G0, L0.fbx, L0.fby, L0.fbz, L0.dd, c->ws, 0));
+        if ((rc = read_results(c, 1))) return rc;
+        if (c->h_pin[0] != 0.0)
+            return set_err(MG_EINVAL, "%s: %.0f cells have no positive diagonal (a + d + faces)", who, c->h_pin[0]);
+        c->has_diag = true;
+    }
     c->has_eps = true;
     c->face0 = true;
     c->cscale = 1.0;
     choose_bottom(c);
     return finish_operator(c, a, mask, bc);
+}
+
+int mg_set_face_coeffs(mg_ctx *c, const double *bx_dev, const double *by_dev, const double *bz_dev, double a,
+                       const mg_bcs *bc) {
+    return set_face_impl("mg_set_face_coeffs", c, bx_dev, by_dev, bz_dev, nullptr, a, bc);
+}
+
+int mg_set_face_coeffs_diag(mg_ctx *c, const double *bx_dev, const double *by_dev, const double *bz_dev,
+                            const double *d_dev, double a, const mg_bcs *bc) {
+    if (!d_dev) return set_err(MG_EINVAL, "mg_set_face_coeffs_diag: null argument");
+    return set_face_impl("mg_set_face_coeffs_diag", c, bx_dev, by_dev, bz_dev, d_dev, a, bc);
 }
 
 // Result slots of the reduction workspace used by a solve.

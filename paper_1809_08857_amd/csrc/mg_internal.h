@@ -19,7 +19,9 @@ enum Store { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 };
 //   CONST: beta = 1 everywhere (photon groups).
 //   CELL : harmonic mean of the cell coefficient, computed in the kernel.
 //   FACE : stored face arrays (coarse levels: mean of the 4 fine faces).
-enum CoefMode { COEF_CONST = 0, COEF_CELL = 1, COEF_FACE = 2 };
+// COEF_FACED: stored faces plus a per-cell extra diagonal (FP64 only).
+enum CoefMode { COEF_CONST = 0, COEF_CELL = 1, COEF_FACE = 2, COEF_FACED = 3 };
+constexpr bool is_face_mode(int m) { return m == COEF_FACE || m == COEF_FACED; }
 
 inline size_t store_size(int st) { return st == ST_F64 ? 8 : (st == ST_F32 ? 4 : 2); }
 
@@ -42,6 +44,7 @@ struct Coef {
     const void *bx;     // FACE: (nx+1)*ny*nz
     const void *by;     // FACE: nx*(ny+1)*nz
     const void *bz;     // FACE: nx*ny*(nz+1)
+    const double *dd;   // FACED: nx*ny*nz, added to a cell by cell
 };
 
 // Deterministic reduction workspace: per-block partial sums (kMaxRedBlocks
@@ -194,6 +197,11 @@ hipError_t convert(hipStream_t s, const double *src, int st, void *dst, size_t n
 hipError_t convert_back(hipStream_t s, const void *src, int st, double *dst, size_t n, double factor = 1.0);
 // count of entries that are not finite or not > 0, into ws slot (as double)
 hipError_t count_bad(hipStream_t s, const double *x, size_t n, const RedWs &ws, int slot);
+hipError_t count_outside(hipStream_t s, const double *x, size_t n, double lo, double hi, const RedWs &ws,
+                         int slot);
+hipError_t count_singular(hipStream_t s, const Geo &G, const double *bx, const double *by, const double *bz,
+                          const double *d, const RedWs &ws, int slot);
+hipError_t coarsen_cells(hipStream_t s, const Geo &Gf, const double *f, const Geo &Gc, double *c);
 hipError_t fill_zero(hipStream_t s, void *p, size_t bytes, const int *done = nullptr);
 hipError_t copy_f64(hipStream_t s, const double *src, double *dst, size_t n, const int *done = nullptr);
 
@@ -205,13 +213,14 @@ struct TailLevel {
     int nx, ny, nz;
     double h2, ah2;
     const double *bx, *by, *bz;  // FACE arrays (FP64) or null (CONST)
+    const double *dd;            // FACED: per-cell extra diagonal (read from memory)
     int off_u, off_b;            // LDS offsets (doubles) of iterate and right-hand side
     int off_fx, off_fy, off_fz;  // LDS offsets of the staged face coefficients (FACE)
 };
 
 struct TailDesc {
     int nlev;             // levels handled, >= 1 (the last is the coarsest)
-    int mode;             // COEF_CONST or COEF_FACE
+    int mode;             // COEF_CONST, COEF_FACE or COEF_FACED
     int bcmask;
     double g[6];          // Dirichlet values of the top level (0 for corrections)
     int nu1, nu2, ncyc;   // smoothing sweeps and V-cycles inside the bottom

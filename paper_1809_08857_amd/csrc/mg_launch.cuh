@@ -2,6 +2,8 @@
 // once per storage type (mg_kern_f64.hip, mg_kern_f32.hip, mg_kern_bf16.hip).
 #pragma once
 
+#include <type_traits>
+
 #include "mg_stencil.cuh"
 
 namespace mg {
@@ -29,7 +31,7 @@ hipError_t smooth_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *
     const int nblk = tiles_x * tiles_y * chunks;
     const dim3 grid(nblk), block((TX + 4) / 2 * (TY + 4));
     SmoothArgs<T> A{static_cast<const T *>(uin), static_cast<T *>(uout), static_cast<const T *>(b), eps, bx,
-                    by, bz, G, cz, tiles_x, tiles_y, nblk, done};
+                    by, bz, G, cz, tiles_x, tiles_y, nblk, done, Cf.dd};
     constexpr int PD = kSmoothPDOf<T>;
     const bool even = (G.nx & 1) == 0;
     if (zero_in && even)
@@ -65,6 +67,10 @@ hipError_t smooth_T(hipStream_t s, const Geo &G, const Coef &Cf, const void *uin
         case COEF_CONST: return smooth_mode<T, COEF_CONST>(s, G, Cf, uin, uout, b, zero_in, tile, cz, done);
         case COEF_CELL: return smooth_mode<T, COEF_CELL>(s, G, Cf, uin, uout, b, zero_in, tile, cz, done);
         case COEF_FACE: return smooth_mode<T, COEF_FACE>(s, G, Cf, uin, uout, b, zero_in, tile, cz, done);
+        case COEF_FACED:
+            if constexpr (std::is_same<T, double>::value)
+                return smooth_mode<T, COEF_FACED>(s, G, Cf, uin, uout, b, zero_in, tile, cz, done);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -88,7 +94,7 @@ hipError_t rr_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, c
     const int nwg = (chk.slot >= 0 && nblk > kMaxRedBlocks) ? kMaxRedBlocks : nblk;
     RrArgs<T> A{static_cast<const T *>(u), static_cast<const T *>(b), eps, bx, by, bz, G,
                 static_cast<T *>(bc), cz, tiles_x, tiles_y, nblk, chk.ws, chk.slot, chk.ref_slot,
-                chk.rtol2, chk.done_out, chk.done_in};
+                chk.rtol2, chk.done_out, chk.done_in, Cf.dd};
     hipLaunchKernelGGL((rr_col_k<T, MODE, TX, TY, kSmoothPDOf<T>>), dim3(nwg), dim3(NTH), 0, s, A);
     if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
     if (chk.slot >= 0)
@@ -113,6 +119,9 @@ hipError_t resid_restrict_T(hipStream_t s, const Geo &G, const Coef &Cf, const v
         case COEF_CONST: return rr_mode<T, COEF_CONST>(s, G, Cf, u, b, bc, chk);
         case COEF_CELL: return rr_mode<T, COEF_CELL>(s, G, Cf, u, b, bc, chk);
         case COEF_FACE: return rr_mode<T, COEF_FACE>(s, G, Cf, u, b, bc, chk);
+        case COEF_FACED:
+            if constexpr (std::is_same<T, double>::value) return rr_mode<T, COEF_FACED>(s, G, Cf, u, b, bc, chk);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -154,16 +163,23 @@ hipError_t norm2_T(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, c
     switch (Cf.mode) {
         case COEF_CONST:
             hipLaunchKernelGGL((norm2_resid_k<T, COEF_CONST>), dim3(nwg), block, 0, s, uu, bb, eps,
-                               bx, by, bz, G, ws, slot, bslot, kz, gx, gy, nbrick, din);
+                               bx, by, bz, G, ws, slot, bslot, kz, gx, gy, nbrick, din, nullptr);
             break;
         case COEF_CELL:
             hipLaunchKernelGGL((norm2_resid_k<T, COEF_CELL>), dim3(nwg), block, 0, s, uu, bb, eps,
-                               bx, by, bz, G, ws, slot, bslot, kz, gx, gy, nbrick, din);
+                               bx, by, bz, G, ws, slot, bslot, kz, gx, gy, nbrick, din, nullptr);
             break;
         case COEF_FACE:
             hipLaunchKernelGGL((norm2_resid_k<T, COEF_FACE>), dim3(nwg), block, 0, s, uu, bb, eps,
-                               bx, by, bz, G, ws, slot, bslot, kz, gx, gy, nbrick, din);
+                               bx, by, bz, G, ws, slot, bslot, kz, gx, gy, nbrick, din, nullptr);
             break;
+        case COEF_FACED:
+            if constexpr (std::is_same<T, double>::value) {
+                hipLaunchKernelGGL((norm2_resid_k<T, COEF_FACED>), dim3(nwg), block, 0, s, uu, bb, eps,
+                                   bx, by, bz, G, ws, slot, bslot, kz, gx, gy, nbrick, din, Cf.dd);
+                break;
+            }
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
     if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();

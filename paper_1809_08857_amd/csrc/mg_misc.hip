@@ -150,6 +150,7 @@ hipError_t norm2_b(hipStream_t s, const Geo &G, const Coef &C, const double *f, 
                                gx, gy, nbrick);
             break;
         case COEF_FACE:
+        case COEF_FACED:
             hipLaunchKernelGGL((norm2_b_k<COEF_FACE>), dim3(nwg), block, 0, s, f, eps, bx, by, bz, G, ws, slot, kz,
                                gx, gy, nbrick);
             break;
@@ -170,7 +171,7 @@ int default_tile(const Geo &G, int st, int mode) {
     (void)st;
     // stored faces keep nine face values per plane in flight: the 64 x 16
     // tile (680 threads, at most 168 registers each) would spill them
-    if (mode != COEF_FACE && G.nx >= 64 && G.ny >= 16 && (long)G.nx * G.ny * G.nz >= (8L << 20))
+    if (!is_face_mode(mode) && G.nx >= 64 && G.ny >= 16 && (long)G.nx * G.ny * G.nz >= (8L << 20))
         return 1;                             // 64 x 16
     if (G.nx >= 64) return 3;                 // 64 x 8
     if (G.nx >= 32) return 4;                 // 32 x 8
@@ -426,6 +427,79 @@ hipError_t count_bad(hipStream_t s, const double *x, size_t n, const RedWs &ws, 
     return reduce2_final(s, ws, slot, -1, (int)g, -1, 0.0, nullptr, nullptr);
 }
 
+// Entries outside [lo, hi] (or not finite), counted into ws.result[slot].
+__global__ __launch_bounds__(256) void count_outside_k(const double *__restrict__ x, size_t n, double lo,
+                                                       double hi, RedWs ws, int slot) {
+    double c = 0.0;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const double v = x[t];
+        if (!(v >= lo && v <= hi)) c += 1.0;
+    }
+    reduce2_finish<256>(c, 0.0, ws, slot, blockIdx.x);
+}
+
+hipError_t count_outside(hipStream_t s, const double *x, size_t n, double lo, double hi, const RedWs &ws,
+                         int slot) {
+    size_t g = (n + 255) / 256;
+    if (g > (size_t)kMaxRedBlocks) g = kMaxRedBlocks;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(count_outside_k, dim3(g), dim3(256), 0, s, x, n, lo, hi, ws, slot);
+    if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
+    return reduce2_final(s, ws, slot, -1, (int)g, -1, 0.0, nullptr, nullptr);
+}
+
+// Cells whose diagonal a + d + h^-2 (sum of the faces that count) is not
+// positive: interior faces, and box faces that are Dirichlet.
+__global__ __launch_bounds__(256) void count_singular_k(const double *__restrict__ bx, const double *__restrict__ by,
+                                                        const double *__restrict__ bz, const double *__restrict__ d,
+                                                        Geo G, RedWs ws, int slot) {
+    double c = 0.0;
+    const size_t n = (size_t)G.nx * G.ny * G.nz;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(p % G.nx), j = (int)((p / G.nx) % G.ny), k = (int)(p / ((size_t)G.nx * G.ny));
+        const bool in[6] = {i > 0, i < G.nx - 1, j > 0, j < G.ny - 1, k > 0, k < G.nz - 1};
+        const double f[6] = {face_x(bx, G, i, j, k), face_x(bx, G, i + 1, j, k), face_y(by, G, i, j, k),
+                             face_y(by, G, i, j + 1, k), face_z(bz, G, i, j, k), face_z(bz, G, i, j, k + 1)};
+        double dg = 0.0;
+        for (int q = 0; q < 6; ++q)
+            if (in[q] || ((G.bcmask >> q) & 1)) dg += f[q];
+        if (!(G.a + d[p] + G.ih2 * dg > 0.0)) c += 1.0;
+    }
+    reduce2_finish<256>(c, 0.0, ws, slot, blockIdx.x);
+}
+
+hipError_t count_singular(hipStream_t s, const Geo &G, const double *bx, const double *by, const double *bz,
+                          const double *d, const RedWs &ws, int slot) {
+    size_t g = ((size_t)G.nx * G.ny * G.nz + 255) / 256;
+    if (g > (size_t)kMaxRedBlocks) g = kMaxRedBlocks;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(count_singular_k, dim3(g), dim3(256), 0, s, bx, by, bz, d, G, ws, slot);
+    if (hipPeekAtLastError() != hipSuccess) return hipGetLastError();
+    return reduce2_final(s, ws, slot, -1, (int)g, -1, 0.0, nullptr, nullptr);
+}
+
+// Coarse cell values: the mean of the 8 children (even fine dimensions).
+__global__ void coarsen_cells_k(const double *__restrict__ f, Geo Gf, double *__restrict__ c, Geo Gc) {
+    const size_t n = (size_t)Gc.nx * Gc.ny * Gc.nz;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        const int I = (int)(q % Gc.nx), J = (int)((q / Gc.nx) % Gc.ny), K = (int)(q / ((size_t)Gc.nx * Gc.ny));
+        double s = 0.0;
+        for (int o = 0; o < 8; ++o) {
+            const size_t p = ((size_t)(2 * K + (o >> 2)) * Gf.ny + (2 * J + ((o >> 1) & 1))) * Gf.nx + 2 * I + (o & 1);
+            s += f[p];
+        }
+        c[q] = 0.125 * s;
+    }
+}
+
+hipError_t coarsen_cells(hipStream_t s, const Geo &Gf, const double *f, const Geo &Gc, double *c) {
+    size_t g = ((size_t)Gc.nx * Gc.ny * Gc.nz + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(coarsen_cells_k, dim3(g), dim3(256), 0, s, f, Gf, c, Gc);
+    return hipGetLastError();
+}
+
 // Zero fill by a kernel (a plain kernel node, safe inside captured graphs).
 __global__ void fill_zero_k(uint32_t *__restrict__ p, size_t nwords, uint16_t *tail, int has_tail,
                             const int *__restrict__ done) {
@@ -473,12 +547,12 @@ __global__ __launch_bounds__(256) void resid_out_k(const double *__restrict__ u,
                                                    const double *__restrict__ bx,
                                                    const double *__restrict__ by,
                                                    const double *__restrict__ bz, Geo G,
-                                                   double *__restrict__ r) {
+                                                   double *__restrict__ r, const double *__restrict__ dd) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int k = blockIdx.z;
     if (i >= G.nx || j >= G.ny) return;
-    r[((size_t)k * G.ny + j) * G.nx + i] = resid_global<double, MODE>(u, b, eps, bx, by, bz, G, i, j, k);
+    r[((size_t)k * G.ny + j) * G.nx + i] = resid_global<double, MODE>(u, b, eps, bx, by, bz, G, i, j, k, dd);
 }
 
 hipError_t resid_out(hipStream_t s, const Geo &G, const Coef &C, const double *u, const double *b,
@@ -490,13 +564,16 @@ hipError_t resid_out(hipStream_t s, const Geo &G, const Coef &C, const double *u
                  *by = (const double *)C.by, *bz = (const double *)C.bz;
     switch (C.mode) {
         case COEF_CONST:
-            hipLaunchKernelGGL(resid_out_k<COEF_CONST>, grid, block, 0, s, u, b, eps, bx, by, bz, G, r);
+            hipLaunchKernelGGL(resid_out_k<COEF_CONST>, grid, block, 0, s, u, b, eps, bx, by, bz, G, r, nullptr);
             break;
         case COEF_CELL:
-            hipLaunchKernelGGL(resid_out_k<COEF_CELL>, grid, block, 0, s, u, b, eps, bx, by, bz, G, r);
+            hipLaunchKernelGGL(resid_out_k<COEF_CELL>, grid, block, 0, s, u, b, eps, bx, by, bz, G, r, nullptr);
             break;
         case COEF_FACE:
-            hipLaunchKernelGGL(resid_out_k<COEF_FACE>, grid, block, 0, s, u, b, eps, bx, by, bz, G, r);
+            hipLaunchKernelGGL(resid_out_k<COEF_FACE>, grid, block, 0, s, u, b, eps, bx, by, bz, G, r, nullptr);
+            break;
+        case COEF_FACED:
+            hipLaunchKernelGGL(resid_out_k<COEF_FACED>, grid, block, 0, s, u, b, eps, bx, by, bz, G, r, C.dd);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -510,7 +587,7 @@ template <int MODE>
 __global__ __launch_bounds__(256) void apply_k(const double *__restrict__ x, const double *__restrict__ eps,
                                                const double *__restrict__ bx, const double *__restrict__ by,
                                                const double *__restrict__ bz, Geo G, double alpha, double beta,
-                                               double *__restrict__ y, int kz) {
+                                               double *__restrict__ y, int kz, const double *__restrict__ dd) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int k0 = blockIdx.z * kz, k1 = min(k0 + kz, G.nz);
@@ -537,7 +614,8 @@ __global__ __launch_bounds__(256) void apply_k(const double *__restrict__ x, con
             },
             off, dg);
         const double xP = x[p];
-        const double ax = G.a * xP + G.ih2 * (dg * xP - off);
+        double ax = G.a * xP + G.ih2 * (dg * xP - off);
+        if constexpr (MODE == COEF_FACED) ax += dd[p] * xP;
         y[p] = alpha * xP + beta * ax;
     }
 }
@@ -619,7 +697,12 @@ hipError_t apply_op(hipStream_t s, const Geo &G0, const Coef &C, double alpha, d
             hipLaunchKernelGGL(apply_z_k<COEF_CELL>, grid, block, 0, s, x, eps, G, alpha, beta, y, kz);
             break;
         case COEF_FACE:
-            hipLaunchKernelGGL(apply_k<COEF_FACE>, grid, block, 0, s, x, eps, bx, by, bz, G, alpha, beta, y, kz);
+            hipLaunchKernelGGL(apply_k<COEF_FACE>, grid, block, 0, s, x, eps, bx, by, bz, G, alpha, beta, y, kz,
+                               nullptr);
+            break;
+        case COEF_FACED:
+            hipLaunchKernelGGL(apply_k<COEF_FACED>, grid, block, 0, s, x, eps, bx, by, bz, G, alpha, beta, y, kz,
+                               C.dd);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -308,7 +308,8 @@ __device__ __forceinline__ typename Num<T>::C resid_global(const T *__restrict__
                                                            const coef_t<T> *__restrict__ bx,
                                                            const coef_t<T> *__restrict__ by,
                                                            const coef_t<T> *__restrict__ bz, const Geo &G,
-                                                           int i, int j, int k) {
+                                                           int i, int j, int k,
+                                                           const double *__restrict__ dd = nullptr) {
     using N = Num<T>;
     using C = typename N::C;
     const size_t sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
@@ -334,7 +335,9 @@ __device__ __forceinline__ typename Num<T>::C resid_global(const T *__restrict__
         },
         off, dg);
     const C uP = N::ld(u[p]);
-    return N::ld(b[p]) - C(G.a) * uP - C(G.ih2) * (dg * uP - off);
+    C r = N::ld(b[p]) - C(G.a) * uP - C(G.ih2) * (dg * uP - off);
+    if constexpr (MODE == COEF_FACED) r -= C(dd[p]) * uP;
+    return r;
 }
 
 // ---------------------------------------------------------------------
@@ -365,6 +368,7 @@ template <class T> struct SmoothArgs {
     Geo G;
     int cz, tiles_x, tiles_y, nblk;
     const int *done;
+    const double *dd;  // COEF_FACED: per-cell extra diagonal
 };
 
 // LDS elements (of the compute type) used by one smoother workgroup:
@@ -978,7 +982,7 @@ __device__ __forceinline__ void rbgs_const_body(const SmoothArgs<T> &A, const in
 // face is scaled once on arrival by 2 (Dirichlet) or 0 (Neumann) and the
 // cell beyond it carries u = g, so the update is the plain sum over six
 // faces with no branches.
-template <class T, int TX, int TY, bool ZIN, int PD, bool EVEN>
+template <class T, int TX, int TY, bool ZIN, int PD, bool EVEN, bool DIAG = false>
 __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int blk,
                                                typename Num<T>::C *smem) {
     using N = Num<T>;
@@ -1226,7 +1230,8 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
                 off = fma_c<C>(fU, s_u[ry + 1][lr], off);
                 off = fma_c<C>(fB, pick(um, ro), off);
                 off = fma_c<C>(fA, pick(up, ro), off);
-                const C dg = ((fL + fR) + (fD + fU)) + (fB + fA);
+                C dg = ((fL + fR) + (fD + fU)) + (fB + fA);
+                if constexpr (DIAG) dg = fma_c<C>(h2, C(A.dd[(size_t)k * plane + (ro ? le1 : le0)]), dg);
                 rv = qdiv<C>(fma_c<C>(h2, pick(b0, ro), off), ah2 + dg);
             }
             if (ring) s_r[k & 1][ry][lr] = rv;
@@ -1248,7 +1253,8 @@ __device__ __forceinline__ void rbgs_face_body(const SmoothArgs<T> &A, const int
                 off = fma_c<C>(fU, s_r[kb & 1][ry + 1][lb], off);
                 off = fma_c<C>(fB, rn_prev2, off);
                 off = fma_c<C>(fA, rn_cur, off);
-                const C dg = ((fL + fR) + (fD + fU)) + (fB + fA);
+                C dg = ((fL + fR) + (fD + fU)) + (fB + fA);
+                if constexpr (DIAG) dg = fma_c<C>(h2, C(A.dd[(size_t)kb * plane + (bo ? le1 : le0)]), dg);
                 const C vb = qdiv<C>(fma_c<C>(h2, pick(bm, bo), off), ah2 + dg);
                 T *pk = uout + (size_t)kb * plane;
                 if (even_nx) {
@@ -1519,7 +1525,7 @@ __device__ __forceinline__ void rbgs_col_body(const SmoothArgs<T> &A, const int 
                                               typename Num<T>::C *smem) {
     if constexpr (MODE == COEF_CELL) rbgs_cell_body<T, TX, TY, ZIN, PD, EVEN>(A, blk, smem);
     else if constexpr (MODE == COEF_CONST) rbgs_const_body<T, TX, TY, ZIN, PD, EVEN>(A, blk, smem);
-    else rbgs_face_body<T, TX, TY, ZIN, PD, EVEN>(A, blk, smem);
+    else rbgs_face_body<T, TX, TY, ZIN, PD, EVEN, MODE == COEF_FACED>(A, blk, smem);
 }
 
 // EVEN: the level's rows have even length, so a pair is two adjacent
@@ -1558,6 +1564,7 @@ template <class T> struct RrArgs {
     double rtol2;
     int *done_out;
     const int *done_in;
+    const double *dd;  // COEF_FACED: per-cell extra diagonal
 };
 
 template <int MODE, int TX, int TY> constexpr int rr_lds() {
@@ -1664,7 +1671,7 @@ __device__ __forceinline__ double rr_col_body(const RrArgs<T> &A, const int blk,
     };
     // u (and eps) of plane k with the values of the cells outside the box
     auto masku = [&](P2 v, int k) -> P2 {
-        if constexpr (MODE == COEF_FACE) return vmask(v, k, C(0));
+        if constexpr (is_face_mode(MODE)) return vmask(v, k, C(0));
         else return mask_out(v, k, uout, uz_lo, uz_hi);
     };
     auto maske = [&](P2 v, int k) -> P2 { return mask_out(v, k, eout, ez_lo, ez_hi); };
@@ -1800,6 +1807,7 @@ __device__ __forceinline__ double rr_col_body(const RrArgs<T> &A, const int blk,
                 }
                 const C uP = u0.v[c];
                 rr[c] = b0.v[c] - a * uP - ih2 * (dg * uP - off);
+                if constexpr (MODE == COEF_FACED) rr[c] -= C(A.dd[(size_t)k * plane + (size_t)gy * nx + gxc]) * uP;
             }
             acc += rr[0] + rr[1];
             nrm += (double)rr[0] * (double)rr[0] + (double)rr[1] * (double)rr[1];
@@ -1999,7 +2007,8 @@ __global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, co
                                                      const coef_t<T> *__restrict__ by,
                                                      const coef_t<T> *__restrict__ bz, Geo G, RedWs ws,
                                                      int slot, int bslot, int kz, int gx, int gy, int nbrick,
-                                                     const int *__restrict__ done_in) {
+                                                     const int *__restrict__ done_in,
+                                                     const double *__restrict__ dd = nullptr) {
     if (done_in && *done_in) return;
     using N = Num<T>;
     double sr = 0.0, sb = 0.0;
@@ -2011,7 +2020,7 @@ __global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, co
         if (i >= G.nx || j >= G.ny) continue;
         for (int k = k0; k < k1; ++k) {
             const size_t p = ((size_t)k * G.ny + j) * G.nx + i;
-            const double rv = (double)resid_global<T, MODE>(u, b, eps, bx, by, bz, G, i, j, k);
+            const double rv = (double)resid_global<T, MODE>(u, b, eps, bx, by, bz, G, i, j, k, dd);
             sr += rv * rv;
             if (bslot >= 0) {
                 // b + h^-2 sum_Dirichlet 2 beta_b g  (boundary beta as in the operator)
@@ -2028,7 +2037,7 @@ __global__ __launch_bounds__(256) void norm2_resid_k(const T *__restrict__ u, co
                                              : k == G.nz - 1;
                     if (at && ((G.bcmask >> d) & 1)) {
                         double bf = be;
-                        if constexpr (MODE == COEF_FACE) {
+                        if constexpr (is_face_mode(MODE)) {
                             bf = d == 0   ? (double)face_x(bx, G, i, j, k)
                                  : d == 1 ? (double)face_x(bx, G, i + 1, j, k)
                                  : d == 2 ? (double)face_y(by, G, i, j, k)

@@ -44,7 +44,7 @@ __device__ __forceinline__ void tail_terms(const TailDesc &D, int l, const doubl
         }
     };
     auto en = [&](int) { return 1.0; };
-    if (D.mode == COEF_FACE) {
+    if (D.mode == COEF_FACE || D.mode == COEF_FACED) {
         // face coefficients staged in LDS at the start of the kernel (or in memory)
         const double *fx = D.stage ? lds + L.off_fx : L.bx;
         const double *fy = D.stage ? lds + L.off_fy : L.by;
@@ -60,6 +60,7 @@ __device__ __forceinline__ void tail_terms(const TailDesc &D, int l, const doubl
             }
         };
         six_faces<double, COEF_FACE, true>(G, i, j, k, 1.0, un, en, fb, off, dg);
+        if (D.mode == COEF_FACED) dg = fma(L.h2, L.dd[p], dg);  // the extra diagonal, in h^2 units
     } else {
         six_faces<double, COEF_CONST, true>(G, i, j, k, 1.0, un, en, [&](int) { return 1.0; }, off, dg);
     }
@@ -244,7 +245,7 @@ __device__ void tail_body(const TailDesc &D, const T *__restrict__ b_in, const T
     // precedes the first write of u_out.
     const TailLevel &L0 = D.L[0];
     const int n0 = L0.nx * L0.ny * L0.nz;
-    if (D.mode == COEF_FACE && D.stage) {
+    if ((D.mode == COEF_FACE || D.mode == COEF_FACED) && D.stage) {
         for (int l = 0; l < D.nlev; ++l) {
             const TailLevel &L = D.L[l];
             const int nfx = (L.nx + 1) * L.ny * L.nz, nfy = L.nx * (L.ny + 1) * L.nz,
@@ -333,7 +334,7 @@ bool tail_layout(TailDesc &D) {
     for (int l = 0; l < D.nlev; ++l) {
         TailLevel &L = D.L[l];
         L.off_fx = L.off_fy = L.off_fz = 0;
-        if (D.mode != COEF_FACE || !D.stage) continue;
+        if ((D.mode != COEF_FACE && D.mode != COEF_FACED) || !D.stage) continue;
         L.off_fx = off;
         off += (L.nx + 1) * L.ny * L.nz;
         L.off_fy = off;

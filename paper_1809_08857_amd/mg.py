@@ -84,6 +84,7 @@ def load() -> ctypes.CDLL:
         "mg_smooth_level": (I, [P, I, I, P, P, I, I, I]),
         "mg_set_face_coeffs": (I, [P, P, P, P, D, ctypes.POINTER(MgBcs)]),
         "mg_apply": (I, [P, D, D, P, P]),
+        "mg_set_face_coeffs_diag": (I, [P, P, P, P, P, D, ctypes.POINTER(MgBcs)]),
         "mg_field": (I, [P, P, P, D, P, P, P, pD, pD, pD]),
         "mg_relaxation_substeps": (I, [D, D, D, pI]),
         "mg_tga_step": (I, [P, D, P, P, ctypes.c_uint, ctypes.POINTER(MgStats)]),
@@ -183,6 +184,11 @@ def mg_set_coeffs(ctx, eps, a: float, bcs: MgBcs) -> int:
 
 def mg_set_face_coeffs(ctx, bx, by, bz, a: float, bcs: MgBcs) -> int:
     return _check(load().mg_set_face_coeffs(ctx, _ptr(bx), _ptr(by), _ptr(bz), float(a), ctypes.byref(bcs)))
+
+
+def mg_set_face_coeffs_diag(ctx, bx, by, bz, d, a: float, bcs: MgBcs) -> int:
+    return _check(load().mg_set_face_coeffs_diag(ctx, _ptr(bx), _ptr(by), _ptr(bz), _ptr(d), float(a),
+                                                  ctypes.byref(bcs)))
 
 
 def mg_field(ctx, phi, sigma=None, eps0: float = 1.0, ex=None, ey=None, ez=None) -> Tuple[float, float, float]:
