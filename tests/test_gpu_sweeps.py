@@ -81,6 +81,31 @@ def test_lowp_sweep_parity(prec, zchunk, case):
     assert not bad.any(), (int(bad.sum()), float(np.abs(got - ref).max()), float(np.abs(ref).max()))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("zchunk", [0, 5])
+def test_lowp_beta1_every_tile(prec, tile, zchunk):
+    """The 4- and 2-byte beta = 1 sweep in every tile shape, on a grid whose
+    tiles are ragged in x and y (104 = 64 + 40 cells, 40 rows) and whose
+    z-chunks leave a short last chunk."""
+    p = _problem("const", (104, 40, 24), 90 + tile)
+    print(f"lowp beta=1 sweep {prec} tile {tile} zchunk {zchunk}", flush=True)
+    s = make_solver(p, precision=prec)
+    try:
+        rng = np.random.default_rng(tile * 10 + zchunk)
+        b = _round(rng.standard_normal(p.shape) * 50.0, prec)
+        x0 = _round(rng.standard_normal(p.shape), prec)
+        x = dev(x0)
+        mg.mg_smooth_level(s.ctx, 0, STORE[prec], dev(b), x, 1, tile, zchunk)
+        got = x.cpu().numpy()
+    finally:
+        s.close()
+    ref = oracle.rbgs_level(p, 0, b, x0, 1)
+    tol = 1.01 * HALF_ULP[prec] * np.abs(ref) + 4e-6 * np.abs(ref).max()
+    bad = np.abs(got - ref) > tol
+    assert not bad.any(), (int(bad.sum()), float(np.abs(got - ref).max()), float(np.abs(ref).max()))
+
+
 @pytest.mark.parametrize("zchunk", [0, 1, 3, 8, 9])
 @pytest.mark.parametrize("dims,level", [((64, 32, 48), 1), ((64, 32, 48), 2), ((60, 20, 44), 1),
                                         ((60, 20, 44), 2), ((96, 64, 64), 3)])
