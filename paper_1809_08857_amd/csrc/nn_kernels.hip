@@ -19,7 +19,9 @@
 // tensors.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "nn_internal.h"
 
@@ -60,13 +62,10 @@ __device__ __forceinline__ u32x4 pack8(const unsigned (&e)[8]) {
     return r;
 }
 
-// Epilogue of one lane: output channels co..co+3 of output cell ov.
-__device__ __forceinline__ void store4(const ConvArgs &a, size_t ov, int co, f32x4 acc) {
-    float v[4] = {acc.x, acc.y, acc.z, acc.w};
-    if (a.bias) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] += a.bias[co + r];
-    }
+// Epilogue of one lane: output channels co..co+3 of output cell ov, with
+// the bias of those channels (zero without one) already in registers.
+__device__ __forceinline__ void store4b(const ConvArgs &a, size_t ov, int co, f32x4 acc, f32x4 bias) {
+    float v[4] = {acc.x + bias.x, acc.y + bias.y, acc.z + bias.z, acc.w + bias.w};
     if (a.relu) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
@@ -98,6 +97,33 @@ __device__ __forceinline__ void store4(const ConvArgs &a, size_t ov, int co, f32
     st.x = f2bf(v[0]) | (f2bf(v[1]) << 16);
     st.y = f2bf(v[2]) | (f2bf(v[3]) << 16);
     *reinterpret_cast<u32x2 *>(d + off) = st;
+}
+
+// Two floats -> packed bfloat16 pair (hardware conversion, round to nearest even).
+__device__ __forceinline__ unsigned pk_bf16(float lo, float hi) {
+    typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+    typedef float f32x2_t __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2_t){lo, hi}, bf16x2_t));
+}
+
+__device__ __forceinline__ f32x4 bias4(const ConvArgs &a, int co) {
+    return a.bias ? f32x4{a.bias[co], a.bias[co + 1], a.bias[co + 2], a.bias[co + 3]} : f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Epilogue of one lane: output channels co..co+3 of output cell ov.
+__device__ __forceinline__ void store4(const ConvArgs &a, size_t ov, int co, f32x4 acc) {
+    store4b(a, ov, co, acc, bias4(a, co));
+}
+
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// fences global memory, which makes every wave wait for its outstanding
+// global loads and stores; the z-marching convolution shares only LDS
+// between its waves and keeps loads of the next plane in flight across the
+// barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Hardware block w of n -> logical block, so that each of the 8 XCDs (which
@@ -419,6 +445,226 @@ __global__ __launch_bounds__(256) void conv3_reg_k(ConvArgs a) {
         const size_t ov = ((size_t)oz * a.ony + oy) * a.onx + ox;
 #pragma unroll
         for (int m = 0; m < MTW; ++m) store4(a, ov, (wm * MTW + m) * 16 + grp * 4, acc[m][r]);
+    }
+}
+
+// 3x3x3 convolution marching along z, for 16 or 32 input channels and 16
+// or 32 output channels.  Block: 4 waves on an xy tile of 16 x BY output
+// cells and a chunk of zc output planes.  Wave w owns the 16-channel output
+// tile w % MT and the RW rows (w / MT) * RW + 0..RW-1 of the tile; its
+// weights stay in registers for the whole block.
+//
+// The block streams the input planes zb-1 .. zb+zc through LDS (two
+// slots: the plane being read and the next one, loaded into registers
+// during the products of the current one).  Input plane z' contributes to
+// output planes z'+1, z', z'-1 (taps tz = 0, 1, 2), so each wave keeps
+// three planes of accumulators in a ring; after plane z' the output plane
+// z'-1 is complete and is stored.  Every B operand read from LDS (16 cells
+// of one input row at one x offset) serves the 3 output rows and the 3
+// output planes it reaches: up to 9 MFMAs per LDS read.
+//
+// K-chunks of 32 reduction indices per (ty, tz): with 16 input channels,
+// chunk 0 = taps tx = 0, 1 and chunk 1 = tap tx = 2 (upper half of the
+// weights zero); with 32, chunk c = tap tx = c.
+//
+// The bias enters as the accumulator operand of each output plane's first
+// MFMA, which also starts the plane's accumulators afresh.
+//
+// PLAIN: the epilogue is ReLU (if RELU) into dstA only (no mask, no
+// accumulation, no second destination, dstA under 2 GiB), converted by the
+// hardware's packed bfloat16 conversion.  Its stores are buffer stores
+// issued by every lane in every step, with an offset past the end of the
+// buffer where there is nothing to write (the hardware drops those), so the
+// number of memory operations per step does not depend on a branch and the
+// waits for the next plane's loads do not also wait for the completion of
+// the stores issued after them.
+template <int CIN, int MT, bool PLAIN, bool RELU>
+__global__ __launch_bounds__(256, 2) void conv3_zm_k(ConvArgs a, int zc) {
+    constexpr int RW = 4;                              // output rows per wave
+    constexpr int WR = 4 / MT;                         // wave groups along y
+    constexpr int BY = RW * WR;                        // output rows per block
+    constexpr int HX = 18, HY = BY + 2;
+    constexpr int NV = HX * HY;                        // cells per staged plane
+    constexpr int G8 = CIN / 8;                        // 16-byte groups per cell
+    constexpr int VS = (G8 % 2 == 0) ? CIN + 8 : CIN;  // LDS stride per cell (odd 16-byte count)
+    constexpr int NCK = CIN == 16 ? 2 : 3;             // K-chunks per (ty, tz)
+    constexpr int CPW = 256 / G8;                      // cells staged per pass of the block
+    constexpr int NLD = (NV + CPW - 1) / CPW;          // staging loads per thread and plane
+    constexpr int NVS = NLD * CPW;                     // cells per LDS slot (the last pass whole)
+    static_assert(CIN == 16 || CIN == 32, "16 or 32 input channels");
+    static_assert(MT == 1 || MT == 2, "16 or 32 output channels");
+    __shared__ __align__(16) bf16_t tile[2 * NVS * VS];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int wm = wave % MT, wr = wave / MT;
+    const int cin = a.ca + a.cb;
+    const int ntx = (a.onx + 15) / 16, nty = (a.ony + BY - 1) / BY, ntz = (a.onz + zc - 1) / zc;
+    const int b = xcd_order(blockIdx.x, ntx * nty * ntz);
+    const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
+    const int x0 = bx * 16, y0 = by * BY, zb = bz * zc;
+    const int nout = min(zc, a.onz - zb);  // output planes of this block
+    const int nsteps = nout + 2;           // input planes zb-1 .. zb+nout
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+
+    // this lane's x tap and channel offset in each K-chunk
+    int ctx[NCK], cci[NCK];
+    bool cok[NCK];
+#pragma unroll
+    for (int c = 0; c < NCK; ++c) {
+        if constexpr (CIN == 16) {
+            ctx[c] = c == 0 ? grp / 2 : 2;
+            cci[c] = (grp % 2) * 8;
+            cok[c] = c == 0 || grp < 2;
+        } else {
+            ctx[c] = c;
+            cci[c] = grp * 8;
+            cok[c] = true;
+        }
+    }
+    // weights A[ty][tz][c]: output channel wm*16 + col, reduction lanes of grp
+    u32x4 A[3][3][NCK];
+    {
+        const bf16_t *wr0 = a.w + (size_t)(wm * 16 + col) * 27 * cin;
+#pragma unroll
+        for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+            for (int tz = 0; tz < 3; ++tz)
+#pragma unroll
+                for (int c = 0; c < NCK; ++c) {
+                    const u32x4 w = ld16(wr0 + (tz * 9 + ty * 3 + ctx[c]) * cin + cci[c]);
+                    A[ty][tz][c] = cok[c] ? w : zero;
+                }
+    }
+
+    // staging: thread t loads 8 channels (group t % G8) of cells t / G8 + k * CPW
+    const int q = threadIdx.x % G8, v0 = threadIdx.x / G8;
+    const int ch = q * 8;
+    const bool fromA = ch < a.ca;
+    const bf16_t *sbase = fromA ? a.srcA + ch : a.srcB + (ch - a.ca);
+    const int cs = fromA ? a.ca : a.cb;
+    const size_t plane = (size_t)a.inx * a.iny;
+    // Loads are unconditional (cells outside the grid read cell 0 of the
+    // plane, planes outside read plane 0) and the zeros are put in where
+    // the values are written to LDS, so no load waits under a branch.
+    int soff[NLD];   // cell offset within a plane
+    bool sok[NLD];   // inside the grid and the tile
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int v = v0 + k * CPW;
+        const int hx = v % HX, hy = v / HX;
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+        sok[k] = v < NV && gx >= 0 && gx < a.inx && gy >= 0 && gy < a.iny;
+        soff[k] = sok[k] ? gy * a.inx + gx : 0;
+    }
+    auto load_plane = [&](int z, u32x4 (&R)[NLD]) {
+        const bf16_t *p = sbase + (size_t)(z >= 0 && z < a.inz ? z : 0) * plane * cs;
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) R[k] = ld16(p + (size_t)soff[k] * cs);
+    };
+    auto store_plane = [&](int slot, int z, const u32x4 (&R)[NLD]) {
+        bf16_t *t = tile + slot * (NVS * VS);
+        const bool zok = z >= 0 && z < a.inz;
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const unsigned m = (zok && sok[k]) ? 0xffffffffu : 0u;
+            *reinterpret_cast<u32x4 *>(t + (v0 + k * CPW) * VS + ch) = R[k] & m;
+        }
+    };
+
+    f32x4 acc[3][RW];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int r = 0; r < RW; ++r) acc[p][r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+
+    // B operand addresses: row j of the wave's RW + 2 input rows, chunk c
+    int boff[NCK];
+#pragma unroll
+    for (int c = 0; c < NCK; ++c) boff[c] = ((wr * RW) * HX + col + ctx[c]) * VS + cci[c];
+
+    const f32x4 bv = bias4(a, wm * 16 + grp * 4);
+    // destination as a buffer resource (plain epilogue only)
+    const __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc(
+        a.dstA, (short)0, PLAIN ? (int)((size_t)a.onx * a.ony * a.onz * a.da * sizeof(bf16_t)) : 0, 0x00020000);
+    // R holds the next input plane from the LDS write of one plane to that
+    // of the next, so its loads are in flight across a barrier, an epilogue
+    // and a plane of products.
+    u32x4 R[NLD];
+    load_plane(zb - 1, R);
+    store_plane(0, zb - 1, R);
+    // weights, bias and the first plane are in registers: nothing is left
+    // outstanding that the loop would have to wait for
+    __builtin_amdgcn_s_waitcnt(0);
+    if (nsteps > 1) load_plane(zb, R);
+    lds_barrier();
+
+    const int ox = x0 + col;
+    // plain epilogue: byte offset of each output row of this lane in plane zb, bytes per plane
+    bool rok[RW];
+    unsigned roff[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int oy = y0 + wr * RW + r;
+        rok[r] = ox < a.onx && oy < a.ony;
+        roff[r] = (unsigned)(((((size_t)zb * a.ony + oy) * a.onx + ox) * a.da + wm * 16 + grp * 4) * sizeof(bf16_t));
+    }
+    const unsigned pbytes = (unsigned)((size_t)a.onx * a.ony * a.da * sizeof(bf16_t));
+    // input plane zb - 1 + s; S3 = s % 3 fixes the accumulator ring at compile time
+    auto step = [&](auto s3c, int s) {
+        constexpr int S3 = decltype(s3c)::value;
+        const bf16_t *t = tile + (s & 1) * (NVS * VS);
+#pragma unroll
+        for (int j = 0; j < RW + 2; ++j) {
+            u32x4 B[NCK];
+#pragma unroll
+            for (int c = 0; c < NCK; ++c) B[c] = *reinterpret_cast<const u32x4 *>(t + boff[c] + j * HX * VS);
+#pragma unroll
+            for (int c = 0; c < NCK; ++c)
+#pragma unroll
+                for (int r = j - 2; r <= j; ++r)
+                    if (r >= 0 && r < RW)
+#pragma unroll
+                        for (int tz = 0; tz < 3; ++tz) {
+                            // the first product into output plane zb + s (tap tz = 0) starts from the bias
+                            f32x4 &d = acc[(S3 + 3 - tz) % 3][r];
+                            d = mfma(A[j - r][tz][c], B[c], (tz == 0 && j == r && c == 0) ? bv : d);
+                        }
+        }
+        if (s + 1 < nsteps) store_plane((s + 1) & 1, zb + s, R);
+        if (s + 2 < nsteps) load_plane(zb + s + 1, R);
+        lds_barrier();
+        // output plane zb + s - 2 is complete
+        constexpr int P = (S3 + 1) % 3;
+        const int oz = zb + s - 2;
+        if constexpr (PLAIN) {
+            const unsigned pofs = (unsigned)(s - 2) * pbytes;
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                f32x4 v = acc[P][r];
+                if constexpr (RELU) {
+                    v.x = fmaxf(v.x, 0.f), v.y = fmaxf(v.y, 0.f);
+                    v.z = fmaxf(v.z, 0.f), v.w = fmaxf(v.w, 0.f);
+                }
+                u32x2 st;
+                st.x = pk_bf16(v.x, v.y);
+                st.y = pk_bf16(v.z, v.w);
+                __builtin_amdgcn_raw_buffer_store_b64(st, dst, (s >= 2 && rok[r]) ? roff[r] + pofs : 0x80000000u, 0, 0);
+            }
+        } else if (s >= 2) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const int oy = y0 + wr * RW + r;
+                if (ox < a.onx && oy < a.ony)
+                    store4b(a, ((size_t)oz * a.ony + oy) * a.onx + ox, wm * 16 + grp * 4, acc[P][r], zero4);
+            }
+        }
+    };
+    for (int s = 0; s < nsteps; s += 3) {
+        step(std::integral_constant<int, 0>{}, s);
+        if (s + 1 < nsteps) step(std::integral_constant<int, 1>{}, s + 1);
+        if (s + 2 < nsteps) step(std::integral_constant<int, 2>{}, s + 2);
     }
 }
 
@@ -1022,9 +1268,35 @@ hipError_t lds_tile(hipStream_t s, const ConvArgs &a) {
     }
 }
 
+// z-marching kernel: the block count is raised towards two blocks per CU by
+// splitting z into chunks, each chunk keeping at least 8 output planes
+// (every chunk re-reads two halo planes).
+template <int CIN, int MT>
+hipError_t zm_launch(hipStream_t s, const ConvArgs &a) {
+    constexpr int BY = 16 / MT;
+    const long txy = (long)((a.onx + 15) / 16) * ((a.ony + BY - 1) / BY);
+    const long want = (512 + txy - 1) / txy;
+    int zc = (int)((a.onz + want - 1) / want);
+    zc = std::max(zc, std::min(8, a.onz));
+    const long nb = txy * ((a.onz + zc - 1) / zc);
+    const bool plain = !a.maskA && !a.maskB && !a.accA && !a.accB && a.db == 0 &&
+                       (size_t)a.onx * a.ony * a.onz * a.da * sizeof(bf16_t) < (1ull << 31);
+    if (plain && a.relu)
+        conv3_zm_k<CIN, MT, true, true><<<(unsigned)nb, 256, 0, s>>>(a, zc);
+    else if (plain)
+        conv3_zm_k<CIN, MT, true, false><<<(unsigned)nb, 256, 0, s>>>(a, zc);
+    else
+        conv3_zm_k<CIN, MT, false, false><<<(unsigned)nb, 256, 0, s>>>(a, zc);
+    return hipGetLastError();
+}
+
 template <int COUT>
 hipError_t lds_cc(hipStream_t s, const ConvArgs &a) {
     const int cin = a.ca + a.cb;
+    if constexpr (COUT == 16 || COUT == 32) {
+        if (cin == 16) return zm_launch<16, COUT / 16>(s, a);
+        if (cin == 32) return zm_launch<32, COUT / 16>(s, a);
+    }
     if (cin == 8) return lds_tile<COUT, 8>(s, a);
     if (cin == 16) return lds_tile<COUT, 16>(s, a);
     if (cin % 32 == 0 && a.ca % 8 == 0) return lds_tile<COUT, 32>(s, a);
