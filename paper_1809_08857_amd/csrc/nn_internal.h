@@ -105,12 +105,6 @@ hipError_t head_predict(hipStream_t s, const bf16_t *a, const double *src, int n
 int head_train_blocks(int nx, int ny, int nz);
 hipError_t head_train(hipStream_t s, const bf16_t *a, const double *src, int nx, int ny, int nz, const float *wh,
                       const float *bh, const double *sigma, const float *t, bf16_t *ga, float *partials);
-// First layer (1 -> 16 channels, 3x3x3): out = ReLU(b + W x) with x the
-// bfloat16-rounded s / sigma and W the bfloat16 weights wf[16][27][8]
-// (channel 0 used), FP32 arithmetic.
-hipError_t conv_in(hipStream_t s, const double *src, int nx, int ny, int nz, const double *sigma, const bf16_t *wf,
-                   const float *bias, bf16_t *out);
-
 // Targets: t[v][i] = kappa2_i psi_i[v] / (*sigma * scale_i) (FP32), and
 // max_i |t| into maxbits[i] (as float bit patterns; must start at 0).
 hipError_t make_target(hipStream_t s, const double *psi0, const double *psi1, const double *psi2,

@@ -172,13 +172,16 @@ __global__ __launch_bounds__(256) void conv_k(ConvArgs a) {
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const u32x4 zero = {0u, 0u, 0u, 0u};
 
-    for (int c = 0; c < nchunk; ++c) {
+    // Operands of chunk c + 1 are loaded before the products of chunk c.
+    // Loads are unconditional (from clamped addresses) and the operands
+    // outside the reduction range or the grid are zeroed by a mask where
+    // they are used, so that no load is waited for under a branch.
+    auto fetch = [&](int c, u32x4 (&A)[MT], u32x4 (&B)[NT], unsigned &am, unsigned (&bm)[NT]) {
         const int k0 = c * 32 + grp * 8;
         const bool kok = k0 < K;
         const int tap = kok ? k0 / cin : 0;
-        const int ci = k0 - tap * cin;
+        const int ci = kok ? k0 - tap * cin : 0;
         const bf16_t *src;
         int cs, cl;
         if (ci < a.ca) {
@@ -197,13 +200,9 @@ __global__ __launch_bounds__(256) void conv_k(ConvArgs a) {
             dx = tap & 1;
         }
         const int wt = GEOM == G_UP2 ? par : tap;
-        u32x4 A[MT];
+        am = kok ? 0xffffffffu : 0u;
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const int co = m * 16 + col;
-            A[m] = kok ? ld16(a.w + ((size_t)co * WT + wt) * cin + ci) : zero;
-        }
-        u32x4 B[NT];
+        for (int m = 0; m < MT; ++m) A[m] = ld16(a.w + ((size_t)(m * 16 + col) * WT + wt) * cin + ci);
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
             const int z = z0 + n;
@@ -217,12 +216,29 @@ __global__ __launch_bounds__(256) void conv_k(ConvArgs a) {
             } else {
                 sx = x, sy = y, sz = z;
             }
-            B[n] = ok ? ld16(src + (((size_t)sz * a.iny + sy) * a.inx + sx) * cs + cl) : zero;
+            sx = min(max(sx, 0), a.inx - 1), sy = min(max(sy, 0), a.iny - 1), sz = min(max(sz, 0), a.inz - 1);
+            bm[n] = ok ? 0xffffffffu : 0u;
+            B[n] = ld16(src + (((size_t)sz * a.iny + sy) * a.inx + sx) * cs + cl);
         }
+    };
+    u32x4 An[MT], Bn[NT];
+    unsigned amn, bmn[NT];
+    fetch(0, An, Bn, amn, bmn);
+    for (int c = 0; c < nchunk; ++c) {
+        u32x4 A[MT], B[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) A[m] = An[m];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) B[n] = Bn[n];
+        const unsigned am = amn;
+        unsigned bm[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) bm[n] = bmn[n];
+        if (c + 1 < nchunk) fetch(c + 1, An, Bn, amn, bmn);
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
-            for (int n = 0; n < NT; ++n) acc[m][n] = mfma(A[m], B[n], acc[m][n]);
+            for (int n = 0; n < NT; ++n) acc[m][n] = mfma(A[m] & am, B[n] & bm[n], acc[m][n]);
     }
 
     int px = 0, py = 0, pz = 0;
@@ -240,6 +256,55 @@ __global__ __launch_bounds__(256) void conv_k(ConvArgs a) {
         const size_t ov = ((size_t)oz * a.ony + oy) * a.onx + ox;
 #pragma unroll
         for (int m = 0; m < MT; ++m) store4(a, ov, m * 16 + grp * 4, acc[m][n]);
+    }
+}
+
+// Transposed stride-2 convolution (UP2) with 32 input channels (one K-chunk)
+// and 16 or 32 output channels.  Wave w of a block owns 16 coarse cells of
+// row 4 * blockIdx.y + w on NT coarse planes: it reads each coarse row once
+// and forms all 8 output parities from it (8 MFMAs per 16-channel tile, the
+// weights of every parity in registers).  The parities px = 0, 1 of a lane
+// are adjacent fine cells, so the stores of a fine row are contiguous.
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void up2_k(ConvArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int x = blockIdx.x * 16 + col, y = blockIdx.y * 4 + wave, z0 = blockIdx.z * NT;
+    const bool colok = x < a.inx && y < a.iny;
+    u32x4 A[8][MT];
+    f32x4 bv[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        bv[m] = bias4(a, m * 16 + grp * 4);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) A[p][m] = ld16(a.w + ((size_t)(m * 16 + col) * 8 + p) * 32 + grp * 8);
+    }
+    // coarse cells outside the grid read a clamped cell and store nothing
+    const int ch = grp * 8;
+    const bf16_t *src = ch < a.ca ? a.srcA + ch : a.srcB + (ch - a.ca);
+    const int cs = ch < a.ca ? a.ca : a.cb;
+    const int xc = min(x, a.inx - 1), yc = min(y, a.iny - 1);
+    u32x4 B[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int zc = min(z0 + n, a.inz - 1);
+        B[n] = ld16(src + (((size_t)zc * a.iny + yc) * a.inx + xc) * cs);
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int z = z0 + n;
+        f32x4 acc[8][MT];
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[p][m] = mfma(A[p][m], B[n], bv[m]);
+        if (!colok || z >= a.inz) continue;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const size_t ov = ((size_t)(2 * z + (p >> 2)) * a.ony + 2 * y + ((p >> 1) & 1)) * a.onx + 2 * x + (p & 1);
+#pragma unroll
+            for (int m = 0; m < MT; ++m) store4b(a, ov, m * 16 + grp * 4, acc[p][m], f32x4{0.f, 0.f, 0.f, 0.f});
+        }
     }
 }
 
@@ -448,11 +513,12 @@ __global__ __launch_bounds__(256) void conv3_reg_k(ConvArgs a) {
     }
 }
 
-// 3x3x3 convolution marching along z, for 16 or 32 input channels and 16
-// or 32 output channels.  Block: 4 waves on an xy tile of 16 x BY output
-// cells and a chunk of zc output planes.  Wave w owns the 16-channel output
-// tile w % MT and the RW rows (w / MT) * RW + 0..RW-1 of the tile; its
-// weights stay in registers for the whole block.
+// 3x3x3 convolution marching along z, for 8, 16, 32 or 64 input channels
+// and 16, 32 or 64 output channels.  Block: NWV waves on an xy tile of
+// 16 x BY output cells and a chunk of zc output planes.  A wave owns one
+// 16-channel output tile (wm), one share of the input channels (kh of KS,
+// CK channels each) and RW rows of the tile (row group wr); its weights
+// stay in registers for the whole block.
 //
 // The block streams the input planes zb-1 .. zb+zc through LDS (two
 // slots: the plane being read and the next one, loaded into registers
@@ -463,12 +529,20 @@ __global__ __launch_bounds__(256) void conv3_reg_k(ConvArgs a) {
 // of one input row at one x offset) serves the 3 output rows and the 3
 // output planes it reaches: up to 9 MFMAs per LDS read.
 //
-// K-chunks of 32 reduction indices per (ty, tz): with 16 input channels,
-// chunk 0 = taps tx = 0, 1 and chunk 1 = tap tx = 2 (upper half of the
-// weights zero); with 32, chunk c = tap tx = c.
+// K-chunks of 32 reduction indices per (ty, tz), over the wave's CK
+// channels: with 8, one chunk of the taps tx = 0, 1, 2 (last quarter of the
+// weights zero); with 16, chunk 0 = taps tx = 0, 1 and chunk 1 = tap tx = 2
+// (upper half of the weights zero); with 32, chunk c = tap tx = c.
+//
+// With the input channels split over two waves (KS = 2, 64 input
+// channels), the wave with kh = 0 stores the even rows and the other the
+// odd rows: before the plane's barrier each wave writes to LDS its partial
+// sums of the rows the other one stores, and adds the other's partial sums
+// of its own rows after it (two LDS slots of partial sums, by plane parity).
 //
 // The bias enters as the accumulator operand of each output plane's first
-// MFMA, which also starts the plane's accumulators afresh.
+// MFMA (in the wave with kh = 0), which also starts the plane's
+// accumulators afresh.
 //
 // PLAIN: the epilogue is ReLU (if RELU) into dstA only (no mask, no
 // accumulation, no second destination, dstA under 2 GiB), converted by the
@@ -478,26 +552,39 @@ __global__ __launch_bounds__(256) void conv3_reg_k(ConvArgs a) {
 // number of memory operations per step does not depend on a branch and the
 // waits for the next plane's loads do not also wait for the completion of
 // the stores issued after them.
-template <int CIN, int MT, bool PLAIN, bool RELU>
-__global__ __launch_bounds__(256, 2) void conv3_zm_k(ConvArgs a, int zc) {
+template <int MT, int KS>
+constexpr int zm_waves() {
+    return MT * KS <= 4 ? 4 : MT * KS;
+}
+
+template <int CIN, int MT, int KS, bool PLAIN, bool RELU>
+__global__ __launch_bounds__((64 * zm_waves<MT, KS>()), (8 / zm_waves<MT, KS>())) void conv3_zm_k(ConvArgs a, int zc) {
+    constexpr int NWV = zm_waves<MT, KS>();            // waves per block
+    constexpr int NTH = 64 * NWV;
+    constexpr int CK = CIN / KS;                       // input channels per wave
     constexpr int RW = 4;                              // output rows per wave
-    constexpr int WR = 4 / MT;                         // wave groups along y
+    constexpr int WR = NWV / (MT * KS);                // wave groups along y
     constexpr int BY = RW * WR;                        // output rows per block
     constexpr int HX = 18, HY = BY + 2;
     constexpr int NV = HX * HY;                        // cells per staged plane
     constexpr int G8 = CIN / 8;                        // 16-byte groups per cell
     constexpr int VS = (G8 % 2 == 0) ? CIN + 8 : CIN;  // LDS stride per cell (odd 16-byte count)
-    constexpr int NCK = CIN == 16 ? 2 : 3;             // K-chunks per (ty, tz)
-    constexpr int CPW = 256 / G8;                      // cells staged per pass of the block
+    constexpr int NCK = CK == 32 ? 3 : (CK == 16 ? 2 : 1);  // K-chunks per (ty, tz)
+    constexpr int CPW = NTH / G8;                      // cells staged per pass of the block
     constexpr int NLD = (NV + CPW - 1) / CPW;          // staging loads per thread and plane
     constexpr int NVS = NLD * CPW;                     // cells per LDS slot (the last pass whole)
-    static_assert(CIN == 16 || CIN == 32, "16 or 32 input channels");
-    static_assert(MT == 1 || MT == 2, "16 or 32 output channels");
+    constexpr int RS = RW / KS;                        // rows a wave stores
+    static_assert(CK == 8 || CK == 16 || CK == 32, "8, 16 or 32 input channels per wave");
+    static_assert(KS == 1 || KS == 2, "input channels split over at most two waves");
+    static_assert(NWV % (MT * KS) == 0, "whole wave groups");
+    static_assert(KS == 1 || WR == 1, "the partial sums are indexed by output tile and row only");
     __shared__ __align__(16) bf16_t tile[2 * NVS * VS];
+    __shared__ __align__(16) f32x4 part[KS == 2 ? 2 * MT * RW * 64 : 1];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
-    const int wm = wave % MT, wr = wave / MT;
+    const int wm = wave % MT, kh = (wave / MT) % KS, wr = wave / (MT * KS);
+    const int kc = kh * CK;  // first input channel of this wave
     const int cin = a.ca + a.cb;
     const int ntx = (a.onx + 15) / 16, nty = (a.ony + BY - 1) / BY, ntz = (a.onz + zc - 1) / zc;
     const int b = xcd_order(blockIdx.x, ntx * nty * ntz);
@@ -512,7 +599,11 @@ __global__ __launch_bounds__(256, 2) void conv3_zm_k(ConvArgs a, int zc) {
     bool cok[NCK];
 #pragma unroll
     for (int c = 0; c < NCK; ++c) {
-        if constexpr (CIN == 16) {
+        if constexpr (CK == 8) {
+            ctx[c] = grp < 3 ? grp : 2;
+            cci[c] = 0;
+            cok[c] = grp < 3;
+        } else if constexpr (CK == 16) {
             ctx[c] = c == 0 ? grp / 2 : 2;
             cci[c] = (grp % 2) * 8;
             cok[c] = c == 0 || grp < 2;
@@ -521,6 +612,7 @@ __global__ __launch_bounds__(256, 2) void conv3_zm_k(ConvArgs a, int zc) {
             cci[c] = grp * 8;
             cok[c] = true;
         }
+        cci[c] += kc;
     }
     // weights A[ty][tz][c]: output channel wm*16 + col, reduction lanes of grp
     u32x4 A[3][3][NCK];
@@ -537,16 +629,16 @@ __global__ __launch_bounds__(256, 2) void conv3_zm_k(ConvArgs a, int zc) {
                 }
     }
 
-    // staging: thread t loads 8 channels (group t % G8) of cells t / G8 + k * CPW
+    // staging: thread t loads 8 channels (group t % G8) of cells t / G8 + k * CPW.
+    // Loads are unconditional (cells outside the grid read cell 0 of the
+    // plane, planes outside read plane 0) and the zeros are put in where
+    // the values are written to LDS, so no load waits under a branch.
     const int q = threadIdx.x % G8, v0 = threadIdx.x / G8;
     const int ch = q * 8;
     const bool fromA = ch < a.ca;
     const bf16_t *sbase = fromA ? a.srcA + ch : a.srcB + (ch - a.ca);
     const int cs = fromA ? a.ca : a.cb;
     const size_t plane = (size_t)a.inx * a.iny;
-    // Loads are unconditional (cells outside the grid read cell 0 of the
-    // plane, planes outside read plane 0) and the zeros are put in where
-    // the values are written to LDS, so no load waits under a branch.
     int soff[NLD];   // cell offset within a plane
     bool sok[NLD];   // inside the grid and the tile
 #pragma unroll
@@ -585,6 +677,7 @@ __global__ __launch_bounds__(256, 2) void conv3_zm_k(ConvArgs a, int zc) {
     for (int c = 0; c < NCK; ++c) boff[c] = ((wr * RW) * HX + col + ctx[c]) * VS + cci[c];
 
     const f32x4 bv = bias4(a, wm * 16 + grp * 4);
+    const f32x4 bstart = kh == 0 ? bv : zero4;  // the bias enters once
     // destination as a buffer resource (plain epilogue only)
     const __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc(
         a.dstA, (short)0, PLAIN ? (int)((size_t)a.onx * a.ony * a.onz * a.da * sizeof(bf16_t)) : 0, 0x00020000);
@@ -601,14 +694,15 @@ __global__ __launch_bounds__(256, 2) void conv3_zm_k(ConvArgs a, int zc) {
     lds_barrier();
 
     const int ox = x0 + col;
-    // plain epilogue: byte offset of each output row of this lane in plane zb, bytes per plane
-    bool rok[RW];
-    unsigned roff[RW];
+    // rows this wave stores: r = KS * i + kh; plain epilogue: their byte
+    // offsets in plane zb and the bytes per plane
+    bool rok[RS];
+    unsigned roff[RS];
 #pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const int oy = y0 + wr * RW + r;
-        rok[r] = ox < a.onx && oy < a.ony;
-        roff[r] = (unsigned)(((((size_t)zb * a.ony + oy) * a.onx + ox) * a.da + wm * 16 + grp * 4) * sizeof(bf16_t));
+    for (int i = 0; i < RS; ++i) {
+        const int oy = y0 + wr * RW + KS * i + kh;
+        rok[i] = ox < a.onx && oy < a.ony;
+        roff[i] = (unsigned)(((((size_t)zb * a.ony + oy) * a.onx + ox) * a.da + wm * 16 + grp * 4) * sizeof(bf16_t));
     }
     const unsigned pbytes = (unsigned)((size_t)a.onx * a.ony * a.da * sizeof(bf16_t));
     // input plane zb - 1 + s; S3 = s % 3 fixes the accumulator ring at compile time
@@ -629,20 +723,38 @@ __global__ __launch_bounds__(256, 2) void conv3_zm_k(ConvArgs a, int zc) {
                         for (int tz = 0; tz < 3; ++tz) {
                             // the first product into output plane zb + s (tap tz = 0) starts from the bias
                             f32x4 &d = acc[(S3 + 3 - tz) % 3][r];
-                            d = mfma(A[j - r][tz][c], B[c], (tz == 0 && j == r && c == 0) ? bv : d);
+                            d = mfma(A[j - r][tz][c], B[c], (tz == 0 && j == r && c == 0) ? bstart : d);
                         }
+        }
+        // output plane zb + s - 2 is complete (in acc[P]); the rows this wave stores
+        constexpr int P = (S3 + 1) % 3;
+        f32x4 out[RS];
+        if constexpr (KS == 2) {
+            // partial sums of the other wave's rows to LDS
+            f32x4 *pw = part + ((s & 1) * MT + wm) * RW * 64 + lane;
+#pragma unroll
+            for (int i = 0; i < RS; ++i) {
+                pw[(2 * i + 1 - kh) * 64] = kh ? acc[P][2 * i] : acc[P][2 * i + 1];
+                out[i] = kh ? acc[P][2 * i + 1] : acc[P][2 * i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < RS; ++i) out[i] = acc[P][i];
         }
         if (s + 1 < nsteps) store_plane((s + 1) & 1, zb + s, R);
         if (s + 2 < nsteps) load_plane(zb + s + 1, R);
         lds_barrier();
-        // output plane zb + s - 2 is complete
-        constexpr int P = (S3 + 1) % 3;
+        if constexpr (KS == 2) {
+            const f32x4 *pr = part + ((s & 1) * MT + wm) * RW * 64 + lane;
+#pragma unroll
+            for (int i = 0; i < RS; ++i) out[i] += pr[(2 * i + kh) * 64];
+        }
         const int oz = zb + s - 2;
         if constexpr (PLAIN) {
             const unsigned pofs = (unsigned)(s - 2) * pbytes;
 #pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                f32x4 v = acc[P][r];
+            for (int i = 0; i < RS; ++i) {
+                f32x4 v = out[i];
                 if constexpr (RELU) {
                     v.x = fmaxf(v.x, 0.f), v.y = fmaxf(v.y, 0.f);
                     v.z = fmaxf(v.z, 0.f), v.w = fmaxf(v.w, 0.f);
@@ -650,14 +762,14 @@ __global__ __launch_bounds__(256, 2) void conv3_zm_k(ConvArgs a, int zc) {
                 u32x2 st;
                 st.x = pk_bf16(v.x, v.y);
                 st.y = pk_bf16(v.z, v.w);
-                __builtin_amdgcn_raw_buffer_store_b64(st, dst, (s >= 2 && rok[r]) ? roff[r] + pofs : 0x80000000u, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b64(st, dst, (s >= 2 && rok[i]) ? roff[i] + pofs : 0x80000000u, 0, 0);
             }
         } else if (s >= 2) {
 #pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                const int oy = y0 + wr * RW + r;
+            for (int i = 0; i < RS; ++i) {
+                const int oy = y0 + wr * RW + KS * i + kh;
                 if (ox < a.onx && oy < a.ony)
-                    store4b(a, ((size_t)oz * a.ony + oy) * a.onx + ox, wm * 16 + grp * 4, acc[P][r], zero4);
+                    store4b(a, ((size_t)oz * a.ony + oy) * a.onx + ox, wm * 16 + grp * 4, out[i], zero4);
             }
         }
     };
@@ -960,10 +1072,23 @@ __global__ __launch_bounds__(256) void reduce_k(const float *P, int nslice, int 
     out[o] = accumulate ? out[o] + s : s;
 }
 
+// Blocks take chunks of 4096 values, 16 per thread, whose loads are all
+// issued before the first comparison (an index past the end reads the last
+// value again, which leaves the maximum unchanged).  At most 256 blocks, so
+// that at most 256 atomics meet at the result.
 __global__ __launch_bounds__(256) void maxabs_k(const double *x, size_t n, unsigned long long *out) {
     __shared__ double red[256];
     double m = 0.0;
-    for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) m = fmax(m, fabs(x[i]));
+    for (size_t b = (size_t)blockIdx.x * 4096; b < n; b += (size_t)gridDim.x * 4096) {
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const size_t i = b + k * 256 + threadIdx.x;
+            v[k] = x[i < n ? i : n - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) m = fmax(m, fabs(v[k]));
+    }
     red[threadIdx.x] = m;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -1010,20 +1135,31 @@ struct InTile {
     float v[3][kInTY + 2][kInTX + 2];
 };
 
+// All of a thread's loads are issued (from clamped addresses) before the
+// first value is scaled, so their latencies overlap.
 __device__ __forceinline__ void stage_input(const double *s, Grid3 g, double sg, bool round_bf16, InTile &t) {
     const int x0 = blockIdx.x * kInTX, y0 = blockIdx.y * kInTY, z = blockIdx.z;
     constexpr int N = 3 * (kInTY + 2) * (kInTX + 2);
-    for (int i = threadIdx.x; i < N; i += 256) {
+    constexpr int NI = (N + 255) / 256;
+    double sv[NI];
+    bool ok[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int i = threadIdx.x + 256 * k;
         const int hx = i % (kInTX + 2), r = i / (kInTX + 2);
         const int hy = r % (kInTY + 2), hz = r / (kInTY + 2);
         const int qx = x0 + hx - 1, qy = y0 + hy - 1, qz = z + hz - 1;
-        float v = 0.f;
-        if (qx >= 0 && qx < g.nx && qy >= 0 && qy < g.ny && qz >= 0 && qz < g.nz) {
-            const double sv = s[((size_t)qz * g.ny + qy) * g.nx + qx];
-            v = (float)(sg > 0.0 ? sv / sg : sv);
-            if (round_bf16) v = bf2f(f2bf(v));
-        }
-        t.v[hz][hy][hx] = v;
+        ok[k] = i < N && qx >= 0 && qx < g.nx && qy >= 0 && qy < g.ny && qz >= 0 && qz < g.nz;
+        const int cx = min(max(qx, 0), g.nx - 1), cy = min(max(qy, 0), g.ny - 1), cz = min(max(qz, 0), g.nz - 1);
+        sv[k] = s[((size_t)cz * g.ny + cy) * g.nx + cx];
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i >= N) break;
+        float v = (float)(sg > 0.0 ? sv[k] / sg : sv[k]);
+        if (round_bf16) v = bf2f(f2bf(v));
+        (&t.v[0][0][0])[i] = ok[k] ? v : 0.f;
     }
     __syncthreads();
 }
@@ -1131,38 +1267,6 @@ __global__ __launch_bounds__(256) void head_train_k(const bf16_t *a, const doubl
         partials[bid * kHeadRed + k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
 }
 
-// First layer (1 input channel -> 16): direct FP32 products of the
-// bfloat16-rounded scaled input x = s / sigma at the 27 taps (staged in LDS)
-// with the bfloat16 weights wf[16][27][8] (channel 0), + bias, ReLU.  One
-// thread per cell.
-__global__ __launch_bounds__(256) void conv_in_k(const double *s, Grid3 g, const double *sigma, const bf16_t *wf,
-                                                 const float *bias, bf16_t *out) {
-    __shared__ float w[16 * 27];
-    __shared__ InTile tile;
-    for (int i = threadIdx.x; i < 16 * 27; i += 256) w[i] = bf2f(wf[i * 8]);
-    stage_input(s, g, *sigma, true, tile);
-    const int lx = threadIdx.x % kInTX, ly = threadIdx.x / kInTX;
-    const int px = blockIdx.x * kInTX + lx, py = blockIdx.y * kInTY + ly, pz = blockIdx.z;
-    if (px >= g.nx || py >= g.ny) return;
-    const size_t v = ((size_t)pz * g.ny + py) * g.nx + px;
-    float xt[27];
-#pragma unroll
-    for (int q = 0; q < 27; ++q) xt[q] = tile.v[q / 9][ly + (q / 3) % 3][lx + q % 3];
-    unsigned pk[8];
-#pragma unroll
-    for (int c = 0; c < 16; c += 2) {
-        float y0 = bias[c], y1 = bias[c + 1];
-#pragma unroll
-        for (int q = 0; q < 27; ++q) {
-            y0 = fmaf(w[c * 27 + q], xt[q], y0);
-            y1 = fmaf(w[(c + 1) * 27 + q], xt[q], y1);
-        }
-        pk[c / 2] = f2bf(fmaxf(y0, 0.f)) | (f2bf(fmaxf(y1, 0.f)) << 16);
-    }
-    *reinterpret_cast<u32x4 *>(out + v * 16) = u32x4{pk[0], pk[1], pk[2], pk[3]};
-    *reinterpret_cast<u32x4 *>(out + v * 16 + 8) = u32x4{pk[4], pk[5], pk[6], pk[7]};
-}
-
 __global__ __launch_bounds__(256) void make_target_k(const double *p0, const double *p1, const double *p2, size_t n,
                                                      Coef3 k2, Coef3 scale, const double *sigma, float *t,
                                                      unsigned *maxbits) {
@@ -1268,25 +1372,29 @@ hipError_t lds_tile(hipStream_t s, const ConvArgs &a) {
     }
 }
 
-// z-marching kernel: the block count is raised towards two blocks per CU by
-// splitting z into chunks, each chunk keeping at least 8 output planes
-// (every chunk re-reads two halo planes).
-template <int CIN, int MT>
+// z-marching kernel: the block count is raised towards the number of
+// blocks the chip holds at once (two per CU for 4 waves, one for 8) by
+// splitting z into chunks.  Every chunk re-reads two halo planes; chunks of
+// 4-wave blocks keep at least 8 output planes (shorter ones measured slower
+// at 64^3 and 128^3), those of 8-wave blocks (the small grids of the
+// 64-channel layers) at least 2.
+template <int CIN, int MT, int KS>
 hipError_t zm_launch(hipStream_t s, const ConvArgs &a) {
-    constexpr int BY = 16 / MT;
+    constexpr int NWV = zm_waves<MT, KS>();
+    constexpr int BY = 4 * (NWV / (MT * KS));
     const long txy = (long)((a.onx + 15) / 16) * ((a.ony + BY - 1) / BY);
-    const long want = (512 + txy - 1) / txy;
+    const long want = (512 * 4 / NWV + txy - 1) / txy;
     int zc = (int)((a.onz + want - 1) / want);
-    zc = std::max(zc, std::min(8, a.onz));
+    zc = std::max(zc, std::min(NWV == 4 ? 8 : 2, a.onz));
     const long nb = txy * ((a.onz + zc - 1) / zc);
     const bool plain = !a.maskA && !a.maskB && !a.accA && !a.accB && a.db == 0 &&
                        (size_t)a.onx * a.ony * a.onz * a.da * sizeof(bf16_t) < (1ull << 31);
     if (plain && a.relu)
-        conv3_zm_k<CIN, MT, true, true><<<(unsigned)nb, 256, 0, s>>>(a, zc);
+        conv3_zm_k<CIN, MT, KS, true, true><<<(unsigned)nb, 64 * NWV, 0, s>>>(a, zc);
     else if (plain)
-        conv3_zm_k<CIN, MT, true, false><<<(unsigned)nb, 256, 0, s>>>(a, zc);
+        conv3_zm_k<CIN, MT, KS, true, false><<<(unsigned)nb, 64 * NWV, 0, s>>>(a, zc);
     else
-        conv3_zm_k<CIN, MT, false, false><<<(unsigned)nb, 256, 0, s>>>(a, zc);
+        conv3_zm_k<CIN, MT, KS, false, false><<<(unsigned)nb, 64 * NWV, 0, s>>>(a, zc);
     return hipGetLastError();
 }
 
@@ -1294,8 +1402,12 @@ template <int COUT>
 hipError_t lds_cc(hipStream_t s, const ConvArgs &a) {
     const int cin = a.ca + a.cb;
     if constexpr (COUT == 16 || COUT == 32) {
-        if (cin == 16) return zm_launch<16, COUT / 16>(s, a);
-        if (cin == 32) return zm_launch<32, COUT / 16>(s, a);
+        if (cin == 8) return zm_launch<8, COUT / 16, 1>(s, a);
+        if (cin == 16) return zm_launch<16, COUT / 16, 1>(s, a);
+        if (cin == 32) return zm_launch<32, COUT / 16, 1>(s, a);
+    }
+    if constexpr (COUT == 32 || COUT == 64) {
+        if (cin == 64) return zm_launch<64, COUT / 16, 2>(s, a);
     }
     if (cin == 8) return lds_tile<COUT, 8>(s, a);
     if (cin == 16) return lds_tile<COUT, 16>(s, a);
@@ -1362,7 +1474,20 @@ hipError_t conv(hipStream_t s, int geom, const ConvArgs &a) {
     switch (geom) {
         case G_SAME3: return conv_same3(s, a);
         case G_DOWN2: return conv_geom<G_DOWN2>(s, a);
-        case G_UP2: return conv_geom<G_UP2>(s, a);
+        case G_UP2: {
+            const int cout = a.da + a.db;
+            if (a.ca + a.cb == 32 && (cout == 16 || cout == 32) && a.onx == 2 * a.inx && a.ony == 2 * a.iny &&
+                a.onz == 2 * a.inz) {
+                constexpr int NT = 2;
+                const dim3 grid((a.inx + 15) / 16, (a.iny + 3) / 4, (a.inz + NT - 1) / NT);
+                if (cout == 16)
+                    up2_k<1, NT><<<grid, 256, 0, s>>>(a);
+                else
+                    up2_k<2, NT><<<grid, 256, 0, s>>>(a);
+                return hipGetLastError();
+            }
+            return conv_geom<G_UP2>(s, a);
+        }
         default: return hipErrorInvalidValue;
     }
 }
@@ -1415,8 +1540,8 @@ hipError_t reduce_partials(hipStream_t s, const float *partials, int nslice, int
 }
 
 hipError_t maxabs(hipStream_t s, const double *x, size_t n, double *out) {
-    unsigned g = nblk(n);
-    if (g > 1024) g = 1024;
+    if (n == 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<size_t>((n + 4095) / 4096, 256);
     maxabs_k<<<g, 256, 0, s>>>(x, n, reinterpret_cast<unsigned long long *>(out));
     return hipGetLastError();
 }
@@ -1444,12 +1569,6 @@ int head_train_blocks(int nx, int ny, int nz) {
 hipError_t head_train(hipStream_t s, const bf16_t *a, const double *src, int nx, int ny, int nz, const float *wh,
                       const float *bh, const double *sigma, const float *t, bf16_t *ga, float *partials) {
     head_train_k<<<in_grid(nx, ny, nz), 256, 0, s>>>(a, src, Grid3{nx, ny, nz}, wh, bh, sigma, t, ga, partials);
-    return hipGetLastError();
-}
-
-hipError_t conv_in(hipStream_t s, const double *src, int nx, int ny, int nz, const double *sigma, const bf16_t *wf,
-                   const float *bias, bf16_t *out) {
-    conv_in_k<<<in_grid(nx, ny, nz), 256, 0, s>>>(src, Grid3{nx, ny, nz}, sigma, wf, bias, out);
     return hipGetLastError();
 }
 

@@ -177,16 +177,16 @@ void inputs(const mgl_net *n, int l, const bf16_t *&a, int &ca, const bf16_t *&b
     }
 }
 
-// Forward pass; with_x8 also writes the padded input tensor that the
-// weight gradient of the first layer reads.
-int forward(mgl_net *n, const double *s, bool with_x8) {
+// Forward pass.  The first layer is a convolution of the padded input
+// tensor x8 (channel 0 = bfloat16(s / max|s|), channels 1-7 zero), which the
+// weight gradient of the first layer also reads.
+int forward(mgl_net *n, const double *s) {
     hipStream_t st = n->stream;
     const size_t n0 = n->cells(0);
     CK(fill_zero(st, n->sigma, 8));
     CK(maxabs(st, s, n0, n->sigma));
-    if (with_x8) CK(prep_input(st, s, n0, n->sigma, n->x8));
-    CK(conv_in(st, s, n->nx, n->ny, n->nz, n->sigma, n->wf[0], n->theta + kOff.b[0], n->act[0]));
-    for (int l = 1; l < kLayers; ++l) {
+    CK(prep_input(st, s, n0, n->sigma, n->x8));
+    for (int l = 0; l < kLayers; ++l) {
         const LayerDef &L = kNet[l];
         if (L.geom == kHead) continue;
         ConvArgs a{};
@@ -453,7 +453,7 @@ int mgl_train_step(mgl_net *n, int count, const double *const *s, const float *c
     CK(fill_zero(st, n->grad, kOff.total * 4));
     CK(fill_zero(st, n->lossacc, 4));
     for (int k = 0; k < count; ++k) {
-        if (int rc = forward(n, s[k], true)) return rc;
+        if (int rc = forward(n, s[k])) return rc;
         if (int rc = head_backward(n, s[k], t[k], true)) return rc;
         if (int rc = backward(n)) return rc;
     }
@@ -477,7 +477,7 @@ int mgl_eval_loss(mgl_net *n, const double *s, const float *t, double *loss) {
     if (!s || !t || !loss) return set_err(MG_EINVAL, "mgl_eval_loss: null argument");
     hipStream_t st = n->stream;
     CK(fill_zero(st, n->lossacc, 4));
-    if (int rc = forward(n, s, false)) return rc;
+    if (int rc = forward(n, s)) return rc;
     if (int rc = head_backward(n, s, t, false)) return rc;
     float l;
     CK(hipMemcpyAsync(&l, n->lossacc, 4, hipMemcpyDeviceToHost, st));
@@ -496,7 +496,7 @@ int mgl_predict(mgl_net *n, const double *s, const double kappa2[3], double *con
             return set_err(MG_EINVAL, "mgl_predict: kappa2[%d] must be finite and > 0", i);
         coef[i] = n->scale[i] / kappa2[i];
     }
-    if (int rc = forward(n, s, false)) return rc;
+    if (int rc = forward(n, s)) return rc;
     CK(head_predict(n->stream, n->act[19], s, n->nx, n->ny, n->nz, n->theta + kOff.w[kHeadLayer],
                     n->theta + kOff.b[kHeadLayer], n->sigma, coef, guess[0], guess[1], guess[2]));
     return MG_OK;
