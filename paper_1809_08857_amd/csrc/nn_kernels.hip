@@ -259,6 +259,59 @@ __global__ __launch_bounds__(256) void conv_k(ConvArgs a) {
     }
 }
 
+// Stride-2 convolution (DOWN2) with 16, 32 or 64 input channels: a block
+// computes 16 output cells of one row on NT planes for all MT channel tiles,
+// and its 4 waves split the reduction (8 taps x cin = 4 * CPW K-chunks of
+// 32): wave w takes chunks w, w + 4, ...  Each wave issues the loads of all
+// its chunks before its first product, so a block waits for one memory
+// latency, not one per chunk.  The partial sums meet in LDS and each wave
+// adds the four (in wave order) for a quarter of the output tiles.
+template <int MT, int NT, int CPW>
+__global__ __launch_bounds__(256) void down2_k(ConvArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int cin = a.ca + a.cb;
+    const int x = blockIdx.x * 16 + col, y = blockIdx.y, z0 = blockIdx.z * NT;
+    const int xc = min(x, a.onx - 1);
+    u32x4 A[CPW][MT], B[CPW][NT];
+#pragma unroll
+    for (int i = 0; i < CPW; ++i) {
+        const int k0 = (wave + 4 * i) * 32 + grp * 8;
+        const int tap = k0 / cin, ci = k0 - tap * cin;
+        const int dz = tap >> 2, dy = (tap >> 1) & 1, dx = tap & 1;
+        const bf16_t *src = ci < a.ca ? a.srcA + ci : a.srcB + (ci - a.ca);
+        const int cs = ci < a.ca ? a.ca : a.cb;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) A[i][m] = ld16(a.w + ((size_t)(m * 16 + col) * 8 + tap) * cin + ci);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int zc = min(z0 + n, a.onz - 1);
+            B[i][n] = ld16(src + (((size_t)(2 * zc + dz) * a.iny + 2 * y + dy) * a.inx + 2 * xc + dx) * cs);
+        }
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < CPW; ++i) acc[m][n] = mfma(A[i][m], B[i][n], acc[m][n]);
+        }
+    __shared__ __align__(16) f32x4 part[4][MT * NT][64];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) part[wave][m * NT + n][lane] = acc[m][n];
+    __syncthreads();
+    for (int p = wave; p < MT * NT; p += 4) {
+        const int m = p / NT, n = p % NT;
+        const f32x4 v = part[0][p][lane] + part[1][p][lane] + part[2][p][lane] + part[3][p][lane];
+        const int z = z0 + n;
+        if (x < a.onx && z < a.onz) store4(a, ((size_t)z * a.ony + y) * a.onx + x, m * 16 + grp * 4, v);
+    }
+}
+
 // Transposed stride-2 convolution (UP2) with 32 input channels (one K-chunk)
 // and 16 or 32 output channels.  Wave w of a block owns 16 coarse cells of
 // row 4 * blockIdx.y + w on NT coarse planes: it reads each coarse row once
@@ -1473,7 +1526,25 @@ hipError_t conv(hipStream_t s, int geom, const ConvArgs &a) {
     if ((a.ca & 7) || (a.cb & 7) || (a.da & 3) || (a.db & 3)) return hipErrorInvalidValue;
     switch (geom) {
         case G_SAME3: return conv_same3(s, a);
-        case G_DOWN2: return conv_geom<G_DOWN2>(s, a);
+        case G_DOWN2: {
+            const int cin = a.ca + a.cb, cout = a.da + a.db;
+            if ((cin == 16 || cin == 32 || cin == 64) && (cout == 32 || cout == 64) && a.inx == 2 * a.onx &&
+                a.iny == 2 * a.ony && a.inz == 2 * a.onz) {
+                constexpr int NT = 2;
+                const dim3 grid((a.onx + 15) / 16, a.ony, (a.onz + NT - 1) / NT);
+                const int key = cin * 1000 + cout;
+                switch (key) {
+                    case 16032: down2_k<2, NT, 1><<<grid, 256, 0, s>>>(a); break;
+                    case 16064: down2_k<4, NT, 1><<<grid, 256, 0, s>>>(a); break;
+                    case 32032: down2_k<2, NT, 2><<<grid, 256, 0, s>>>(a); break;
+                    case 32064: down2_k<4, NT, 2><<<grid, 256, 0, s>>>(a); break;
+                    case 64032: down2_k<2, NT, 4><<<grid, 256, 0, s>>>(a); break;
+                    default: down2_k<4, NT, 4><<<grid, 256, 0, s>>>(a); break;
+                }
+                return hipGetLastError();
+            }
+            return conv_geom<G_DOWN2>(s, a);
+        }
         case G_UP2: {
             const int cout = a.da + a.db;
             if (a.ca + a.cb == 32 && (cout == 16 || cout == 32) && a.onx == 2 * a.inx && a.ony == 2 * a.iny &&
