@@ -1408,11 +1408,12 @@ hipError_t reg_launch(hipStream_t s, const ConvArgs &a) {
     return hipGetLastError();
 }
 
-// Tile: 16 x 4 x 4 cells on grids with enough tiles to fill the chip,
-// 16 x 2 x 2 on small grids.  With 32 or 64 output channels the weights of
-// a wave stay in registers (conv3_reg_k); with 16 (one channel tile, the
-// weights a small L1-resident set) and 128 conv3_lds_k keeps more waves
-// in flight.
+// Staged-tile kernels, for the channel counts the z-marching kernel does
+// not take (128 input or output channels, 64 -> 16).  Tile: 16 x 4 x 4
+// cells on grids with enough tiles to fill the chip, 16 x 2 x 2 on small
+// grids.  With 32 or 64 output channels the weights of a wave stay in
+// registers (conv3_reg_k); with 16 and 128 conv3_lds_k keeps more waves in
+// flight.
 template <int COUT, int CC>
 hipError_t lds_tile(hipStream_t s, const ConvArgs &a) {
     const long tiles44 = (long)((a.onx + 15) / 16) * ((a.ony + 3) / 4) * ((a.onz + 3) / 4);
