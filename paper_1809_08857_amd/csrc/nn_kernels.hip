@@ -312,51 +312,62 @@ __global__ __launch_bounds__(256) void down2_k(ConvArgs a) {
     }
 }
 
-// Transposed stride-2 convolution (UP2) with 32 input channels (one K-chunk)
-// and 16 or 32 output channels.  Wave w of a block owns 16 coarse cells of
-// row 4 * blockIdx.y + w on NT coarse planes: it reads each coarse row once
-// and forms all 8 output parities from it (8 MFMAs per 16-channel tile, the
-// weights of every parity in registers).  The parities px = 0, 1 of a lane
-// are adjacent fine cells, so the stores of a fine row are contiguous.
-template <int MT, int NT>
+// Transposed stride-2 convolution (UP2) with 32 or 64 input channels (NCH
+// K-chunks) and 16, 32 or 64 output channels.  A block owns 16 coarse cells
+// of one row on NT coarse planes; wave w forms the output parities
+// (px, py, pz) = (0 and 1, w & 1, w >> 1) from them, the weights of its two
+// parities in registers.  The two px parities of a lane are adjacent fine
+// cells, so the stores of a fine row are contiguous.  Coarse cells outside
+// the grid read a clamped cell and store nothing.
+template <int MT, int NT, int NCH>
 __global__ __launch_bounds__(256) void up2_k(ConvArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
-    const int x = blockIdx.x * 16 + col, y = blockIdx.y * 4 + wave, z0 = blockIdx.z * NT;
-    const bool colok = x < a.inx && y < a.iny;
-    u32x4 A[8][MT];
+    const int cin = a.ca + a.cb;
+    const int x = blockIdx.x * 16 + col, y = blockIdx.y, z0 = blockIdx.z * NT;
+    const int py = wave & 1, pz = wave >> 1;
+    u32x4 A[2][NCH][MT];
     f32x4 bv[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         bv[m] = bias4(a, m * 16 + grp * 4);
 #pragma unroll
-        for (int p = 0; p < 8; ++p) A[p][m] = ld16(a.w + ((size_t)(m * 16 + col) * 8 + p) * 32 + grp * 8);
-    }
-    // coarse cells outside the grid read a clamped cell and store nothing
-    const int ch = grp * 8;
-    const bf16_t *src = ch < a.ca ? a.srcA + ch : a.srcB + (ch - a.ca);
-    const int cs = ch < a.ca ? a.ca : a.cb;
-    const int xc = min(x, a.inx - 1), yc = min(y, a.iny - 1);
-    u32x4 B[NT];
+        for (int px = 0; px < 2; ++px)
 #pragma unroll
-    for (int n = 0; n < NT; ++n) {
-        const int zc = min(z0 + n, a.inz - 1);
-        B[n] = ld16(src + (((size_t)zc * a.iny + yc) * a.inx + xc) * cs);
+            for (int c = 0; c < NCH; ++c)
+                A[px][c][m] = ld16(a.w + ((size_t)(m * 16 + col) * 8 + pz * 4 + py * 2 + px) * cin + c * 32 + grp * 8);
+    }
+    const int xc = min(x, a.inx - 1);
+    u32x4 B[NT][NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int ch = c * 32 + grp * 8;
+        const bf16_t *src = ch < a.ca ? a.srcA + ch : a.srcB + (ch - a.ca);
+        const int cs = ch < a.ca ? a.ca : a.cb;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int zc = min(z0 + n, a.inz - 1);
+            B[n][c] = ld16(src + (((size_t)zc * a.iny + y) * a.inx + xc) * cs);
+        }
     }
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
         const int z = z0 + n;
-        f32x4 acc[8][MT];
+        f32x4 acc[2][MT];
 #pragma unroll
-        for (int p = 0; p < 8; ++p)
+        for (int px = 0; px < 2; ++px)
 #pragma unroll
-            for (int m = 0; m < MT; ++m) acc[p][m] = mfma(A[p][m], B[n], bv[m]);
-        if (!colok || z >= a.inz) continue;
+            for (int m = 0; m < MT; ++m) {
+                acc[px][m] = bv[m];
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const size_t ov = ((size_t)(2 * z + (p >> 2)) * a.ony + 2 * y + ((p >> 1) & 1)) * a.onx + 2 * x + (p & 1);
+                for (int c = 0; c < NCH; ++c) acc[px][m] = mfma(A[px][c][m], B[n][c], acc[px][m]);
+            }
+        if (x >= a.inx || z >= a.inz) continue;
 #pragma unroll
-            for (int m = 0; m < MT; ++m) store4b(a, ov, m * 16 + grp * 4, acc[p][m], f32x4{0.f, 0.f, 0.f, 0.f});
+        for (int px = 0; px < 2; ++px) {
+            const size_t ov = ((size_t)(2 * z + pz) * a.ony + 2 * y + py) * a.onx + 2 * x + px;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) store4b(a, ov, m * 16 + grp * 4, acc[px][m], f32x4{0.f, 0.f, 0.f, 0.f});
         }
     }
 }
@@ -1229,29 +1240,88 @@ __device__ __forceinline__ void head_features(const bf16_t *a, size_t v, const I
     for (int q = 0; q < 27; ++q) f[16 + q] = t.v[q / 9][ly + (q / 3) % 3][lx + q % 3];
 }
 
+// Prediction head, marching along z: a block owns a 64 x 4 tile of kHeadZ
+// planes.  x = s / sigma (FP32) of the tile and its one-cell halo sits in a
+// ring of four LDS planes, each staged once: while plane z is predicted
+// (taps on planes z-1, z, z+1), plane z+2 is written to the fourth slot,
+// which the previous plane's barrier has freed.
+constexpr int kHeadZ = 8;
 __global__ __launch_bounds__(256) void head_predict_k(const bf16_t *a, const double *s, Grid3 g, const float *wh,
                                                       const float *bh, const double *sigma, Coef3 coef, double *g0,
                                                       double *g1, double *g2) {
-    __shared__ InTile tile;
+    constexpr int PX = kInTX + 2, PY = kInTY + 2, NP = PX * PY;
+    constexpr int NI = (NP + 255) / 256;
+    __shared__ float ring[4][NP];
     const double sg = *sigma > 0.0 ? *sigma : 1.0;
-    stage_input(s, g, sg, false, tile);
-    const int lx = threadIdx.x % kInTX, ly = threadIdx.x / kInTX;
-    const int px = blockIdx.x * kInTX + lx, py = blockIdx.y * kInTY + ly, pz = blockIdx.z;
-    if (px >= g.nx || py >= g.ny) return;
-    const size_t v = ((size_t)pz * g.ny + py) * g.nx + px;
-    float f[kHeadIn];
-    head_features(a, v, tile, lx, ly, f);
-    float y[3];
+    const int x0 = blockIdx.x * kInTX, y0 = blockIdx.y * kInTY, zb = blockIdx.z * kHeadZ;
+    const int nzb = min(kHeadZ, g.nz - zb);
+    // staging of a plane: cells i = threadIdx.x + 256 k of the halo tile,
+    // loaded from clamped addresses (zero outside the grid)
+    size_t soff[NI];
+    bool sok[NI];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        float acc = bh[i];
-#pragma unroll
-        for (int c = 0; c < kHeadIn; ++c) acc = fmaf(wh[i * kHeadIn + c], f[c], acc);
-        y[i] = acc;
+    for (int k = 0; k < NI; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        const int qx = x0 + i % PX - 1, qy = y0 + i / PX - 1;
+        sok[k] = i < NP && qx >= 0 && qx < g.nx && qy >= 0 && qy < g.ny;
+        soff[k] = (size_t)min(max(qy, 0), g.ny - 1) * g.nx + min(max(qx, 0), g.nx - 1);
     }
-    g0[v] = sg * coef.c[0] * (double)y[0];
-    g1[v] = sg * coef.c[1] * (double)y[1];
-    g2[v] = sg * coef.c[2] * (double)y[2];
+    const size_t plane = (size_t)g.nx * g.ny;
+    auto load = [&](int z, double (&v)[NI]) {
+        const double *p = s + (size_t)min(max(z, 0), g.nz - 1) * plane;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) v[k] = p[soff[k]];
+    };
+    auto put = [&](int z, const double (&v)[NI]) {
+        float *r = ring[(z - zb + 1) & 3];
+        const bool zok = z >= 0 && z < g.nz;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            if (i < NP) r[i] = (zok && sok[k]) ? (float)(v[k] / sg) : 0.f;
+        }
+    };
+    double v[NI];
+    load(zb - 1, v);
+    put(zb - 1, v);
+    load(zb, v);
+    put(zb, v);
+    load(zb + 1, v);
+    put(zb + 1, v);
+    __syncthreads();
+
+    const int lx = threadIdx.x % kInTX, ly = threadIdx.x / kInTX;
+    const int px = x0 + lx, py = y0 + ly;
+    const bool ok = px < g.nx && py < g.ny;
+    const size_t c0 = (size_t)min(py, g.ny - 1) * g.nx + min(px, g.nx - 1);
+    for (int t = 0; t < nzb; ++t) {
+        const int z = zb + t;
+        if (t + 1 < nzb) load(z + 2, v);
+        const size_t cell = (size_t)z * plane + c0;
+        float f[kHeadIn];
+        float x16[16];
+        load16ch(a, cell, x16);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) f[c] = x16[c];
+#pragma unroll
+        for (int q = 0; q < 27; ++q)
+            f[16 + q] = ring[(t + q / 9) & 3][(ly + (q / 3) % 3) * PX + lx + q % 3];
+        float y[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            float acc = bh[i];
+#pragma unroll
+            for (int c = 0; c < kHeadIn; ++c) acc = fmaf(wh[i * kHeadIn + c], f[c], acc);
+            y[i] = acc;
+        }
+        if (ok) {
+            g0[cell] = sg * coef.c[0] * (double)y[0];
+            g1[cell] = sg * coef.c[1] * (double)y[1];
+            g2[cell] = sg * coef.c[2] * (double)y[2];
+        }
+        if (t + 1 < nzb) put(z + 2, v);
+        __syncthreads();
+    }
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -1547,15 +1617,19 @@ hipError_t conv(hipStream_t s, int geom, const ConvArgs &a) {
             return conv_geom<G_DOWN2>(s, a);
         }
         case G_UP2: {
-            const int cout = a.da + a.db;
-            if (a.ca + a.cb == 32 && (cout == 16 || cout == 32) && a.onx == 2 * a.inx && a.ony == 2 * a.iny &&
-                a.onz == 2 * a.inz) {
+            const int cin = a.ca + a.cb, cout = a.da + a.db;
+            if ((cin == 32 || cin == 64) && (cout == 16 || cout == 32 || cout == 64) && a.onx == 2 * a.inx &&
+                a.ony == 2 * a.iny && a.onz == 2 * a.inz) {
                 constexpr int NT = 2;
-                const dim3 grid((a.inx + 15) / 16, (a.iny + 3) / 4, (a.inz + NT - 1) / NT);
-                if (cout == 16)
-                    up2_k<1, NT><<<grid, 256, 0, s>>>(a);
-                else
-                    up2_k<2, NT><<<grid, 256, 0, s>>>(a);
+                const dim3 grid((a.inx + 15) / 16, a.iny, (a.inz + NT - 1) / NT);
+                switch (cin * 1000 + cout) {
+                    case 32016: up2_k<1, NT, 1><<<grid, 256, 0, s>>>(a); break;
+                    case 32032: up2_k<2, NT, 1><<<grid, 256, 0, s>>>(a); break;
+                    case 32064: up2_k<4, NT, 1><<<grid, 256, 0, s>>>(a); break;
+                    case 64016: up2_k<1, NT, 2><<<grid, 256, 0, s>>>(a); break;
+                    case 64032: up2_k<2, NT, 2><<<grid, 256, 0, s>>>(a); break;
+                    default: up2_k<4, NT, 2><<<grid, 256, 0, s>>>(a); break;
+                }
                 return hipGetLastError();
             }
             return conv_geom<G_UP2>(s, a);
@@ -1629,7 +1703,8 @@ hipError_t head_predict(hipStream_t s, const bf16_t *a, const double *src, int n
                         const float *bh, const double *sigma, const double coef[3], double *g0, double *g1,
                         double *g2) {
     Coef3 c{{coef[0], coef[1], coef[2]}};
-    head_predict_k<<<in_grid(nx, ny, nz), 256, 0, s>>>(a, src, Grid3{nx, ny, nz}, wh, bh, sigma, c, g0, g1, g2);
+    const dim3 grid((nx + kInTX - 1) / kInTX, (ny + kInTY - 1) / kInTY, (nz + kHeadZ - 1) / kHeadZ);
+    head_predict_k<<<grid, 256, 0, s>>>(a, src, Grid3{nx, ny, nz}, wh, bh, sigma, c, g0, g1, g2);
     return hipGetLastError();
 }
 
