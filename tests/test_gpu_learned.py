@@ -108,6 +108,35 @@ def case_big():
 BIG_LAYERS = ["e0a", "e0b", "d0", "u0", "c0a", "c0b"]
 
 
+@pytest.fixture(scope="module")
+def case_ragged():
+    """56x40x24: x and y are not multiples of the 16-cell convolution
+    tiles on any level, the 64-channel layers run on 14x10x6 and 7x5x3, and
+    the head's 64-wide tile is partial."""
+    out = _run_case((24, 40, 56), 13, 7, 8)
+    yield out
+    L.mgl_destroy(out["net"])
+
+
+@pytest.mark.parametrize("name", NAMES[:-1])
+def test_forward_layer_ragged(case_ragged, name):
+    test_forward_layer(case_ragged, name)
+
+
+@pytest.mark.parametrize("name", NAMES[:-2])
+def test_input_gradient_ragged(case_ragged, name):
+    test_input_gradient(case_ragged, name)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_weight_gradient_ragged(case_ragged, name):
+    test_weight_gradient(case_ragged, name)
+
+
+def test_prediction_ragged(case_ragged):
+    test_prediction_matches_oracle(case_ragged)
+
+
 @pytest.mark.parametrize("name", BIG_LAYERS)
 def test_forward_layer_large_tiles(case_big, name):
     test_forward_layer(case_big, name)
