@@ -1569,7 +1569,9 @@ template <class T> struct RrArgs {
 };
 
 template <int MODE, int TX, int TY> constexpr int rr_lds() {
-    return (1 + (MODE == COEF_CELL ? 1 : 0)) * (TY + 2) * (TX + 4) + (TY + 2) * ((TX + 4) / 2);
+    // u plane, accumulators; cell coefficients add an eps plane and two
+    // planes (by parity) of x faces (one per pair) and of y faces
+    return (MODE == COEF_CELL ? 4 : 1) * (TY + 2) * (TX + 4) + (MODE == COEF_CELL ? 3 : 1) * (TY + 2) * ((TX + 4) / 2);
 }
 template <int TX, int TY> constexpr int rr_threads() { return (((TX + 4) / 2 * (TY + 2)) + 63) / 64 * 64; }
 
@@ -1583,8 +1585,18 @@ __device__ __forceinline__ double rr_col_body(const RrArgs<T> &A, const int blk,
     constexpr int NTP = (NTH + 63) / 64 * 64;
     constexpr bool CELL = (MODE == COEF_CELL);
     C(*s_u)[RX] = reinterpret_cast<C(*)[RX]>(smem);
-    C(*s_e)[RX] = reinterpret_cast<C(*)[RX]>(smem + RY * RX);
+    C(*s_e)[RX] = reinterpret_cast<C(*)[RX]>(smem + RY * RX);  // eps of plane k+1 at step k
     C(*s_acc)[PXW] = reinterpret_cast<C(*)[PXW]>(smem + (CELL ? 2 : 1) * RY * RX);
+    // Cell coefficients: every face is formed once, by the pair below or to
+    // its left, one plane ahead (from the eps plane k+1 in LDS): s_fx[q][ry][pc]
+    // is the face between the pair's second cell and the next pair's first
+    // cell, s_fy[q][ry][c] the face between rows ry and ry+1 of column c, for
+    // planes of parity q.  The pair's inner face and its two vertical faces
+    // stay in registers (the face below plane k is the one above plane k-1).
+    // harm_face is symmetric to the last bit, so every face has the value
+    // either of its cells would form.
+    C(*s_fx)[RY][PXW] = reinterpret_cast<C(*)[RY][PXW]>(smem + 2 * RY * RX + RY * PXW);
+    C(*s_fy)[RY][RX] = reinterpret_cast<C(*)[RY][RX]>(smem + 2 * RY * RX + 3 * RY * PXW);
     const T *__restrict__ u = A.u;
     const T *__restrict__ b = A.b;
     const coef_t<T> *__restrict__ eps = A.eps;
@@ -1737,6 +1749,18 @@ __device__ __forceinline__ double rr_col_body(const RrArgs<T> &A, const int blk,
     mask_at(std::integral_constant<int, 2>{}, z0 + 1);
     double nrm = 0.0;
     C acc = C(0);
+    // the faces of plane k+1 this pair shares: x face to its right, y faces above
+    auto share_faces = [&](const P2 &e1, int k1) __attribute__((always_inline)) {
+        if constexpr (CELL) {
+            const int q1 = k1 & 1;
+            if (live && pc < PXW - 1) s_fx[q1][ry][pc] = harm_face(e1.v[1], s_e[ry][lx + 2]);
+            if (live && ry < RY - 1) {
+                s_fy[q1][ry][lx] = harm_face(e1.v[0], s_e[ry + 1][lx]);
+                s_fy[q1][ry][lx + 1] = harm_face(e1.v[1], s_e[ry + 1][lx + 1]);
+            }
+        }
+    };
+    C fzb0 = C(0), fzb1 = C(0);  // vertical faces below plane k (cell coefficients)
     auto step = [&](const P2 &um, const P2 &u0, const P2 &up, const P2 &e_m, const P2 &e0, const P2 &e_p,
                     const P2 &b0, int k) __attribute__((always_inline)) {
         if (live) {
@@ -1745,14 +1769,17 @@ __device__ __forceinline__ double rr_col_body(const RrArgs<T> &A, const int blk,
             w.v[1] = u0.v[1];
             *reinterpret_cast<Pair<C> *>(&s_u[ry][lx]) = w;
             if constexpr (CELL) {
-                w.v[0] = e0.v[0];
-                w.v[1] = e0.v[1];
+                w.v[0] = e_p.v[0];
+                w.v[1] = e_p.v[1];
                 *reinterpret_cast<Pair<C> *>(&s_e[ry][lx]) = w;
             }
         }
         lds_barrier();
+        share_faces(e_p, k + 1);
         if (core) {
             C rr[2];
+            [[maybe_unused]] C fI = C(0);
+            if constexpr (CELL) fI = harm_face(e0.v[0], e0.v[1]);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const int lc = lx + c;
@@ -1764,11 +1791,13 @@ __device__ __forceinline__ double rr_col_body(const RrArgs<T> &A, const int blk,
                     off = ((uL + uR) + (uD + uU)) + (um.v[c] + up.v[c]);
                     dg = (c ? dxy1 : dxy0) + (csel<C>(k > 0, C(1), wz_lo) + csel<C>(k < nz - 1, C(1), wz_hi));
                 } else if constexpr (MODE == COEF_CELL) {
-                    const C eP = e0.v[c];
-                    const C fL = harm_face(eP, c ? e0.v[0] : s_e[ry][lc - 1]);
-                    const C fR = harm_face(eP, c ? s_e[ry][lc + 1] : e0.v[1]);
-                    const C fD = harm_face(eP, s_e[ry - 1][lc]), fU = harm_face(eP, s_e[ry + 1][lc]);
-                    const C fB = harm_face(eP, e_m.v[c]), fA = harm_face(eP, e_p.v[c]);
+                    const int q = k & 1;
+                    const C fL = c ? fI : s_fx[q][ry][pc - 1];
+                    const C fR = c ? s_fx[q][ry][pc] : fI;
+                    const C fD = s_fy[q][ry - 1][lc], fU = s_fy[q][ry][lc];
+                    const C fB = c ? fzb1 : fzb0, fA = harm_face(e0.v[c], e_p.v[c]);
+                    if (c) fzb1 = fA;
+                    else fzb0 = fA;
                     off = fL * uL;
                     off = fma_c<C>(fR, uR, off);
                     off = fma_c<C>(fD, uD, off);
@@ -1837,6 +1866,20 @@ __device__ __forceinline__ double rr_col_body(const RrArgs<T> &A, const int blk,
         mask_at(I3{}, k + 1);
         step(SU(I1{}), SU(I2{}), SU(I3{}), SE(I1{}), SE(I2{}), SE(I3{}), SB(I2{}), k);
     };
+    if constexpr (CELL) {
+        // faces of the chunk's first plane, and the vertical faces below it
+        if (live) {
+            Pair<C> w;
+            w.v[0] = se1.v[0];
+            w.v[1] = se1.v[1];
+            *reinterpret_cast<Pair<C> *>(&s_e[ry][lx]) = w;
+        }
+        lds_barrier();
+        share_faces(se1, z0);
+        fzb0 = harm_face(se0.v[0], se1.v[0]);
+        fzb1 = harm_face(se0.v[1], se1.v[1]);
+        lds_barrier();  // the first step rewrites the eps plane
+    }
     step(su0, su1, su2, se0, se1, se2, sb1, z0);
     for (int kk = z0 + 1; kk < z1; kk += R) {
         iter(std::integral_constant<int, 0>{}, kk);
