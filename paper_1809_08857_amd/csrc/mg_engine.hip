@@ -818,7 +818,16 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
         }
     }
     if ((rc = check(0))) return rc;
+    double *chk0 = cur;  // the iterate check(0) measures
+    // With a guess, the first cycle from it is enqueued before the host
+    // reads the screen (as every later cycle is enqueued before the host
+    // reads the previous norm), so the GPU does not wait for the host.  A
+    // fallback discards it: the zero start's kernels follow it on the stream.
+    bool spec = false;
     if (screen) {
+        if ((rc = advance(0))) return rc;
+        if ((rc = check(1))) return rc;
+        spec = true;
         CK(hipEventSynchronize(c->ev_cyc[0]));
         const double rel_s = std::sqrt(c->h_pin[SLOT_CYC]) / bn;
         if (!(rel_s <= 1.0)) {  // worse than the zero guess (or not finite): start from zero
@@ -829,18 +838,20 @@ static int solve_impl(Ctx *c, const double *f, double *x, unsigned flags, mg_sta
             S.fell_back = 1;
             S.rel_res0 = 1.0;
             if ((rc = check(0))) return rc;
+            chk0 = cur;
+            spec = false;
         } else {
             S.rel_res0 = rel_s;
         }
     }
-    double *at_check[2] = {cur, nullptr};
+    double *at_check[2] = {chk0, spec ? cur : nullptr};
     DivergenceWatch watch;
     int cycles = 0;
     double rel = S.rel_res0;
     double *final_x = cur;
     bool converged = false;
     for (int cyc = 0;; ++cyc) {
-        if (cyc < c->d.max_cycles) {
+        if (cyc < c->d.max_cycles && !(spec && cyc == 0)) {
             if ((rc = advance(cyc))) return rc;
             if ((rc = check(cyc + 1))) return rc;
             at_check[(cyc + 1) & 1] = cur;
