@@ -577,8 +577,9 @@ __global__ __launch_bounds__(256) void conv3_reg_k(ConvArgs a) {
     }
 }
 
-// 3x3x3 convolution marching along z, for 8, 16, 32 or 64 input channels
-// and 16, 32 or 64 output channels.  Block: NWV waves on an xy tile of
+// 3x3x3 convolution marching along z: 8, 16 or 32 input channels with 16
+// or 32 output channels, 64 input channels with 32 or 64 output channels
+// (the other shapes take the staged-tile kernels).  Block: NWV waves on an xy tile of
 // 16 x BY output cells and a chunk of zc output planes.  A wave owns one
 // 16-channel output tile (wm), one share of the input channels (kh of KS,
 // CK channels each) and RW rows of the tile (row group wr); its weights
