@@ -604,6 +604,10 @@ __global__ __launch_bounds__(256) void conv3_reg_k(ConvArgs a) {
 // odd rows: before the plane's barrier each wave writes to LDS its partial
 // sums of the rows the other one stores, and adds the other's partial sums
 // of its own rows after it (two LDS slots of partial sums, by plane parity).
+// With four (KS = 4, 128 input channels) wave kh stores row kh and adds the
+// three other waves' partial sums of it in wave order; a block then covers
+// 32 of the output channels, the channel group g being part of the block
+// index.
 //
 // The bias enters as the accumulator operand of each output plane's first
 // MFMA (in the wave with kh = 0), which also starts the plane's
@@ -640,21 +644,24 @@ __global__ __launch_bounds__((64 * zm_waves<MT, KS>()), (8 / zm_waves<MT, KS>())
     constexpr int NVS = NLD * CPW;                     // cells per LDS slot (the last pass whole)
     constexpr int RS = RW / KS;                        // rows a wave stores
     static_assert(CK == 8 || CK == 16 || CK == 32, "8, 16 or 32 input channels per wave");
-    static_assert(KS == 1 || KS == 2, "input channels split over at most two waves");
+    static_assert(KS == 1 || KS == 2 || KS == 4, "input channels split over 1, 2 or 4 waves");
     static_assert(NWV % (MT * KS) == 0, "whole wave groups");
     static_assert(KS == 1 || WR == 1, "the partial sums are indexed by output tile and row only");
     __shared__ __align__(16) bf16_t tile[2 * NVS * VS];
-    __shared__ __align__(16) f32x4 part[KS == 2 ? 2 * MT * RW * 64 : 1];
+    __shared__ __align__(16) f32x4 part[KS == 1 ? 1 : 2 * MT * RW * (KS == 4 ? 4 : 1) * 64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
     const int wm = wave % MT, kh = (wave / MT) % KS, wr = wave / (MT * KS);
     const int kc = kh * CK;  // first input channel of this wave
     const int cin = a.ca + a.cb;
+    const int ng = (a.da + a.db) / (16 * MT);  // output channel groups (one unless KS = 4)
     const int ntx = (a.onx + 15) / 16, nty = (a.ony + BY - 1) / BY, ntz = (a.onz + zc - 1) / zc;
-    const int b = xcd_order(blockIdx.x, ntx * nty * ntz);
+    const int bg = xcd_order(blockIdx.x, ntx * nty * ntz * ng);
+    const int g = bg % ng, b = bg / ng;
     const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
     const int x0 = bx * 16, y0 = by * BY, zb = bz * zc;
+    const int mo = (g * MT + wm) * 16;     // first output channel of this wave
     const int nout = min(zc, a.onz - zb);  // output planes of this block
     const int nsteps = nout + 2;           // input planes zb-1 .. zb+nout
     const u32x4 zero = {0u, 0u, 0u, 0u};
@@ -682,7 +689,7 @@ __global__ __launch_bounds__((64 * zm_waves<MT, KS>()), (8 / zm_waves<MT, KS>())
     // weights A[ty][tz][c]: output channel wm*16 + col, reduction lanes of grp
     u32x4 A[3][3][NCK];
     {
-        const bf16_t *wr0 = a.w + (size_t)(wm * 16 + col) * 27 * cin;
+        const bf16_t *wr0 = a.w + (size_t)(mo + col) * 27 * cin;
 #pragma unroll
         for (int ty = 0; ty < 3; ++ty)
 #pragma unroll
@@ -741,7 +748,7 @@ __global__ __launch_bounds__((64 * zm_waves<MT, KS>()), (8 / zm_waves<MT, KS>())
 #pragma unroll
     for (int c = 0; c < NCK; ++c) boff[c] = ((wr * RW) * HX + col + ctx[c]) * VS + cci[c];
 
-    const f32x4 bv = bias4(a, wm * 16 + grp * 4);
+    const f32x4 bv = bias4(a, mo + grp * 4);
     const f32x4 bstart = kh == 0 ? bv : zero4;  // the bias enters once
     // destination as a buffer resource (plain epilogue only)
     const __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc(
@@ -767,7 +774,7 @@ __global__ __launch_bounds__((64 * zm_waves<MT, KS>()), (8 / zm_waves<MT, KS>())
     for (int i = 0; i < RS; ++i) {
         const int oy = y0 + wr * RW + KS * i + kh;
         rok[i] = ox < a.onx && oy < a.ony;
-        roff[i] = (unsigned)(((((size_t)zb * a.ony + oy) * a.onx + ox) * a.da + wm * 16 + grp * 4) * sizeof(bf16_t));
+        roff[i] = (unsigned)(((((size_t)zb * a.ony + oy) * a.onx + ox) * a.da + mo + grp * 4) * sizeof(bf16_t));
     }
     const unsigned pbytes = (unsigned)((size_t)a.onx * a.ony * a.da * sizeof(bf16_t));
     // input plane zb - 1 + s; S3 = s % 3 fixes the accumulator ring at compile time
@@ -802,6 +809,13 @@ __global__ __launch_bounds__((64 * zm_waves<MT, KS>()), (8 / zm_waves<MT, KS>())
                 pw[(2 * i + 1 - kh) * 64] = kh ? acc[P][2 * i] : acc[P][2 * i + 1];
                 out[i] = kh ? acc[P][2 * i + 1] : acc[P][2 * i];
             }
+        } else if constexpr (KS == 4) {
+            // partial sums of the other waves' rows to LDS, by row and writer
+            f32x4 *pw = part + ((s & 1) * MT + wm) * RW * 4 * 64 + kh * 64 + lane;
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+                if (r != kh) pw[r * 4 * 64] = acc[P][r];
+            out[0] = kh == 0 ? acc[P][0] : kh == 1 ? acc[P][1] : kh == 2 ? acc[P][2] : acc[P][3];
         } else {
 #pragma unroll
             for (int i = 0; i < RS; ++i) out[i] = acc[P][i];
@@ -813,6 +827,11 @@ __global__ __launch_bounds__((64 * zm_waves<MT, KS>()), (8 / zm_waves<MT, KS>())
             const f32x4 *pr = part + ((s & 1) * MT + wm) * RW * 64 + lane;
 #pragma unroll
             for (int i = 0; i < RS; ++i) out[i] += pr[(2 * i + kh) * 64];
+        } else if constexpr (KS == 4) {
+            const f32x4 *pr = part + (((s & 1) * MT + wm) * RW + kh) * 4 * 64 + lane;
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (w != kh) out[0] += pr[w * 64];
         }
         const int oz = zb + s - 2;
         if constexpr (PLAIN) {
@@ -834,7 +853,7 @@ __global__ __launch_bounds__((64 * zm_waves<MT, KS>()), (8 / zm_waves<MT, KS>())
             for (int i = 0; i < RS; ++i) {
                 const int oy = y0 + wr * RW + KS * i + kh;
                 if (ox < a.onx && oy < a.ony)
-                    store4b(a, ((size_t)oz * a.ony + oy) * a.onx + ox, wm * 16 + grp * 4, out[i], zero4);
+                    store4b(a, ((size_t)oz * a.ony + oy) * a.onx + ox, mo + grp * 4, out[i], zero4);
             }
         }
     };
@@ -1516,7 +1535,8 @@ template <int CIN, int MT, int KS>
 hipError_t zm_launch(hipStream_t s, const ConvArgs &a) {
     constexpr int NWV = zm_waves<MT, KS>();
     constexpr int BY = 4 * (NWV / (MT * KS));
-    const long txy = (long)((a.onx + 15) / 16) * ((a.ony + BY - 1) / BY);
+    const long ng = (a.da + a.db) / (16 * MT);  // output channel groups (blocks per tile)
+    const long txy = (long)((a.onx + 15) / 16) * ((a.ony + BY - 1) / BY) * ng;
     const long want = (512 * 4 / NWV + txy - 1) / txy;
     int zc = (int)((a.onz + want - 1) / want);
     zc = std::max(zc, std::min(NWV == 4 ? 8 : 2, a.onz));
@@ -1542,6 +1562,9 @@ hipError_t lds_cc(hipStream_t s, const ConvArgs &a) {
     }
     if constexpr (COUT == 32 || COUT == 64) {
         if (cin == 64) return zm_launch<64, COUT / 16, 2>(s, a);
+    }
+    if constexpr (COUT == 64) {
+        if (cin == 128) return zm_launch<128, 2, 4>(s, a);
     }
     if (cin == 8) return lds_tile<COUT, 8>(s, a);
     if (cin == 16) return lds_tile<COUT, 16>(s, a);
