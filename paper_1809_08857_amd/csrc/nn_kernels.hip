@@ -605,9 +605,9 @@ __global__ __launch_bounds__(256) void conv3_reg_k(ConvArgs a) {
 // sums of the rows the other one stores, and adds the other's partial sums
 // of its own rows after it (two LDS slots of partial sums, by plane parity).
 // With four (KS = 4, 128 input channels) wave kh stores row kh and adds the
-// three other waves' partial sums of it in wave order; a block then covers
-// 32 of the output channels, the channel group g being part of the block
-// index.
+// three other waves' partial sums of it in wave order.  A block covers
+// 16 * MT output channels; where the layer has more, the channel group g is
+// part of the block index.
 //
 // The bias enters as the accumulator operand of each output plane's first
 // MFMA (in the wave with kh = 0), which also starts the plane's
@@ -655,7 +655,7 @@ __global__ __launch_bounds__((64 * zm_waves<MT, KS>()), (8 / zm_waves<MT, KS>())
     const int wm = wave % MT, kh = (wave / MT) % KS, wr = wave / (MT * KS);
     const int kc = kh * CK;  // first input channel of this wave
     const int cin = a.ca + a.cb;
-    const int ng = (a.da + a.db) / (16 * MT);  // output channel groups (one unless KS = 4)
+    const int ng = (a.da + a.db) / (16 * MT);  // output channel groups
     const int ntx = (a.onx + 15) / 16, nty = (a.ony + BY - 1) / BY, ntz = (a.onz + zc - 1) / zc;
     const int bg = xcd_order(blockIdx.x, ntx * nty * ntz * ng);
     const int g = bg % ng, b = bg / ng;
@@ -1529,17 +1529,20 @@ hipError_t lds_tile(hipStream_t s, const ConvArgs &a) {
 // blocks the chip holds at once (two per CU for 4 waves, one for 8) by
 // splitting z into chunks.  Every chunk re-reads two halo planes; chunks of
 // 4-wave blocks keep at least 8 output planes (shorter ones measured slower
-// at 64^3 and 128^3), those of 8-wave blocks (the small grids of the
-// 64-channel layers) at least 2.
+// at 64^3 and 128^3), those of 8-wave blocks at least 2.  On grids of at
+// most 32 planes 4-wave blocks aim at one block per CU with chunks of any
+// length (64 -> 64 channels: 15.2 us at 32^3 with 4-plane chunks against
+// 18.5 with 2 and 20.3 with 8; 9.5 us at 16^3 with 1-plane chunks).
 template <int CIN, int MT, int KS>
 hipError_t zm_launch(hipStream_t s, const ConvArgs &a) {
     constexpr int NWV = zm_waves<MT, KS>();
     constexpr int BY = 4 * (NWV / (MT * KS));
     const long ng = (a.da + a.db) / (16 * MT);  // output channel groups (blocks per tile)
     const long txy = (long)((a.onx + 15) / 16) * ((a.ony + BY - 1) / BY) * ng;
-    const long want = (512 * 4 / NWV + txy - 1) / txy;
+    const bool small = NWV == 4 && a.onz <= 32;
+    const long want = ((small ? 256 : 512 * 4 / NWV) + txy - 1) / txy;
     int zc = (int)((a.onz + want - 1) / want);
-    zc = std::max(zc, std::min(NWV == 4 ? 8 : 2, a.onz));
+    zc = std::max(zc, std::min(small ? 1 : NWV == 4 ? 8 : 2, a.onz));
     const long nb = txy * ((a.onz + zc - 1) / zc);
     const bool plain = !a.maskA && !a.maskB && !a.accA && !a.accB && a.db == 0 &&
                        (size_t)a.onx * a.ony * a.onz * a.da * sizeof(bf16_t) < (1ull << 31);
@@ -1561,7 +1564,9 @@ hipError_t lds_cc(hipStream_t s, const ConvArgs &a) {
         if (cin == 32) return zm_launch<32, COUT / 16, 1>(s, a);
     }
     if constexpr (COUT == 32 || COUT == 64) {
-        if (cin == 64) return zm_launch<64, COUT / 16, 2>(s, a);
+        // 64 -> 64: two blocks of 32 output channels per tile (4 waves each)
+        // fill the small grids better than one 8-wave block
+        if (cin == 64) return zm_launch<64, 2, 2>(s, a);
     }
     if constexpr (COUT == 64) {
         if (cin == 128) return zm_launch<128, 2, 4>(s, a);
