@@ -145,7 +145,7 @@ int tile_for(const Ctx *c, const Geo &G, int st, int mode, int l, int *zc) {
         z = (st == ST_F64) ? c->zc64 : c->zc_lp;
     }
     if (t <= 0) t = default_tile(G, st, mode);
-    if (z <= 0) z = default_zchunk(G, t, st);
+    if (z <= 0) z = default_zchunk(G, t, st, mode);
     *zc = z;
     return t;
 }
@@ -1037,7 +1037,7 @@ int mg_smooth_level(mg_ctx *c, int l, int store, const double *b_dev, double *x_
     int t = tile_for(c, G, st, C.mode, l, &zc);
     if (tile > 0) t = tile;
     if (zchunk > 0) zc = zchunk;
-    else if (tile > 0) zc = default_zchunk(G, t, st);
+    else if (tile > 0) zc = default_zchunk(G, t, st, C.mode);
     void *u, *w;
     const void *b;
     if (!lowp && l == 0) {

@@ -124,7 +124,7 @@ inline void brick_shape(int nxi, int ny, int nz, int max_blocks, dim3 *grid, dim
 constexpr int kNumTiles = 6;
 void tile_shape(int t, int *tx, int *ty);
 int default_tile(const Geo &G, int st, int mode);
-int default_zchunk(const Geo &G, int tile, int st);
+int default_zchunk(const Geo &G, int tile, int st, int mode);
 
 // One fused red-black Gauss-Seidel sweep, out of place: uout = sweep(uin).
 // zero_in: treat uin as identically zero (uin is not read).

@@ -83,10 +83,11 @@ hipError_t rr_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, c
     const int tiles_x = (G.nx + TX - 1) / TX, tiles_y = (G.ny + TY - 1) / TY;
     const long cols = (long)tiles_x * tiles_y;
     // about as many workgroups as the chip holds at once: two per CU, but one
-    // for the FP64 cell-permittivity pass, whose registers (116 per lane)
-    // leave room for one 10-wave workgroup per CU; a second round of
-    // workgroups measured slower there (91.6 against 87.3 us at 256^3)
-    constexpr long kTarget = (MODE == COEF_CELL && sizeof(T) == 8) ? 256 : 512;
+    // for the cell-permittivity pass on 64 x 16 tiles, whose registers
+    // (102-116 per lane) leave room for one 10-wave workgroup per CU; a
+    // second round of workgroups measured slower there (FP64 at 256^3: 91.6
+    // against 87.3 us)
+    constexpr long kTarget = (MODE == COEF_CELL && TX * TY >= 1024) ? 256 : 512;
     long chunks = (kTarget + cols - 1) / cols;
     long maxch = G.nz / 8;
     if (maxch < 1) maxch = 1;

@@ -178,16 +178,19 @@ int default_tile(const Geo &G, int st, int mode) {
     return 6;                                 // 16 x 8
 }
 
-int default_zchunk(const Geo &G, int tile, int st) {
+int default_zchunk(const Geo &G, int tile, int st, int mode) {
     int tx, ty;
     tile_shape(tile, &tx, &ty);
     const long cols = (long)((G.nx + tx - 1) / tx) * ((G.ny + ty - 1) / ty);
     // about one workgroup per CU (a workgroup holds 5-12 waves) for FP64,
     // two for the FP32/BF16 sweeps, whose smaller register footprint lets
-    // two workgroups share a CU and hide each other's per-plane latency;
+    // two workgroups share a CU and hide each other's per-plane latency
+    // (but one for their cell-permittivity sweeps on 64 x 16 tiles, whose
+    // 97-105 registers per lane leave room for one 11-wave workgroup: a
+    // second round of workgroups would follow the first);
     // >= 8 planes per chunk, so the two planes recomputed at each chunk
     // boundary stay a small overhead
-    const long target = st == ST_F64 ? 256 : 512;
+    const long target = (st == ST_F64 || (mode == COEF_CELL && tx * ty >= 1024)) ? 256 : 512;
     long chunks = (target + cols - 1) / cols;
     long maxchunks = G.nz / 8;
     if (maxchunks < 1) maxchunks = 1;
