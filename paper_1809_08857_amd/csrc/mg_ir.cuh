@@ -16,12 +16,17 @@ namespace mg {
 //
 // One call covers one tile: a TX x TY tile of columns (one thread each)
 // marching up a chunk of z planes.  xn (and eps) of planes k-1, k, k+1 stay
-// in the thread's registers, loaded one step ahead of use; the in-plane
-// neighbours of plane k come from an LDS plane with a one-cell halo (two
-// buffers by plane parity, so one barrier per plane).  Edge threads also
-// carry the halo cell beyond their edge; neighbours outside the box are
-// never read.  A workgroup that covers several tiles separates them by a
-// barrier (ir_tiles).
+// in the thread's registers; the in-plane neighbours of plane k come from an
+// LDS plane with a one-cell halo (two buffers by plane parity, so one
+// barrier per plane).  Edge threads also carry the halo cell beyond their
+// edge; neighbours outside the box are never read.  A workgroup that covers
+// several tiles separates them by a barrier (ir_tiles).
+//
+// The raw loads of a step (own column plane k+3, halo cells and b of plane
+// k+2) go to one of two register sets, alternating by step (the loop is
+// unrolled by two, so the sets are fixed registers): a value is consumed at
+// the end of the step after the one that loaded it, and no load is waited
+// for in the step that issues it.
 template <class TL, int MODE, bool HAS_E, int TX, int TY>
 __device__ __forceinline__ void ir_col_body(const double *__restrict__ x, const TL *__restrict__ e,
                                             double *__restrict__ xout, const double *__restrict__ b,
@@ -80,11 +85,19 @@ __device__ __forceinline__ void ir_col_body(const double *__restrict__ x, const 
     double hx0 = xval(hx, z0, ldx(colx, z0)), hy0 = xval(hy, z0, ldx(coly, z0));
     double ehx0 = eval(hx, z0, lde(colx, z0)), ehy0 = eval(hy, z0, lde(coly, z0));
     double b0 = b[at(col, z0)];
-    for (int k = z0; k < z1; ++k) {
-        // loads for the next step (raw)
-        const XR uq = ldx(col, k + 2), hx1 = ldx(colx, k + 1), hy1 = ldx(coly, k + 1);
-        const double eq = lde(col, k + 2), ehx1 = lde(colx, k + 1), ehy1 = lde(coly, k + 1);
-        const double b1 = b[at(col, k + 1)];
+    // raw loads of one step: own column (x, e, eps), halo cells, b
+    struct Raw { XR u, hx, hy; double e, ehx, ehy, b; };
+    auto issue = [&](Raw &r, int k) {  // own plane k + 1, halo and b of plane k
+        r.u = ldx(col, k + 1), r.hx = ldx(colx, k), r.hy = ldx(coly, k);
+        r.e = lde(col, k + 1), r.ehx = lde(colx, k), r.ehy = lde(coly, k);
+        r.b = b[at(col, k)];
+    };
+    Raw ra, rb;
+    issue(rb, z0 + 1);  // consumed at the end of step z0
+    // step k: issue own plane k+3 and halo/b of plane k+2 into L, compute
+    // plane k, then move in own plane k+2 and halo/b of plane k+1 from C
+    auto step = [&](int k, Raw &L, const Raw &C) __attribute__((always_inline)) {
+        issue(L, k + 2);
         // publish plane k
         const int q = k & 1;
         su[q][ly + 1][lx + 1] = u0;
@@ -138,11 +151,16 @@ __device__ __forceinline__ void ir_col_body(const double *__restrict__ x, const 
                 sb += bb * bb;
             }
         }
-        um = u0, u0 = up, up = xval(inc, k + 2, uq);
-        em = e0, e0 = ep, ep = eval(inc, k + 2, eq);
-        hx0 = xval(hx, k + 1, hx1), hy0 = xval(hy, k + 1, hy1);
-        ehx0 = eval(hx, k + 1, ehx1), ehy0 = eval(hy, k + 1, ehy1);
-        b0 = b1;
+        um = u0, u0 = up, up = xval(inc, k + 2, C.u);
+        em = e0, e0 = ep, ep = eval(inc, k + 2, C.e);
+        hx0 = xval(hx, k + 1, C.hx), hy0 = xval(hy, k + 1, C.hy);
+        ehx0 = eval(hx, k + 1, C.ehx), ehy0 = eval(hy, k + 1, C.ehy);
+        b0 = C.b;
+    };
+    for (int k = z0; k < z1; k += 2) {
+        step(k, ra, rb);
+        if (k + 1 >= z1) break;
+        step(k + 1, rb, ra);
     }
 }
 
