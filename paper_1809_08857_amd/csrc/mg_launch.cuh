@@ -83,11 +83,14 @@ hipError_t rr_tile(hipStream_t s, const Geo &G, const Coef &Cf, const void *u, c
     const int tiles_x = (G.nx + TX - 1) / TX, tiles_y = (G.ny + TY - 1) / TY;
     const long cols = (long)tiles_x * tiles_y;
     // about as many workgroups as the chip holds at once: two per CU, but one
-    // for the cell-permittivity pass on 64 x 16 tiles, whose registers
-    // (102-116 per lane) leave room for one 10-wave workgroup per CU; a
-    // second round of workgroups measured slower there (FP64 at 256^3: 91.6
-    // against 87.3 us)
-    constexpr long kTarget = (MODE == COEF_CELL && TX * TY >= 1024) ? 256 : 512;
+    // where a 10-wave workgroup of a 64 x 16 tile is all that fits, by its
+    // registers per lane: cell permittivity (102-116), stored faces in FP64
+    // or FP32 (108-136); beta = 1 (63-86) and BF16 stored faces (96) fit
+    // two.  A second round of workgroups measured slower (FP64 cell
+    // permittivity at 256^3: 91.6 against 87.3 us)
+    constexpr bool kOnePerCu =
+        TX * TY >= 1024 && (MODE == COEF_CELL || (MODE != COEF_CONST && !std::is_same<T, bf16>::value));
+    constexpr long kTarget = kOnePerCu ? 256 : 512;
     long chunks = (kTarget + cols - 1) / cols;
     long maxch = G.nz / 8;
     if (maxch < 1) maxch = 1;

@@ -185,12 +185,14 @@ int default_zchunk(const Geo &G, int tile, int st, int mode) {
     // about one workgroup per CU (a workgroup holds 5-12 waves) for FP64,
     // two for the FP32/BF16 sweeps, whose smaller register footprint lets
     // two workgroups share a CU and hide each other's per-plane latency
-    // (but one for their cell-permittivity sweeps on 64 x 16 tiles, whose
-    // 97-105 registers per lane leave room for one 11-wave workgroup: a
-    // second round of workgroups would follow the first);
+    // (but one where only one fits, which a second round of workgroups would
+    // follow: their cell-permittivity sweeps on 64 x 16 tiles, 97-105
+    // registers per lane for 11 waves, and their stored-face sweeps on 64 x 8
+    // or larger tiles, 153-168 registers for 7 or 11 waves);
     // >= 8 planes per chunk, so the two planes recomputed at each chunk
     // boundary stay a small overhead
-    const long target = (st == ST_F64 || (mode == COEF_CELL && tx * ty >= 1024)) ? 256 : 512;
+    const bool one_per_cu = (mode == COEF_CELL && tx * ty >= 1024) || (is_face_mode(mode) && tx * ty >= 512);
+    const long target = (st == ST_F64 || one_per_cu) ? 256 : 512;
     long chunks = (target + cols - 1) / cols;
     long maxchunks = G.nz / 8;
     if (maxchunks < 1) maxchunks = 1;
